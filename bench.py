@@ -1,0 +1,197 @@
+"""Benchmark of the SBQA time-stepping loop on one MI355X.
+
+Default workload (the configuration the replica-spin-update metric is quoted
+on): random 6-regular graph, N = 4096, J_e ~ N(0,1) on the edges,
+h_i ~ N(0, 0.1^2), R = 32 replicas x 64 runs (C = 2048 columns), 5000 steps,
+dt = 0.5, a0 = 1, c0 = 0.5/(sqrt(N) rms J), ternary f (Eq. 8), J_perp linear
+0.5 -> 0, x, y ~ U[-0.1, 0.1]; fp32 CSR contraction fused with the update.
+
+A bench "step" is one SBQA time step over all runs and replicas (operand,
+contraction, update). The timed region is K steps of a fresh solve followed by
+the readout (energies of all replicas and the best per run). value =
+N*R*runs*K / seconds. The dominant kernel's average duration comes from HIP
+events around every step on the context's stream; its roofline uses the
+algorithmic bytes per launch stated in the design doc.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+                       [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK = {"fp8": 5030.0, "bf16": 2520.0, "fp32": 157.3, "fp64": 78.6}  # TFLOP/s dense MFMA
+
+
+def make_workload(name: str):
+    import sbqa_instances as inst
+    if name == "sparse6":
+        N, d, R, runs, S = 4096, 6, 32, 64, 5000
+        E = inst.regular_graph(N, d, 2001)
+        csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 2002))
+        h = inst.gaussian_fields(N, 0.1, 2003)
+        desc = ("random 6-regular N=4096, J~N(0,1) on edges, h~N(0,0.1^2), R=32 x 64 runs, "
+                "5000 steps, dt=0.5, ternary f, J_perp linear 0.5->0, fp32 CSR")
+        return dict(csr=csr, h=h, N=N, R=R, runs=runs, S=S, prec=None, fmode=0, desc=desc, d=d, dtype="f32")
+    if name == "sk_fp8":
+        N, R, runs, S = 16384, 16, 16, 10000
+        return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP8", fmode=0,
+                    desc="SK N=16384 J=+-1 (e4m3), R=16 x 16 runs, 10000 steps, ternary f", dtype="fp8")
+    if name == "sk_fp32":
+        N, R, runs, S = 16384, 16, 16, 10000
+        return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32", fmode=0,
+                    desc="SK N=16384 J=+-1 (fp32 path), R=16 x 16 runs, 10000 steps, ternary f", dtype="f32")
+    if name == "gauss_bf16x3":
+        N, R, runs, S = 8192, 16, 32, 5000
+        return dict(J=inst.dense_gaussian(N, 4001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_BF16X3",
+                    fmode=2, desc="dense N=8192 J~N(0,1), ballistic, bf16 hi+lo, R=16 x 32 runs, 5000 steps",
+                    dtype="bf16x3")
+    if name == "gauss_fp32":
+        N, R, runs, S = 8192, 16, 32, 5000
+        return dict(J=inst.dense_gaussian(N, 4001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32",
+                    fmode=2, desc="dense N=8192 J~N(0,1), ballistic, fp32, R=16 x 32 runs, 5000 steps",
+                    dtype="f32")
+    if name == "sk64":
+        N, R, runs, S = 64, 8, 4, 1000
+        return dict(J=inst.sk_pm1(N, 1001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32", fmode=0,
+                    desc="SK N=64, R=8 x 4 runs, 1000 steps, fp32", dtype="f32")
+    raise SystemExit("unknown workload " + name)
+
+
+def create(sb, w, seed):
+    kw = dict(R=w["R"], runs=w["runs"], steps=w["S"], dt=0.5, a0=1.0, fmode=w["fmode"],
+              jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0, seed=seed, init_amp=0.1)
+    if w["prec"]:
+        kw["precision"] = getattr(sb, w["prec"])
+    return sb.sbqa_create(J=w.get("J"), csr=w.get("csr"), h=w.get("h"), **kw)
+
+
+def algorithmic_bytes(w, info):
+    """Bytes the dominant kernel must move per launch (one step)."""
+    N, C = w["N"], w["R"] * w["runs"]
+    if info["path"] == "csr_fp32":
+        nnz = len(w["csr"][1])
+        # x, y read + write (fp32) + int8 operand written once and read once
+        return N * C * (16 + 2) + 4 * (N + 1) + 8 * nnz + 4 * N
+    eb = {"dense_fp8": 1, "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
+    # GEMM: J streamed once + operand read once + fp32 field partial written
+    return N * N * eb + C * N * eb + C * N * 4
+
+
+def algorithmic_flops(w):
+    N, C = w["N"], w["R"] * w["runs"]
+    return 2.0 * N * N * C
+
+
+def cpu_baseline(w, sb, target_s=15.0):
+    import oracle
+    oracle.build()
+    N, R, runs, S = w["N"], w["R"], w["runs"], w["S"]
+    ctx = create(sb, w, seed=99)
+    c0 = sb.sbqa_info(ctx)["c0"]
+    X0, Y0 = sb.sbqa_get_state(ctx)
+    jt = sb.sbqa_jperp_table(ctx).astype(np.float64)
+    sb.sbqa_destroy(ctx)
+    P = oracle.Problem(N, R, runs, J=w.get("J"), csr=w.get("csr"), h=w.get("h"), dt=0.5, a0=1.0, c0=c0,
+                       fmode=w["fmode"])
+    X, Y = X0.astype(np.float64), Y0.astype(np.float64)
+    t0 = time.perf_counter()
+    n = 0
+    while n < S and (time.perf_counter() - t0) < target_s:
+        X, Y = P.step(X, Y, oracle.pump(n, S), oracle.delta32(0.7, n, S), jt[:, n])
+        n += 1
+    dt = time.perf_counter() - t0
+    return {"value": N * R * runs * n / dt, "unit": "replica-spin updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle", "sample": "first %d of %d steps of the same workload (FP64 C oracle, OpenMP)" % (n, S)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="sparse6")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-events", action="store_true", help="no per-step events in the timed region")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print("bench.py measures one GPU only: the SBQA runs of one instance are independent and the "
+              "library has no multi-GPU path; run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2604_01050_amd as sb
+    torch.cuda.set_device(0)
+    w = make_workload(a.workload)
+    K = a.steps if a.steps is not None else w["S"]
+    if K < 1 or K > w["S"]:
+        raise SystemExit("--steps must be in [1, %d] (one solve of the schedule)" % w["S"])
+    stream = torch.cuda.Stream()
+
+    # warmup: a separate solve
+    ctx = create(sb, w, seed=1)
+    sb.sbqa_set_stream(ctx, stream)
+    sb.sbqa_step(ctx, min(a.warmup, w["S"]))
+    sb.sbqa_best(ctx)
+    sb.sbqa_destroy(ctx)
+
+    ctx = create(sb, w, seed=2)
+    sb.sbqa_set_stream(ctx, stream)
+    info = sb.sbqa_info(ctx)
+    torch.cuda.synchronize()
+    ev = [] if a.no_events else [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                                 for _ in range(K)]
+    t0 = time.perf_counter()
+    for q in range(K):
+        if ev:
+            ev[q][0].record(stream)
+        sb.sbqa_step(ctx, 1)
+        if ev:
+            ev[q][1].record(stream)
+    E, spins = sb.sbqa_best(ctx)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    N, R, runs = w["N"], w["R"], w["runs"]
+    value = N * R * runs * K / t
+    step_ms = [s.elapsed_time(e) for s, e in ev] if ev else []
+    out = {
+        "metric": "replica-spin updates/s (N*R*runs*steps/s)",
+        "value": value, "unit": "replica-spin updates/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
+        "ms_per_step": 1e3 * t / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": w["dtype"], "data": "synthetic",
+        "config": {"workload": w["desc"], "N": N, "R": R, "runs": runs, "schedule_steps": w["S"],
+                   "path": info["path"]},
+        "best_energy": {"mean": float(np.mean(E)), "min": float(np.min(E))},
+    }
+    if step_ms:
+        avg_s = float(np.mean(step_ms)) * 1e-3
+        if info["path"] == "csr_fp32":
+            ab = algorithmic_bytes(w, info)
+            out["roofline"] = {"bound": "hbm", "achieved": ab / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ab / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                               "kernel": "k_csr_step", "avg_launch_us": avg_s * 1e6,
+                               "algorithmic_bytes_per_launch": ab}
+        else:
+            fl = algorithmic_flops(w)
+            peak = PEAK[{"dense_fp8": "fp8", "dense_fp32": "fp32", "dense_bf16x3": "bf16"}[info["path"]]]
+            out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+                               "frac": fl / avg_s / 1e12 / peak, "traffic": None, "kernel": "k_gemm + k_dense_update",
+                               "avg_step_us": avg_s * 1e6, "algorithmic_flops_per_step": fl}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, sb)
+    sb.sbqa_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -72,6 +72,7 @@ def _declare(L):
     L.orc_fields_dense.argtypes = [i32, i32, vp, vp, vp]
     L.orc_fields_csr.argtypes = [i32, i32, vp, vp, vp, vp, vp]
     L.orc_step.argtypes = [ct.POINTER(_Problem), vp, vp, d, f32, vp, vp, vp]
+    L.orc_step_rows.argtypes = [ct.POINTER(_Problem), vp, vp, d, f32, vp, i32, vp, vp, vp, vp, vp]
     L.orc_run.argtypes = [ct.POINTER(_Problem), vp, vp, i64, vp, d, i64, vp, vp, vp]
     L.orc_run.restype = i32
     L.orc_auto_c0_dense.argtypes, L.orc_auto_c0_dense.restype = [i32, vp], d
@@ -217,6 +218,19 @@ class Problem:
         lib().orc_step(ct.byref(self._s), _p(X), _p(Y), float(a_n),
                        float(np.float32(delta_n)), _p(jr), _p(scratch), _p(Phi))
         return (X, Y, Phi) if want_phi else (X, Y)
+
+    def step_rows(self, X, Y, a_n, delta_n, jperp_r, rows):
+        """The step restricted to the given rows: returns (X', Y', Phi) of shape (len(rows), C)."""
+        X = _f64(X)
+        Y = _f64(Y)
+        rows = _i32(rows)
+        jr = _f64(np.broadcast_to(np.asarray(jperp_r, dtype=np.float64), (self.runs,)))
+        n = rows.size
+        Xo, Yo, Po = (np.empty((n, self.C)) for _ in range(3))
+        scratch = np.empty(X.size)
+        lib().orc_step_rows(ct.byref(self._s), _p(X), _p(Y), float(a_n), float(np.float32(delta_n)),
+                            _p(jr), n, _p(rows), _p(scratch), _p(Xo), _p(Yo), _p(Po))
+        return Xo, Yo, Po
 
     def run(self, X, Y, S, jperp_table, delta_max=0.7, energy_every=0):
         """S steps from (X, Y); jperp_table (runs, S). Returns dict of results."""

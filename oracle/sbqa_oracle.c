@@ -223,50 +223,96 @@ typedef struct {
     int32_t fmode;
 } orc_problem;
 
+/* Coupling sum of row i for all C columns: phi[c] = sum_j J_ij G[j][c]. */
+static void field_row(const orc_problem *P, int32_t i, const double *G, double *phi) {
+    const int32_t N = P->N, C = P->R * P->runs;
+    for (int32_t c = 0; c < C; ++c) phi[c] = 0.0;
+    if (P->dense) {
+        for (int32_t j = 0; j < N; ++j) {
+            const double w = P->dense[(int64_t)i * N + j];
+            const double *g = G + (int64_t)j * C;
+            for (int32_t c = 0; c < C; ++c) phi[c] += w * g[c];
+        }
+    } else {
+        for (int32_t p = P->row_ptr[i]; p < P->row_ptr[i + 1]; ++p) {
+            const double w = P->val[p];
+            const double *g = G + (int64_t)P->col[p] * C;
+            for (int32_t c = 0; c < C; ++c) phi[c] += w * g[c];
+        }
+    }
+}
+
 /*
- * Advance (X, Y) by one step:
- *   G    = f(X) with threshold delta_n                         (Eq. 8)
- *   Phi  = J G                                                 (Eq. 7, coupling sum)
- *   ring = X[i, r*R + (k-1 mod R)] + X[i, r*R + (k+1 mod R)]   (Eq. 7, periodic ring of S1)
- *   Y   += dt * ( -((a0 - a_n)/R) X + (c0/R)(Phi + h_i) + J_perp[r] ring )
- *   X   += dt * (a0/R) Y
- *   |X| > 1  ->  X = sign(X), Y = 0                            (wall, Sec. II.A)
+ * Update of row i (all columns) from the step-n positions X0 (Eqs. 6-7 + wall):
+ *   ring = X0[i, r*R + (k-1 mod R)] + X0[i, r*R + (k+1 mod R)]   (periodic ring, S1)
+ *   y'   = y + dt * ( -((a0 - a_n)/R) x + (c0/R)(phi + h_i) + J_perp[r] ring )
+ *   x'   = x + dt * (a0/R) y'
+ *   |x'| > 1  ->  x' = sign(x'), y' = 0                         (wall, Sec. II.A)
+ */
+static void update_row(const orc_problem *P, int32_t i, const double *X0, const double *Yin,
+                       const double *phi, double a_n, const double *jperp_r, double *xo, double *yo) {
+    const int32_t R = P->R, C = P->R * P->runs;
+    const double Rd = (double)R;
+    const double hi = P->h ? P->h[i] : 0.0;
+    const double *xrow = X0 + (int64_t)i * C;
+    for (int32_t c = 0; c < C; ++c) {
+        const int32_t r = c / R, k = c % R;
+        const double x = xrow[c];
+        const double xl = xrow[r * R + (k + R - 1) % R];
+        const double xr = xrow[r * R + (k + 1) % R];
+        const double force = -((P->a0 - a_n) / Rd) * x
+                             + (P->c0 / Rd) * (phi[c] + hi)
+                             + jperp_r[r] * (xl + xr);
+        double y = Yin[(int64_t)i * C + c] + P->dt * force;
+        double xn = x + P->dt * (P->a0 / Rd) * y;
+        float xf = (float)xn;                       /* wall decision in binary32 */
+        if (fabsf(xf) > 1.0f) {
+            xn = xn > 0.0 ? 1.0 : -1.0;
+            y = 0.0;
+        }
+        xo[c] = xn;
+        yo[c] = y;
+    }
+}
+
+/*
+ * Advance (X, Y) by one step, all runs and replicas (Jacobi: every term uses
+ * the step-n positions): G = f(X) with threshold delta_n (Eq. 8), phi = J G,
+ * then update_row for every row.
  * scratch: 3*N*C doubles (G, Phi, old X). Phi_out (optional) receives Phi.
  */
 void orc_step(const orc_problem *P, double *X, double *Y, double a_n, float delta_n,
               const double *jperp_r, double *scratch, double *Phi_out) {
-    const int32_t N = P->N, R = P->R, C = P->R * P->runs;
+    const int32_t N = P->N, C = P->R * P->runs;
     const int64_t NC = (int64_t)N * C;
     double *G = scratch, *Phi = scratch + NC, *X0 = scratch + 2 * NC;
     memcpy(X0, X, sizeof(double) * (size_t)NC);
     orc_apply_f(P->fmode, delta_n, NC, X0, G);
-    if (P->dense) orc_fields_dense(N, C, P->dense, G, Phi);
-    else orc_fields_csr(N, C, P->row_ptr, P->col, P->val, G, Phi);
-    if (Phi_out) memcpy(Phi_out, Phi, sizeof(double) * (size_t)NC);
-
-    const double Rd = (double)R;
     #pragma omp parallel for schedule(static)
     for (int32_t i = 0; i < N; ++i) {
-        const double hi = P->h ? P->h[i] : 0.0;
-        for (int32_t c = 0; c < C; ++c) {
-            const int32_t r = c / R, k = c % R;
-            const int64_t e = (int64_t)i * C + c;
-            const double x = X0[e];
-            const double xl = X0[(int64_t)i * C + r * R + (k + R - 1) % R];
-            const double xr = X0[(int64_t)i * C + r * R + (k + 1) % R];
-            const double force = -((P->a0 - a_n) / Rd) * x
-                                 + (P->c0 / Rd) * (Phi[e] + hi)
-                                 + jperp_r[r] * (xl + xr);
-            double y = Y[e] + P->dt * force;
-            double xn = x + P->dt * (P->a0 / Rd) * y;
-            float xf = (float)xn;                       /* wall decision in binary32 */
-            if (fabsf(xf) > 1.0f) {
-                xn = xn > 0.0 ? 1.0 : -1.0;
-                y = 0.0;
-            }
-            X[e] = xn;
-            Y[e] = y;
-        }
+        field_row(P, i, G, Phi + (int64_t)i * C);
+        update_row(P, i, X0, Y, Phi + (int64_t)i * C, a_n, jperp_r,
+                   X + (int64_t)i * C, Y + (int64_t)i * C);
+    }
+    if (Phi_out) memcpy(Phi_out, Phi, sizeof(double) * (size_t)NC);
+}
+
+/*
+ * The same step for a sample of rows only (for checks at sizes where a full
+ * step is too slow): X, Y unchanged; rows[nrows]; outputs Xo, Yo, Phio are
+ * nrows x C. scratch: N*C doubles (G).
+ */
+void orc_step_rows(const orc_problem *P, const double *X, const double *Y, double a_n,
+                   float delta_n, const double *jperp_r, int32_t nrows, const int32_t *rows,
+                   double *scratch, double *Xo, double *Yo, double *Phio) {
+    const int32_t N = P->N, C = P->R * P->runs;
+    double *G = scratch;
+    orc_apply_f(P->fmode, delta_n, (int64_t)N * C, X, G);
+    #pragma omp parallel for schedule(static)
+    for (int32_t q = 0; q < nrows; ++q) {
+        field_row(P, rows[q], G, Phio + (int64_t)q * C);
+        update_row(P, rows[q], X, Y, Phio + (int64_t)q * C, a_n, jperp_r,
+                   Xo + (int64_t)q * C, Yo + (int64_t)q * C);
     }
 }
 

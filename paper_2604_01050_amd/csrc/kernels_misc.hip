@@ -1,0 +1,255 @@
+// Initial state, readout, energies and best-solution selection for gfx950.
+//   * Initial state: x, y ~ U[-amp, amp] ("random state", Sec. II.A) from the
+//     counter-based Philox4x32-10 generator (Salmon et al., SC'11), keyed by
+//     the seed and counted by (i, c), so the draw is layout-independent.
+//   * Energies E(s) = -1/2 s^T J s - h^T s of readouts s = sign(x) (sign(0) =
+//     +1) in float64 with fixed-order reductions (exact for integer J, h).
+//   * Best per run over its R replicas (Sec. II.B), ties -> lowest replica,
+//     earlier evaluations kept on equal energy.
+#include "sbqa_internal.h"
+
+namespace sbqa {
+namespace {
+
+// Philox4x32 round constants (multipliers and Weyl key increments).
+constexpr uint32_t PHILOX_M0 = 0xD2511F53u, PHILOX_M1 = 0xCD9E8D57u;
+constexpr uint32_t PHILOX_W0 = 0x9E3779B9u, PHILOX_W1 = 0xBB67AE85u;
+
+__device__ __forceinline__ uint4 philox4x32_10(uint4 ctr, uint2 key) {
+#pragma unroll
+    for (int rnd = 0; rnd < 10; ++rnd) {
+        if (rnd > 0) {
+            key.x += PHILOX_W0;
+            key.y += PHILOX_W1;
+        }
+        const uint64_t p0 = (uint64_t)PHILOX_M0 * ctr.x;
+        const uint64_t p1 = (uint64_t)PHILOX_M1 * ctr.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        ctr = make_uint4(hi1 ^ ctr.y ^ key.x, lo1, hi0 ^ ctr.w ^ key.y, lo0);
+    }
+    return ctr;
+}
+
+// u in [0, 1) with 24 random bits, then amp*(2u - 1) in float64 rounded once.
+__device__ __forceinline__ float uniform_sym(uint32_t bits, double amp) {
+    const double u = (double)(bits >> 8) * (1.0 / 16777216.0);
+    return (float)(amp * (2.0 * u - 1.0));
+}
+
+__global__ void k_init_state(int N, int C, int ld, int spin_major, uint32_t key_lo, uint32_t key_hi,
+                             double amp, float *__restrict__ x, float *__restrict__ y) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * C) return;
+    const int i = (int)(e / C), c = (int)(e % C);
+    const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)c, 0u, 0u), make_uint2(key_lo, key_hi));
+    const int64_t o = spin_major ? (int64_t)i * ld + c : (int64_t)c * ld + i;
+    x[o] = uniform_sym(r.x, amp);
+    y[o] = uniform_sym(r.y, amp);
+}
+
+__global__ void k_readout_f64(int N, int Np, int C, int ld, int spin_major, const float *__restrict__ x,
+                              double *__restrict__ S) {
+    const int c = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Np) return;
+    double s = 0.0;
+    if (i < N && c < C) {
+        const float v = spin_major ? x[(int64_t)i * ld + c] : x[(int64_t)c * ld + i];
+        s = v >= 0.0f ? 1.0 : -1.0;
+    }
+    S[(int64_t)c * Np + i] = s;
+}
+
+__global__ void k_spins_to_f64(int N, int Np, int count, const int8_t *__restrict__ spins, double *__restrict__ S) {
+    const int m = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Np) return;
+    S[(int64_t)m * Np + i] = (i < N && m < count) ? (double)spins[(int64_t)m * N + i] : 0.0;
+}
+
+// Block per configuration; per-thread strided sums, then a fixed LDS tree.
+__global__ __launch_bounds__(256) void k_energy_reduce(int N, int Np, int Cp, int splits,
+                                                       const double *__restrict__ phis,
+                                                       const double *__restrict__ S,
+                                                       const double *__restrict__ h, double *__restrict__ E) {
+    __shared__ double sq[256], sl[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    double q = 0.0, l = 0.0;
+    for (int i = t; i < N; i += 256) {
+        double phi = phis[(int64_t)c * Np + i];
+        for (int z = 1; z < splits; ++z) phi += phis[((int64_t)z * Cp + c) * Np + i];
+        const double s = S[(int64_t)c * Np + i];
+        q += s * phi;
+        if (h) l += h[i] * s;
+    }
+    sq[t] = q;
+    sl[t] = l;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sq[t] += sq[t + w];
+            sl[t] += sl[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) E[c] = -0.5 * sq[0] - sl[0];
+}
+
+// CSR energies of the readout of a spin-major state. Stage 1: block (row
+// block rb, 256 columns) accumulates per column over its rows in row order.
+__global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int Cs, int C, int rows_per_blk,
+                                                            const int32_t *__restrict__ row_ptr,
+                                                            const int32_t *__restrict__ col,
+                                                            const double *__restrict__ val,
+                                                            const double *__restrict__ h,
+                                                            const float *__restrict__ x,
+                                                            double *__restrict__ partial) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int rb = blockIdx.y;
+    if (c >= C) return;
+    double q = 0.0, l = 0.0;
+    const int i0 = rb * rows_per_blk, i1 = min(N, i0 + rows_per_blk);
+    for (int i = i0; i < i1; ++i) {
+        double phi = 0.0;
+        for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+            const float xv = x[(int64_t)col[p] * Cs + c];
+            phi += val[p] * (xv >= 0.0f ? 1.0 : -1.0);
+        }
+        const double s = x[(int64_t)i * Cs + c] >= 0.0f ? 1.0 : -1.0;
+        q += s * phi;
+        if (h) l += h[i] * s;
+    }
+    partial[((int64_t)rb * C + c) * 2] = q;
+    partial[((int64_t)rb * C + c) * 2 + 1] = l;
+}
+
+__global__ void k_csr_energy_final(int C, int nrb, const double *__restrict__ partial, double *__restrict__ E) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    double q = 0.0, l = 0.0;
+    for (int rb = 0; rb < nrb; ++rb) {
+        q += partial[((int64_t)rb * C + c) * 2];
+        l += partial[((int64_t)rb * C + c) * 2 + 1];
+    }
+    E[c] = -0.5 * q - l;
+}
+
+__global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *__restrict__ row_ptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const double *__restrict__ val,
+                                                          const double *__restrict__ h,
+                                                          const int8_t *__restrict__ spins, double *__restrict__ E) {
+    __shared__ double sq[256], sl[256];
+    const int m = blockIdx.x, t = threadIdx.x;
+    const int8_t *s = spins + (int64_t)m * N;
+    double q = 0.0, l = 0.0;
+    for (int i = t; i < N; i += 256) {
+        double phi = 0.0;
+        for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) phi += val[p] * (double)s[col[p]];
+        q += (double)s[i] * phi;
+        if (h) l += h[i] * (double)s[i];
+    }
+    sq[t] = q;
+    sl[t] = l;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sq[t] += sq[t + w];
+            sl[t] += sl[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) E[m] = -0.5 * sq[0] - sl[0];
+}
+
+// Block per run: argmin over the run's replicas (tie -> lowest k); replace the
+// stored best only when strictly lower; copy the winner's readout spins.
+__global__ __launch_bounds__(256) void k_best_update(int N, int R, int ld, int spin_major,
+                                                     const float *__restrict__ x, const double *__restrict__ E,
+                                                     double *__restrict__ best_E, int64_t *__restrict__ best_step,
+                                                     int8_t *__restrict__ best_spins, int64_t step) {
+    __shared__ int s_win;
+    const int r = blockIdx.x;
+    if (threadIdx.x == 0) {
+        int kb = 0;
+        double eb = E[(int64_t)r * R];
+        for (int k = 1; k < R; ++k) {
+            const double e = E[(int64_t)r * R + k];
+            if (e < eb) { eb = e; kb = k; }
+        }
+        s_win = (eb < best_E[r]) ? kb : -1;
+        if (s_win >= 0) {
+            best_E[r] = eb;
+            best_step[r] = step;
+        }
+    }
+    __syncthreads();
+    const int kb = s_win;
+    if (kb < 0) return;
+    const int c = r * R + kb;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+        const float v = spin_major ? x[(int64_t)i * ld + c] : x[(int64_t)c * ld + i];
+        best_spins[(int64_t)r * N + i] = v >= 0.0f ? 1 : -1;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_init_state(int N, int C, int ld, bool spin_major, uint64_t seed, double amp, float *x, float *y,
+                             hipStream_t st) {
+    const int64_t n = (int64_t)N * C;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_init_state, grid, block, 0, st, N, C, ld, spin_major ? 1 : 0, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), amp, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_readout_f64(int N, int Np, int C, int ld, bool spin_major, const float *x, double *S,
+                              hipStream_t st) {
+    // S has Cp >= C rows; rows c >= C are written as zero by the grid below.
+    const int Cp = (C + GEMM_BM - 1) / GEMM_BM * GEMM_BM;
+    dim3 grid((Np + 255) / 256, Cp), block(256);
+    hipLaunchKernelGGL(k_readout_f64, grid, block, 0, st, N, Np, C, ld, spin_major ? 1 : 0, x, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_spins_to_f64(int N, int Np, int count, const int8_t *spins, double *S, hipStream_t st) {
+    const int Cp = (count + GEMM_BM - 1) / GEMM_BM * GEMM_BM;
+    dim3 grid((Np + 255) / 256, Cp), block(256);
+    hipLaunchKernelGGL(k_spins_to_f64, grid, block, 0, st, N, Np, count, spins, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_reduce(int N, int Np, int count, int Cp, int splits, const double *phis, const double *S,
+                                const double *h, double *E, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_reduce, dim3(count), dim3(256), 0, st, N, Np, Cp, splits, phis, S, h, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_energy_state(int N, int Cs, int C, const int32_t *row_ptr, const int32_t *col,
+                                   const double *val, const double *h, const float *x, double *partial,
+                                   int nblk_rows, double *E, hipStream_t st) {
+    const int rows_per_blk = (N + nblk_rows - 1) / nblk_rows;
+    dim3 grid((C + 255) / 256, nblk_rows), block(256);
+    hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, Cs, C, rows_per_blk, row_ptr, col, val, h, x,
+                       partial);
+    hipLaunchKernelGGL(k_csr_energy_final, dim3((C + 255) / 256), dim3(256), 0, st, C, nblk_rows, partial, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col, const double *val,
+                                   const double *h, const int8_t *spins, double *E, hipStream_t st) {
+    hipLaunchKernelGGL(k_csr_energy_spins, dim3(count), dim3(256), 0, st, N, row_ptr, col, val, h, spins, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_best_update(int N, int R, int runs, int ld, bool spin_major, const float *x, const double *E,
+                              double *best_E, int64_t *best_step, int8_t *best_spins, int64_t step,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_best_update, dim3(runs), dim3(256), 0, st, N, R, ld, spin_major ? 1 : 0, x, E, best_E,
+                       best_step, best_spins, step);
+    return hipGetLastError();
+}
+
+}  // namespace sbqa

@@ -1,0 +1,781 @@
+// Host runtime of the SBQA library: validation, schedules (Eq. 5, Eq. 8 and
+// the pump of Sec. II.A), the per-run (beta, alpha) auto-tuning draw of
+// Sec. II.B, device buffers, and the step / readout / energy dispatch.
+#include "sbqa_ctx.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace sbqa {
+
+static thread_local std::string g_err;
+
+sbqa_status fail(sbqa_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+void clear_error() { g_err.clear(); }
+const char *last_error() { return g_err.c_str(); }
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return fail(e_ == hipErrorOutOfMemory ? SBQA_ENOMEM : SBQA_EDEVICE, "%s: %s (%s:%d)", \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                     \
+    } while (0)
+
+static int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// splitmix64 (Steele, Lea, Flood 2014): host stream for the (beta, alpha) draws.
+static uint64_t splitmix64(uint64_t &s) {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+static double unit_double(uint64_t &s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0); }
+
+static uint16_t bf16_rne_host(float v) {
+    uint32_t u;
+    std::memcpy(&u, &v, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+static float bf16_to_float_host(uint16_t b) {
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// ---------------------------------------------------------------- validation
+sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
+                              const sbqa_schedule *s, InstanceFacts *facts) {
+    if (!J || !s) return fail(SBQA_EINVAL, "J and schedule must be non-NULL");
+    if (N < 1 || R < 1 || runs < 1) return fail(SBQA_EINVAL, "N, R and runs must be >= 1 (got %d, %d, %d)", N, R, runs);
+    if ((int64_t)R * runs > (1 << 24)) return fail(SBQA_EINVAL, "runs*R too large");
+    if (s->steps < 1) return fail(SBQA_EINVAL, "steps must be >= 1");
+    if (!(s->dt > 0) || !std::isfinite(s->dt)) return fail(SBQA_EINVAL, "dt must be finite and > 0");
+    if (!(s->a0 > 0) || !std::isfinite(s->a0)) return fail(SBQA_EINVAL, "a0 must be finite and > 0");
+    if (!std::isfinite(s->c0)) return fail(SBQA_EINVAL, "c0 must be finite");
+    if (s->fmode < 0 || s->fmode > 2) return fail(SBQA_EINVAL, "unknown fmode %d", s->fmode);
+    if (!std::isfinite(s->delta_max) || s->delta_max < 0) return fail(SBQA_EINVAL, "delta_max must be finite and >= 0");
+    if (s->precision < 0 || s->precision > 3) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
+    if (!(s->init_amp >= 0) || !std::isfinite(s->init_amp)) return fail(SBQA_EINVAL, "init_amp must be finite and >= 0");
+    switch (s->jp_kind) {
+        case SBQA_JP_LINEAR:
+            if (!std::isfinite(s->jp_start) || !std::isfinite(s->jp_end)) return fail(SBQA_EINVAL, "jp_start/jp_end must be finite");
+            break;
+        case SBQA_JP_PAPER:
+            if (!(s->gamma0_over_R > 0) || !std::isfinite(s->gamma0_over_R)) return fail(SBQA_EINVAL, "gamma0_over_R must be > 0");
+            if (!s->beta && !(s->beta_lo > 0 && s->beta_hi >= s->beta_lo && std::isfinite(s->beta_hi)))
+                return fail(SBQA_EINVAL, "need 0 < beta_lo <= beta_hi");
+            if (!s->alpha && !(s->alpha_lo > 0 && s->alpha_hi >= s->alpha_lo && std::isfinite(s->alpha_hi)))
+                return fail(SBQA_EINVAL, "need 0 < alpha_lo <= alpha_hi");
+            if (s->beta)
+                for (int r = 0; r < runs; ++r)
+                    if (!(s->beta[r] > 0) || !std::isfinite(s->beta[r])) return fail(SBQA_EINVAL, "beta[%d] must be > 0", r);
+            if (s->alpha)
+                for (int r = 0; r < runs; ++r)
+                    if (!(s->alpha[r] > 0) || !std::isfinite(s->alpha[r])) return fail(SBQA_EINVAL, "alpha[%d] must be > 0", r);
+            break;
+        case SBQA_JP_TABLE:
+            if (!s->jp_table) return fail(SBQA_EINVAL, "JP_TABLE needs jp_table");
+            for (int64_t q = 0; q < (int64_t)runs * s->steps; ++q)
+                if (!std::isfinite(s->jp_table[q])) return fail(SBQA_EINVAL, "jp_table[%lld] not finite", (long long)q);
+            break;
+        default: return fail(SBQA_EINVAL, "unknown jp_kind %d", s->jp_kind);
+    }
+
+    const bool dense = J->dense != nullptr;
+    const bool csr = J->row_ptr || J->col || J->val;
+    if (dense == csr) return fail(SBQA_EINVAL, "exactly one of J.dense or the CSR arrays must be given");
+    bool integral = true, ternary = true;
+    double ss = 0.0;
+    auto note = [&](double v) {
+        if (v != std::floor(v) || std::fabs(v) > 2147483647.0) integral = false;
+        if (!(v == 0.0 || v == 1.0 || v == -1.0)) ternary = false;
+    };
+    if (dense) {
+        if ((int64_t)N * N > (int64_t)1 << 32) return fail(SBQA_EINVAL, "dense N too large");
+        const double *A = J->dense;
+        for (int64_t i = 0; i < N; ++i) {
+            if (A[i * N + i] != 0.0) return fail(SBQA_EINVAL, "J has a non-zero diagonal at %lld", (long long)i);
+            for (int64_t j = 0; j < N; ++j) {
+                const double v = A[i * N + j];
+                if (!std::isfinite(v)) return fail(SBQA_EINVAL, "J[%lld][%lld] is not finite", (long long)i, (long long)j);
+                if (j > i && v != A[j * N + i]) return fail(SBQA_EINVAL, "J is not symmetric at (%lld,%lld)", (long long)i, (long long)j);
+                note(v);
+                ss += v * v;
+            }
+        }
+        facts->nnz = 0;
+    } else {
+        if (!J->row_ptr || !J->col || !J->val) return fail(SBQA_EINVAL, "CSR needs row_ptr, col and val");
+        const int32_t *rp = J->row_ptr, *cl = J->col;
+        const double *vl = J->val;
+        if (rp[0] != 0 || (int64_t)rp[N] != J->nnz || J->nnz < 0) return fail(SBQA_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] == nnz");
+        for (int32_t i = 0; i < N; ++i) {
+            if (rp[i + 1] < rp[i]) return fail(SBQA_EINVAL, "row_ptr decreases at row %d", i);
+            for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+                if (cl[p] < 0 || cl[p] >= N) return fail(SBQA_EINVAL, "col[%d] = %d out of range", p, cl[p]);
+                if (p > rp[i] && cl[p] <= cl[p - 1]) return fail(SBQA_EINVAL, "columns of row %d not strictly ascending", i);
+                if (!std::isfinite(vl[p])) return fail(SBQA_EINVAL, "val[%d] not finite", p);
+                if (cl[p] == i && vl[p] != 0.0) return fail(SBQA_EINVAL, "J has a non-zero diagonal at %d", i);
+                const int32_t j = cl[p];
+                const int32_t *b = cl + rp[j], *e = cl + rp[j + 1];
+                const int32_t *f = std::lower_bound(b, e, i);
+                if (f == e || *f != i || vl[rp[j] + (f - b)] != vl[p])
+                    return fail(SBQA_EINVAL, "CSR J is not symmetric at (%d,%d)", i, j);
+                note(vl[p]);
+                if (cl[p] != i) ss += vl[p] * vl[p];
+            }
+        }
+        facts->nnz = J->nnz;
+    }
+    if (h)
+        for (int32_t i = 0; i < N; ++i) {
+            if (!std::isfinite(h[i])) return fail(SBQA_EINVAL, "h[%d] not finite", i);
+            if (h[i] != std::floor(h[i])) integral = false;
+        }
+    facts->dense = dense;
+    facts->integral = integral;
+    facts->ternary = ternary;
+    facts->rms = (N > 1 && ss > 0) ? std::sqrt(ss / ((double)N * (double)(N - 1))) : 0.0;
+
+    // contraction path
+    int prec = s->precision;
+    if (!dense) {
+        if (prec != SBQA_PREC_AUTO && prec != SBQA_PREC_FP32)
+            return fail(SBQA_EINVAL, "CSR couplings support only fp32 precision");
+        facts->path = PATH_CSR;
+    } else {
+        if (prec == SBQA_PREC_AUTO) prec = (ternary && s->fmode != SBQA_F_BALLISTIC) ? SBQA_PREC_FP8 : SBQA_PREC_FP32;
+        if (prec == SBQA_PREC_FP8) {
+            if (s->fmode == SBQA_F_BALLISTIC) return fail(SBQA_EINVAL, "FP8 precision needs ternary or sign f (ballistic operands are not exact in e4m3)");
+            if (!ternary) return fail(SBQA_EINVAL, "FP8 precision needs J in {-1,0,+1}");
+        }
+        facts->path = prec == SBQA_PREC_FP8 ? PATH_FP8 : prec == SBQA_PREC_BF16X3 ? PATH_BF16X3 : PATH_F32;
+    }
+    return SBQA_OK;
+}
+
+// Geometry and byte count of a context (also used by the server's admission).
+void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Layout *L) {
+    const int64_t C = (int64_t)R * runs;
+    L->C = (int)C;
+    L->Np = (int)round_up(N, GEMM_BN);
+    L->Cp = (int)round_up(C, GEMM_BM);
+    L->Cs = (int)round_up(C, 4);
+    L->splits = 1;
+    L->esplits = 1;
+    int64_t b = 0;
+    if (f.path == PATH_CSR) {
+        b += 2 * (int64_t)N * L->Cs * 4 + (int64_t)N * L->Cs * 4;        // x ping-pong, y
+        b += 2 * (int64_t)N * L->Cs;                                      // int8 operand ping-pong
+        b += (int64_t)(N + 1) * 4 + f.nnz * (4 + 4 + 8);                 // CSR
+        b += (int64_t)N * 12;                                             // h32, h64
+        L->csr_nrb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (N + 63) / 64));
+        b += (int64_t)L->csr_nrb * C * 16;
+        b += (int64_t)N * L->Cs * 4;                                      // phi (fields hook)
+    } else {
+        const int eb = f.path == PATH_F32 ? 4 : f.path == PATH_FP8 ? 1 : 2;
+        const int64_t tiles = (int64_t)(L->Np / GEMM_BN) * (L->Cp / GEMM_BM);
+        const int64_t nk = (int64_t)L->Np * eb / GEMM_KB;
+        int sp = 1;
+        while (tiles * sp < 512 && sp < 8 && nk % (2 * sp) == 0 && nk / (2 * sp) >= 4) sp *= 2;
+        L->splits = sp;
+        const int64_t nke = (int64_t)L->Np * 8 / GEMM_KB;
+        int es = 1;
+        while (tiles * es < 512 && es < 8 && nke % (2 * es) == 0 && nke / (2 * es) >= 4) es *= 2;
+        L->esplits = es;
+        b += 3 * C * (int64_t)L->Np * 4;                                  // x ping-pong, y
+        b += (int64_t)L->Cp * L->Np * eb * (f.path == PATH_BF16X3 ? 2 : 1);  // operand
+        b += (int64_t)sp * L->Cp * L->Np * 4;                             // phi partials
+        b += (int64_t)L->Np * L->Np * eb * (f.path == PATH_BF16X3 ? 2 : 1);  // J
+        b += (int64_t)L->Np * L->Np * 8;                                  // J fp64 (energies)
+        b += (int64_t)L->Np * 12;                                         // h
+        b += (int64_t)L->Cp * L->Np * 8 * (1 + es);                      // readout + energy partials
+        L->csr_nrb = 0;
+    }
+    b += (int64_t)runs * (int64_t)0;  // schedule tables counted by the caller (steps known there)
+    b += C * 8 + (int64_t)runs * (16 + N);                                // E, best
+    L->bytes = (size_t)b;
+}
+
+size_t instance_bytes(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, uint32_t steps) {
+    Layout L;
+    plan_layout(N, R, runs, f, &L);
+    return L.bytes + (size_t)runs * steps * 4;
+}
+
+// ----------------------------------------------------------------- schedules
+void build_schedule_host(const sbqa_schedule *s, int32_t runs, std::vector<double> &beta, std::vector<double> &alpha,
+                         std::vector<float> &jp) {
+    const uint32_t S = s->steps;
+    beta.assign(runs, 0.0);
+    alpha.assign(runs, 0.0);
+    uint64_t st = s->seed ^ 0xA5A5F00DBAADC0DEull;
+    for (int r = 0; r < runs; ++r) {
+        const double u1 = unit_double(st), u2 = unit_double(st);
+        beta[r] = s->beta ? s->beta[r] : s->beta_lo + (s->beta_hi - s->beta_lo) * u1;
+        alpha[r] = s->alpha ? s->alpha[r] : s->alpha_lo + (s->alpha_hi - s->alpha_lo) * u2;
+    }
+    jp.assign((size_t)runs * S, 0.0f);
+    for (int r = 0; r < runs; ++r)
+        for (uint32_t n = 0; n < S; ++n) {
+            const double sn = (double)n / (double)S;   // t/T at the start of step n
+            double v;
+            if (s->jp_kind == SBQA_JP_LINEAR) v = s->jp_start + (s->jp_end - s->jp_start) * sn;
+            else if (s->jp_kind == SBQA_JP_PAPER) {
+                const double gx = s->gamma0_over_R * (std::pow(1.0 - sn, alpha[r]) + 1e-5);  // Eq. 5
+                v = -std::log(std::tanh(beta[r] * gx)) / (2.0 * beta[r]);
+            } else v = s->jp_table[(size_t)r * S + n];
+            jp[(size_t)r * S + n] = (float)v;
+        }
+}
+
+StepCoef step_coef(const sbqa_schedule *s, double c0, int R, uint32_t n) {
+    const double S = (double)s->steps;
+    StepCoef k;
+    k.kA = (float)((s->a0 - (double)n / S) / (double)R);
+    k.kB = (float)(c0 / (double)R);
+    k.dt = (float)s->dt;
+    k.kD = (float)(s->dt * s->a0 / (double)R);
+    k.delta_next = (float)((s->delta_max * (double)(n + 1)) / S);
+    return k;
+}
+
+float delta_at(const sbqa_schedule *s, uint32_t n) {
+    return (float)((s->delta_max * (double)n) / (double)s->steps);
+}
+
+}  // namespace sbqa
+
+using namespace sbqa;
+
+// =========================================================================== //
+//                                 context                                     //
+// =========================================================================== //
+
+sbqa_ctx::~sbqa_ctx() {
+    for (void *p : allocs) (void)hipFree(p);
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+}
+
+template <class T>
+static hipError_t dalloc(sbqa_ctx *c, T **p, size_t n) {
+    void *q = nullptr;
+    const size_t bytes = std::max<size_t>(n * sizeof(T), 256);
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return e;
+    c->allocs.push_back(q);
+    c->bytes += bytes;
+    e = hipMemsetAsync(q, 0, bytes, c->stream);
+    *p = static_cast<T *>(q);
+    return e;
+}
+
+static sbqa_status check_device(int *dev) {
+    HIP_TRY(hipGetDevice(dev));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, *dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(SBQA_EDEVICE, "device %d is %s; this library is built for gfx950 (MI355X) only", *dev,
+                    prop.gcnArchName);
+    return SBQA_OK;
+}
+
+namespace sbqa {
+
+// Build operand f(X) of the current step from the current state.
+sbqa_status rebuild_operand(sbqa_ctx *c) {
+    const float d = delta_at(&c->s, c->step);
+    if (c->facts.path == PATH_CSR) {
+        if (c->s.fmode != SBQA_F_BALLISTIC)
+            HIP_TRY(launch_csr_operand(c->s.fmode, c->N, c->L.Cs, c->L.C, c->x[c->cur], (int8_t *)c->g[c->cur], d, c->stream));
+    } else {
+        HIP_TRY(launch_dense_operand(c->facts.path, c->s.fmode, c->N, c->L.Np, c->L.C, c->x[c->cur], c->g[0], c->g_lo[0], d,
+                                     c->stream));
+    }
+    return SBQA_OK;
+}
+
+sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
+    const int N = c->N, Np = c->L.Np, Cs = c->L.Cs, C = c->L.C, Cp = c->L.Cp;
+    const Path path = c->facts.path;
+    const int runs = c->runs;
+    const uint32_t S = c->s.steps;
+    HIP_TRY(dalloc(c, &c->jp, (size_t)runs * S));
+    HIP_TRY(hipMemcpyAsync(c->jp, c->jp_host.data(), sizeof(float) * runs * S, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(dalloc(c, &c->E, (size_t)std::max(C, Cp)));
+    HIP_TRY(dalloc(c, &c->bestE, (size_t)runs));
+    HIP_TRY(dalloc(c, &c->bestStep, (size_t)runs));
+    HIP_TRY(dalloc(c, &c->bestSpins, (size_t)runs * N));
+
+    std::vector<float> h32((size_t)Np, 0.0f);
+    std::vector<double> h64((size_t)N, 0.0);
+    if (h)
+        for (int i = 0; i < N; ++i) {
+            h32[i] = (float)h[i];
+            h64[i] = h[i];
+        }
+    HIP_TRY(dalloc(c, &c->h32, (size_t)Np));
+    HIP_TRY(dalloc(c, &c->h64, (size_t)N));
+    HIP_TRY(hipMemcpyAsync(c->h32, h32.data(), sizeof(float) * Np, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h64, h64.data(), sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
+    c->has_h = h != nullptr;
+
+    if (path == PATH_CSR) {
+        const int64_t nnz = J->nnz;
+        HIP_TRY(dalloc(c, &c->x[0], (size_t)N * Cs));
+        HIP_TRY(dalloc(c, &c->x[1], (size_t)N * Cs));
+        HIP_TRY(dalloc(c, &c->y, (size_t)N * Cs));
+        int8_t *g0, *g1;
+        HIP_TRY(dalloc(c, &g0, (size_t)N * Cs));
+        HIP_TRY(dalloc(c, &g1, (size_t)N * Cs));
+        c->g[0] = g0;
+        c->g[1] = g1;
+        HIP_TRY(dalloc(c, &c->rp, (size_t)N + 1));
+        HIP_TRY(dalloc(c, &c->col, (size_t)nnz));
+        HIP_TRY(dalloc(c, &c->val, (size_t)nnz));
+        HIP_TRY(dalloc(c, &c->val64, (size_t)nnz));
+        HIP_TRY(dalloc(c, &c->csr_partial, (size_t)c->L.csr_nrb * C * 2));
+        HIP_TRY(dalloc(c, &c->phi, (size_t)N * Cs));
+        std::vector<float> v32((size_t)nnz);
+        for (int64_t p = 0; p < nnz; ++p) v32[p] = (float)J->val[p];
+        HIP_TRY(hipMemcpyAsync(c->rp, J->row_ptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->col, J->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->val64, J->val, sizeof(double) * nnz, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
+        return SBQA_OK;
+    }
+
+    const int eb = path == PATH_F32 ? 4 : path == PATH_FP8 ? 1 : 2;
+    HIP_TRY(dalloc(c, &c->x[0], (size_t)C * Np));
+    HIP_TRY(dalloc(c, &c->x[1], (size_t)C * Np));
+    HIP_TRY(dalloc(c, &c->y, (size_t)C * Np));
+    uint8_t *gbuf, *glo = nullptr;
+    HIP_TRY(dalloc(c, &gbuf, (size_t)Cp * Np * eb));
+    if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &glo, (size_t)Cp * Np * eb));
+    c->g[0] = gbuf;
+    c->g_lo[0] = glo;
+    HIP_TRY(dalloc(c, &c->phi, (size_t)c->L.splits * Cp * Np));
+    HIP_TRY(dalloc(c, &c->S64, (size_t)Cp * Np));
+    HIP_TRY(dalloc(c, &c->phis64, (size_t)c->L.esplits * Cp * Np));
+
+    // J in the contraction precision and in float64 (energies), zero padded.
+    const double *A = J->dense;
+    uint8_t *jd, *jlo = nullptr;
+    double *j64;
+    HIP_TRY(dalloc(c, &jd, (size_t)Np * Np * eb));
+    if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &jlo, (size_t)Np * Np * eb));
+    HIP_TRY(dalloc(c, &j64, (size_t)Np * Np));
+    c->Jd = jd;
+    c->Jd_lo = jlo;
+    c->J64 = j64;
+    // Upload row blocks through a bounded host staging buffer.
+    const int RB = 256;
+    std::vector<uint8_t> stage((size_t)RB * Np * eb), stage_lo(path == PATH_BF16X3 ? (size_t)RB * Np * eb : 0);
+    std::vector<double> stage64((size_t)RB * Np);
+    for (int i0 = 0; i0 < N; i0 += RB) {
+        const int nr = std::min(RB, N - i0);
+        std::fill(stage.begin(), stage.end(), 0);
+        std::fill(stage_lo.begin(), stage_lo.end(), 0);
+        std::fill(stage64.begin(), stage64.end(), 0.0);
+        for (int ii = 0; ii < nr; ++ii) {
+            const double *row = A + (int64_t)(i0 + ii) * N;
+            for (int j = 0; j < N; ++j) {
+                const double v = row[j];
+                stage64[(size_t)ii * Np + j] = v;
+                if (path == PATH_F32) {
+                    const float f = (float)v;
+                    std::memcpy(&stage[((size_t)ii * Np + j) * 4], &f, 4);
+                } else if (path == PATH_FP8) {
+                    stage[(size_t)ii * Np + j] = v > 0 ? 0x38 : (v < 0 ? 0xB8 : 0x00);
+                } else {
+                    const uint16_t hi = bf16_rne_host((float)v);
+                    const uint16_t lo = bf16_rne_host((float)(v - (double)bf16_to_float_host(hi)));
+                    std::memcpy(&stage[((size_t)ii * Np + j) * 2], &hi, 2);
+                    std::memcpy(&stage_lo[((size_t)ii * Np + j) * 2], &lo, 2);
+                }
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(jd + (size_t)i0 * Np * eb, stage.data(), (size_t)nr * Np * eb, hipMemcpyHostToDevice, c->stream));
+        if (path == PATH_BF16X3)
+            HIP_TRY(hipMemcpyAsync(jlo + (size_t)i0 * Np * eb, stage_lo.data(), (size_t)nr * Np * eb, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(j64 + (size_t)i0 * Np, stage64.data(), sizeof(double) * nr * Np, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers are reused
+    }
+    return SBQA_OK;
+}
+
+// One step of Eqs. 6-7 on the device (asynchronous).
+sbqa_status ctx_step_once(sbqa_ctx *c) {
+    const uint32_t n = c->step;
+    const StepCoef k = step_coef(&c->s, c->c0, c->R, n);
+    const float *jp = c->jp + n;
+    const int64_t jp_stride = c->s.steps;
+    const int in = c->cur, out = 1 - c->cur;
+    if (c->facts.path == PATH_CSR) {
+        HIP_TRY(launch_csr_step(c->s.fmode, c->N, c->L.Cs, c->R, c->runs, c->rp, c->col, c->val, c->h32, c->x[in],
+                                c->x[out], c->y, (const int8_t *)c->g[in], (int8_t *)c->g[out], jp, jp_stride, k,
+                                c->stream));
+    } else {
+        const GemmKind gk = c->facts.path == PATH_F32 ? GK_F32 : c->facts.path == PATH_FP8 ? GK_FP8 : GK_BF16X3;
+        HIP_TRY(launch_gemm(gk, c->g[0], c->g_lo[0], c->Jd, c->Jd_lo, c->phi, c->L.Np, c->L.Cp, c->L.splits, c->stream));
+        HIP_TRY(launch_dense_update(c->facts.path, c->s.fmode, c->N, c->L.Np, c->R, c->runs, c->L.Cp, c->L.splits, c->phi,
+                                    c->h32, c->x[in], c->x[out], c->y, c->g[0], c->g_lo[0], jp, jp_stride, k, c->stream));
+    }
+    c->cur = out;
+    c->step = n + 1;
+    return SBQA_OK;
+}
+
+// Energies of the readout of the current state into c->E[0..C).
+sbqa_status ctx_state_energies(sbqa_ctx *c) {
+    const bool sm = c->facts.path == PATH_CSR;
+    const double *h64 = c->has_h ? c->h64 : nullptr;
+    if (sm) {
+        HIP_TRY(launch_csr_energy_state(c->N, c->L.Cs, c->L.C, c->rp, c->col, c->val64, h64, c->x[c->cur], c->csr_partial,
+                                        c->L.csr_nrb, c->E, c->stream));
+    } else {
+        HIP_TRY(launch_readout_f64(c->N, c->L.Np, c->L.C, c->L.Np, false, c->x[c->cur], c->S64, c->stream));
+        HIP_TRY(launch_gemm(GK_F64, c->S64, nullptr, c->J64, nullptr, c->phis64, c->L.Np, c->L.Cp, c->L.esplits, c->stream));
+        HIP_TRY(launch_energy_reduce(c->N, c->L.Np, c->L.C, c->L.Cp, c->L.esplits, c->phis64, c->S64, h64, c->E, c->stream));
+    }
+    return SBQA_OK;
+}
+
+sbqa_status ctx_evaluate(sbqa_ctx *c) {
+    sbqa_status st = ctx_state_energies(c);
+    if (st != SBQA_OK) return st;
+    const bool sm = c->facts.path == PATH_CSR;
+    const int ld = sm ? c->L.Cs : c->L.Np;
+    HIP_TRY(launch_best_update(c->N, c->R, c->runs, ld, sm, c->x[c->cur], c->E, c->bestE, c->bestStep, c->bestSpins,
+                               (int64_t)c->step, c->stream));
+    c->last_eval_step = c->step;
+    return SBQA_OK;
+}
+
+sbqa_status ctx_reset_best(sbqa_ctx *c) {
+    std::vector<double> inf((size_t)c->runs, INFINITY);
+    HIP_TRY(hipMemcpyAsync(c->bestE, inf.data(), sizeof(double) * c->runs, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->last_eval_step = -1;
+    return SBQA_OK;
+}
+
+sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
+                       const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out) {
+    sbqa_ctx *c = new (std::nothrow) sbqa_ctx();
+    if (!c) return fail(SBQA_ENOMEM, "out of host memory");
+    c->N = N;
+    c->R = R;
+    c->runs = runs;
+    c->s = *s;
+    c->s.beta = c->s.alpha = nullptr;
+    c->s.jp_table = nullptr;
+    c->facts = facts;
+    c->c0 = s->c0 > 0 ? s->c0 : (facts.rms > 0 ? 0.5 / (std::sqrt((double)N) * facts.rms) : 0.0);
+    plan_layout(N, R, runs, facts, &c->L);
+    build_schedule_host(s, runs, c->beta, c->alpha, c->jp_host);
+    sbqa_status st = check_device(&c->device);
+    if (st != SBQA_OK) { delete c; return st; }
+    if (stream) c->stream = stream;
+    else {
+        hipError_t e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { delete c; return fail(SBQA_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
+        c->stream = c->own_stream;
+    }
+    st = ctx_upload(c, J, h);
+    if (st == SBQA_OK) {
+        const bool sm = facts.path == PATH_CSR;
+        hipError_t e = launch_init_state(N, c->L.C, sm ? c->L.Cs : c->L.Np, sm, s->seed, s->init_amp, c->x[0], c->y, c->stream);
+        if (e != hipSuccess) st = fail(SBQA_EDEVICE, "init: %s", hipGetErrorString(e));
+    }
+    if (st == SBQA_OK) st = rebuild_operand(c);
+    if (st == SBQA_OK) st = ctx_reset_best(c);
+    if (st != SBQA_OK) { delete c; return st; }
+    *out = c;
+    return SBQA_OK;
+}
+
+sbqa_status ctx_step(sbqa_ctx *c, uint32_t n) {
+    if ((uint64_t)c->step + n > c->s.steps)
+        return fail(SBQA_ESTATE, "step %u + %u exceeds the schedule of %u steps", c->step, n, c->s.steps);
+    for (uint32_t q = 0; q < n; ++q) {
+        sbqa_status st = ctx_step_once(c);
+        if (st != SBQA_OK) return st;
+        if (c->s.energy_every && c->step % c->s.energy_every == 0) {
+            st = ctx_evaluate(c);
+            if (st != SBQA_OK) return st;
+        }
+    }
+    return SBQA_OK;
+}
+
+sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins) {
+    sbqa_status st;
+    if (c->s.energy_every == 0) {
+        st = ctx_reset_best(c);
+        if (st != SBQA_OK) return st;
+    }
+    if (c->last_eval_step != (int64_t)c->step) {
+        st = ctx_evaluate(c);
+        if (st != SBQA_OK) return st;
+    }
+    if (energies) HIP_TRY(hipMemcpyAsync(energies, c->bestE, sizeof(double) * c->runs, hipMemcpyDeviceToHost, c->stream));
+    if (spins) HIP_TRY(hipMemcpyAsync(spins, c->bestSpins, (size_t)c->runs * c->N, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SBQA_OK;
+}
+
+}  // namespace sbqa
+
+// =========================================================================== //
+//                                 C ABI                                       //
+// =========================================================================== //
+
+extern "C" {
+
+sbqa_schedule sbqa_schedule_default(void) {
+    sbqa_schedule s;
+    std::memset(&s, 0, sizeof s);
+    s.steps = 1000;
+    s.dt = 0.5;
+    s.a0 = 1.0;
+    s.c0 = 0.0;
+    s.fmode = SBQA_F_TERNARY;
+    s.delta_max = 0.7;
+    s.jp_kind = SBQA_JP_PAPER;
+    s.jp_start = 0.5;
+    s.jp_end = 0.0;
+    s.gamma0_over_R = 1.0;
+    s.beta_lo = 0.5;
+    s.beta_hi = 1.5;
+    s.alpha_lo = 0.5;
+    s.alpha_hi = 1.0;
+    s.seed = 0;
+    s.init_amp = 0.1;
+    s.precision = SBQA_PREC_AUTO;
+    s.energy_every = 0;
+    return s;
+}
+
+const char *sbqa_last_error(void) { return last_error(); }
+
+sbqa_status sbqa_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
+                        const sbqa_schedule *s, sbqa_ctx **out) {
+    clear_error();
+    if (!out) return fail(SBQA_EINVAL, "out must be non-NULL");
+    *out = nullptr;
+    InstanceFacts facts;
+    sbqa_status st = validate_instance(J, h, N, R, runs, s, &facts);
+    if (st != SBQA_OK) return st;
+    return ctx_create(J, h, N, R, runs, s, facts, nullptr, out);
+}
+
+sbqa_status sbqa_step(sbqa_ctx *c, uint32_t n) {
+    clear_error();
+    if (!c) return fail(SBQA_EINVAL, "NULL context");
+    return ctx_step(c, n);
+}
+
+sbqa_status sbqa_best(sbqa_ctx *c, double *energies, int8_t *spins) {
+    clear_error();
+    if (!c) return fail(SBQA_EINVAL, "NULL context");
+    return ctx_best(c, energies, spins);
+}
+
+sbqa_status sbqa_best_step(sbqa_ctx *c, int64_t *step_of_best) {
+    clear_error();
+    if (!c || !step_of_best) return fail(SBQA_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(step_of_best, c->bestStep, sizeof(int64_t) * c->runs, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_energy(sbqa_ctx *c, const int8_t *spins, int32_t count, double *out) {
+    clear_error();
+    if (!c || (!spins && count) || (!out && count)) return fail(SBQA_EINVAL, "NULL argument");
+    if (count < 0) return fail(SBQA_EINVAL, "count must be >= 0");
+    if (count == 0) return SBQA_OK;
+    const int N = c->N;
+    for (int64_t q = 0; q < (int64_t)count * N; ++q)
+        if (spins[q] != 1 && spins[q] != -1) return fail(SBQA_EINVAL, "spins must be +-1 (index %lld)", (long long)q);
+    const double *h64 = c->has_h ? c->h64 : nullptr;
+    int8_t *ds = nullptr;
+    double *E = nullptr;
+    HIP_TRY(hipMalloc(&ds, (size_t)count * N));
+    hipError_t e = hipMalloc(&E, sizeof(double) * count);
+    if (e != hipSuccess) { (void)hipFree(ds); return fail(SBQA_ENOMEM, "hipMalloc: %s", hipGetErrorString(e)); }
+    struct Guard { void *a, *b, *c2, *d; ~Guard() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c2); (void)hipFree(d); } } gd{ds, E, nullptr, nullptr};
+    HIP_TRY(hipMemcpyAsync(ds, spins, (size_t)count * N, hipMemcpyHostToDevice, c->stream));
+    if (c->facts.path == PATH_CSR) {
+        HIP_TRY(launch_csr_energy_spins(N, count, c->rp, c->col, c->val64, h64, ds, E, c->stream));
+    } else {
+        const int Np = c->L.Np;
+        const int cp = (int)round_up(count, GEMM_BM);
+        const int64_t tiles = (int64_t)(Np / GEMM_BN) * (cp / GEMM_BM);
+        const int64_t nke = (int64_t)Np * 8 / GEMM_KB;
+        int es = 1;
+        while (tiles * es < 512 && es < 8 && nke % (2 * es) == 0 && nke / (2 * es) >= 4) es *= 2;
+        double *S = nullptr, *P = nullptr;
+        HIP_TRY(hipMalloc(&S, sizeof(double) * cp * Np));
+        gd.c2 = S;
+        HIP_TRY(hipMalloc(&P, sizeof(double) * es * cp * Np));
+        gd.d = P;
+        HIP_TRY(launch_spins_to_f64(N, Np, count, ds, S, c->stream));
+        HIP_TRY(launch_gemm(GK_F64, S, nullptr, c->J64, nullptr, P, Np, cp, es, c->stream));
+        HIP_TRY(launch_energy_reduce(N, Np, count, cp, es, P, S, h64, E, c->stream));
+    }
+    HIP_TRY(hipMemcpyAsync(out, E, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_fields(sbqa_ctx *c, float *phi) {
+    clear_error();
+    if (!c || !phi) return fail(SBQA_EINVAL, "NULL argument");
+    const int N = c->N, C = c->L.C;
+    std::vector<float> buf;
+    if (c->facts.path == PATH_CSR) {
+        const int Cs = c->L.Cs;
+        HIP_TRY(launch_csr_fields(c->s.fmode, N, Cs, C, c->rp, c->col, c->val, c->x[c->cur], (const int8_t *)c->g[c->cur],
+                                  c->phi, c->stream));
+        buf.resize((size_t)N * Cs);
+        HIP_TRY(hipMemcpyAsync(buf.data(), c->phi, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < N; ++i) std::memcpy(phi + (size_t)i * C, buf.data() + (size_t)i * Cs, sizeof(float) * C);
+        return SBQA_OK;
+    }
+    const int Np = c->L.Np;
+    const GemmKind gk = c->facts.path == PATH_F32 ? GK_F32 : c->facts.path == PATH_FP8 ? GK_FP8 : GK_BF16X3;
+    float *sum = nullptr;
+    HIP_TRY(hipMalloc(&sum, sizeof(float) * (size_t)C * Np));
+    struct G1 { void *p; ~G1() { (void)hipFree(p); } } g1{sum};
+    HIP_TRY(launch_gemm(gk, c->g[0], c->g_lo[0], c->Jd, c->Jd_lo, c->phi, Np, c->L.Cp, c->L.splits, c->stream));
+    HIP_TRY(launch_sum_partials(N, Np, C, c->L.Cp, c->L.splits, c->phi, sum, c->stream));
+    buf.resize((size_t)C * Np);
+    HIP_TRY(hipMemcpyAsync(buf.data(), sum, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < N; ++i)
+        for (int cc = 0; cc < C; ++cc) phi[(size_t)i * C + cc] = buf[(size_t)cc * Np + i];
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_get_state(sbqa_ctx *c, float *x, float *y) {
+    clear_error();
+    if (!c) return fail(SBQA_EINVAL, "NULL context");
+    const int N = c->N, C = c->L.C;
+    const bool sm = c->facts.path == PATH_CSR;
+    const int ld = sm ? c->L.Cs : c->L.Np;
+    const size_t tot = sm ? (size_t)N * ld : (size_t)C * ld;
+    std::vector<float> bx(tot), by(tot);
+    HIP_TRY(hipMemcpyAsync(bx.data(), c->x[c->cur], sizeof(float) * tot, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipMemcpyAsync(by.data(), c->y, sizeof(float) * tot, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < N; ++i)
+        for (int cc = 0; cc < C; ++cc) {
+            const size_t o = sm ? (size_t)i * ld + cc : (size_t)cc * ld + i;
+            if (x) x[(size_t)i * C + cc] = bx[o];
+            if (y) y[(size_t)i * C + cc] = by[o];
+        }
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_set_state(sbqa_ctx *c, const float *x, const float *y) {
+    clear_error();
+    if (!c || !x || !y) return fail(SBQA_EINVAL, "NULL argument");
+    const int N = c->N, C = c->L.C;
+    const bool sm = c->facts.path == PATH_CSR;
+    const int ld = sm ? c->L.Cs : c->L.Np;
+    const size_t tot = sm ? (size_t)N * ld : (size_t)C * ld;
+    for (size_t q = 0; q < (size_t)N * C; ++q)
+        if (!std::isfinite(x[q]) || !std::isfinite(y[q]) || std::fabs(x[q]) > 1.0f)
+            return fail(SBQA_EINVAL, "state must be finite with |x| <= 1 (index %zu)", q);
+    std::vector<float> bx(tot, 0.0f), by(tot, 0.0f);
+    for (int i = 0; i < N; ++i)
+        for (int cc = 0; cc < C; ++cc) {
+            const size_t o = sm ? (size_t)i * ld + cc : (size_t)cc * ld + i;
+            bx[o] = x[(size_t)i * C + cc];
+            by[o] = y[(size_t)i * C + cc];
+        }
+    HIP_TRY(hipMemcpyAsync(c->x[c->cur], bx.data(), sizeof(float) * tot, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->y, by.data(), sizeof(float) * tot, hipMemcpyHostToDevice, c->stream));
+    sbqa_status st = rebuild_operand(c);
+    if (st != SBQA_OK) return st;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->last_eval_step = -1;
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_run_params(sbqa_ctx *c, double *beta, double *alpha) {
+    clear_error();
+    if (!c) return fail(SBQA_EINVAL, "NULL context");
+    if (beta) std::memcpy(beta, c->beta.data(), sizeof(double) * c->runs);
+    if (alpha) std::memcpy(alpha, c->alpha.data(), sizeof(double) * c->runs);
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_jperp_table(sbqa_ctx *c, float *jp) {
+    clear_error();
+    if (!c || !jp) return fail(SBQA_EINVAL, "NULL argument");
+    std::memcpy(jp, c->jp_host.data(), sizeof(float) * c->jp_host.size());
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_set_stream(sbqa_ctx *c, void *hip_stream) {
+    clear_error();
+    if (!c) return fail(SBQA_EINVAL, "NULL context");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
+    if (!c->stream) return fail(SBQA_ESTATE, "context has no own stream");
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_info(sbqa_ctx *c, sbqa_info_t *info) {
+    clear_error();
+    if (!c || !info) return fail(SBQA_EINVAL, "NULL argument");
+    info->N = c->N;
+    info->R = c->R;
+    info->runs = c->runs;
+    info->steps = c->s.steps;
+    info->step = c->step;
+    info->path = c->facts.path;
+    info->fmode = c->s.fmode;
+    info->c0 = c->c0;
+    info->j_integral = c->facts.integral ? 1 : 0;
+    info->device_bytes = c->bytes;
+    return SBQA_OK;
+}
+
+sbqa_status sbqa_sync(sbqa_ctx *c) {
+    clear_error();
+    if (!c) return fail(SBQA_EINVAL, "NULL context");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SBQA_OK;
+}
+
+void sbqa_destroy(sbqa_ctx *c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    delete c;
+}
+
+}  // extern "C"

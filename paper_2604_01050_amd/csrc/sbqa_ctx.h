@@ -1,0 +1,91 @@
+// Solver context of the SBQA library (host side) and the internal entry points
+// shared by the C ABI (sbqa_api.cpp) and the serving loop (sbqa_serve.cpp).
+#pragma once
+
+#include "../../include/sbqa.h"
+#include "sbqa_internal.h"
+
+#include <vector>
+
+namespace sbqa {
+
+// What validation learned about an instance.
+struct InstanceFacts {
+    bool dense = true;
+    bool integral = false;   // every J_ij and h_i is an integer
+    bool ternary = false;    // every J_ij in {-1, 0, +1}
+    double rms = 0.0;        // rms of the N(N-1) off-diagonal couplings
+    int64_t nnz = 0;
+    Path path = PATH_F32;
+};
+
+// Device geometry of a context.
+struct Layout {
+    int C = 0;        // runs * R
+    int Np = 0;       // N padded to GEMM_BN (dense)
+    int Cp = 0;       // C padded to GEMM_BM (dense operand rows)
+    int Cs = 0;       // C padded to 4 (CSR row stride)
+    int splits = 1;   // K splits of the contraction GEMM
+    int esplits = 1;  // K splits of the fp64 energy GEMM
+    int csr_nrb = 0;  // row blocks of the CSR energy reduction
+    size_t bytes = 0; // device bytes (without the schedule table)
+};
+
+sbqa_status fail(sbqa_status st, const char *fmt, ...);
+void clear_error();
+const char *last_error();
+
+sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
+                              const sbqa_schedule *s, InstanceFacts *facts);
+void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Layout *L);
+size_t instance_bytes(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, uint32_t steps);
+StepCoef step_coef(const sbqa_schedule *s, double c0, int R, uint32_t n);
+
+sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
+                       const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out);
+sbqa_status ctx_step(sbqa_ctx *c, uint32_t n);
+sbqa_status ctx_step_once(sbqa_ctx *c);
+sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins);
+
+}  // namespace sbqa
+
+struct sbqa_ctx {
+    int N = 0, R = 0, runs = 0;
+    sbqa_schedule s{};                 // copy; borrowed pointers cleared
+    sbqa::InstanceFacts facts;
+    sbqa::Layout L;
+    std::vector<double> beta, alpha;   // per-run (Sec. II.B)
+    std::vector<float> jp_host;        // J_perp[r][n], run-major
+    double c0 = 0.0;
+    uint32_t step = 0;
+    int64_t last_eval_step = -1;
+    int device = 0;
+    hipStream_t own_stream = nullptr, stream = nullptr;
+    size_t bytes = 0;
+    std::vector<void *> allocs;
+    bool has_h = false;
+
+    // state (dense: [C][Np] replica-major; CSR: [N][Cs] spin-major)
+    float *x[2] = {nullptr, nullptr};
+    float *y = nullptr;
+    int cur = 0;
+    void *g[2] = {nullptr, nullptr};    // operand f(X): dense uses g[0]; CSR ping-pongs int8
+    void *g_lo[2] = {nullptr, nullptr}; // bf16 low part (BF16X3)
+    float *phi = nullptr;               // dense: [splits][Cp][Np] partials; CSR: [N][Cs] fields hook
+    void *Jd = nullptr, *Jd_lo = nullptr;  // dense J in contraction precision [Np][Np]
+    double *J64 = nullptr;              // dense J in float64 (energies)
+    int32_t *rp = nullptr, *col = nullptr;
+    float *val = nullptr;
+    double *val64 = nullptr;
+    float *h32 = nullptr;
+    double *h64 = nullptr;
+    float *jp = nullptr;                // device J_perp table [runs][steps]
+    double *S64 = nullptr, *phis64 = nullptr;
+    double *csr_partial = nullptr;
+    double *E = nullptr;
+    double *bestE = nullptr;
+    int64_t *bestStep = nullptr;
+    int8_t *bestSpins = nullptr;
+
+    ~sbqa_ctx();
+};
