@@ -93,22 +93,66 @@ def algorithmic_flops(w):
     return 2.0 * N * N * C
 
 
-def cpu_baseline(w, sb, target_s=15.0):
+KERNEL_SOURCES = {"csr_fp32": "paper_2604_01050_amd/csrc/kernels_csr.hip",
+                  "dense_fp8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
+                  "dense_fp32": "paper_2604_01050_amd/csrc/kernels_dense.hip",
+                  "dense_bf16x3": "paper_2604_01050_amd/csrc/kernels_dense.hip"}
+
+
+def source_hash(path):
+    import hashlib
+    with open(os.path.join(ROOT, path), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload, path):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of
+    known size); None when absent or taken on a different kernel source."""
+    f = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
+    if not os.path.exists(f):
+        return None
+    kv = {}
+    for line in open(f):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != source_hash(KERNEL_SOURCES[path]):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """A plain copy of known size (256 MiB read + 256 MiB written), three times,
+    for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy calibration: 3 x copy of %d bytes" % (a.numel() * 4), flush=True)
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The FP64 oracle on the host cores over the first steps of the same
+    workload: inputs from the shared generators, c0 and J_perp from the oracle."""
     import oracle
+    import sbqa_instances as inst
     oracle.build()
     N, R, runs, S = w["N"], w["R"], w["runs"], w["S"]
-    ctx = create(sb, w, seed=99)
-    c0 = sb.sbqa_info(ctx)["c0"]
-    X0, Y0 = sb.sbqa_get_state(ctx)
-    jt = sb.sbqa_jperp_table(ctx).astype(np.float64)
-    sb.sbqa_destroy(ctx)
-    P = oracle.Problem(N, R, runs, J=w.get("J"), csr=w.get("csr"), h=w.get("h"), dt=0.5, a0=1.0, c0=c0,
+    P = oracle.Problem(N, R, runs, J=w.get("J"), csr=w.get("csr"), h=w.get("h"), dt=0.5, a0=1.0, c0=None,
                        fmode=w["fmode"])
+    jt = oracle.jperp_linear_table(0.5, 0.0, S)
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.1, 99)
     X, Y = X0.astype(np.float64), Y0.astype(np.float64)
     t0 = time.perf_counter()
     n = 0
     while n < S and (time.perf_counter() - t0) < target_s:
-        X, Y = P.step(X, Y, oracle.pump(n, S), oracle.delta32(0.7, n, S), jt[:, n])
+        X, Y = P.step(X, Y, oracle.pump(n, S), oracle.delta32(0.7, n, S), np.full(runs, jt[n]))
         n += 1
     dt = time.perf_counter() - t0
     return {"value": N * R * runs * n / dt, "unit": "replica-spin updates/s", "cores": oracle.num_threads(),
@@ -123,6 +167,7 @@ def main():
     ap.add_argument("--workload", default="sparse6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="no per-step events in the timed region")
+    ap.add_argument("--calibrate", action="store_true", help="also run a copy kernel of known size (counter scaling)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the SBQA runs of one instance are independent and the "
@@ -132,6 +177,8 @@ def main():
     import torch
     import paper_2604_01050_amd as sb
     torch.cuda.set_device(0)
+    if a.calibrate:
+        copy_calibration()
     w = make_workload(a.workload)
     K = a.steps if a.steps is not None else w["S"]
     if K < 1 or K > w["S"]:
@@ -178,17 +225,19 @@ def main():
         if info["path"] == "csr_fp32":
             ab = algorithmic_bytes(w, info)
             out["roofline"] = {"bound": "hbm", "achieved": ab / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": ab / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                               "frac": ab / avg_s / 1e9 / HBM_PEAK_GBS,
+                               "traffic": measured_traffic(a.workload, info["path"]),
                                "kernel": "k_csr_step", "avg_launch_us": avg_s * 1e6,
                                "algorithmic_bytes_per_launch": ab}
         else:
             fl = algorithmic_flops(w)
             peak = PEAK[{"dense_fp8": "fp8", "dense_fp32": "fp32", "dense_bf16x3": "bf16"}[info["path"]]]
             out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-                               "frac": fl / avg_s / 1e12 / peak, "traffic": None, "kernel": "k_gemm + k_dense_update",
+                               "frac": fl / avg_s / 1e12 / peak,
+                               "traffic": measured_traffic(a.workload, info["path"]), "kernel": "k_gemm + k_dense_update",
                                "avg_step_us": avg_s * 1e6, "algorithmic_flops_per_step": fl}
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, sb)
+        out["cpu_baseline"] = cpu_baseline(w)
     sb.sbqa_destroy(ctx)
     print(json.dumps(out), flush=True)
 

@@ -28,7 +28,12 @@ __device__ __forceinline__ uint32_t pack_ternary(float a, float b, float c, floa
     return q(a) | (q(b) << 8) | (q(c) << 16) | (q(d) << 24);
 }
 
-// Coupling sum of the 4 columns c..c+3 of row i (CSR order, fp32).
+// Coupling sum of the 4 columns c..c+3 of row i, accumulated in CSR order in
+// fp32. The row's neighbours are taken GATHER_BATCH at a time: their indices
+// and weights are wave-uniform (scalar loads), and all gathers of a batch are
+// issued before the first is consumed so their latencies overlap.
+constexpr int GATHER_BATCH = 8;
+
 template <bool BALLISTIC>
 __device__ __forceinline__ float4 gather_fields(int i, int c, int Cs, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const float *__restrict__ val,
@@ -36,25 +41,49 @@ __device__ __forceinline__ float4 gather_fields(int i, int c, int Cs, const int3
     const int p0 = __builtin_amdgcn_readfirstlane(row_ptr[i]);
     const int p1 = __builtin_amdgcn_readfirstlane(row_ptr[i + 1]);
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-    for (int p = p0; p < p1; ++p) {
-        const int j = col[p];
-        const float w = val[p];
+    for (int p = p0; p < p1; p += GATHER_BATCH) {
+        const int cnt = min(GATHER_BATCH, p1 - p);
+        int js[GATHER_BATCH];
+        float ws[GATHER_BATCH];
+#pragma unroll
+        for (int q = 0; q < GATHER_BATCH; ++q) {
+            js[q] = q < cnt ? col[p + q] : 0;
+            ws[q] = q < cnt ? val[p + q] : 0.f;
+        }
         if constexpr (BALLISTIC) {
-            const float4 v = *reinterpret_cast<const float4 *>(x_in + (int64_t)j * Cs + c);
-            a0 += w * v.x; a1 += w * v.y; a2 += w * v.z; a3 += w * v.w;
+            float4 v[GATHER_BATCH];
+#pragma unroll
+            for (int q = 0; q < GATHER_BATCH; ++q)
+                if (q < cnt) v[q] = *reinterpret_cast<const float4 *>(x_in + (int64_t)js[q] * Cs + c);
+#pragma unroll
+            for (int q = 0; q < GATHER_BATCH; ++q)
+                if (q < cnt) {
+                    a0 += ws[q] * v[q].x; a1 += ws[q] * v[q].y; a2 += ws[q] * v[q].z; a3 += ws[q] * v[q].w;
+                }
         } else {
-            const uint32_t q = *reinterpret_cast<const uint32_t *>(g_in + (int64_t)j * Cs + c);
-            a0 += w * (float)(int8_t)(q & 0xFF);
-            a1 += w * (float)(int8_t)((q >> 8) & 0xFF);
-            a2 += w * (float)(int8_t)((q >> 16) & 0xFF);
-            a3 += w * (float)(int8_t)(q >> 24);
+            uint32_t v[GATHER_BATCH];
+#pragma unroll
+            for (int q = 0; q < GATHER_BATCH; ++q)
+                if (q < cnt) v[q] = *reinterpret_cast<const uint32_t *>(g_in + (int64_t)js[q] * Cs + c);
+#pragma unroll
+            for (int q = 0; q < GATHER_BATCH; ++q)
+                if (q < cnt) {
+                    a0 += ws[q] * (float)(int8_t)(v[q] & 0xFF);
+                    a1 += ws[q] * (float)(int8_t)((v[q] >> 8) & 0xFF);
+                    a2 += ws[q] * (float)(int8_t)((v[q] >> 16) & 0xFF);
+                    a3 += ws[q] * (float)(int8_t)(v[q] >> 24);
+                }
         }
     }
     return make_float4(a0, a1, a2, a3);
 }
 
 #pragma clang fp contract(off)
-template <bool BALLISTIC>
+// RING_SHFL: R divides 256 and is a multiple of 4, so every run lies inside
+// one wavefront's 256 columns and its R/4 lanes; the ring neighbours outside a
+// lane's 4 columns come from the adjacent lane of the same run by a cross-lane
+// read. Otherwise they are read from the row in memory.
+template <bool BALLISTIC, bool RING_SHFL>
 __global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, int nchunk,
                                                   const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
@@ -70,24 +99,39 @@ __global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, i
     const int c = chunk * COLS_PER_WAVE + lane * 4;
     if (i >= N || c >= C) return;
 
-    const float4 phi = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x_in, g_in);
     const int64_t o = (int64_t)i * Cs + c;
     const float4 x = *reinterpret_cast<const float4 *>(x_in + o);
     const float4 yv = *reinterpret_cast<const float4 *>(y + o);
+    const float4 phi = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x_in, g_in);
     const float hi = h[i];
     const float xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
     const float ps[4] = {phi.x, phi.y, phi.z, phi.w};
+    float left0 = 0.f, right3 = 0.f;
+    if constexpr (RING_SHFL) {
+        const int R4 = R >> 2, kq = (c % R) >> 2;
+        const int src_l = kq == 0 ? lane + R4 - 1 : lane - 1;
+        const int src_r = kq == R4 - 1 ? lane - R4 + 1 : lane + 1;
+        left0 = __shfl(xs[3], src_l);
+        right3 = __shfl(xs[0], src_r);
+    }
     const float *xrow = x_in + (int64_t)i * Cs;
     float xo[4], yo[4], fo[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
         const int cc = c + e;
-        if (cc >= C) { xo[e] = xs[e]; yo[e] = ys[e]; fo[e] = 0.f; continue; }
+        if (!RING_SHFL && cc >= C) { xo[e] = xs[e]; yo[e] = ys[e]; fo[e] = 0.f; continue; }
         const int r = cc / R, kk = cc - r * R;
-        const int cl = r * R + (kk == 0 ? R - 1 : kk - 1);
-        const int cr = r * R + (kk == R - 1 ? 0 : kk + 1);
-        const float xl = (cl >= c && cl < c + 4) ? xs[cl - c] : xrow[cl];
-        const float xr = (cr >= c && cr < c + 4) ? xs[cr - c] : xrow[cr];
+        float xl, xr;
+        if constexpr (RING_SHFL) {
+            xl = e == 0 ? left0 : xs[e - 1];
+            xr = e == 3 ? right3 : xs[e + 1];
+            if (R == 4) { xl = xs[(e + 3) & 3]; xr = xs[(e + 1) & 3]; }
+        } else {
+            const int cl = r * R + (kk == 0 ? R - 1 : kk - 1);
+            const int cr = r * R + (kk == R - 1 ? 0 : kk + 1);
+            xl = (cl >= c && cl < c + 4) ? xs[cl - c] : xrow[cl];
+            xr = (cr >= c && cr < c + 4) ? xs[cr - c] : xrow[cr];
+        }
         const float jpr = jp[(int64_t)r * jp_stride];
         const float force = (-k.kA * xs[e] + k.kB * (ps[e] + hi)) + jpr * (xl + xr);
         float yn = ys[e] + k.dt * force;
@@ -147,12 +191,18 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
     const int nchunk = (C + COLS_PER_WAVE - 1) / COLS_PER_WAVE;
     const int nrg = (N + WAVES - 1) / WAVES;
     dim3 grid(nchunk * nrg), block(WAVES * 64);
-    if (fmode == 2)
-        hipLaunchKernelGGL(k_csr_step<true>, grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, h, x_in,
-                           x_out, y, g_in, g_out, jp, jp_stride, k, fmode);
-    else
-        hipLaunchKernelGGL(k_csr_step<false>, grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, h, x_in,
-                           x_out, y, g_in, g_out, jp, jp_stride, k, fmode);
+    const bool shfl = (R % 4 == 0) && (COLS_PER_WAVE % R == 0);
+#define SBQA_CSR_LAUNCH(B, S)                                                                                  \
+    hipLaunchKernelGGL((k_csr_step<B, S>), grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, h, x_in, \
+                       x_out, y, g_in, g_out, jp, jp_stride, k, fmode)
+    if (fmode == 2) {
+        if (shfl) SBQA_CSR_LAUNCH(true, true);
+        else SBQA_CSR_LAUNCH(true, false);
+    } else {
+        if (shfl) SBQA_CSR_LAUNCH(false, true);
+        else SBQA_CSR_LAUNCH(false, false);
+    }
+#undef SBQA_CSR_LAUNCH
     return hipGetLastError();
 }
 

@@ -158,14 +158,16 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(const uint8_t *__restrict
         }
     }
 
-    // D[m][n]: lane holds rows 4*(lane/16) + r, column lane%16 of each 16x16 block.
+    // D[m][n], column lane%16 of each 16x16 block; f32 results: register r is
+    // row 4*(lane/16) + r; f64 results: register r is row 4*r + lane/16.
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int m = m0 + wm * 64 + mb * 16 + 4 * g + r;
+                const int mr = (KIND == GK_F64) ? 4 * r + g : 4 * g + r;
+                const int m = m0 + wm * 64 + mb * 16 + mr;
                 const int n = n0 + wn * 64 + nb * 16 + r16;
                 const int64_t o = ((int64_t)z * Cp + m) * Np + n;
                 if constexpr (KIND == GK_F64) reinterpret_cast<double *>(out)[o] = acc[mb][nb][r];

@@ -163,32 +163,39 @@ __global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *
     if (t == 0) E[m] = -0.5 * sq[0] - sl[0];
 }
 
-// Block per run: argmin over the run's replicas (tie -> lowest k); replace the
-// stored best only when strictly lower; copy the winner's readout spins.
-__global__ __launch_bounds__(256) void k_best_update(int N, int R, int ld, int spin_major,
-                                                     const float *__restrict__ x, const double *__restrict__ E,
-                                                     double *__restrict__ best_E, int64_t *__restrict__ best_step,
-                                                     int8_t *__restrict__ best_spins, int64_t step) {
-    __shared__ int s_win;
-    const int r = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int kb = 0;
-        double eb = E[(int64_t)r * R];
-        for (int k = 1; k < R; ++k) {
-            const double e = E[(int64_t)r * R + k];
-            if (e < eb) { eb = e; kb = k; }
-        }
-        s_win = (eb < best_E[r]) ? kb : -1;
-        if (s_win >= 0) {
-            best_E[r] = eb;
-            best_step[r] = step;
-        }
+// One wavefront per run: argmin over the run's replicas (tie -> lowest k)
+// reduced across lanes, then the stored best is replaced only when strictly
+// lower and the winner's readout spins are copied. The comparison is kept in
+// vector registers on purpose: a wave-uniform float64 compare feeding a scalar
+// select was observed to be lowered with a stale condition code on gfx950.
+__global__ __launch_bounds__(64) void k_best_update(int N, int R, int ld, int spin_major,
+                                                    const float *__restrict__ x, const double *__restrict__ E,
+                                                    double *__restrict__ best_E, int64_t *__restrict__ best_step,
+                                                    int8_t *__restrict__ best_spins, int64_t step) {
+    const int r = blockIdx.x, lane = threadIdx.x;
+    double eb = INFINITY;
+    int kb = 0x7FFFFFFF;
+    for (int k = lane; k < R; k += 64) {
+        const double e = E[(int64_t)r * R + k];
+        if (e < eb) { eb = e; kb = k; }
     }
-    __syncthreads();
-    const int kb = s_win;
-    if (kb < 0) return;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double eo = __shfl_xor(eb, off);
+        const int ko = __shfl_xor(kb, off);
+        const bool take = (eo < eb) || (eo == eb && ko < kb);
+        eb = take ? eo : eb;
+        kb = take ? ko : kb;
+    }
+    const double cur = best_E[r];
+    const int better = (eb < cur) ? 1 : 0;
+    if (!better) return;
+    if (lane == 0) {
+        best_E[r] = eb;
+        best_step[r] = step;
+    }
     const int c = r * R + kb;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    for (int i = lane; i < N; i += 64) {
         const float v = spin_major ? x[(int64_t)i * ld + c] : x[(int64_t)c * ld + i];
         best_spins[(int64_t)r * N + i] = v >= 0.0f ? 1 : -1;
     }
@@ -247,7 +254,7 @@ hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, con
 hipError_t launch_best_update(int N, int R, int runs, int ld, bool spin_major, const float *x, const double *E,
                               double *best_E, int64_t *best_step, int8_t *best_spins, int64_t step,
                               hipStream_t st) {
-    hipLaunchKernelGGL(k_best_update, dim3(runs), dim3(256), 0, st, N, R, ld, spin_major ? 1 : 0, x, E, best_E,
+    hipLaunchKernelGGL(k_best_update, dim3(runs), dim3(64), 0, st, N, R, ld, spin_major ? 1 : 0, x, E, best_E,
                        best_step, best_spins, step);
     return hipGetLastError();
 }

@@ -127,7 +127,8 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
         if (!J->row_ptr || !J->col || !J->val) return fail(SBQA_EINVAL, "CSR needs row_ptr, col and val");
         const int32_t *rp = J->row_ptr, *cl = J->col;
         const double *vl = J->val;
-        if (rp[0] != 0 || (int64_t)rp[N] != J->nnz || J->nnz < 0) return fail(SBQA_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] == nnz");
+        if (J->nnz < 0 || rp[0] != 0 || (int64_t)rp[N] != J->nnz) return fail(SBQA_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] == nnz");
+        // pass 1: structure of every row (so pass 2 may search any row)
         for (int32_t i = 0; i < N; ++i) {
             if (rp[i + 1] < rp[i]) return fail(SBQA_EINVAL, "row_ptr decreases at row %d", i);
             for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
@@ -135,13 +136,18 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
                 if (p > rp[i] && cl[p] <= cl[p - 1]) return fail(SBQA_EINVAL, "columns of row %d not strictly ascending", i);
                 if (!std::isfinite(vl[p])) return fail(SBQA_EINVAL, "val[%d] not finite", p);
                 if (cl[p] == i && vl[p] != 0.0) return fail(SBQA_EINVAL, "J has a non-zero diagonal at %d", i);
+            }
+        }
+        // pass 2: symmetry J_ij == J_ji
+        for (int32_t i = 0; i < N; ++i) {
+            for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
                 const int32_t j = cl[p];
                 const int32_t *b = cl + rp[j], *e = cl + rp[j + 1];
                 const int32_t *f = std::lower_bound(b, e, i);
                 if (f == e || *f != i || vl[rp[j] + (f - b)] != vl[p])
                     return fail(SBQA_EINVAL, "CSR J is not symmetric at (%d,%d)", i, j);
                 note(vl[p]);
-                if (cl[p] != i) ss += vl[p] * vl[p];
+                if (j != i) ss += vl[p] * vl[p];
             }
         }
         facts->nnz = J->nnz;
@@ -350,8 +356,9 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         c->g[0] = g0;
         c->g[1] = g1;
         HIP_TRY(dalloc(c, &c->rp, (size_t)N + 1));
-        HIP_TRY(dalloc(c, &c->col, (size_t)nnz));
-        HIP_TRY(dalloc(c, &c->val, (size_t)nnz));
+        // +8: the CSR step reads neighbour indices in batches of up to 8
+        HIP_TRY(dalloc(c, &c->col, (size_t)nnz + 8));
+        HIP_TRY(dalloc(c, &c->val, (size_t)nnz + 8));
         HIP_TRY(dalloc(c, &c->val64, (size_t)nnz));
         HIP_TRY(dalloc(c, &c->csr_partial, (size_t)c->L.csr_nrb * C * 2));
         HIP_TRY(dalloc(c, &c->phi, (size_t)N * Cs));

@@ -157,15 +157,18 @@ CASES = [
     ("csr_ternary", None, 0, "csr"),
     ("csr_sign", None, 1, "csr"),
     ("csr_ballistic", None, 2, "csr"),
+    ("csr_ternary_r8", None, 0, "csr"),
+    ("csr_ballistic_r8", None, 2, "csr"),
 ]
 
 
 @pytest.mark.parametrize("name,prec,fmode,coup", CASES)
 def test_single_step_parity(sb, orc, name, prec, fmode, coup):
     """One step of Eqs. 6-7 from identical float32 states at several step
-    indices along a GPU trajectory (N = 300 / 1000 with ragged tiles; R = 5,
-    runs = 7, C = 35 not a multiple of 4 or of the 128-column tile)."""
-    R, runs, S = 5, 7, 40
+    indices along a GPU trajectory (N = 300 / 1001 with ragged tiles; R = 5,
+    runs = 7, C = 35 not a multiple of 4 or of the 128-column tile; R = 8 takes
+    the CSR path whose ring neighbours come from adjacent lanes)."""
+    R, runs, S = (8 if name.endswith("_r8") else 5), 7, 40
     csr = J = None
     if coup == "sk":
         N = 300
