@@ -68,9 +68,10 @@ def make_workload(name: str):
     raise SystemExit("unknown workload " + name)
 
 
-def create(sb, w, seed):
+def create(sb, w, seed, sparse_kernel="auto"):
     kw = dict(R=w["R"], runs=w["runs"], steps=w["S"], dt=0.5, a0=1.0, fmode=w["fmode"],
-              jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0, seed=seed, init_amp=0.1)
+              jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0, seed=seed, init_amp=0.1,
+              sparse_kernel={"auto": sb.SPARSE_AUTO, "stream": sb.SPARSE_STREAM, "resident": sb.SPARSE_RESIDENT}[sparse_kernel])
     if w["prec"]:
         kw["precision"] = getattr(sb, w["prec"])
     return sb.sbqa_create(J=w.get("J"), csr=w.get("csr"), h=w.get("h"), **kw)
@@ -88,12 +89,26 @@ def algorithmic_bytes(w, info):
     return N * N * eb + C * N * eb + C * N * 4
 
 
+# fp32 vector peak of MI355X (256 CUs, 2.4 GHz); the kernels here are built
+# without packed fp32, so half of it is the reachable ceiling.
+PEAK_VALU_FP32 = 157.3
+
+
+def resident_flops_per_step(w):
+    """Arithmetic of one step of the resident sparse loop per replica-spin update:
+    2d for the coupling sum, 11 for the update (pump, field, ring, kick, drift)."""
+    N, C = w["N"], w["R"] * w["runs"]
+    nnz = len(w["csr"][1])
+    return 2.0 * nnz * C + 11.0 * N * C
+
+
 def algorithmic_flops(w):
     N, C = w["N"], w["R"] * w["runs"]
     return 2.0 * N * N * C
 
 
 KERNEL_SOURCES = {"csr_fp32": "paper_2604_01050_amd/csrc/kernels_csr.hip",
+                  "csr_resident": "paper_2604_01050_amd/csrc/kernels_csr.hip",
                   "dense_fp8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
                   "dense_fp32": "paper_2604_01050_amd/csrc/kernels_dense.hip",
                   "dense_bf16x3": "paper_2604_01050_amd/csrc/kernels_dense.hip"}
@@ -168,6 +183,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="no per-step events in the timed region")
     ap.add_argument("--calibrate", action="store_true", help="also run a copy kernel of known size (counter scaling)")
+    ap.add_argument("--sparse-kernel", default="auto", choices=["auto", "stream", "resident"])
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the SBQA runs of one instance are independent and the "
@@ -186,43 +202,60 @@ def main():
     stream = torch.cuda.Stream()
 
     # warmup: a separate solve
-    ctx = create(sb, w, seed=1)
+    ctx = create(sb, w, seed=1, sparse_kernel=a.sparse_kernel)
     sb.sbqa_set_stream(ctx, stream)
     sb.sbqa_step(ctx, min(a.warmup, w["S"]))
     sb.sbqa_best(ctx)
     sb.sbqa_destroy(ctx)
 
-    ctx = create(sb, w, seed=2)
+    ctx = create(sb, w, seed=2, sparse_kernel=a.sparse_kernel)
     sb.sbqa_set_stream(ctx, stream)
     info = sb.sbqa_info(ctx)
     torch.cuda.synchronize()
-    ev = [] if a.no_events else [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                                 for _ in range(K)]
+    resident = info["resident"]
+    # Resident sparse loop: the K steps are one launch, bracketed by one event
+    # pair. Otherwise one event pair per step brackets that step's kernels.
+    nev = 0 if a.no_events else (1 if resident else K)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nev)]
     t0 = time.perf_counter()
-    for q in range(K):
+    if resident:
         if ev:
-            ev[q][0].record(stream)
-        sb.sbqa_step(ctx, 1)
+            ev[0][0].record(stream)
+        sb.sbqa_step(ctx, K)
         if ev:
-            ev[q][1].record(stream)
+            ev[0][1].record(stream)
+    else:
+        for q in range(K):
+            if ev:
+                ev[q][0].record(stream)
+            sb.sbqa_step(ctx, 1)
+            if ev:
+                ev[q][1].record(stream)
     E, spins = sb.sbqa_best(ctx)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     N, R, runs = w["N"], w["R"], w["runs"]
     value = N * R * runs * K / t
-    step_ms = [s.elapsed_time(e) for s, e in ev] if ev else []
+    launch_ms = [s.elapsed_time(e) for s, e in ev]
     out = {
         "metric": "replica-spin updates/s (N*R*runs*steps/s)",
         "value": value, "unit": "replica-spin updates/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
         "ms_per_step": 1e3 * t / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": w["dtype"], "data": "synthetic",
         "config": {"workload": w["desc"], "N": N, "R": R, "runs": runs, "schedule_steps": w["S"],
-                   "path": info["path"]},
+                   "path": info["path"] + ("_resident" if resident else "")},
         "best_energy": {"mean": float(np.mean(E)), "min": float(np.min(E))},
     }
-    if step_ms:
-        avg_s = float(np.mean(step_ms)) * 1e-3
-        if info["path"] == "csr_fp32":
+    if launch_ms:
+        avg_s = float(np.mean(launch_ms)) * 1e-3
+        if resident:
+            fl = K * resident_flops_per_step(w)
+            peak = PEAK_VALU_FP32
+            out["roofline"] = {"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+                               "frac": fl / avg_s / 1e12 / peak, "traffic": measured_traffic(a.workload + "_resident", "csr_resident"),
+                               "kernel": "k_csr_resident", "avg_launch_us": avg_s * 1e6, "steps_per_launch": K,
+                               "algorithmic_flops_per_launch": fl}
+        elif info["path"] == "csr_fp32":
             ab = algorithmic_bytes(w, info)
             out["roofline"] = {"bound": "hbm", "achieved": ab / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                                "frac": ab / avg_s / 1e9 / HBM_PEAK_GBS,

@@ -78,6 +78,15 @@ typedef enum {
  *   TABLE   caller-supplied float32 table jp_table[runs*steps]. */
 typedef enum { SBQA_JP_LINEAR = 0, SBQA_JP_PAPER = 1, SBQA_JP_TABLE = 2 } sbqa_jpkind;
 
+/* Kernel of the sparse (CSR) path; both compute the same bits.
+ *   AUTO      the register-resident loop when the instance fits it (ternary or
+ *             sign f, R a multiple of 8, N <= 4096, small degree, all column
+ *             blocks co-resident on the GPU), else the streaming kernel.
+ *   STREAM    one fused launch per step, state streamed through HBM.
+ *   RESIDENT  the register-resident loop; sbqa_create fails with EINVAL when
+ *             the instance does not fit it. */
+typedef enum { SBQA_SPARSE_AUTO = 0, SBQA_SPARSE_STREAM = 1, SBQA_SPARSE_RESIDENT = 2 } sbqa_sparse_kernel;
+
 /* Couplings: exactly one of `dense` or the CSR triple is non-NULL.
  * J must be symmetric with a zero diagonal and finite entries.
  *   dense    N*N float64, row-major.
@@ -112,11 +121,13 @@ typedef struct {
     int32_t precision;       /* sbqa_prec                                          */
     uint32_t energy_every;   /* 0: best over the final state only; K > 0: also
                                 track the best after every K-th step              */
+    int32_t sparse_kernel;   /* sbqa_sparse_kernel (CSR couplings only)            */
 } sbqa_schedule;
 
 /* Defaults: steps 1000, dt 0.5, a0 1, c0 auto, ternary f, delta_max 0.7,
  * PAPER schedule with gamma0_over_R 1, beta in [0.5,1.5], alpha in [0.5,1.0]
- * (Sec. II.B), seed 0, init_amp 0.1, precision AUTO, energy_every 0. */
+ * (Sec. II.B), seed 0, init_amp 0.1, precision AUTO, energy_every 0,
+ * sparse_kernel AUTO. */
 sbqa_schedule sbqa_schedule_default(void);
 
 /* Context information (sbqa_info). */
@@ -129,6 +140,8 @@ typedef struct {
     double c0;               /* c0 actually used                                   */
     int32_t j_integral;      /* 1 when every J_ij and h_i is an integer            */
     size_t device_bytes;     /* device memory held by the context                  */
+    int32_t resident;        /* 1 when the sparse path runs the register-resident
+                                loop, 0 otherwise                                 */
 } sbqa_info_t;
 
 /*
@@ -141,7 +154,8 @@ typedef struct {
  *   out   receives the context; owned by the caller until sbqa_destroy.
  * Errors: EINVAL (N, R, runs, steps < 1; dt, a0 <= 0; J not symmetric, non-zero
  * diagonal, non-finite, malformed CSR; FP8 with ballistic f or J outside
- * {-1,0,+1}; BF16X3 with CSR), ENOMEM, EDEVICE.
+ * {-1,0,+1}; BF16X3 with CSR; SPARSE_RESIDENT for an instance that does not
+ * fit the resident loop), ENOMEM, EDEVICE.
  */
 sbqa_status sbqa_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R,
                         int32_t runs, const sbqa_schedule *s, sbqa_ctx **out);
@@ -149,7 +163,9 @@ sbqa_status sbqa_create(const sbqa_coupling *J, const double *h, int32_t N, int3
 /*
  * Advance every run and replica by n steps of Eqs. 6-7 (contraction J.f(X),
  * fused pump/ring/kick/drift/wall update). Asynchronous on the context stream.
- * Errors: ESTATE if step + n > steps (nothing is done), EDEVICE.
+ * Errors: ESTATE if step + n > steps (nothing is done), EDEVICE (also reported
+ * by the next synchronising call when a resident launch could not complete a
+ * step: the state is then invalid).
  */
 sbqa_status sbqa_step(sbqa_ctx *ctx, uint32_t n);
 

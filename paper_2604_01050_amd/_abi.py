@@ -18,6 +18,7 @@ OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 F_TERNARY, F_SIGN, F_BALLISTIC = 0, 1, 2
 PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3 = 0, 1, 2, 3
 JP_LINEAR, JP_PAPER, JP_TABLE = 0, 1, 2
+SPARSE_AUTO, SPARSE_STREAM, SPARSE_RESIDENT = 0, 1, 2
 PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32"}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EBUDGET", -6: "EAGAIN"}
 
@@ -41,13 +42,13 @@ class Schedule(ct.Structure):
                 ("beta_lo", ct.c_double), ("beta_hi", ct.c_double), ("alpha_lo", ct.c_double),
                 ("alpha_hi", ct.c_double), ("beta", ct.c_void_p), ("alpha", ct.c_void_p),
                 ("jp_table", ct.c_void_p), ("seed", ct.c_uint64), ("init_amp", ct.c_double),
-                ("precision", ct.c_int32), ("energy_every", ct.c_uint32)]
+                ("precision", ct.c_int32), ("energy_every", ct.c_uint32), ("sparse_kernel", ct.c_int32)]
 
 
 class Info(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("R", ct.c_int32), ("runs", ct.c_int32), ("steps", ct.c_uint32),
                 ("step", ct.c_uint32), ("path", ct.c_int32), ("fmode", ct.c_int32), ("c0", ct.c_double),
-                ("j_integral", ct.c_int32), ("device_bytes", ct.c_size_t)]
+                ("j_integral", ct.c_int32), ("device_bytes", ct.c_size_t), ("resident", ct.c_int32)]
 
 
 def _load() -> ct.CDLL:
@@ -239,7 +240,7 @@ def sbqa_info(ctx: Context) -> dict:
     _check(lib.sbqa_info(ctx.ptr, ct.byref(i)))
     return {"N": i.N, "R": i.R, "runs": i.runs, "steps": i.steps, "step": i.step,
             "path": PATHS[i.path], "fmode": i.fmode, "c0": i.c0, "j_integral": bool(i.j_integral),
-            "device_bytes": i.device_bytes}
+            "device_bytes": i.device_bytes, "resident": bool(i.resident)}
 
 
 def sbqa_sync(ctx: Context) -> None:

@@ -74,6 +74,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     if (s->fmode < 0 || s->fmode > 2) return fail(SBQA_EINVAL, "unknown fmode %d", s->fmode);
     if (!std::isfinite(s->delta_max) || s->delta_max < 0) return fail(SBQA_EINVAL, "delta_max must be finite and >= 0");
     if (s->precision < 0 || s->precision > 3) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
+    if (s->sparse_kernel < 0 || s->sparse_kernel > 2) return fail(SBQA_EINVAL, "unknown sparse_kernel %d", s->sparse_kernel);
     if (!(s->init_amp >= 0) || !std::isfinite(s->init_amp)) return fail(SBQA_EINVAL, "init_amp must be finite and >= 0");
     switch (s->jp_kind) {
         case SBQA_JP_LINEAR:
@@ -279,6 +280,7 @@ using namespace sbqa;
 
 sbqa_ctx::~sbqa_ctx() {
     for (void *p : allocs) (void)hipFree(p);
+    if (err_host) (void)hipHostFree(err_host);
     if (own_stream) (void)hipStreamDestroy(own_stream);
 }
 
@@ -332,27 +334,29 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     HIP_TRY(dalloc(c, &c->bestStep, (size_t)runs));
     HIP_TRY(dalloc(c, &c->bestSpins, (size_t)runs * N));
 
-    std::vector<float> h32((size_t)Np, 0.0f);
+    const int hrows = std::max(Np, c->resident ? c->res_rows : 0);
+    std::vector<float> h32((size_t)hrows, 0.0f);
     std::vector<double> h64((size_t)N, 0.0);
     if (h)
         for (int i = 0; i < N; ++i) {
             h32[i] = (float)h[i];
             h64[i] = h[i];
         }
-    HIP_TRY(dalloc(c, &c->h32, (size_t)Np));
+    HIP_TRY(dalloc(c, &c->h32, (size_t)hrows));
     HIP_TRY(dalloc(c, &c->h64, (size_t)N));
-    HIP_TRY(hipMemcpyAsync(c->h32, h32.data(), sizeof(float) * Np, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->h32, h32.data(), sizeof(float) * hrows, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->h64, h64.data(), sizeof(double) * N, hipMemcpyHostToDevice, c->stream));
     c->has_h = h != nullptr;
 
     if (path == PATH_CSR) {
         const int64_t nnz = J->nnz;
-        HIP_TRY(dalloc(c, &c->x[0], (size_t)N * Cs));
-        HIP_TRY(dalloc(c, &c->x[1], (size_t)N * Cs));
-        HIP_TRY(dalloc(c, &c->y, (size_t)N * Cs));
+        const int rows = c->resident ? c->res_rows : N;   // resident rows are padded with zero rows
+        HIP_TRY(dalloc(c, &c->x[0], (size_t)rows * Cs));
+        HIP_TRY(dalloc(c, &c->x[1], (size_t)rows * Cs));
+        HIP_TRY(dalloc(c, &c->y, (size_t)rows * Cs));
         int8_t *g0, *g1;
-        HIP_TRY(dalloc(c, &g0, (size_t)N * Cs));
-        HIP_TRY(dalloc(c, &g1, (size_t)N * Cs));
+        HIP_TRY(dalloc(c, &g0, (size_t)rows * Cs));
+        HIP_TRY(dalloc(c, &g1, (size_t)rows * Cs));
         c->g[0] = g0;
         c->g[1] = g1;
         HIP_TRY(dalloc(c, &c->rp, (size_t)N + 1));
@@ -368,6 +372,38 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         HIP_TRY(hipMemcpyAsync(c->col, J->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(c->val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(c->val64, J->val, sizeof(double) * nnz, hipMemcpyHostToDevice, c->stream));
+        std::vector<int32_t> cp;
+        std::vector<float> vp, ca, dtab;
+        if (c->resident) {
+            // padded neighbour lists (CSR order, then index 0 with weight 0),
+            // per-step pump and threshold tables, ring exchange buffers
+            const int D = c->res_D, NR = c->res_rows, S = (int)c->s.steps;
+            cp.assign((size_t)NR * D, 0);
+            vp.assign((size_t)D * NR, 0.0f);
+            for (int i = 0; i < N; ++i)
+                for (int q = 0; q < J->row_ptr[i + 1] - J->row_ptr[i]; ++q) {
+                    cp[(size_t)i * D + q] = J->col[J->row_ptr[i] + q];
+                    vp[(size_t)q * NR + i] = (float)J->val[J->row_ptr[i] + q];
+                }
+            ca.resize(S);
+            dtab.resize((size_t)S + 1);
+            for (int n = 0; n < S; ++n) ca[n] = step_coef(&c->s, c->c0, c->R, (uint32_t)n).kA;
+            for (int n = 0; n <= S; ++n) dtab[n] = delta_at(&c->s, (uint32_t)n);
+            HIP_TRY(dalloc(c, &c->colpad, cp.size()));
+            HIP_TRY(dalloc(c, &c->valpad, vp.size()));
+            HIP_TRY(dalloc(c, &c->coefA, ca.size()));
+            HIP_TRY(dalloc(c, &c->delta_tab, dtab.size()));
+            HIP_TRY(dalloc(c, &c->xpub, (size_t)2 * c->res_nwg * 2 * NR));
+            HIP_TRY(dalloc(c, &c->flags, (size_t)c->res_nwg));
+            HIP_TRY(dalloc(c, &c->epoch_cnt, (size_t)c->res_nwg));
+            HIP_TRY(dalloc(c, &c->err, 1));
+            HIP_TRY(hipHostMalloc((void **)&c->err_host, sizeof(int), hipHostMallocDefault));
+            *c->err_host = 0;
+            HIP_TRY(hipMemcpyAsync(c->colpad, cp.data(), sizeof(int32_t) * cp.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->valpad, vp.data(), sizeof(float) * vp.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->coefA, ca.data(), sizeof(float) * ca.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->delta_tab, dtab.data(), sizeof(float) * dtab.size(), hipMemcpyHostToDevice, c->stream));
+        }
         HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
         return SBQA_OK;
     }
@@ -487,8 +523,33 @@ sbqa_status ctx_reset_best(sbqa_ctx *c) {
     return SBQA_OK;
 }
 
+// Whether the register-resident CSR loop fits this instance on this device.
+static bool resident_plan(sbqa_ctx *c, const sbqa_coupling *J, std::string *why) {
+    if (c->s.fmode == SBQA_F_BALLISTIC) { *why = "ballistic f needs a float32 operand"; return false; }
+    if (c->R % resident_cols()) { *why = "R is not a multiple of 8"; return false; }
+    const int rpt = resident_rpt(c->N);
+    if (rpt < 0 || c->N > 65535) { *why = "N above 4096"; return false; }
+    int maxdeg = 0;
+    for (int i = 0; i < c->N; ++i) maxdeg = std::max(maxdeg, J->row_ptr[i + 1] - J->row_ptr[i]);
+    const int D = resident_degree(maxdeg);
+    if (D < 0) { *why = "degree above 16"; return false; }
+    if (rpt == 8 && D > 6) { *why = "N above 2048 with degree above 6 exceeds the register budget"; return false; }
+    const size_t lds = resident_lds_bytes(c->N, D);
+    if (lds > 160 * 1024) { *why = "LDS demand above 160 KiB"; return false; }
+    int bpc = 0, cus = 0;
+    if (resident_max_blocks(D, c->N, &bpc) != hipSuccess) { *why = "occupancy query failed"; return false; }
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) != hipSuccess) { *why = "no CU count"; return false; }
+    const int nwg = c->L.C / resident_cols();
+    if (nwg > bpc * cus) { *why = "more column blocks than co-resident workgroups"; return false; }
+    c->res_D = D;
+    c->res_rows = resident_rows(c->N);
+    c->res_nwg = nwg;
+    return true;
+}
+
 sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
-                       const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out) {
+                       const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out,
+                       bool allow_resident) {
     sbqa_ctx *c = new (std::nothrow) sbqa_ctx();
     if (!c) return fail(SBQA_ENOMEM, "out of host memory");
     c->N = N;
@@ -509,6 +570,14 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
         if (e != hipSuccess) { delete c; return fail(SBQA_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
         c->stream = c->own_stream;
     }
+    if (facts.path == PATH_CSR) {
+        std::string why;
+        c->resident = allow_resident && s->sparse_kernel != SBQA_SPARSE_STREAM && resident_plan(c, J, &why);
+        if (!c->resident && s->sparse_kernel == SBQA_SPARSE_RESIDENT) {
+            delete c;
+            return fail(SBQA_EINVAL, "instance does not fit the resident sparse loop: %s", why.c_str());
+        }
+    }
     st = ctx_upload(c, J, h);
     if (st == SBQA_OK) {
         const bool sm = facts.path == PATH_CSR;
@@ -522,9 +591,65 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
     return SBQA_OK;
 }
 
+// K steps of the register-resident loop in one cooperative launch.
+static sbqa_status ctx_step_resident(sbqa_ctx *c, uint32_t K) {
+    ResidentArgs a;
+    a.N = c->N;
+    a.Cs = c->L.Cs;
+    a.R = c->R;
+    a.S = (int)c->s.steps;
+    a.n0 = (int)c->step;
+    a.K = (int)K;
+    a.fmode = c->s.fmode;
+    a.nwg = c->res_nwg;
+    a.colpad = c->colpad;
+    a.valpad = c->valpad;
+    a.h = c->h32;
+    a.x = c->x[c->cur];
+    a.y = c->y;
+    a.g = (int8_t *)c->g[c->cur];
+    a.jp = c->jp;
+    a.coefA = c->coefA;
+    a.delta = c->delta_tab;
+    const StepCoef k = step_coef(&c->s, c->c0, c->R, c->step);
+    a.kB = k.kB;
+    a.dt = k.dt;
+    a.kD = k.kD;
+    a.xpub = c->xpub;
+    a.flags = c->flags;
+    a.epoch_cnt = c->epoch_cnt;
+    a.epoch = ++c->epoch;
+    a.err = c->err;
+    HIP_TRY(launch_csr_resident(a, c->res_D, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->err_host, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->step += K;
+    return SBQA_OK;
+}
+
+sbqa_status ctx_check_async(sbqa_ctx *c) {
+    if (c->err_host && *c->err_host)
+        return fail(SBQA_EDEVICE, "resident sparse loop: a ring-neighbour wait timed out; the state is invalid");
+    return SBQA_OK;
+}
+
 sbqa_status ctx_step(sbqa_ctx *c, uint32_t n) {
     if ((uint64_t)c->step + n > c->s.steps)
         return fail(SBQA_ESTATE, "step %u + %u exceeds the schedule of %u steps", c->step, n, c->s.steps);
+    if (c->resident) {
+        uint32_t left = n;
+        while (left) {
+            uint32_t K = left;
+            if (c->s.energy_every) K = std::min(K, c->s.energy_every - c->step % c->s.energy_every);
+            sbqa_status st = ctx_step_resident(c, K);
+            if (st != SBQA_OK) return st;
+            left -= K;
+            if (c->s.energy_every && c->step % c->s.energy_every == 0) {
+                st = ctx_evaluate(c);
+                if (st != SBQA_OK) return st;
+            }
+        }
+        return SBQA_OK;
+    }
     for (uint32_t q = 0; q < n; ++q) {
         sbqa_status st = ctx_step_once(c);
         if (st != SBQA_OK) return st;
@@ -549,7 +674,7 @@ sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins) {
     if (energies) HIP_TRY(hipMemcpyAsync(energies, c->bestE, sizeof(double) * c->runs, hipMemcpyDeviceToHost, c->stream));
     if (spins) HIP_TRY(hipMemcpyAsync(spins, c->bestSpins, (size_t)c->runs * c->N, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    return SBQA_OK;
+    return ctx_check_async(c);
 }
 
 }  // namespace sbqa
@@ -581,6 +706,7 @@ sbqa_schedule sbqa_schedule_default(void) {
     s.init_amp = 0.1;
     s.precision = SBQA_PREC_AUTO;
     s.energy_every = 0;
+    s.sparse_kernel = SBQA_SPARSE_AUTO;
     return s;
 }
 
@@ -594,7 +720,7 @@ sbqa_status sbqa_create(const sbqa_coupling *J, const double *h, int32_t N, int3
     InstanceFacts facts;
     sbqa_status st = validate_instance(J, h, N, R, runs, s, &facts);
     if (st != SBQA_OK) return st;
-    return ctx_create(J, h, N, R, runs, s, facts, nullptr, out);
+    return ctx_create(J, h, N, R, runs, s, facts, nullptr, out, true);
 }
 
 sbqa_status sbqa_step(sbqa_ctx *c, uint32_t n) {
@@ -697,6 +823,10 @@ sbqa_status sbqa_get_state(sbqa_ctx *c, float *x, float *y) {
     HIP_TRY(hipMemcpyAsync(bx.data(), c->x[c->cur], sizeof(float) * tot, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(by.data(), c->y, sizeof(float) * tot, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    {
+        sbqa_status e = ctx_check_async(c);
+        if (e != SBQA_OK) return e;
+    }
     for (int i = 0; i < N; ++i)
         for (int cc = 0; cc < C; ++cc) {
             const size_t o = sm ? (size_t)i * ld + cc : (size_t)cc * ld + i;
@@ -769,6 +899,7 @@ sbqa_status sbqa_info(sbqa_ctx *c, sbqa_info_t *info) {
     info->c0 = c->c0;
     info->j_integral = c->facts.integral ? 1 : 0;
     info->device_bytes = c->bytes;
+    info->resident = c->resident ? 1 : 0;
     return SBQA_OK;
 }
 
@@ -776,7 +907,7 @@ sbqa_status sbqa_sync(sbqa_ctx *c) {
     clear_error();
     if (!c) return fail(SBQA_EINVAL, "NULL context");
     HIP_TRY(hipStreamSynchronize(c->stream));
-    return SBQA_OK;
+    return ctx_check_async(c);
 }
 
 void sbqa_destroy(sbqa_ctx *c) {

@@ -5,6 +5,7 @@
 #include "../../include/sbqa.h"
 #include "sbqa_internal.h"
 
+#include <string>
 #include <vector>
 
 namespace sbqa {
@@ -41,11 +42,15 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
 size_t instance_bytes(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, uint32_t steps);
 StepCoef step_coef(const sbqa_schedule *s, double c0, int R, uint32_t n);
 
+// allow_resident: false for contexts that share the GPU with other work (the
+// resident loop needs all its workgroups co-resident).
 sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
-                       const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out);
+                       const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out,
+                       bool allow_resident);
 sbqa_status ctx_step(sbqa_ctx *c, uint32_t n);
 sbqa_status ctx_step_once(sbqa_ctx *c);
 sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins);
+sbqa_status ctx_check_async(sbqa_ctx *c);  // after a stream synchronisation
 
 }  // namespace sbqa
 
@@ -86,6 +91,18 @@ struct sbqa_ctx {
     double *bestE = nullptr;
     int64_t *bestStep = nullptr;
     int8_t *bestSpins = nullptr;
+
+    // register-resident CSR loop (see kernels_csr.hip)
+    bool resident = false;
+    int res_D = 0, res_rows = 0, res_nwg = 0;
+    int32_t *colpad = nullptr;          // [rows][D]
+    float *valpad = nullptr;            // [D][rows]
+    float *coefA = nullptr;             // [S]
+    float *delta_tab = nullptr;         // [S+1]
+    float *xpub = nullptr;              // [2][nwg][2][rows]
+    int *flags = nullptr, *epoch_cnt = nullptr, *err = nullptr;
+    int *err_host = nullptr;            // pinned copy of err
+    int epoch = 0;
 
     ~sbqa_ctx();
 };

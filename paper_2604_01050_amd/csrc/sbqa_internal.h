@@ -68,6 +68,35 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
                            int8_t *g_out, const float *jp, int64_t jp_stride, StepCoef k,
                            hipStream_t st);
 
+// Register-resident CSR loop (K steps per cooperative launch); see
+// kernels_csr.hip. Arrays are device pointers; NR = resident_rows(N) rows,
+// rows N..NR-1 are zero padding.
+struct ResidentArgs {
+    int N, Cs, R, S, n0, K, fmode, nwg;
+    const int32_t *colpad;  // [NR][D] neighbour indices (padding: index 0, weight 0)
+    const float *valpad;    // [D][NR] weights, padded with 0
+    const float *h;         // [NR]
+    float *x, *y;           // [NR][Cs] state, updated in place
+    int8_t *g;              // [NR][Cs] operand, updated in place
+    const float *jp;        // [runs][S]
+    const float *coefA;     // [S]   (a0 - a_n)/R
+    const float *delta;     // [S+1] Delta_n
+    float kB, dt, kD;
+    float *xpub;            // [2][nwg][2][NR] published edge columns
+    int *flags;             // [nwg] steps completed (monotonic)
+    int *epoch_cnt;         // [nwg] launches started (monotonic)
+    int epoch;              // this launch's number (>= 1)
+    int *err;               // [1] set on a wait timeout
+};
+int resident_degree(int maxdeg);        // padded degree D, or -1 when too large
+size_t resident_lds_bytes(int N, int D);
+int resident_cols();
+int resident_rpt(int N);             // rows per thread, or -1 when N is too large
+int resident_rows(int N);            // padded row count NR, or -1
+int resident_threads();
+hipError_t resident_max_blocks(int D, int N, int *blocks_per_cu);
+hipError_t launch_csr_resident(const ResidentArgs &a, int D, hipStream_t st);
+
 // CSR operand from state [N][Cs].
 hipError_t launch_csr_operand(int fmode, int N, int Cs, int C, const float *x, int8_t *g,
                               float delta, hipStream_t st);

@@ -145,7 +145,7 @@ static void scheduler(sbqa_server *srv) {
             s.alpha = r.alpha.empty() ? nullptr : r.alpha.data();
             s.jp_table = r.jp_table.empty() ? nullptr : r.jp_table.data();
             sbqa_status st = ctx_create(&J, r.h.empty() ? nullptr : r.h.data(), r.N, r.R, r.runs, &s, r.facts, sl.stream,
-                                        &sl.ctx);
+                                        &sl.ctx, false);
             if (st != SBQA_OK) {
                 sl.ctx = nullptr;
                 finish(srv, sl, st, last_error());

@@ -478,3 +478,71 @@ def test_torch_stream_interop(sb):
         sb.sbqa_step(ctx, 20)
         outs.append(sb.sbqa_get_state(ctx)[0])
     assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------ resident loop
+RESIDENT_CASES = [
+    # name, N, degree, R, runs, fmode, energy_every
+    ("bench_shape", 4096, 6, 32, 64, 0, 0),
+    ("one_block_per_run", 1001, 6, 8, 7, 0, 0),
+    ("two_blocks_sign", 700, 5, 16, 5, 1, 0),
+    ("three_blocks_deg12_tracking", 2000, 12, 24, 3, 0, 7),
+    ("small_ring_tracking", 333, 3, 8, 2, 0, 5),
+]
+
+
+@pytest.mark.parametrize("name,N,d,R,runs,fmode,ee", RESIDENT_CASES)
+def test_resident_loop_matches_streaming(sb, orc, name, N, d, R, runs, fmode, ee):
+    """The register-resident CSR loop (many steps per launch, state in
+    registers, ring edges exchanged between workgroups) computes exactly the
+    bits of the one-launch-per-step kernel, over several launches, with energy
+    tracking and a state overwrite in between; and one of its steps matches the
+    oracle."""
+    if d % 2 and N % 2:
+        N += 1
+    _log("resident vs streaming %s N=%d d=%d R=%d runs=%d" % (name, N, d, R, runs))
+    E = inst.regular_graph(N, d, 5001)
+    csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 5002))
+    h = inst.gaussian_fields(N, 0.1, 5003)
+    S = 120
+    out = {}
+    for kern in (sb.SPARSE_STREAM, sb.SPARSE_RESIDENT):
+        ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, sparse_kernel=kern, seed=5004,
+                   energy_every=ee, jp_kind=sb.JP_PAPER)
+        assert sb.sbqa_info(ctx)["resident"] == (kern == sb.SPARSE_RESIDENT)
+        sb.sbqa_step(ctx, 37)
+        mid = sb.sbqa_get_state(ctx)
+        sb.sbqa_step(ctx, 1)
+        one = sb.sbqa_get_state(ctx)
+        x, y = one
+        sb.sbqa_set_state(ctx, x, y)
+        sb.sbqa_step(ctx, 50)
+        sb.sbqa_step(ctx, S - 88)
+        fin = sb.sbqa_get_state(ctx)
+        best = sb.sbqa_best(ctx)
+        out[kern] = (mid, one, fin, best, sb.sbqa_best_step(ctx), sb.sbqa_info(ctx)["c0"])
+    a, b = out[sb.SPARSE_STREAM], out[sb.SPARSE_RESIDENT]
+    for u, v in zip(a[:3], b[:3]):
+        assert np.array_equal(u[0], v[0]) and np.array_equal(u[1], v[1])
+    assert np.array_equal(a[3][0], b[3][0]) and np.array_equal(a[3][1], b[3][1])
+    assert np.array_equal(a[4], b[4])
+    # one resident step (37 -> 38) against the oracle
+    (X, Y), (xg, yg) = b[0], b[1]
+    P = orc.Problem(N, R, runs, csr=csr, h=h, dt=0.5, a0=1.0, c0=b[5], fmode=fmode)
+    ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, sparse_kernel=sb.SPARSE_RESIDENT, seed=5004,
+               jp_kind=sb.JP_PAPER)
+    jr = sb.sbqa_jperp_table(ctx)[:, 37].astype(np.float64)
+    _check_step(orc, P, ctx, sb, X, Y, 37, S, jr, xg, yg, csr=csr, h=h)
+
+
+def test_resident_rejects_unfit_instances(sb):
+    """SPARSE_RESIDENT on an instance the loop cannot hold is EINVAL with a reason;
+    AUTO then falls back to the streaming kernel."""
+    E = inst.regular_graph(300, 4, 5101)
+    csr = inst.edges_to_csr(300, E, inst.gaussian_edges(len(E), 5102))
+    for kw, why in ((dict(R=5, runs=4), "multiple of 8"), (dict(R=8, runs=2, fmode=sb.F_BALLISTIC), "ballistic")):
+        with pytest.raises(sb.SbqaError) as ei:
+            _ctx(sb, csr=csr, sparse_kernel=sb.SPARSE_RESIDENT, **kw)
+        assert ei.value.status == sb.EINVAL and why in ei.value.message
+        ctx = _ctx(sb, csr=csr, **kw)
+        assert not sb.sbqa_info(ctx)["resident"]
