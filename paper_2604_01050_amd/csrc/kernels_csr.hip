@@ -34,15 +34,21 @@ __device__ __forceinline__ uint32_t pack_ternary(float a, float b, float c, floa
 __device__ __forceinline__ void update_elem(float x, float y, float phi, float hv, float xl, float xr, float jpr,
                                             float kA, float kB, float dt, float kD, float &xo, float &yo) {
 #pragma clang fp contract(off)
-    const float force = (-kA * x + kB * (phi + hv)) + jpr * (xl + xr);
-    float yn = y + dt * force;
-    float xn = x + kD * yn;
+    // force = -kA x + kB (phi + h) + J_perp (x_left + x_right), with explicit
+    // fused multiply-adds so every kernel that calls this rounds identically
+    const float force = __builtin_fmaf(jpr, xl + xr, __builtin_fmaf(kB, phi + hv, -kA * x));
+    float yn = __builtin_fmaf(dt, force, y);
+    float xn = __builtin_fmaf(kD, yn, x);
     if (fabsf(xn) > 1.0f) {
         xn = xn > 0.0f ? 1.0f : -1.0f;
         yn = 0.0f;
     }
     xo = xn;
     yo = yn;
+}
+
+__device__ __forceinline__ uint32_t ternary_byte(float x, float d) {
+    return (uint32_t)(uint8_t)(int8_t)(x > d ? 1 : (x < -d ? -1 : 0));
 }
 
 // Coupling sum of the 4 columns c..c+3 of row i, accumulated in CSR order in
@@ -207,8 +213,8 @@ __global__ __launch_bounds__(256) void k_csr_fields(int N, int Cs, int C, int nc
 // that crosses workgroups is the ring coupling at the edges of the column
 // block: after each step a workgroup publishes its first and last column and
 // reads the neighbouring columns of the two workgroups next to it in the ring
-// (agent-scope release/acquire on per-workgroup step counters, double-buffered
-// by step parity). Every wait is bounded: on timeout the error word is set and
+// (coherent agent-scope accesses and per-workgroup step counters,
+// double-buffered by step parity). Every wait is bounded: on timeout the error word is set and
 // every later wait ends at once, so the grid always drains. The launch is
 // cooperative, so all workgroups are co-resident.
 // ---------------------------------------------------------------------------
@@ -217,12 +223,27 @@ constexpr int RES_THREADS = 512;
 constexpr int RES_MAX_RPT = 8;
 constexpr int RES_SPIN_LIMIT = 1 << 22;
 
-// Bounded wait of thread 0 until both ring-neighbour counters reach target.
+// Edge columns cross workgroups (possibly on different XCDs) through
+// agent-scope atomic stores and loads: these are performed coherently for the
+// whole device without writing back or invalidating the L2 caches. A producer
+// waits for its stores to complete before its step counter is raised; a
+// consumer reads the data only after it has seen the counter, so the data read
+// is the data written for that step.
+__device__ __forceinline__ void publish(float *p, float v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ float fetch(const float *p) {
+    return __hip_atomic_load(const_cast<float *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded wait of thread 0 until both ring-neighbour counters reach target; on
+// timeout the error word is set and every later wait returns at once, so the
+// grid always drains.
 __device__ __forceinline__ void wait_neighbours(const int *cnt, int wl, int wr, int target, int *err) {
     int spins = 0;
     for (;;) {
-        const int fl = __hip_atomic_load(cnt + wl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int fr = __hip_atomic_load(cnt + wr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int fl = __hip_atomic_load(const_cast<int *>(cnt) + wl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int fr = __hip_atomic_load(const_cast<int *>(cnt) + wr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (fl >= target && fr >= target) break;
         if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
         if (++spins > RES_SPIN_LIMIT) {
@@ -263,51 +284,58 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
 
     float xs[RPT][RES_COLS], ys[RPT][RES_COLS];
     uint32_t cpk[RPT][(D + 1) / 2];
-    int buf = a.n0 & 1;
-    float *pub = a.xpub + ((int64_t)buf * a.nwg + w) * 2 * NR;
+    // exchange buffer of parity b, block v, edge e (0: first column, 1: last)
+    auto slot = [&](int b, int v, int e) { return a.xpub + (((int64_t)b * a.nwg + v) * 2 + e) * NR; };
+    {
+        float *pf = slot(a.n0 & 1, w, 0), *pl = slot(a.n0 & 1, w, 1);
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        int r = t + q * RES_THREADS;
-        asm volatile("" : "+v"(r));
-        const float *xrow = a.x + (int64_t)r * a.Cs + c0;
-        const float *yrow = a.y + (int64_t)r * a.Cs + c0;
-        const float4 x0 = *reinterpret_cast<const float4 *>(xrow);
-        const float4 x1 = *reinterpret_cast<const float4 *>(xrow + 4);
-        const float4 y0 = *reinterpret_cast<const float4 *>(yrow);
-        const float4 y1 = *reinterpret_cast<const float4 *>(yrow + 4);
-        xs[q][0] = x0.x; xs[q][1] = x0.y; xs[q][2] = x0.z; xs[q][3] = x0.w;
-        xs[q][4] = x1.x; xs[q][5] = x1.y; xs[q][6] = x1.z; xs[q][7] = x1.w;
-        ys[q][0] = y0.x; ys[q][1] = y0.y; ys[q][2] = y0.z; ys[q][3] = y0.w;
-        ys[q][4] = y1.x; ys[q][5] = y1.y; ys[q][6] = y1.z; ys[q][7] = y1.w;
+        for (int q = 0; q < RPT; ++q) {
+            int r = t + q * RES_THREADS;
+            asm volatile("" : "+v"(r));
+            const float *xrow = a.x + (int64_t)r * a.Cs + c0;
+            const float *yrow = a.y + (int64_t)r * a.Cs + c0;
+            const float4 x0 = *reinterpret_cast<const float4 *>(xrow);
+            const float4 x1 = *reinterpret_cast<const float4 *>(xrow + 4);
+            const float4 y0 = *reinterpret_cast<const float4 *>(yrow);
+            const float4 y1 = *reinterpret_cast<const float4 *>(yrow + 4);
+            xs[q][0] = x0.x; xs[q][1] = x0.y; xs[q][2] = x0.z; xs[q][3] = x0.w;
+            xs[q][4] = x1.x; xs[q][5] = x1.y; xs[q][6] = x1.z; xs[q][7] = x1.w;
+            ys[q][0] = y0.x; ys[q][1] = y0.y; ys[q][2] = y0.z; ys[q][3] = y0.w;
+            ys[q][4] = y1.x; ys[q][5] = y1.y; ys[q][6] = y1.z; ys[q][7] = y1.w;
 #pragma unroll
-        for (int p = 0; p < D; p += 2) {
-            const uint32_t j0 = (uint32_t)a.colpad[(int64_t)r * D + p];
-            const uint32_t j1 = (p + 1 < D) ? (uint32_t)a.colpad[(int64_t)r * D + p + 1] : 0u;
-            cpk[q][p / 2] = j0 | (j1 << 16);
+            for (int p = 0; p < D; p += 2) {
+                const uint32_t j0 = (uint32_t)a.colpad[(int64_t)r * D + p];
+                const uint32_t j1 = (p + 1 < D) ? (uint32_t)a.colpad[(int64_t)r * D + p + 1] : 0u;
+                cpk[q][p / 2] = j0 | (j1 << 16);
+            }
+            publish(pf + r, xs[q][0]);                   // edges of the starting state
+            publish(pl + r, xs[q][RES_COLS - 1]);
         }
-        pub[r] = xs[q][0];
-        pub[NR + r] = xs[q][RES_COLS - 1];
     }
-    // edge columns of the starting state: one round on the launch counters
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // one round on the launch counters: every block's starting edges are out
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (t == 0) {
-        __hip_atomic_store(a.epoch_cnt + w, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.epoch_cnt + w, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         wait_neighbours(a.epoch_cnt, wl, wr, a.epoch, a.err);
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 
+    float kA = a.coefA[a.n0], dn = a.delta[a.n0 + 1], jpr = a.jp[(int64_t)run * a.S + a.n0];
     for (int s = 0; s < a.K; ++s) {
         // compiler-only barrier: the loop-invariant LDS weights and fields are
         // re-read every step instead of being pinned in registers
         asm volatile("" ::: "memory");
         const int n = a.n0 + s;
-        const float kA = a.coefA[n];
-        const float d = (a.fmode == 1) ? 0.0f : a.delta[n + 1];
-        const float jpr = a.jp[(int64_t)run * a.S + n];
-        const float *publ = a.xpub + ((int64_t)buf * a.nwg + wl) * 2 * NR + NR;  // last column, left block
-        const float *pubr = a.xpub + ((int64_t)buf * a.nwg + wr) * 2 * NR;       // first column, right block
+        const float d = (a.fmode == 1) ? 0.0f : dn;
+        const float kA_n = kA, jp_n = jpr;
+        if (s + 1 < a.K) {  // the next step's scalars load while this step runs
+            kA = a.coefA[n + 1];
+            dn = a.delta[n + 2];
+            jpr = a.jp[(int64_t)run * a.S + n + 1];
+        }
+        const float *publ = slot(n & 1, wl, 1);   // last column of the left block
+        const float *pubr = slot(n & 1, wr, 0);   // first column of the right block
         uint2 fnew[RPT];
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
@@ -328,20 +356,20 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
                 }
             }
             const float hv = hs[q * RES_THREADS + t];
-            const float br = pubr[r];
+            const float br = fetch(pubr + r);
             // columns left to right, in place: the left ring term reads the
             // step-n value of column c-1 kept in prev, the right one the
             // not yet updated column c+1
             uint32_t lo = 0, hi = 0;
-            float prev = publ[r];
+            float prev = fetch(publ + r);
 #pragma unroll
             for (int c = 0; c < RES_COLS; ++c) {
                 const float xr = c == RES_COLS - 1 ? br : xs[q][c + 1];
                 float xn, yn;
-                update_elem(xs[q][c], ys[q][c], acc[c], hv, prev, xr, jpr, kA, a.kB, a.dt, a.kD, xn, yn);
-                const uint32_t fb = (uint32_t)(uint8_t)(int8_t)(xn > d ? 1 : (xn < -d ? -1 : 0));
-                if (c < 4) lo |= fb << (8 * c);
-                else hi |= fb << (8 * (c - 4));
+                update_elem(xs[q][c], ys[q][c], acc[c], hv, prev, xr, jp_n, kA_n, a.kB, a.dt, a.kD, xn, yn);
+                const uint32_t f = ternary_byte(xn, d);
+                if (c < 4) lo |= f << (8 * c);
+                else hi |= f << (8 * (c - 4));
                 prev = xs[q][c];
                 xs[q][c] = xn;
                 ys[q][c] = yn;
@@ -352,24 +380,22 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
             __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();  // every wave is done reading the step-n operand
-        buf ^= 1;
-        pub = a.xpub + ((int64_t)buf * a.nwg + w) * 2 * NR;
+        float *pf = slot((n + 1) & 1, w, 0), *pl = slot((n + 1) & 1, w, 1);
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int r = t + q * RES_THREADS;
             asm volatile("" : "+v"(r));
             op[r] = fnew[q];
-            pub[r] = xs[q][0];
-            pub[NR + r] = xs[q][RES_COLS - 1];
+            publish(pf + r, xs[q][0]);
+            publish(pl + r, xs[q][RES_COLS - 1]);
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's edge stores have completed
         __syncthreads();
         if (t == 0) {
-            __hip_atomic_store(a.flags + w, n + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(a.flags + w, n + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             wait_neighbours(a.flags, wl, wr, n + 1, a.err);
         }
         __syncthreads();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
 
     // write back the state and the operand of the own columns (the row index

@@ -99,7 +99,7 @@ struct sbqa_ctx {
     float *valpad = nullptr;            // [D][rows]
     float *coefA = nullptr;             // [S]
     float *delta_tab = nullptr;         // [S+1]
-    float *xpub = nullptr;              // [2][nwg][2][rows]
+    float *xpub = nullptr;              // [2][nwg][2][rows] published edge columns
     int *flags = nullptr, *epoch_cnt = nullptr, *err = nullptr;
     int *err_host = nullptr;            // pinned copy of err
     int epoch = 0;
