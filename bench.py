@@ -89,17 +89,21 @@ def algorithmic_bytes(w, info):
     return N * N * eb + C * N * eb + C * N * 4
 
 
-# fp32 vector peak of MI355X (256 CUs, 2.4 GHz); the kernels here are built
-# without packed fp32, so half of it is the reachable ceiling.
-PEAK_VALU_FP32 = 157.3
+# VALU peak of MI355X in fp32 lane operations: 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz = 39.3 Tops/s, one operation per lane per cycle (the 157.3 TFLOP/s
+# fp32 vector figure counts an FMA as two flops and needs packed fp32, which
+# this build does not emit).
+PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
-def resident_flops_per_step(w):
-    """Arithmetic of one step of the resident sparse loop per replica-spin update:
-    2d for the coupling sum, 11 for the update (pump, field, ring, kick, drift)."""
+def resident_ops_per_step(w):
+    """Operations one step of the resident sparse loop must perform per
+    replica-spin update: per neighbour one int8->fp32 conversion and one FMA
+    (2d), then 7 for the kick and drift, 3 for the wall, 3 for the ternary
+    decision of Eq. 8 (2d + 13)."""
     N, C = w["N"], w["R"] * w["runs"]
     nnz = len(w["csr"][1])
-    return 2.0 * nnz * C + 11.0 * N * C
+    return 2.0 * nnz * C + 13.0 * N * C
 
 
 def algorithmic_flops(w):
@@ -121,9 +125,10 @@ def source_hash(path):
 
 
 def measured_traffic(workload, path):
-    """HBM bytes per launch of the dominant kernel from the committed counter
-    summary (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of
-    known size); None when absent or taken on a different kernel source."""
+    """HBM bytes per launch (or per step, for the many-step resident loop) of
+    the dominant kernel from the committed counter summary (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size); None when
+    absent or taken on a different kernel source."""
     f = os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)
     if not os.path.exists(f):
         return None
@@ -135,8 +140,8 @@ def measured_traffic(workload, path):
     if kv.get("source_sha256_16") != source_hash(KERNEL_SOURCES[path]):
         return None
     try:
-        return float(kv["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
+        return float(kv.get("hbm_bytes_per_launch", kv.get("hbm_bytes_per_step")))
+    except (TypeError, ValueError):
         return None
 
 
@@ -249,12 +254,13 @@ def main():
     if launch_ms:
         avg_s = float(np.mean(launch_ms)) * 1e-3
         if resident:
-            fl = K * resident_flops_per_step(w)
-            peak = PEAK_VALU_FP32
-            out["roofline"] = {"bound": "alu", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-                               "frac": fl / avg_s / 1e12 / peak, "traffic": measured_traffic(a.workload + "_resident", "csr_resident"),
+            ops = K * resident_ops_per_step(w)
+            tr = measured_traffic(a.workload + "_resident", "csr_resident")
+            out["roofline"] = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": PEAK_VALU_OPS,
+                               "unit": "Tops/s (fp32 VALU lane ops)", "frac": ops / avg_s / 1e12 / PEAK_VALU_OPS,
+                               "traffic": None if tr is None else tr * K,
                                "kernel": "k_csr_resident", "avg_launch_us": avg_s * 1e6, "steps_per_launch": K,
-                               "algorithmic_flops_per_launch": fl}
+                               "algorithmic_ops_per_launch": ops}
         elif info["path"] == "csr_fp32":
             ab = algorithmic_bytes(w, info)
             out["roofline"] = {"bound": "hbm", "achieved": ab / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
