@@ -273,7 +273,7 @@ def main():
             peak = PEAK[{"dense_fp8": "fp8", "dense_fp32": "fp32", "dense_bf16x3": "bf16"}[info["path"]]]
             out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
                                "frac": fl / avg_s / 1e12 / peak,
-                               "traffic": measured_traffic(a.workload, info["path"]), "kernel": "k_gemm + k_dense_update",
+                               "traffic": measured_traffic(a.workload, info["path"]), "kernel": "k_dense_step",
                                "avg_step_us": avg_s * 1e6, "algorithmic_flops_per_step": fl}
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)

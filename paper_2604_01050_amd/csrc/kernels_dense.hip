@@ -1,12 +1,16 @@
 // Dense SBQA kernels for gfx950 (CDNA4, wave64):
-//   * the coupling sum of Eq. 7 as an MFMA GEMM over all runs and replicas,
-//     Phi^T[c][i] = sum_j f(X)^T[c][j] J[i][j]  (J symmetric, zero diagonal),
-//     in fp32, e4m3 fp8, bf16 hi+lo (three products) or fp64 (energies);
-//   * the fused update of Eqs. 6-7 (pump, Trotter ring, kick, drift, wall)
-//     that also emits the next contraction operand f(X) (Eq. 8).
-// State and operands are replica-major ([C][Np]): both GEMM operands are then
-// K-contiguous and the update streams rows of Np spins.
+//   * one step of the dense path: the coupling sum of Eq. 7 over all runs and
+//     replicas, Phi^T[c][i] = sum_j f(X)^T[c][j] J[i][j] (J symmetric, zero
+//     diagonal), on MFMA in fp32, e4m3 fp8 or bf16 hi+lo (three products),
+//     with the update of Eqs. 6-7 (pump, Trotter ring, kick, drift, wall) and
+//     the next operand f(X) (Eq. 8) fused into its epilogue;
+//   * the fp64 GEMM of the energies (Eq. 2 at the corners).
+// State is replica-major ([C][Np]); the contraction operands are
+// fragment-tiled (see sbqa_internal.h).
 #include "sbqa_internal.h"
+
+#include <type_traits>
+#include <utility>
 
 namespace sbqa {
 namespace {
@@ -16,16 +20,19 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef int i8v __attribute__((ext_vector_type(8)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-constexpr int LDS_STRIDE = GEMM_KB + 16;  // padded LDS row (bytes): spreads rows over banks
-constexpr int TILE_BYTES = GEMM_BM * LDS_STRIDE;
-static_assert(GEMM_BM == GEMM_BN, "square block tile assumed by the loaders");
-
 // e4m3 encodings of the ternary values.
 constexpr uint8_t FP8_P1 = 0x38, FP8_M1 = 0xB8;
 // E8M0 block scale 2^(127-127) = 1 for the scaled fp8 MFMA.
 constexpr int E8M0_ONE = 127;
 
-struct Frag32 { uint4 lo, hi; };  // 32 contiguous bytes of one LDS row
+struct Frag32 { uint4 lo, hi; };  // the 32 K bytes of one lane for a 16x16 block
+
+// ---------------------------------------------------------------------------
+// fp64 energy GEMM (row-major operands staged through LDS).
+// ---------------------------------------------------------------------------
+constexpr int LDS_STRIDE = GEMM_KB + 16;  // padded LDS row (bytes): spreads rows over banks
+constexpr int TILE_BYTES = GEMM_BM * LDS_STRIDE;
+static_assert(GEMM_BM == GEMM_BN, "square block tile assumed by the loaders");
 
 __device__ __forceinline__ Frag32 lds_frag(const uint8_t *tile, int row, int g) {
     const uint8_t *p = tile + row * LDS_STRIDE + g * 32;
@@ -35,73 +42,23 @@ __device__ __forceinline__ Frag32 lds_frag(const uint8_t *tile, int row, int g) 
     return f;
 }
 
-template <int KIND> struct AccT { typedef f4 T; };
-template <> struct AccT<GK_F64> { typedef d4 T; };
-
-// One 16x16 block update with the 32-byte K slices a, b of this lane.
-// Lane group g = lane/16 holds the same K slice for A and B, so the products
-// pair correctly whatever K order the instruction uses inside a slice.
-template <int KIND>
-__device__ __forceinline__ void mma(typename AccT<KIND>::T &acc, const Frag32 &a, const Frag32 &b,
-                                    const Frag32 &a2, const Frag32 &b2) {
-    if constexpr (KIND == GK_F32) {
-        const float *af = reinterpret_cast<const float *>(&a);
-        const float *bf = reinterpret_cast<const float *>(&b);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[t], bf[t], acc, 0, 0, 0);
-    } else if constexpr (KIND == GK_F64) {
-        const double *ad = reinterpret_cast<const double *>(&a);
-        const double *bd = reinterpret_cast<const double *>(&b);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[t], bd[t], acc, 0, 0, 0);
-    } else if constexpr (KIND == GK_FP8) {
-        i8v av, bv;
-        __builtin_memcpy(&av, &a, 32);
-        __builtin_memcpy(&bv, &b, 32);
-        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, E8M0_ONE, 0,
-                                                                E8M0_ONE);
-    } else {  // GK_BF16X3: hi*hi + hi*lo + lo*hi
-        bf8v ah0, ah1, bh0, bh1, al0, al1, bl0, bl1;
-        __builtin_memcpy(&ah0, &a.lo, 16);
-        __builtin_memcpy(&ah1, &a.hi, 16);
-        __builtin_memcpy(&bh0, &b.lo, 16);
-        __builtin_memcpy(&bh1, &b.hi, 16);
-        __builtin_memcpy(&al0, &a2.lo, 16);
-        __builtin_memcpy(&al1, &a2.hi, 16);
-        __builtin_memcpy(&bl0, &b2.lo, 16);
-        __builtin_memcpy(&bl1, &b2.hi, 16);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al0, bh0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al1, bh1, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bl0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bl1, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah0, bh0, acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah1, bh1, acc, 0, 0, 0);
-    }
-}
-
 // Block tile: GEMM_BM operand rows (m = replica column c) x GEMM_BN J rows
 // (n = spin i); 4 waves in 2x2, each wave 64x64 = 4x4 MFMA 16x16 blocks.
-// K tiles of GEMM_KB bytes are staged through LDS; the next tile is fetched
-// into registers while the current one is multiplied.
-template <int KIND>
-__global__ __launch_bounds__(GEMM_THREADS) void k_gemm(const uint8_t *__restrict__ A,
-                                                       const uint8_t *__restrict__ A2,
-                                                       const uint8_t *__restrict__ B,
-                                                       const uint8_t *__restrict__ B2,
-                                                       void *__restrict__ out, int Np, int Cp,
-                                                       int ebytes, int kchunk_bytes) {
-    constexpr int NT = (KIND == GK_BF16X3) ? 4 : 2;
-    __shared__ __align__(16) uint8_t lds[NT * TILE_BYTES];
-    typedef typename AccT<KIND>::T Acc;
-
+// Lane group g = lane/16 holds the same 32-byte K slice for A and B, so the
+// products pair correctly whatever K order the instruction uses in a slice.
+__global__ __launch_bounds__(GEMM_THREADS) void k_gemm_f64(const uint8_t *__restrict__ A,
+                                                           const uint8_t *__restrict__ B,
+                                                           double *__restrict__ out, int Np, int Cp,
+                                                           int kchunk_bytes) {
+    __shared__ __align__(16) uint8_t lds[2 * TILE_BYTES];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
     const int n0 = blockIdx.x * GEMM_BN, m0 = blockIdx.y * GEMM_BM, z = blockIdx.z;
-    const int64_t rowbytes = (int64_t)Np * ebytes;
+    const int64_t rowbytes = (int64_t)Np * 8;
     const int64_t kb0 = (int64_t)z * kchunk_bytes;
     const int ntiles = kchunk_bytes / GEMM_KB;
 
-    uint4 ra[4], rb[4], ra2[4], rb2[4];
+    uint4 ra[4], rb[4];
     auto gload = [&](int kt) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -109,75 +66,68 @@ __global__ __launch_bounds__(GEMM_THREADS) void k_gemm(const uint8_t *__restrict
             const int64_t off = kb0 + (int64_t)kt * GEMM_KB + c16 * 16;
             ra[p] = *reinterpret_cast<const uint4 *>(A + (int64_t)(m0 + row) * rowbytes + off);
             rb[p] = *reinterpret_cast<const uint4 *>(B + (int64_t)(n0 + row) * rowbytes + off);
-            if constexpr (KIND == GK_BF16X3) {
-                ra2[p] = *reinterpret_cast<const uint4 *>(A2 + (int64_t)(m0 + row) * rowbytes + off);
-                rb2[p] = *reinterpret_cast<const uint4 *>(B2 + (int64_t)(n0 + row) * rowbytes + off);
-            }
         }
     };
-    auto lstore = [&]() {
+    d4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = d4{0, 0, 0, 0};
+
+    const int g = lane >> 4, r16 = lane & 15;
+    gload(0);
+    for (int kt = 0; kt < ntiles; ++kt) {
+        __syncthreads();
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int q = tid + GEMM_THREADS * p, row = q >> 3, c16 = q & 7;
             const int o = row * LDS_STRIDE + c16 * 16;
             *reinterpret_cast<uint4 *>(lds + o) = ra[p];
             *reinterpret_cast<uint4 *>(lds + TILE_BYTES + o) = rb[p];
-            if constexpr (KIND == GK_BF16X3) {
-                *reinterpret_cast<uint4 *>(lds + 2 * TILE_BYTES + o) = ra2[p];
-                *reinterpret_cast<uint4 *>(lds + 3 * TILE_BYTES + o) = rb2[p];
-            }
         }
-    };
-
-    Acc acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = Acc{0, 0, 0, 0};
-
-    const int g = lane >> 4, r16 = lane & 15;
-    gload(0);
-    for (int kt = 0; kt < ntiles; ++kt) {
-        __syncthreads();
-        lstore();
         __syncthreads();
         if (kt + 1 < ntiles) gload(kt + 1);
-        Frag32 bf[4], bf2[4];
+        Frag32 bf[4];
 #pragma unroll
-        for (int nb = 0; nb < 4; ++nb) {
-            bf[nb] = lds_frag(lds + TILE_BYTES, wn * 64 + nb * 16 + r16, g);
-            if constexpr (KIND == GK_BF16X3) bf2[nb] = lds_frag(lds + 3 * TILE_BYTES, wn * 64 + nb * 16 + r16, g);
-        }
+        for (int nb = 0; nb < 4; ++nb) bf[nb] = lds_frag(lds + TILE_BYTES, wn * 64 + nb * 16 + r16, g);
 #pragma unroll
         for (int mb = 0; mb < 4; ++mb) {
-            Frag32 af = lds_frag(lds, wm * 64 + mb * 16 + r16, g);
-            Frag32 af2 = af;
-            if constexpr (KIND == GK_BF16X3) af2 = lds_frag(lds + 2 * TILE_BYTES, wm * 64 + mb * 16 + r16, g);
+            const Frag32 af = lds_frag(lds, wm * 64 + mb * 16 + r16, g);
+            const double *ad = reinterpret_cast<const double *>(&af);
 #pragma unroll
-            for (int nb = 0; nb < 4; ++nb) mma<KIND>(acc[mb][nb], af, bf[nb], af2, bf2[nb]);
+            for (int nb = 0; nb < 4; ++nb) {
+                const double *bd = reinterpret_cast<const double *>(&bf[nb]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    acc[mb][nb] = __builtin_amdgcn_mfma_f64_16x16x4f64(ad[t], bd[t], acc[mb][nb], 0, 0, 0);
+            }
         }
     }
-
-    // D[m][n], column lane%16 of each 16x16 block; f32 results: register r is
-    // row 4*(lane/16) + r; f64 results: register r is row 4*r + lane/16.
+    // D[m][n]: column lane%16 of each 16x16 block; register r is row 4*r + lane/16.
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 4; ++nb)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int mr = (KIND == GK_F64) ? 4 * r + g : 4 * g + r;
-                const int m = m0 + wm * 64 + mb * 16 + mr;
+                const int m = m0 + wm * 64 + mb * 16 + 4 * r + g;
                 const int n = n0 + wn * 64 + nb * 16 + r16;
-                const int64_t o = ((int64_t)z * Cp + m) * Np + n;
-                if constexpr (KIND == GK_F64) reinterpret_cast<double *>(out)[o] = acc[mb][nb][r];
-                else reinterpret_cast<float *>(out)[o] = acc[mb][nb][r];
+                out[((int64_t)z * Cp + m) * Np + n] = acc[mb][nb][r];
             }
 }
 
 // ---------------------------------------------------------------------------
-// Fused update (Eqs. 6-7 + wall) and operand emission (Eq. 8).
+// Operand formats and the fragment-tiled layout.
 // ---------------------------------------------------------------------------
+
+// Byte offset of element (row, k) in a fragment-tiled matrix with nkc K chunks
+// and groups of G row blocks.
+__device__ __forceinline__ int64_t tf_offset(int row, int k, int nkc, int eb, int G) {
+    const int kbyte = k * eb;
+    const int kc = kbyte >> 7, kb = kbyte & 127, rb = row >> 4;
+    const int l = ((kb >> 5) << 4) | (row & 15);
+    return (((int64_t)(rb / G) * nkc + kc) * G + rb % G) * FRAG_BYTES + ((kb >> 4) & 1) * 1024 + l * 16 + (kb & 15);
+}
 
 __device__ __forceinline__ float f_value(int fmode, float x, float delta) {
     if (fmode == 2) return x;                       // bSB
@@ -194,10 +144,14 @@ __device__ __forceinline__ uint16_t bf16_rne(float v) {
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
+// Four consecutive operand values (same row, K positions k..k+3) at byte
+// offset o of the fragment-tiled operand (o from tf_offset: the four values
+// are contiguous there).
 template <int PATH>
 __device__ __forceinline__ void store_operand(void *g, void *g_lo, int64_t o, float4 f, int fmode) {
+    uint8_t *gb = reinterpret_cast<uint8_t *>(g);
     if constexpr (PATH == PATH_F32) {
-        *reinterpret_cast<float4 *>(reinterpret_cast<float *>(g) + o) = f;
+        *reinterpret_cast<float4 *>(gb + o) = f;
     } else if constexpr (PATH == PATH_FP8) {
         const float v[4] = {f.x, f.y, f.z, f.w};
         uint32_t w = 0;
@@ -206,7 +160,7 @@ __device__ __forceinline__ void store_operand(void *g, void *g_lo, int64_t o, fl
             const uint32_t b = v[e] > 0.0f ? FP8_P1 : (v[e] < 0.0f ? FP8_M1 : 0u);
             w |= b << (8 * e);
         }
-        *reinterpret_cast<uint32_t *>(reinterpret_cast<uint8_t *>(g) + o) = w;
+        *reinterpret_cast<uint32_t *>(gb + o) = w;
     } else {  // BF16X3
         const float v[4] = {f.x, f.y, f.z, f.w};
         uint16_t hi[4], lo[4];
@@ -220,141 +174,365 @@ __device__ __forceinline__ void store_operand(void *g, void *g_lo, int64_t o, fl
         H.y = hi[2] | ((uint32_t)hi[3] << 16);
         L.x = lo[0] | ((uint32_t)lo[1] << 16);
         L.y = lo[2] | ((uint32_t)lo[3] << 16);
-        *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(g) + o) = H;
-        *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(g_lo) + o) = L;
+        *reinterpret_cast<uint2 *>(gb + o) = H;
+        *reinterpret_cast<uint2 *>(reinterpret_cast<uint8_t *>(g_lo) + o) = L;
     }
 }
 
-#pragma clang fp contract(off)
-// One thread: 4 consecutive spins i of one replica column c (grid.y = c).
+// ---------------------------------------------------------------------------
+// MFMA terms of one 16x16 block with the 32 K bytes a (operand) and b (J) of
+// this lane (a2, b2: bf16 low parts). Term t of T<PATH>::terms; every block
+// accumulates its terms in the same order.
+// ---------------------------------------------------------------------------
+template <int PATH> struct Terms;
+template <> struct Terms<PATH_F32> { static constexpr int n = 8; };     // 8 x 16x16x4 f32
+template <> struct Terms<PATH_FP8> { static constexpr int n = 1; };     // 1 x 16x16x128 f8f6f4
+template <> struct Terms<PATH_BF16X3> { static constexpr int n = 6; };  // lo*hi, hi*lo, hi*hi x 2 halves
+
+template <int PATH, int T>
+__device__ __forceinline__ void mma_term(f4 &acc, const Frag32 &a, const Frag32 &b, const Frag32 &a2,
+                                         const Frag32 &b2) {
+    if constexpr (PATH == PATH_F32) {
+        const float *af = reinterpret_cast<const float *>(&a);
+        const float *bf = reinterpret_cast<const float *>(&b);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[T], bf[T], acc, 0, 0, 0);
+    } else if constexpr (PATH == PATH_FP8) {
+        i8v av, bv;
+        __builtin_memcpy(&av, &a, 32);
+        __builtin_memcpy(&bv, &b, 32);
+        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, E8M0_ONE, 0, E8M0_ONE);
+    } else {
+        // small products first: lo*hi, hi*lo, then hi*hi; each over both halves
+        const Frag32 &x = (T < 2) ? a2 : a;
+        const Frag32 &y = (T >= 2 && T < 4) ? b2 : b;
+        const uint4 &xs = (T & 1) ? x.hi : x.lo;
+        const uint4 &ys = (T & 1) ? y.hi : y.lo;
+        bf8v xv, yv;
+        __builtin_memcpy(&xv, &xs, 16);
+        __builtin_memcpy(&yv, &ys, 16);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xv, yv, acc, 0, 0, 0);
+    }
+}
+
+template <int PATH> struct Pipe {
+    static constexpr int planes = (PATH == PATH_BF16X3) ? 2 : 1;  // bf16: hi and lo
+    static constexpr int depth = dense_depth(Path(PATH));          // K chunks in flight
+};
+
+__device__ __forceinline__ uint4 ld16(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+// f(integral_constant<int, I>) for I = B..E-1, unrolled at compile time.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused update (Eqs. 6-7 + wall) and operand emission (Eq. 8) for four
+// consecutive spins i4..i4+3 of replica column c, with their fields ph. The
+// inputs are gathered first (UpdIn) so that a lane can have the loads of all
+// its items in flight before the first store.
 // The ring neighbours are columns r*R + (k -+ 1 mod R) of the same run.
-template <int PATH>
-__global__ __launch_bounds__(256) void k_dense_update(int N, int Np, int R, int Cp, int splits,
-                                                      const float *__restrict__ phi,
-                                                      const float *__restrict__ h,
-                                                      const float *__restrict__ x_in,
-                                                      float *__restrict__ x_out, float *__restrict__ y,
-                                                      void *g, void *g_lo, const float *__restrict__ jp,
-                                                      int64_t jp_stride, StepCoef k, int fmode) {
-    const int c = blockIdx.y;
-    const int i4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
-    if (i4 >= Np) return;
+// ---------------------------------------------------------------------------
+struct UpdIn {
+    float4 x, xl, xr, y, h;
+    float jp;
+};
+
+__device__ __forceinline__ UpdIn update_load(const DenseStepArgs &a, int c, int i4) {
+    const int Np = a.Np, R = a.R;
     const int r = c / R, kk = c - r * R;
     const int cl = r * R + (kk == 0 ? R - 1 : kk - 1);
     const int cr = r * R + (kk == R - 1 ? 0 : kk + 1);
-    const int64_t o = (int64_t)c * Np + i4;
-    const float4 x = *reinterpret_cast<const float4 *>(x_in + o);
-    const float4 xl = *reinterpret_cast<const float4 *>(x_in + (int64_t)cl * Np + i4);
-    const float4 xr = *reinterpret_cast<const float4 *>(x_in + (int64_t)cr * Np + i4);
-    const float4 yv = *reinterpret_cast<const float4 *>(y + o);
-    const float4 hv = *reinterpret_cast<const float4 *>(h + i4);
-    float4 ph = *reinterpret_cast<const float4 *>(phi + o);
-    for (int zz = 1; zz < splits; ++zz) {
-        const float4 q = *reinterpret_cast<const float4 *>(phi + ((int64_t)zz * Cp + c) * Np + i4);
-        ph.x += q.x; ph.y += q.y; ph.z += q.z; ph.w += q.w;
-    }
-    const float jpr = jp[(int64_t)r * jp_stride];
-    const float xs[4] = {x.x, x.y, x.z, x.w}, ls[4] = {xl.x, xl.y, xl.z, xl.w};
-    const float rs[4] = {xr.x, xr.y, xr.z, xr.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
-    const float hs[4] = {hv.x, hv.y, hv.z, hv.w}, ps[4] = {ph.x, ph.y, ph.z, ph.w};
+    UpdIn u;
+    u.x = *reinterpret_cast<const float4 *>(a.x_in + (int64_t)c * Np + i4);
+    u.xl = *reinterpret_cast<const float4 *>(a.x_in + (int64_t)cl * Np + i4);
+    u.xr = *reinterpret_cast<const float4 *>(a.x_in + (int64_t)cr * Np + i4);
+    u.y = *reinterpret_cast<const float4 *>(a.y + (int64_t)c * Np + i4);
+    u.h = *reinterpret_cast<const float4 *>(a.h + i4);
+    u.jp = a.jp[(int64_t)r * a.jp_stride];
+    return u;
+}
+
+#pragma clang fp contract(off)
+template <int PATH, int MBW>
+__device__ __forceinline__ void update_store(const DenseStepArgs &a, int c, int i4, const UpdIn &u, float4 ph) {
+    const StepCoef k = a.k;
+    const float xs[4] = {u.x.x, u.x.y, u.x.z, u.x.w}, ls[4] = {u.xl.x, u.xl.y, u.xl.z, u.xl.w};
+    const float rs[4] = {u.xr.x, u.xr.y, u.xr.z, u.xr.w}, ys[4] = {u.y.x, u.y.y, u.y.z, u.y.w};
+    const float hs[4] = {u.h.x, u.h.y, u.h.z, u.h.w}, ps[4] = {ph.x, ph.y, ph.z, ph.w};
     float xo[4], yo[4], fo[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const float force = (-k.kA * xs[e] + k.kB * (ps[e] + hs[e])) + jpr * (ls[e] + rs[e]);
+        const float force = (-k.kA * xs[e] + k.kB * (ps[e] + hs[e])) + u.jp * (ls[e] + rs[e]);
         float yn = ys[e] + k.dt * force;
         float xn = xs[e] + k.kD * yn;
         if (fabsf(xn) > 1.0f) {
             xn = xn > 0.0f ? 1.0f : -1.0f;
             yn = 0.0f;
         }
-        if (i4 + e >= N) { xn = 0.0f; yn = 0.0f; }  // padding stays zero
+        if (i4 + e >= a.N) { xn = 0.0f; yn = 0.0f; }  // padding stays zero
         xo[e] = xn;
         yo[e] = yn;
-        fo[e] = f_value(fmode, xn, k.delta_next);
+        fo[e] = f_value(a.fmode, xn, k.delta_next);
     }
-    *reinterpret_cast<float4 *>(x_out + o) = make_float4(xo[0], xo[1], xo[2], xo[3]);
-    *reinterpret_cast<float4 *>(y + o) = make_float4(yo[0], yo[1], yo[2], yo[3]);
-    store_operand<PATH>(g, g_lo, o, make_float4(fo[0], fo[1], fo[2], fo[3]), fmode);
+    const int64_t o = (int64_t)c * a.Np + i4;
+    *reinterpret_cast<float4 *>(a.x_out + o) = make_float4(xo[0], xo[1], xo[2], xo[3]);
+    *reinterpret_cast<float4 *>(a.y + o) = make_float4(yo[0], yo[1], yo[2], yo[3]);
+    constexpr int eb = (PATH == PATH_F32) ? 4 : (PATH == PATH_FP8) ? 1 : 2;
+    store_operand<PATH>(a.g_next, a.g_next_lo, tf_offset(c, i4, a.nkc, eb, MBW),
+                        make_float4(fo[0], fo[1], fo[2], fo[3]), a.fmode);
 }
 #pragma clang fp contract(on)
 
+// ---------------------------------------------------------------------------
+// One dense step. Workgroup tile: DENSE_TN = 64 spins (4 row blocks of J) x
+// 64*MBW replica columns. Wave w owns m-blocks [w*MBW, (w+1)*MBW) of the
+// column chunk and all 4 J row blocks: every J fragment is read once per step
+// and column chunk, shared by the 4 waves through a double-buffered LDS slot
+// (wave w stages row block w), while each wave streams its own operand
+// fragments straight into registers, Pipe::depth K chunks ahead. reverse = 1
+// walks K backwards: alternating the direction every step starts each step on
+// the J chunks the previous one touched last.
+// ---------------------------------------------------------------------------
+template <int PATH, int MBW, int EPI>
+__global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArgs a) {
+    constexpr int PL = Pipe<PATH>::planes;
+    constexpr int PD = Pipe<PATH>::depth;
+    constexpr int NT = Terms<PATH>::n;
+    constexpr int RBT = DENSE_TN / 16;          // J row blocks per tile
+    constexpr int SLOT = PL * RBT * FRAG_BYTES;  // J fragments of one K chunk
+    constexpr int TS = DENSE_TN + 4;             // epilogue transpose row stride (floats)
+    constexpr int TBYTES = 4 * 16 * TS * 4;
+    constexpr int LDS_BYTES = (2 * SLOT > TBYTES) ? 2 * SLOT : TBYTES;
+    __shared__ __align__(16) uint8_t lds[LDS_BYTES];
+
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nt = blockIdx.x, n0 = nt * DENSE_TN;
+    const int mb0 = (blockIdx.y * 4 + w) * MBW;   // first m-block of this wave
+    const int nkc = a.nkc;
+    const int l16 = lane * 16;
+    constexpr int JCH = RBT * FRAG_BYTES;   // J bytes of one tile and K chunk
+    constexpr int XCH = MBW * FRAG_BYTES;   // operand bytes of one wave and K chunk
+
+    // this wave stages J row block w of tile nt (both planes); its operand
+    // group is m-blocks mb0..mb0+MBW-1
+    const int64_t jgrp = (int64_t)nt * nkc * JCH + w * FRAG_BYTES + l16;
+    const int64_t xgrp = (int64_t)(blockIdx.y * 4 + w) * nkc * XCH + l16;
+    const uint8_t *jsrc = a.J + jgrp;
+    const uint8_t *jsrc_lo = (PL == 2) ? a.J_lo + jgrp : jsrc;
+    const uint8_t *xsrc = a.g + xgrp;
+    const uint8_t *xsrc_lo = (PL == 2) ? a.g_lo + xgrp : xsrc;
+
+    uint4 jr[PD][PL][2];
+    uint4 xr[PD][MBW][PL][2];
+    f4 acc[MBW][RBT];
+#pragma unroll
+    for (int i = 0; i < MBW; ++i)
+#pragma unroll
+        for (int j = 0; j < RBT; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+    const int rev = a.reverse;
+    auto chunk_at = [&](int kc) -> int64_t { return rev ? nkc - 1 - kc : kc; };
+    auto load_j = [&](uint4 (&d)[PL][2], int kc) {
+        const int64_t o = chunk_at(kc) * JCH;
+        d[0][0] = ld16(jsrc + o);
+        d[0][1] = ld16(jsrc + o + 1024);
+        if constexpr (PL == 2) {
+            d[PL - 1][0] = ld16(jsrc_lo + o);
+            d[PL - 1][1] = ld16(jsrc_lo + o + 1024);
+        }
+    };
+    auto load_x = [&](uint4 (&d)[MBW][PL][2], int kc) {
+        const int64_t o = chunk_at(kc) * XCH;
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb) {
+            d[mb][0][0] = ld16(xsrc + o + mb * FRAG_BYTES);
+            d[mb][0][1] = ld16(xsrc + o + mb * FRAG_BYTES + 1024);
+            if constexpr (PL == 2) {
+                d[mb][PL - 1][0] = ld16(xsrc_lo + o + mb * FRAG_BYTES);
+                d[mb][PL - 1][1] = ld16(xsrc_lo + o + mb * FRAG_BYTES + 1024);
+            }
+        }
+    };
+
+    // nkc is a multiple of PD (the host pads N accordingly). Every chunk
+    // issues the same loads (the last PD chunks re-read their own chunk
+    // instead of prefetching past the end), so the memory counters the
+    // compiler waits on are exact and the loop body has no branches; the
+    // prologue issues its loads in the loop's order, J then operand per chunk.
+#pragma unroll
+    for (int s = 0; s < PD; ++s) {
+        load_j(jr[s], s);
+        __builtin_amdgcn_sched_barrier(0);
+        load_x(xr[s], s);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+
+#pragma unroll 1
+    for (int kc0 = 0; kc0 < nkc; kc0 += PD) {
+#pragma unroll
+        for (int s = 0; s < PD; ++s) {
+            const int kc = kc0 + s;
+            const int kn = (kc + PD < nkc) ? kc + PD : kc;
+            uint8_t *slot = lds + (kc & 1) * SLOT;
+            // publish this wave's J fragment of chunk kc; slot (kc & 1) was
+            // last read in chunk kc - 2, which every wave finished before the
+            // barrier of chunk kc - 1
+#pragma unroll
+            for (int pl = 0; pl < PL; ++pl) {
+                uint8_t *dst = slot + (pl * RBT + w) * FRAG_BYTES + l16;
+                *reinterpret_cast<uint4 *>(dst) = jr[s][pl][0];
+                *reinterpret_cast<uint4 *>(dst + 1024) = jr[s][pl][1];
+            }
+            load_j(jr[s], kn);
+            __syncthreads();
+            // J fragments of the 4 row blocks, two in registers at a time
+            Frag32 bjb[2][PL];
+            auto read_j = [&](Frag32 (&d)[PL], int p) {
+#pragma unroll
+                for (int pl = 0; pl < PL; ++pl) {
+                    d[pl].lo = *reinterpret_cast<const uint4 *>(slot + (pl * RBT + p) * FRAG_BYTES + l16);
+                    d[pl].hi = *reinterpret_cast<const uint4 *>(slot + (pl * RBT + p) * FRAG_BYTES + 1024 + l16);
+                }
+            };
+            read_j(bjb[0], 0);
+#pragma unroll
+            for (int p = 0; p < RBT; ++p) {
+                if (p + 1 < RBT) read_j(bjb[(p + 1) & 1], p + 1);
+                const Frag32 &bj = bjb[p & 1][0], &bj2 = bjb[p & 1][PL - 1];
+                // term-major order: consecutive MFMAs go to different blocks
+                static_for<0, NT>([&](auto tc) {
+                    constexpr int T = decltype(tc)::value;
+#pragma unroll
+                    for (int mb = 0; mb < MBW; ++mb) {
+                        const Frag32 ax{xr[s][mb][0][0], xr[s][mb][0][1]};
+                        const Frag32 ax2{xr[s][mb][PL - 1][0], xr[s][mb][PL - 1][1]};
+                        mma_term<PATH, T>(acc[mb][p], ax, bj, ax2, bj2);
+                    }
+                });
+                // keeps the fragment reads two row blocks deep (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            load_x(xr[s], kn);
+        }
+    }
+
+    // Epilogue: transpose each 16 x DENSE_TN block of Phi through LDS so that
+    // a lane holds 4 consecutive spins of one replica column (f32 MFMA
+    // results: register r of a lane is row 4*(lane/16) + r, column lane%16);
+    // then load every input of the lane's items before the first store.
+    __syncthreads();
+    float *T = reinterpret_cast<float *>(lds) + w * 16 * TS;
+    const int g = lane >> 4, r16 = lane & 15;
+    constexpr int QPR = DENSE_TN / 4;         // spin quads per row
+    constexpr int ITEMS = 16 * QPR / 64;      // (row, quad) items per lane and m-block
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb) {
+#pragma unroll
+        for (int p = 0; p < RBT; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T[(4 * g + r) * TS + 16 * p + r16] = acc[mb][p][r];
+        __syncthreads();
+        float4 ph[ITEMS];
+        int cc[ITEMS], ii[ITEMS];
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int flat = it * 64 + lane, row = flat / QPR, q = flat % QPR;
+            ph[it] = *reinterpret_cast<const float4 *>(T + row * TS + 4 * q);
+            cc[it] = 16 * (mb0 + mb) + row;
+            ii[it] = n0 + 4 * q;
+        }
+        if constexpr (EPI == EPI_UPDATE) {
+            UpdIn u[ITEMS];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (cc[it] < a.C) u[it] = update_load(a, cc[it], ii[it]);
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (cc[it] < a.C) update_store<PATH, MBW>(a, cc[it], ii[it], u[it], ph[it]);
+        } else {
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (cc[it] < a.C) *reinterpret_cast<float4 *>(a.phi + (int64_t)cc[it] * a.Np + ii[it]) = ph[it];
+        }
+        __syncthreads();
+    }
+}
+
+// Operand f(X) from the state: one thread per 4 consecutive spins of column c.
 template <int PATH>
-__global__ __launch_bounds__(256) void k_dense_operand(int N, int Np, const float *__restrict__ x, void *g,
+__global__ __launch_bounds__(256) void k_dense_operand(int Np, int nkc, int mbw, const float *__restrict__ x, void *g,
                                                        void *g_lo, float delta, int fmode) {
     const int c = blockIdx.y;
     const int i4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
     if (i4 >= Np) return;
-    const int64_t o = (int64_t)c * Np + i4;
-    const float4 v = *reinterpret_cast<const float4 *>(x + o);
-    float4 f = make_float4(f_value(fmode, v.x, delta), f_value(fmode, v.y, delta),
-                           f_value(fmode, v.z, delta), f_value(fmode, v.w, delta));
-    (void)N;
-    store_operand<PATH>(g, g_lo, o, f, fmode);
+    const float4 v = *reinterpret_cast<const float4 *>(x + (int64_t)c * Np + i4);
+    const float4 f = make_float4(f_value(fmode, v.x, delta), f_value(fmode, v.y, delta),
+                                 f_value(fmode, v.z, delta), f_value(fmode, v.w, delta));
+    constexpr int eb = (PATH == PATH_F32) ? 4 : (PATH == PATH_FP8) ? 1 : 2;
+    store_operand<PATH>(g, g_lo, tf_offset(c, i4, nkc, eb, mbw), f, fmode);
 }
 
-__global__ __launch_bounds__(256) void k_sum_partials(int Np, int Cp, int splits, const float *__restrict__ phi,
-                                                      float *__restrict__ out) {
-    const int c = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Np) return;
-    float s = phi[(int64_t)c * Np + i];
-    for (int zz = 1; zz < splits; ++zz) s += phi[((int64_t)zz * Cp + c) * Np + i];
-    out[(int64_t)c * Np + i] = s;
+template <int PATH, int EPI>
+hipError_t launch_step_mbw(int mbw, dim3 grid, const DenseStepArgs &a, hipStream_t st) {
+    switch (mbw) {
+        case 1: hipLaunchKernelGGL((k_dense_step<PATH, 1, EPI>), grid, dim3(DENSE_THREADS), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_dense_step<PATH, 2, EPI>), grid, dim3(DENSE_THREADS), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_dense_step<PATH, 4, EPI>), grid, dim3(DENSE_THREADS), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int PATH>
+hipError_t launch_step_path(DenseEpilogue epi, int mbw, dim3 grid, const DenseStepArgs &a, hipStream_t st) {
+    return epi == EPI_UPDATE ? launch_step_mbw<PATH, EPI_UPDATE>(mbw, grid, a, st)
+                             : launch_step_mbw<PATH, EPI_FIELDS>(mbw, grid, a, st);
 }
 
 }  // namespace
 
-hipError_t launch_gemm(GemmKind kind, const void *A, const void *A2, const void *B, const void *B2,
-                       void *out, int Np, int Cp, int splits, hipStream_t st) {
-    const int eb = (kind == GK_F32) ? 4 : (kind == GK_FP8) ? 1 : (kind == GK_F64) ? 8 : 2;
-    const int64_t kbytes = (int64_t)Np * eb;
+hipError_t launch_gemm_f64(const double *A, const double *B, double *out, int Np, int Cp, int splits,
+                           hipStream_t st) {
+    const int64_t kbytes = (int64_t)Np * 8;
     if (Np % GEMM_BN || Cp % GEMM_BM || splits < 1 || kbytes % ((int64_t)splits * GEMM_KB))
         return hipErrorInvalidValue;
     const int kchunk = (int)(kbytes / splits);
     dim3 grid(Np / GEMM_BN, Cp / GEMM_BM, splits), block(GEMM_THREADS);
-    const uint8_t *a = static_cast<const uint8_t *>(A), *a2 = static_cast<const uint8_t *>(A2);
-    const uint8_t *b = static_cast<const uint8_t *>(B), *b2 = static_cast<const uint8_t *>(B2);
-    switch (kind) {
-        case GK_F32: hipLaunchKernelGGL(k_gemm<GK_F32>, grid, block, 0, st, a, a2, b, b2, out, Np, Cp, eb, kchunk); break;
-        case GK_FP8: hipLaunchKernelGGL(k_gemm<GK_FP8>, grid, block, 0, st, a, a2, b, b2, out, Np, Cp, eb, kchunk); break;
-        case GK_BF16X3: hipLaunchKernelGGL(k_gemm<GK_BF16X3>, grid, block, 0, st, a, a2, b, b2, out, Np, Cp, eb, kchunk); break;
-        case GK_F64: hipLaunchKernelGGL(k_gemm<GK_F64>, grid, block, 0, st, a, a2, b, b2, out, Np, Cp, eb, kchunk); break;
-    }
+    hipLaunchKernelGGL(k_gemm_f64, grid, block, 0, st, reinterpret_cast<const uint8_t *>(A),
+                       reinterpret_cast<const uint8_t *>(B), out, Np, Cp, kchunk);
     return hipGetLastError();
 }
 
-hipError_t launch_dense_update(Path path, int fmode, int N, int Np, int R, int runs, int Cp,
-                               int splits, const float *phi, const float *h, const float *x_in,
-                               float *x_out, float *y, void *g, void *g_lo, const float *jp,
-                               int64_t jp_stride, StepCoef k, hipStream_t st) {
-    const int C = R * runs;
-    dim3 grid((Np / 4 + 255) / 256, C), block(256);
+hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, const DenseStepArgs &a,
+                             hipStream_t st) {
+    const int tm = 64 * mbw;
+    if (a.Np % DENSE_TN || Cg % tm || a.C > Cg || a.nkc != a.Np * path_ebytes(path) / 128 ||
+        (a.Np * path_ebytes(path)) % 128 || a.nkc % dense_depth(path))
+        return hipErrorInvalidValue;
+    const dim3 grid(a.Np / DENSE_TN, Cg / tm);
     switch (path) {
-        case PATH_F32: hipLaunchKernelGGL(k_dense_update<PATH_F32>, grid, block, 0, st, N, Np, R, Cp, splits, phi, h, x_in, x_out, y, g, g_lo, jp, jp_stride, k, fmode); break;
-        case PATH_FP8: hipLaunchKernelGGL(k_dense_update<PATH_FP8>, grid, block, 0, st, N, Np, R, Cp, splits, phi, h, x_in, x_out, y, g, g_lo, jp, jp_stride, k, fmode); break;
-        case PATH_BF16X3: hipLaunchKernelGGL(k_dense_update<PATH_BF16X3>, grid, block, 0, st, N, Np, R, Cp, splits, phi, h, x_in, x_out, y, g, g_lo, jp, jp_stride, k, fmode); break;
+        case PATH_F32: return launch_step_path<PATH_F32>(epi, mbw, grid, a, st);
+        case PATH_FP8: return launch_step_path<PATH_FP8>(epi, mbw, grid, a, st);
+        case PATH_BF16X3: return launch_step_path<PATH_BF16X3>(epi, mbw, grid, a, st);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, const float *x, void *g,
+hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int nkc, int mbw, const float *x, void *g,
                                 void *g_lo, float delta, hipStream_t st) {
+    (void)N;
     dim3 grid((Np / 4 + 255) / 256, C), block(256);
     switch (path) {
-        case PATH_F32: hipLaunchKernelGGL(k_dense_operand<PATH_F32>, grid, block, 0, st, N, Np, x, g, g_lo, delta, fmode); break;
-        case PATH_FP8: hipLaunchKernelGGL(k_dense_operand<PATH_FP8>, grid, block, 0, st, N, Np, x, g, g_lo, delta, fmode); break;
-        case PATH_BF16X3: hipLaunchKernelGGL(k_dense_operand<PATH_BF16X3>, grid, block, 0, st, N, Np, x, g, g_lo, delta, fmode); break;
+        case PATH_F32: hipLaunchKernelGGL(k_dense_operand<PATH_F32>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
+        case PATH_FP8: hipLaunchKernelGGL(k_dense_operand<PATH_FP8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
+        case PATH_BF16X3: hipLaunchKernelGGL(k_dense_operand<PATH_BF16X3>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
-}
-
-hipError_t launch_sum_partials(int N, int Np, int C, int Cp, int splits, const float *phi, float *out,
-                               hipStream_t st) {
-    (void)N;
-    dim3 grid((Np + 255) / 256, C), block(256);
-    hipLaunchKernelGGL(k_sum_partials, grid, block, 0, st, Np, Cp, splits, phi, out);
     return hipGetLastError();
 }
 

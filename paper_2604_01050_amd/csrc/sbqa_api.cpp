@@ -61,6 +61,16 @@ static float bf16_to_float_host(uint16_t b) {
     return f;
 }
 
+// Byte offset of element (row, k) of a fragment-tiled matrix with groups of
+// G row blocks (layout of the dense contraction operands, described in
+// sbqa_internal.h).
+static size_t tf_offset_host(int row, int k, int nkc, int eb, int G) {
+    const int kbyte = k * eb, kc = kbyte >> 7, kb = kbyte & 127, rb = row >> 4;
+    const int l = ((kb >> 5) << 4) | (row & 15);
+    return (((size_t)(rb / G) * nkc + kc) * G + rb % G) * FRAG_BYTES + (size_t)((kb >> 4) & 1) * 1024 +
+           (size_t)l * 16 + (kb & 15);
+}
+
 // ---------------------------------------------------------------- validation
 sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                               const sbqa_schedule *s, InstanceFacts *facts) {
@@ -184,10 +194,11 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
 void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Layout *L) {
     const int64_t C = (int64_t)R * runs;
     L->C = (int)C;
-    L->Np = (int)round_up(N, GEMM_BN);
     L->Cp = (int)round_up(C, GEMM_BM);
+    L->mbw = dense_mbw((int)C);
+    L->Cg = (int)round_up(C, 64 * L->mbw);
+    L->Np = (int)round_up(N, f.path == PATH_CSR ? GEMM_BN : dense_pad(f.path));
     L->Cs = (int)round_up(C, 4);
-    L->splits = 1;
     L->esplits = 1;
     int64_t b = 0;
     if (f.path == PATH_CSR) {
@@ -199,20 +210,16 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         b += (int64_t)L->csr_nrb * C * 16;
         b += (int64_t)N * L->Cs * 4;                                      // phi (fields hook)
     } else {
-        const int eb = f.path == PATH_F32 ? 4 : f.path == PATH_FP8 ? 1 : 2;
+        const int eb = path_ebytes(f.path), planes = f.path == PATH_BF16X3 ? 2 : 1;
+        L->nkc = L->Np * eb / 128;
         const int64_t tiles = (int64_t)(L->Np / GEMM_BN) * (L->Cp / GEMM_BM);
-        const int64_t nk = (int64_t)L->Np * eb / GEMM_KB;
-        int sp = 1;
-        while (tiles * sp < 512 && sp < 8 && nk % (2 * sp) == 0 && nk / (2 * sp) >= 4) sp *= 2;
-        L->splits = sp;
         const int64_t nke = (int64_t)L->Np * 8 / GEMM_KB;
         int es = 1;
         while (tiles * es < 512 && es < 8 && nke % (2 * es) == 0 && nke / (2 * es) >= 4) es *= 2;
         L->esplits = es;
         b += 3 * C * (int64_t)L->Np * 4;                                  // x ping-pong, y
-        b += (int64_t)L->Cp * L->Np * eb * (f.path == PATH_BF16X3 ? 2 : 1);  // operand
-        b += (int64_t)sp * L->Cp * L->Np * 4;                             // phi partials
-        b += (int64_t)L->Np * L->Np * eb * (f.path == PATH_BF16X3 ? 2 : 1);  // J
+        b += 2 * (int64_t)L->Cg * L->Np * eb * planes;                    // operand ping-pong
+        b += (int64_t)L->Np * L->Np * eb * planes;                        // J
         b += (int64_t)L->Np * L->Np * 8;                                  // J fp64 (energies)
         b += (int64_t)L->Np * 12;                                         // h
         b += (int64_t)L->Cp * L->Np * 8 * (1 + es);                      // readout + energy partials
@@ -316,8 +323,8 @@ sbqa_status rebuild_operand(sbqa_ctx *c) {
         if (c->s.fmode != SBQA_F_BALLISTIC)
             HIP_TRY(launch_csr_operand(c->s.fmode, c->N, c->L.Cs, c->L.C, c->x[c->cur], (int8_t *)c->g[c->cur], d, c->stream));
     } else {
-        HIP_TRY(launch_dense_operand(c->facts.path, c->s.fmode, c->N, c->L.Np, c->L.C, c->x[c->cur], c->g[0], c->g_lo[0], d,
-                                     c->stream));
+        HIP_TRY(launch_dense_operand(c->facts.path, c->s.fmode, c->N, c->L.Np, c->L.C, c->L.nkc, c->L.mbw, c->x[c->cur],
+                                     c->g[c->cur], c->g_lo[c->cur], d, c->stream));
     }
     return SBQA_OK;
 }
@@ -408,20 +415,22 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         return SBQA_OK;
     }
 
-    const int eb = path == PATH_F32 ? 4 : path == PATH_FP8 ? 1 : 2;
+    const int eb = path_ebytes(path), nkc = c->L.nkc, Cg = c->L.Cg;
     HIP_TRY(dalloc(c, &c->x[0], (size_t)C * Np));
     HIP_TRY(dalloc(c, &c->x[1], (size_t)C * Np));
     HIP_TRY(dalloc(c, &c->y, (size_t)C * Np));
-    uint8_t *gbuf, *glo = nullptr;
-    HIP_TRY(dalloc(c, &gbuf, (size_t)Cp * Np * eb));
-    if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &glo, (size_t)Cp * Np * eb));
-    c->g[0] = gbuf;
-    c->g_lo[0] = glo;
-    HIP_TRY(dalloc(c, &c->phi, (size_t)c->L.splits * Cp * Np));
+    for (int q = 0; q < 2; ++q) {
+        uint8_t *gb, *glo = nullptr;
+        HIP_TRY(dalloc(c, &gb, (size_t)Cg * Np * eb));
+        if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &glo, (size_t)Cg * Np * eb));
+        c->g[q] = gb;
+        c->g_lo[q] = glo;
+    }
     HIP_TRY(dalloc(c, &c->S64, (size_t)Cp * Np));
     HIP_TRY(dalloc(c, &c->phis64, (size_t)c->L.esplits * Cp * Np));
 
-    // J in the contraction precision and in float64 (energies), zero padded.
+    // J in the contraction precision (fragment-tiled) and in float64
+    // (row-major, energies), zero padded.
     const double *A = J->dense;
     uint8_t *jd, *jlo = nullptr;
     double *j64;
@@ -431,12 +440,14 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     c->Jd = jd;
     c->Jd_lo = jlo;
     c->J64 = j64;
-    // Upload row blocks through a bounded host staging buffer.
-    const int RB = 256;
-    std::vector<uint8_t> stage((size_t)RB * Np * eb), stage_lo(path == PATH_BF16X3 ? (size_t)RB * Np * eb : 0);
+    // Upload blocks of RB rows (whole groups of DENSE_TN rows, contiguous in
+    // the tiled layout) through bounded host staging buffers.
+    const int RB = 4 * DENSE_TN;
+    const size_t blk = (size_t)RB * Np * eb;   // RB rows, fragment-tiled, contiguous
+    std::vector<uint8_t> stage(blk), stage_lo(path == PATH_BF16X3 ? blk : 0);
     std::vector<double> stage64((size_t)RB * Np);
     for (int i0 = 0; i0 < N; i0 += RB) {
-        const int nr = std::min(RB, N - i0);
+        const int nr = std::min(RB, N - i0), nrg = (int)round_up(nr, DENSE_TN);
         std::fill(stage.begin(), stage.end(), 0);
         std::fill(stage_lo.begin(), stage_lo.end(), 0);
         std::fill(stage64.begin(), stage64.end(), 0.0);
@@ -445,26 +456,55 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
             for (int j = 0; j < N; ++j) {
                 const double v = row[j];
                 stage64[(size_t)ii * Np + j] = v;
+                const size_t o = tf_offset_host(ii, j, nkc, eb, DENSE_TN / 16);
                 if (path == PATH_F32) {
                     const float f = (float)v;
-                    std::memcpy(&stage[((size_t)ii * Np + j) * 4], &f, 4);
+                    std::memcpy(&stage[o], &f, 4);
                 } else if (path == PATH_FP8) {
-                    stage[(size_t)ii * Np + j] = v > 0 ? 0x38 : (v < 0 ? 0xB8 : 0x00);
+                    stage[o] = v > 0 ? 0x38 : (v < 0 ? 0xB8 : 0x00);
                 } else {
                     const uint16_t hi = bf16_rne_host((float)v);
                     const uint16_t lo = bf16_rne_host((float)(v - (double)bf16_to_float_host(hi)));
-                    std::memcpy(&stage[((size_t)ii * Np + j) * 2], &hi, 2);
-                    std::memcpy(&stage_lo[((size_t)ii * Np + j) * 2], &lo, 2);
+                    std::memcpy(&stage[o], &hi, 2);
+                    std::memcpy(&stage_lo[o], &lo, 2);
                 }
             }
         }
-        HIP_TRY(hipMemcpyAsync(jd + (size_t)i0 * Np * eb, stage.data(), (size_t)nr * Np * eb, hipMemcpyHostToDevice, c->stream));
+        const size_t dst = (size_t)i0 * Np * eb, nbytes = (size_t)nrg * Np * eb;
+        HIP_TRY(hipMemcpyAsync(jd + dst, stage.data(), nbytes, hipMemcpyHostToDevice, c->stream));
         if (path == PATH_BF16X3)
-            HIP_TRY(hipMemcpyAsync(jlo + (size_t)i0 * Np * eb, stage_lo.data(), (size_t)nr * Np * eb, hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(jlo + dst, stage_lo.data(), nbytes, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(j64 + (size_t)i0 * Np, stage64.data(), sizeof(double) * nr * Np, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers are reused
     }
     return SBQA_OK;
+}
+
+// Arguments of the dense step kernel at step n from operand/state buffer `in`.
+static DenseStepArgs dense_args(sbqa_ctx *c, uint32_t n, int in) {
+    DenseStepArgs a{};
+    a.N = c->N;
+    a.Np = c->L.Np;
+    a.R = c->R;
+    a.C = c->L.C;
+    a.nkc = c->L.nkc;
+    a.reverse = (int)(n & 1u);
+    a.J = static_cast<const uint8_t *>(c->Jd);
+    a.J_lo = static_cast<const uint8_t *>(c->Jd_lo);
+    a.g = static_cast<const uint8_t *>(c->g[in]);
+    a.g_lo = static_cast<const uint8_t *>(c->g_lo[in]);
+    a.g_next = static_cast<uint8_t *>(c->g[1 - in]);
+    a.g_next_lo = static_cast<uint8_t *>(c->g_lo[1 - in]);
+    a.h = c->h32;
+    a.x_in = c->x[in];
+    a.x_out = c->x[1 - in];
+    a.y = c->y;
+    a.phi = nullptr;
+    a.jp = c->jp + (n < c->s.steps ? n : 0);
+    a.jp_stride = c->s.steps;
+    a.k = step_coef(&c->s, c->c0, c->R, n);
+    a.fmode = c->s.fmode;
+    return a;
 }
 
 // One step of Eqs. 6-7 on the device (asynchronous).
@@ -479,10 +519,8 @@ sbqa_status ctx_step_once(sbqa_ctx *c) {
                                 c->x[out], c->y, (const int8_t *)c->g[in], (int8_t *)c->g[out], jp, jp_stride, k,
                                 c->stream));
     } else {
-        const GemmKind gk = c->facts.path == PATH_F32 ? GK_F32 : c->facts.path == PATH_FP8 ? GK_FP8 : GK_BF16X3;
-        HIP_TRY(launch_gemm(gk, c->g[0], c->g_lo[0], c->Jd, c->Jd_lo, c->phi, c->L.Np, c->L.Cp, c->L.splits, c->stream));
-        HIP_TRY(launch_dense_update(c->facts.path, c->s.fmode, c->N, c->L.Np, c->R, c->runs, c->L.Cp, c->L.splits, c->phi,
-                                    c->h32, c->x[in], c->x[out], c->y, c->g[0], c->g_lo[0], jp, jp_stride, k, c->stream));
+        const DenseStepArgs a = dense_args(c, n, in);
+        HIP_TRY(launch_dense_step(c->facts.path, EPI_UPDATE, c->L.mbw, c->L.Cg, a, c->stream));
     }
     c->cur = out;
     c->step = n + 1;
@@ -498,7 +536,7 @@ sbqa_status ctx_state_energies(sbqa_ctx *c) {
                                         c->L.csr_nrb, c->E, c->stream));
     } else {
         HIP_TRY(launch_readout_f64(c->N, c->L.Np, c->L.C, c->L.Np, false, c->x[c->cur], c->S64, c->stream));
-        HIP_TRY(launch_gemm(GK_F64, c->S64, nullptr, c->J64, nullptr, c->phis64, c->L.Np, c->L.Cp, c->L.esplits, c->stream));
+        HIP_TRY(launch_gemm_f64(c->S64, c->J64, c->phis64, c->L.Np, c->L.Cp, c->L.esplits, c->stream));
         HIP_TRY(launch_energy_reduce(c->N, c->L.Np, c->L.C, c->L.Cp, c->L.esplits, c->phis64, c->S64, h64, c->E, c->stream));
     }
     return SBQA_OK;
@@ -774,7 +812,7 @@ sbqa_status sbqa_energy(sbqa_ctx *c, const int8_t *spins, int32_t count, double 
         HIP_TRY(hipMalloc(&P, sizeof(double) * es * cp * Np));
         gd.d = P;
         HIP_TRY(launch_spins_to_f64(N, Np, count, ds, S, c->stream));
-        HIP_TRY(launch_gemm(GK_F64, S, nullptr, c->J64, nullptr, P, Np, cp, es, c->stream));
+        HIP_TRY(launch_gemm_f64(S, c->J64, P, Np, cp, es, c->stream));
         HIP_TRY(launch_energy_reduce(N, Np, count, cp, es, P, S, h64, E, c->stream));
     }
     HIP_TRY(hipMemcpyAsync(out, E, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
@@ -798,12 +836,12 @@ sbqa_status sbqa_fields(sbqa_ctx *c, float *phi) {
         return SBQA_OK;
     }
     const int Np = c->L.Np;
-    const GemmKind gk = c->facts.path == PATH_F32 ? GK_F32 : c->facts.path == PATH_FP8 ? GK_FP8 : GK_BF16X3;
     float *sum = nullptr;
     HIP_TRY(hipMalloc(&sum, sizeof(float) * (size_t)C * Np));
     struct G1 { void *p; ~G1() { (void)hipFree(p); } } g1{sum};
-    HIP_TRY(launch_gemm(gk, c->g[0], c->g_lo[0], c->Jd, c->Jd_lo, c->phi, Np, c->L.Cp, c->L.splits, c->stream));
-    HIP_TRY(launch_sum_partials(N, Np, C, c->L.Cp, c->L.splits, c->phi, sum, c->stream));
+    DenseStepArgs a = dense_args(c, c->step, c->cur);
+    a.phi = sum;
+    HIP_TRY(launch_dense_step(c->facts.path, EPI_FIELDS, c->L.mbw, c->L.Cg, a, c->stream));
     buf.resize((size_t)C * Np);
     HIP_TRY(hipMemcpyAsync(buf.data(), sum, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));

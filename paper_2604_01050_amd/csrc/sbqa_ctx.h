@@ -23,10 +23,12 @@ struct InstanceFacts {
 // Device geometry of a context.
 struct Layout {
     int C = 0;        // runs * R
-    int Np = 0;       // N padded to GEMM_BN (dense)
-    int Cp = 0;       // C padded to GEMM_BM (dense operand rows)
+    int Np = 0;       // N padded to dense_pad(path) (dense)
+    int Cp = 0;       // C padded to GEMM_BM (rows of the fp64 energy GEMM)
+    int Cg = 0;       // C padded to 64 * mbw (rows of the contraction operand)
+    int mbw = 1;      // m-blocks per wave of the dense step
+    int nkc = 0;      // K chunks of 128 bytes per operand row (dense)
     int Cs = 0;       // C padded to 4 (CSR row stride)
-    int splits = 1;   // K splits of the contraction GEMM
     int esplits = 1;  // K splits of the fp64 energy GEMM
     int csr_nrb = 0;  // row blocks of the CSR energy reduction
     size_t bytes = 0; // device bytes (without the schedule table)
@@ -74,10 +76,10 @@ struct sbqa_ctx {
     float *x[2] = {nullptr, nullptr};
     float *y = nullptr;
     int cur = 0;
-    void *g[2] = {nullptr, nullptr};    // operand f(X): dense uses g[0]; CSR ping-pongs int8
+    void *g[2] = {nullptr, nullptr};    // operand f(X), ping-pong with x: dense fragment-tiled, CSR int8 [N][Cs]
     void *g_lo[2] = {nullptr, nullptr}; // bf16 low part (BF16X3)
-    float *phi = nullptr;               // dense: [splits][Cp][Np] partials; CSR: [N][Cs] fields hook
-    void *Jd = nullptr, *Jd_lo = nullptr;  // dense J in contraction precision [Np][Np]
+    float *phi = nullptr;               // CSR fields hook [N][Cs]
+    void *Jd = nullptr, *Jd_lo = nullptr;  // dense J in contraction precision, fragment-tiled
     double *J64 = nullptr;              // dense J in float64 (energies)
     int32_t *rp = nullptr, *col = nullptr;
     float *val = nullptr;
@@ -100,7 +102,8 @@ struct sbqa_ctx {
     float *coefA = nullptr;             // [S]
     float *delta_tab = nullptr;         // [S+1]
     float *xpub = nullptr;              // [2][nwg][2][rows] published edge columns
-    int *flags = nullptr, *epoch_cnt = nullptr, *err = nullptr;
+    int *flags = nullptr, *epoch_cnt = nullptr;
+    int *err = nullptr;                 // ring-neighbour wait timeouts
     int *err_host = nullptr;            // pinned copy of err
     int epoch = 0;
 

@@ -11,16 +11,13 @@ namespace sbqa {
 // Contraction path of a context.
 enum Path : int32_t { PATH_F32 = 0, PATH_FP8 = 1, PATH_BF16X3 = 2, PATH_CSR = 3 };
 
-// GEMM tiling shared by the dense kernels and the host planner.
+// Tiling of the fp64 energy GEMM (row-major operands).
 // Output tile: GEMM_BM columns c (replicas) x GEMM_BN rows i (spins);
 // each k-tile carries GEMM_KB bytes of K per row.
 constexpr int GEMM_BM = 128;
 constexpr int GEMM_BN = 128;
 constexpr int GEMM_KB = 128;
 constexpr int GEMM_THREADS = 256;
-
-// Element kinds of the dense GEMM.
-enum GemmKind : int32_t { GK_F32 = 0, GK_FP8 = 1, GK_BF16X3 = 2, GK_F64 = 3 };
 
 // Per-step scalars of the fused update (Eqs. 6-7), precomputed on the host in
 // float64 and rounded once to float32.
@@ -32,32 +29,70 @@ struct StepCoef {
     float delta_next;  // Delta_{n+1} (Eq. 8) for the operand emitted by this step
 };
 
-// Dense GEMM: out[z][Cp][Np] (+= nothing; every tile written once)
-//   = A[Cp][Np] (operand f(X), K-contiguous) x B[Np][Np] (J rows, K-contiguous),
-// K range of split z: [z*kchunk, (z+1)*kchunk). Cp % GEMM_BM == 0,
-// Np % GEMM_BN == 0, kchunk % (GEMM_KB / elem bytes) == 0.
-// A2/B2 are the bf16 low parts for GK_BF16X3, ignored otherwise.
-// GK_F64 writes double outputs, the others float.
-hipError_t launch_gemm(GemmKind kind, const void *A, const void *A2, const void *B,
-                       const void *B2, void *out, int Np, int Cp, int splits,
-                       hipStream_t st);
+// fp64 GEMM for energies: out[z][Cp][Np] = A[Cp][Np] x B[Np][Np] over the K
+// range of split z (both operands row-major, K-contiguous). Cp % GEMM_BM == 0,
+// Np % GEMM_BN == 0, Np*8 % (splits*GEMM_KB) == 0.
+hipError_t launch_gemm_f64(const double *A, const double *B, double *out, int Np, int Cp, int splits,
+                           hipStream_t st);
 
-// Dense update over state [C][Np] (replica-major): reads Phi partials
-// phi[splits][Cp][Np], x_in, y (in place), writes x_out and the next operand
-// in the path's format. jp points at J_perp[r][n] with run stride jp_stride.
-hipError_t launch_dense_update(Path path, int fmode, int N, int Np, int R, int runs,
-                               int Cp, int splits, const float *phi, const float *h,
-                               const float *x_in, float *x_out, float *y, void *g,
-                               void *g_lo, const float *jp, int64_t jp_stride,
-                               StepCoef k, hipStream_t st);
+// ---- dense contraction path -------------------------------------------------
+// The coupling matrix J and the operand f(X) of the dense paths are stored as
+// 2 KiB fragments ("fragment-tiled"): fragment (rb, kc) holds rows
+// 16rb..16rb+15 and K bytes [128kc, 128kc+128); inside it, byte
+// h*1024 + l*16 + e holds row 16rb + l%16, K byte 32*(l/16) + 16h + e.
+// Lane l of a wave loads bytes l*16 and 1024 + l*16 of a fragment: exactly
+// the 32 K bytes it feeds to a 16x16 MFMA. Row blocks are grouped G at a
+// time (G = DENSE_TN/16 for J, mbw for the operand); a group is one
+// contiguous run, ordered by kc and then by row block, so the fragments a
+// workgroup (J) or a wave (operand) needs for one K chunk are adjacent and a
+// group's whole K range streams sequentially.
+constexpr int FRAG_BYTES = 2048;
+constexpr int DENSE_TN = 64;        // J rows (spins) per workgroup: 4 row blocks
+constexpr int DENSE_THREADS = 256;  // 4 waves
 
-// Operand f(X) for the dense paths from state [C][Np] with threshold delta.
-hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, const float *x,
+// Element bytes of the contraction operands.
+constexpr int path_ebytes(Path p) { return p == PATH_F32 ? 4 : p == PATH_FP8 ? 1 : 2; }
+// K chunks in flight per wave (prefetch depth); a row's K chunk count must be a
+// multiple of it.
+constexpr int dense_depth(Path p) { return p == PATH_FP8 ? 4 : 2; }
+// Spin padding of the dense paths: a multiple of 128 and of depth K chunks.
+constexpr int dense_pad(Path p) {
+    return 128 / path_ebytes(p) * dense_depth(p) > 128 ? 128 / path_ebytes(p) * dense_depth(p) : 128;
+}
+// m-blocks of 16 replicas per wave for C replica columns (workgroup covers
+// 4 * 16 * mbw columns).
+inline int dense_mbw(int C) { return C <= 64 ? 1 : C <= 128 ? 2 : 4; }
+
+enum DenseEpilogue : int32_t { EPI_UPDATE = 0, EPI_FIELDS = 1 };
+
+struct DenseStepArgs {
+    int N, Np, R, C;
+    int nkc;                        // K chunks of 128 bytes per row: Np * ebytes / 128
+    int reverse;                    // traverse K chunks from the last one
+    const uint8_t *J, *J_lo;        // fragment-tiled [Np/16][nkc]; J_lo: bf16 low part
+    const uint8_t *g, *g_lo;        // operand f(X_n), fragment-tiled [Cg/16][nkc]
+    uint8_t *g_next, *g_next_lo;    // operand f(X_{n+1}) (update epilogue)
+    const float *h;                 // [Np], zero padded
+    const float *x_in;              // [C][Np]
+    float *x_out, *y;               // [C][Np]; y in place
+    float *phi;                     // [C][Np] (fields epilogue)
+    const float *jp;                // J_perp[r][n] at this step, run stride jp_stride
+    int64_t jp_stride;
+    StepCoef k;
+    int fmode;
+};
+
+// One step of the dense path: Phi = J f(X_n) on MFMA for a workgroup tile of
+// DENSE_TN spins x 64*mbw replica columns, then either the fused update
+// (Eqs. 6-7, wall, next operand) or a plain store of Phi.
+// grid = (Np / DENSE_TN, Cg / (64 * mbw)).
+hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, const DenseStepArgs &a,
+                             hipStream_t st);
+
+// Operand f(X) (fragment-tiled, groups of mbw row blocks) from state [C][Np]
+// with threshold delta.
+hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int nkc, int mbw, const float *x,
                                 void *g, void *g_lo, float delta, hipStream_t st);
-
-// Sum of Phi partials -> phi_out[C][Np] (test hook).
-hipError_t launch_sum_partials(int N, int Np, int C, int Cp, int splits, const float *phi,
-                               float *out, hipStream_t st);
 
 // CSR fused step over state [N][Cs] (spin-major): gathers of the operand
 // (int8 f values, or x itself for ballistic f), pump/ring/kick/drift/wall,
