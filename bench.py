@@ -68,10 +68,10 @@ def make_workload(name: str):
     raise SystemExit("unknown workload " + name)
 
 
-def create(sb, w, seed, sparse_kernel="auto"):
+def create(sb, w, seed, loop_kernel="auto"):
     kw = dict(R=w["R"], runs=w["runs"], steps=w["S"], dt=0.5, a0=1.0, fmode=w["fmode"],
               jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0, seed=seed, init_amp=0.1,
-              sparse_kernel={"auto": sb.SPARSE_AUTO, "stream": sb.SPARSE_STREAM, "resident": sb.SPARSE_RESIDENT}[sparse_kernel])
+              loop_kernel={"auto": sb.LOOP_AUTO, "stream": sb.LOOP_STREAM, "resident": sb.LOOP_RESIDENT}[loop_kernel])
     if w["prec"]:
         kw["precision"] = getattr(sb, w["prec"])
     return sb.sbqa_create(J=w.get("J"), csr=w.get("csr"), h=w.get("h"), **kw)
@@ -97,12 +97,13 @@ PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def resident_ops_per_step(w):
-    """Operations one step of the resident sparse loop must perform per
-    replica-spin update: per neighbour one int8->fp32 conversion and one FMA
-    (2d), then 7 for the kick and drift, 3 for the wall, 3 for the ternary
-    decision of Eq. 8 (2d + 13)."""
+    """Operations one step of a resident loop must perform per replica-spin
+    update. Sparse: per neighbour one int8->fp32 conversion and one FMA (2d);
+    dense (small loop): per coupling one FMA counted as two operations (2N);
+    then 7 for the kick and drift, 3 for the wall, 3 for the ternary decision
+    of Eq. 8 (2d + 13 or 2N + 13)."""
     N, C = w["N"], w["R"] * w["runs"]
-    nnz = len(w["csr"][1])
+    nnz = len(w["csr"][1]) if "csr" in w else N * N
     return 2.0 * nnz * C + 13.0 * N * C
 
 
@@ -188,7 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-events", action="store_true", help="no per-step events in the timed region")
     ap.add_argument("--calibrate", action="store_true", help="also run a copy kernel of known size (counter scaling)")
-    ap.add_argument("--sparse-kernel", default="auto", choices=["auto", "stream", "resident"])
+    ap.add_argument("--loop-kernel", default="auto", choices=["auto", "stream", "resident"],
+                    help="step loop: one launch per step (stream) or many steps per launch (resident)")
     a = ap.parse_args()
     if a.gpus != 1:
         print("bench.py measures one GPU only: the SBQA runs of one instance are independent and the "
@@ -207,13 +209,13 @@ def main():
     stream = torch.cuda.Stream()
 
     # warmup: a separate solve
-    ctx = create(sb, w, seed=1, sparse_kernel=a.sparse_kernel)
+    ctx = create(sb, w, seed=1, loop_kernel=a.loop_kernel)
     sb.sbqa_set_stream(ctx, stream)
     sb.sbqa_step(ctx, min(a.warmup, w["S"]))
     sb.sbqa_best(ctx)
     sb.sbqa_destroy(ctx)
 
-    ctx = create(sb, w, seed=2, sparse_kernel=a.sparse_kernel)
+    ctx = create(sb, w, seed=2, loop_kernel=a.loop_kernel)
     sb.sbqa_set_stream(ctx, stream)
     info = sb.sbqa_info(ctx)
     torch.cuda.synchronize()
@@ -255,11 +257,13 @@ def main():
         avg_s = float(np.mean(launch_ms)) * 1e-3
         if resident:
             ops = K * resident_ops_per_step(w)
-            tr = measured_traffic(a.workload + "_resident", "csr_resident")
+            sparse = "csr" in w
+            tr = measured_traffic(a.workload + "_resident", "csr_resident") if sparse else None
             out["roofline"] = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": PEAK_VALU_OPS,
                                "unit": "Tops/s (fp32 VALU lane ops)", "frac": ops / avg_s / 1e12 / PEAK_VALU_OPS,
                                "traffic": None if tr is None else tr * K,
-                               "kernel": "k_csr_resident", "avg_launch_us": avg_s * 1e6, "steps_per_launch": K,
+                               "kernel": "k_csr_resident" if sparse else "k_dense_small",
+                               "avg_launch_us": avg_s * 1e6, "steps_per_launch": K,
                                "algorithmic_ops_per_launch": ops}
         elif info["path"] == "csr_fp32":
             ab = algorithmic_bytes(w, info)

@@ -78,14 +78,19 @@ typedef enum {
  *   TABLE   caller-supplied float32 table jp_table[runs*steps]. */
 typedef enum { SBQA_JP_LINEAR = 0, SBQA_JP_PAPER = 1, SBQA_JP_TABLE = 2 } sbqa_jpkind;
 
-/* Kernel of the sparse (CSR) path; both compute the same bits.
- *   AUTO      the register-resident loop when the instance fits it (ternary or
- *             sign f, R a multiple of 8, N <= 4096, small degree, all column
- *             blocks co-resident on the GPU), else the streaming kernel.
+/* Step-loop kernel.
+ *   AUTO      RESIDENT when the instance fits a resident loop, else STREAM.
  *   STREAM    one fused launch per step, state streamed through HBM.
- *   RESIDENT  the register-resident loop; sbqa_create fails with EINVAL when
- *             the instance does not fit it. */
-typedef enum { SBQA_SPARSE_AUTO = 0, SBQA_SPARSE_STREAM = 1, SBQA_SPARSE_RESIDENT = 2 } sbqa_sparse_kernel;
+ *   RESIDENT  many steps per launch with the state on chip:
+ *             - sparse (CSR): the register-resident loop (ternary or sign f,
+ *               R a multiple of 8, N <= 4096, small degree, all column blocks
+ *               co-resident on the GPU); it computes the same bits as STREAM;
+ *             - dense: the small-instance loop (N <= 128, R*N <= 4096, FP32 or
+ *               FP8 precision), one workgroup per run with J and the run's
+ *               state in LDS; fields are summed in a fixed order over j (the
+ *               same bits as STREAM when J and the operand are integral).
+ *             sbqa_create fails with EINVAL when the instance does not fit. */
+typedef enum { SBQA_LOOP_AUTO = 0, SBQA_LOOP_STREAM = 1, SBQA_LOOP_RESIDENT = 2 } sbqa_loop_kernel;
 
 /* Couplings: exactly one of `dense` or the CSR triple is non-NULL.
  * J must be symmetric with a zero diagonal and finite entries.
@@ -121,13 +126,13 @@ typedef struct {
     int32_t precision;       /* sbqa_prec                                          */
     uint32_t energy_every;   /* 0: best over the final state only; K > 0: also
                                 track the best after every K-th step              */
-    int32_t sparse_kernel;   /* sbqa_sparse_kernel (CSR couplings only)            */
+    int32_t loop_kernel;     /* sbqa_loop_kernel                                   */
 } sbqa_schedule;
 
 /* Defaults: steps 1000, dt 0.5, a0 1, c0 auto, ternary f, delta_max 0.7,
  * PAPER schedule with gamma0_over_R 1, beta in [0.5,1.5], alpha in [0.5,1.0]
  * (Sec. II.B), seed 0, init_amp 0.1, precision AUTO, energy_every 0,
- * sparse_kernel AUTO. */
+ * loop_kernel AUTO. */
 sbqa_schedule sbqa_schedule_default(void);
 
 /* Context information (sbqa_info). */
@@ -140,8 +145,8 @@ typedef struct {
     double c0;               /* c0 actually used                                   */
     int32_t j_integral;      /* 1 when every J_ij and h_i is an integer            */
     size_t device_bytes;     /* device memory held by the context                  */
-    int32_t resident;        /* 1 when the sparse path runs the register-resident
-                                loop, 0 otherwise                                 */
+    int32_t resident;        /* 1 when steps run in a resident loop
+                                (sbqa_loop_kernel), 0 otherwise                   */
 } sbqa_info_t;
 
 /*
@@ -154,8 +159,8 @@ typedef struct {
  *   out   receives the context; owned by the caller until sbqa_destroy.
  * Errors: EINVAL (N, R, runs, steps < 1; dt, a0 <= 0; J not symmetric, non-zero
  * diagonal, non-finite, malformed CSR; FP8 with ballistic f or J outside
- * {-1,0,+1}; BF16X3 with CSR; SPARSE_RESIDENT for an instance that does not
- * fit the resident loop), ENOMEM, EDEVICE.
+ * {-1,0,+1}; BF16X3 with CSR; LOOP_RESIDENT for an instance that does not
+ * fit a resident loop), ENOMEM, EDEVICE.
  */
 sbqa_status sbqa_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R,
                         int32_t runs, const sbqa_schedule *s, sbqa_ctx **out);

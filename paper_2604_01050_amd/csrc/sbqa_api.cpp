@@ -84,7 +84,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     if (s->fmode < 0 || s->fmode > 2) return fail(SBQA_EINVAL, "unknown fmode %d", s->fmode);
     if (!std::isfinite(s->delta_max) || s->delta_max < 0) return fail(SBQA_EINVAL, "delta_max must be finite and >= 0");
     if (s->precision < 0 || s->precision > 3) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
-    if (s->sparse_kernel < 0 || s->sparse_kernel > 2) return fail(SBQA_EINVAL, "unknown sparse_kernel %d", s->sparse_kernel);
+    if (s->loop_kernel < 0 || s->loop_kernel > 2) return fail(SBQA_EINVAL, "unknown loop_kernel %d", s->loop_kernel);
     if (!(s->init_amp >= 0) || !std::isfinite(s->init_amp)) return fail(SBQA_EINVAL, "init_amp must be finite and >= 0");
     switch (s->jp_kind) {
         case SBQA_JP_LINEAR:
@@ -428,6 +428,21 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     }
     HIP_TRY(dalloc(c, &c->S64, (size_t)Cp * Np));
     HIP_TRY(dalloc(c, &c->phis64, (size_t)c->L.esplits * Cp * Np));
+    if (c->resident) {
+        // small dense loop: J float32 [N][N], per-step pump and threshold tables
+        const int S = (int)c->s.steps;
+        std::vector<float> jsm((size_t)N * N), ca(S), dtab((size_t)S + 1);
+        for (size_t q = 0; q < jsm.size(); ++q) jsm[q] = (float)J->dense[q];
+        for (int n = 0; n < S; ++n) ca[n] = step_coef(&c->s, c->c0, c->R, (uint32_t)n).kA;
+        for (int n = 0; n <= S; ++n) dtab[n] = delta_at(&c->s, (uint32_t)n);
+        HIP_TRY(dalloc(c, &c->Jsm, jsm.size()));
+        HIP_TRY(dalloc(c, &c->coefA, ca.size()));
+        HIP_TRY(dalloc(c, &c->delta_tab, dtab.size()));
+        HIP_TRY(hipMemcpyAsync(c->Jsm, jsm.data(), sizeof(float) * jsm.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->coefA, ca.data(), sizeof(float) * ca.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->delta_tab, dtab.data(), sizeof(float) * dtab.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
+    }
 
     // J in the contraction precision (fragment-tiled) and in float64
     // (row-major, energies), zero padded.
@@ -585,6 +600,15 @@ static bool resident_plan(sbqa_ctx *c, const sbqa_coupling *J, std::string *why)
     return true;
 }
 
+// Whether the small dense resident loop fits this instance.
+static bool small_plan(sbqa_ctx *c, std::string *why) {
+    if (c->facts.path != PATH_F32 && c->facts.path != PATH_FP8) { *why = "the small dense loop computes in float32 (FP32 or FP8 precision only)"; return false; }
+    if (c->N > SMALL_MAX_N) { *why = "N is above the small dense loop's limit"; return false; }
+    if ((int64_t)c->R * c->N > SMALL_MAX_ELEMS) { *why = "R*N is above the small dense loop's limit"; return false; }
+    if (small_lds_bytes(c->N, c->R) > 160 * 1024) { *why = "J and the run state do not fit in LDS"; return false; }
+    return true;
+}
+
 sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                        const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out,
                        bool allow_resident) {
@@ -608,12 +632,14 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
         if (e != hipSuccess) { delete c; return fail(SBQA_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
         c->stream = c->own_stream;
     }
-    if (facts.path == PATH_CSR) {
+    {
         std::string why;
-        c->resident = allow_resident && s->sparse_kernel != SBQA_SPARSE_STREAM && resident_plan(c, J, &why);
-        if (!c->resident && s->sparse_kernel == SBQA_SPARSE_RESIDENT) {
+        const bool plan = facts.path == PATH_CSR ? resident_plan(c, J, &why) : small_plan(c, &why);
+        c->resident = allow_resident && s->loop_kernel != SBQA_LOOP_STREAM && plan;
+        if (!c->resident && s->loop_kernel == SBQA_LOOP_RESIDENT) {
             delete c;
-            return fail(SBQA_EINVAL, "instance does not fit the resident sparse loop: %s", why.c_str());
+            return fail(SBQA_EINVAL, "instance does not fit a resident loop: %s",
+                        allow_resident ? why.c_str() : "contexts of the serving loop step one launch at a time");
         }
     }
     st = ctx_upload(c, J, h);
@@ -629,8 +655,36 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
     return SBQA_OK;
 }
 
+// K steps of the small dense loop in one launch (one workgroup per run);
+// afterwards the fragment-tiled operand is rebuilt from the new state.
+static sbqa_status ctx_step_small(sbqa_ctx *c, uint32_t K) {
+    SmallArgs a;
+    a.N = c->N;
+    a.Np = c->L.Np;
+    a.R = c->R;
+    a.S = (int)c->s.steps;
+    a.n0 = (int)c->step;
+    a.K = (int)K;
+    a.fmode = c->s.fmode;
+    a.J = c->Jsm;
+    a.h = c->h32;
+    a.x = c->x[c->cur];
+    a.y = c->y;
+    a.jp = c->jp;
+    a.coefA = c->coefA;
+    a.delta = c->delta_tab;
+    const StepCoef k = step_coef(&c->s, c->c0, c->R, c->step);
+    a.kB = k.kB;
+    a.dt = k.dt;
+    a.kD = k.kD;
+    HIP_TRY(launch_dense_small(a, c->runs, c->stream));
+    c->step += K;
+    return rebuild_operand(c);
+}
+
 // K steps of the register-resident loop in one cooperative launch.
 static sbqa_status ctx_step_resident(sbqa_ctx *c, uint32_t K) {
+    if (c->facts.path != PATH_CSR) return ctx_step_small(c, K);
     ResidentArgs a;
     a.N = c->N;
     a.Cs = c->L.Cs;
@@ -744,7 +798,7 @@ sbqa_schedule sbqa_schedule_default(void) {
     s.init_amp = 0.1;
     s.precision = SBQA_PREC_AUTO;
     s.energy_every = 0;
-    s.sparse_kernel = SBQA_SPARSE_AUTO;
+    s.loop_kernel = SBQA_LOOP_AUTO;
     return s;
 }
 

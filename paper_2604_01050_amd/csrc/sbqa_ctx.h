@@ -94,8 +94,10 @@ struct sbqa_ctx {
     int64_t *bestStep = nullptr;
     int8_t *bestSpins = nullptr;
 
-    // register-resident CSR loop (see kernels_csr.hip)
+    // resident loops: register-resident CSR loop (kernels_csr.hip) or the
+    // small dense loop (kernels_small.hip)
     bool resident = false;
+    float *Jsm = nullptr;               // small dense loop: J float32 [N][N]
     int res_D = 0, res_rows = 0, res_nwg = 0;
     int32_t *colpad = nullptr;          // [rows][D]
     float *valpad = nullptr;            // [D][rows]

@@ -132,6 +132,24 @@ int resident_threads();
 hipError_t resident_max_blocks(int D, int N, int *blocks_per_cu);
 hipError_t launch_csr_resident(const ResidentArgs &a, int D, hipStream_t st);
 
+// Resident loop for small dense instances (kernels_small.hip): one
+// workgroup per run, K steps per launch, J float32 [N][N] row-major, state
+// [C][Np] replica-major updated in place.
+constexpr int SMALL_MAX_N = 128;
+constexpr int SMALL_MAX_ELEMS = 4096;   // R * N
+struct SmallArgs {
+    int N, Np, R, S, n0, K, fmode;
+    const float *J;       // [N][N]
+    const float *h;       // [Np]
+    float *x, *y;         // [C][Np]
+    const float *jp;      // [runs][S]
+    const float *coefA;   // [S]   (a0 - a_n)/R
+    const float *delta;   // [S+1] Delta_n
+    float kB, dt, kD;
+};
+size_t small_lds_bytes(int N, int R);
+hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st);
+
 // CSR operand from state [N][Cs].
 hipError_t launch_csr_operand(int fmode, int N, int Cs, int C, const float *x, int8_t *g,
                               float delta, hipStream_t st);

@@ -159,6 +159,10 @@ CASES = [
     ("csr_ballistic", None, 2, "csr"),
     ("csr_ternary_r8", None, 0, "csr"),
     ("csr_ballistic_r8", None, 2, "csr"),
+    # small dense loop (one workgroup per run, many steps per launch; here K = 1)
+    ("small_fp32_ternary", "PREC_FP32", 0, "gauss_small"),
+    ("small_fp32_ballistic", "PREC_FP32", 2, "gauss_small"),
+    ("small_fp8_sign", "PREC_FP8", 1, "sk_small"),
 ]
 
 
@@ -170,12 +174,13 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
     the CSR path whose ring neighbours come from adjacent lanes)."""
     R, runs, S = (8 if name.endswith("_r8") else 5), 7, 40
     csr = J = None
-    if coup == "sk":
-        N = 300
+    small = coup.endswith("_small")
+    if coup.startswith("sk"):
+        N = 100 if small else 300
         J = inst.sk_pm1(N, 21)
         h = np.round(inst.gaussian_fields(N, 1.0, 22))
-    elif coup == "gauss":
-        N = 300
+    elif coup.startswith("gauss"):
+        N = 100 if small else 300
         J = inst.dense_gaussian(N, 23)
         h = inst.gaussian_fields(N, 0.2, 24)
     else:
@@ -187,10 +192,12 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
         h = inst.gaussian_fields(N, 0.1, 27)
     _log("single-step parity %s N=%d R=%d runs=%d" % (name, N, R, runs))
     kw = {} if prec is None else {"precision": getattr(sb, prec)}
+    kw["loop_kernel"] = sb.LOOP_RESIDENT if small else sb.LOOP_STREAM
     rng = np.random.default_rng(28)
     beta, alpha = rng.uniform(0.5, 1.5, runs), rng.uniform(0.5, 1.0, runs)
     ctx = _ctx(sb, J=J, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, jp_kind=sb.JP_PAPER,
                beta=beta, alpha=alpha, gamma0_over_R=0.7, **kw)
+    assert sb.sbqa_info(ctx)["resident"] == small
     P = _orc_problem(orc, sb, ctx, J=J, csr=csr, h=h, fmode=fmode)
     jt = np.stack([orc.jperp_paper_table(b, a, 0.7, S) for b, a in zip(beta, alpha)])
     # schedule table of the library equals the oracle's, rounded to float32
@@ -209,7 +216,7 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
             ex, phi_o, phi_abs = _check_step(orc, P, ctx, sb, X, Y, n, S, jr, xg, yg, J=J, csr=csr, h=h,
                                              field_tol=BF16X3_TOL if prec == "PREC_BF16X3" else TOL)
             excluded += ex
-            if prec == "PREC_FP8" or (coup == "sk"):
+            if prec == "PREC_FP8" or coup.startswith("sk"):
                 assert np.array_equal(phi_g, phi_o.astype(np.float32)), "fp8 fields must be exact integers"
             else:
                 ftol = BF16X3_TOL if prec == "PREC_BF16X3" else TOL
@@ -506,10 +513,10 @@ def test_resident_loop_matches_streaming(sb, orc, name, N, d, R, runs, fmode, ee
     h = inst.gaussian_fields(N, 0.1, 5003)
     S = 120
     out = {}
-    for kern in (sb.SPARSE_STREAM, sb.SPARSE_RESIDENT):
-        ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, sparse_kernel=kern, seed=5004,
+    for kern in (sb.LOOP_STREAM, sb.LOOP_RESIDENT):
+        ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, loop_kernel=kern, seed=5004,
                    energy_every=ee, jp_kind=sb.JP_PAPER)
-        assert sb.sbqa_info(ctx)["resident"] == (kern == sb.SPARSE_RESIDENT)
+        assert sb.sbqa_info(ctx)["resident"] == (kern == sb.LOOP_RESIDENT)
         sb.sbqa_step(ctx, 37)
         mid = sb.sbqa_get_state(ctx)
         sb.sbqa_step(ctx, 1)
@@ -521,7 +528,7 @@ def test_resident_loop_matches_streaming(sb, orc, name, N, d, R, runs, fmode, ee
         fin = sb.sbqa_get_state(ctx)
         best = sb.sbqa_best(ctx)
         out[kern] = (mid, one, fin, best, sb.sbqa_best_step(ctx), sb.sbqa_info(ctx)["c0"])
-    a, b = out[sb.SPARSE_STREAM], out[sb.SPARSE_RESIDENT]
+    a, b = out[sb.LOOP_STREAM], out[sb.LOOP_RESIDENT]
     for u, v in zip(a[:3], b[:3]):
         assert np.array_equal(u[0], v[0]) and np.array_equal(u[1], v[1])
     assert np.array_equal(a[3][0], b[3][0]) and np.array_equal(a[3][1], b[3][1])
@@ -529,20 +536,69 @@ def test_resident_loop_matches_streaming(sb, orc, name, N, d, R, runs, fmode, ee
     # one resident step (37 -> 38) against the oracle
     (X, Y), (xg, yg) = b[0], b[1]
     P = orc.Problem(N, R, runs, csr=csr, h=h, dt=0.5, a0=1.0, c0=b[5], fmode=fmode)
-    ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, sparse_kernel=sb.SPARSE_RESIDENT, seed=5004,
+    ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, loop_kernel=sb.LOOP_RESIDENT, seed=5004,
                jp_kind=sb.JP_PAPER)
     jr = sb.sbqa_jperp_table(ctx)[:, 37].astype(np.float64)
     _check_step(orc, P, ctx, sb, X, Y, 37, S, jr, xg, yg, csr=csr, h=h)
 
 
+SMALL_CASES = [
+    # name, N, R, runs, fmode, energy_every
+    ("sk64_cfg_shape", 64, 8, 4, 0, 0),
+    ("sk100_sign_tracking", 100, 5, 3, 1, 7),
+    ("sk128_max_elems", 128, 32, 2, 0, 13),
+    ("sk1_degenerate", 1, 3, 2, 0, 0),
+]
+
+
+@pytest.mark.parametrize("name,N,R,runs,fmode,ee", SMALL_CASES)
+def test_small_dense_loop_matches_streaming(sb, orc, name, N, R, runs, fmode, ee):
+    """The small dense loop (one workgroup per run, J and the run state in
+    LDS, many steps per launch) against the one-launch-per-step MFMA kernel:
+    with J in {-1,0,+1} and a ternary or sign operand both sum exact integers,
+    so states, tracked best energies and best spins agree bit-for-bit; the
+    first step also matches the oracle."""
+    S = 60
+    J = inst.sk_pm1(N, 5201) if N > 1 else np.zeros((1, 1))
+    h = np.round(inst.gaussian_fields(N, 1.0, 5202))
+    _log("small dense loop vs streaming %s N=%d R=%d runs=%d ee=%d" % (name, N, R, runs, ee))
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.2, 5203)
+    out = {}
+    for kern in (sb.LOOP_STREAM, sb.LOOP_RESIDENT):
+        ctx = _ctx(sb, J=J, h=h, R=R, runs=runs, steps=S, fmode=fmode, precision=sb.PREC_FP8,
+                   loop_kernel=kern, energy_every=ee)
+        assert sb.sbqa_info(ctx)["resident"] == (kern == sb.LOOP_RESIDENT)
+        sb.sbqa_set_state(ctx, X0, Y0)
+        sb.sbqa_step(ctx, 1)
+        first = sb.sbqa_get_state(ctx)
+        sb.sbqa_step(ctx, 23)          # launches split at the energy_every boundaries
+        sb.sbqa_step(ctx, S - 24)
+        out[kern] = first + sb.sbqa_get_state(ctx) + sb.sbqa_best(ctx) + (sb.sbqa_best_step(ctx),)
+    for a, b in zip(out[sb.LOOP_STREAM], out[sb.LOOP_RESIDENT]):
+        assert np.array_equal(a, b)
+    P = _orc_problem(orc, sb, ctx, J=J, h=h, fmode=fmode)
+    jr = np.full(runs, 0.5)     # linear J_perp at step 0, exact in float32
+    _check_step(orc, P, ctx, sb, X0, Y0, 0, S, jr, out[sb.LOOP_RESIDENT][0], out[sb.LOOP_RESIDENT][1], J=J, h=h)
+
+
 def test_resident_rejects_unfit_instances(sb):
-    """SPARSE_RESIDENT on an instance the loop cannot hold is EINVAL with a reason;
+    """LOOP_RESIDENT on an instance no resident loop can hold is EINVAL with a reason;
     AUTO then falls back to the streaming kernel."""
     E = inst.regular_graph(300, 4, 5101)
     csr = inst.edges_to_csr(300, E, inst.gaussian_edges(len(E), 5102))
     for kw, why in ((dict(R=5, runs=4), "multiple of 8"), (dict(R=8, runs=2, fmode=sb.F_BALLISTIC), "ballistic")):
         with pytest.raises(sb.SbqaError) as ei:
-            _ctx(sb, csr=csr, sparse_kernel=sb.SPARSE_RESIDENT, **kw)
+            _ctx(sb, csr=csr, loop_kernel=sb.LOOP_RESIDENT, **kw)
         assert ei.value.status == sb.EINVAL and why in ei.value.message
         ctx = _ctx(sb, csr=csr, **kw)
+        assert not sb.sbqa_info(ctx)["resident"]
+    # dense: the small loop holds N <= 128 and R*N <= 4096 in float32 only
+    for J, kw, why in ((inst.sk_pm1(129, 5103), dict(R=4, runs=2), "N is above"),
+                       (inst.sk_pm1(100, 5104), dict(R=41, runs=1), "R*N"),
+                       (inst.dense_gaussian(64, 5105), dict(R=4, runs=2, fmode=sb.F_BALLISTIC,
+                                                            precision=sb.PREC_BF16X3), "float32")):
+        with pytest.raises(sb.SbqaError) as ei:
+            _ctx(sb, J=J, loop_kernel=sb.LOOP_RESIDENT, **kw)
+        assert ei.value.status == sb.EINVAL and why in ei.value.message, ei.value.message
+        ctx = _ctx(sb, J=J, **kw)
         assert not sb.sbqa_info(ctx)["resident"]
