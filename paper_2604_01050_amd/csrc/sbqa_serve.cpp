@@ -218,6 +218,7 @@ sbqa_status sbqa_server_create(size_t hbm_budget_bytes, int32_t max_slots, sbqa_
 sbqa_status sbqa_submit(sbqa_server *srv, const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                         const sbqa_schedule *s, uint64_t *ticket) {
     clear_error();
+    const Clock::time_point t_arrival = Clock::now();   // latency includes validation and copies
     if (!srv || !ticket) return fail(SBQA_EINVAL, "NULL argument");
     std::unique_ptr<Request> r(new (std::nothrow) Request());
     if (!r) return fail(SBQA_ENOMEM, "out of host memory");
@@ -240,7 +241,7 @@ sbqa_status sbqa_submit(sbqa_server *srv, const sbqa_coupling *J, const double *
     if (s->beta) r->beta.assign(s->beta, s->beta + runs);
     if (s->alpha) r->alpha.assign(s->alpha, s->alpha + runs);
     if (s->jp_kind == SBQA_JP_TABLE) r->jp_table.assign(s->jp_table, s->jp_table + (size_t)runs * s->steps);
-    r->t_submit = Clock::now();
+    r->t_submit = t_arrival;
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         if (srv->stop) return fail(SBQA_ESTATE, "server is shutting down");

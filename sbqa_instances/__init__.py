@@ -13,6 +13,12 @@ Instance families stand in for the paper's (whose data are not available):
                       weights; the sparse, rugged families of Sec. III (cubic
                       lattices have degree 6).
 * ``dense_gaussian``  dense J_ij ~ N(0,1), real-valued couplings.
+* ``square_lattice``, ``cubic_lattice``  periodic lattices (degree 4 and 6) for
+                      the large sparse lattice instances of Sec. III.
+* ``planted_square``  square-lattice instances with a planted ground state of
+                      known energy (frustrated plaquettes, hidden by a gauge), for
+                      optimality gaps and time-to-epsilon without a reference
+                      solver.
 
 Coupling convention everywhere: J is symmetric with a zero diagonal, stored
 row-major as float64 (dense) or as CSR (row_ptr int32[N+1], col int32[nnz]
@@ -25,7 +31,7 @@ import numpy as np
 __all__ = [
     "sk_pm1", "dense_gaussian", "regular_graph", "gaussian_edges",
     "edges_to_csr", "csr_to_dense", "dense_to_csr", "gaussian_fields",
-    "uniform_state", "spins_pm1",
+    "uniform_state", "spins_pm1", "square_lattice", "cubic_lattice", "planted_square",
 ]
 
 
@@ -174,3 +180,69 @@ def uniform_state(N: int, C: int, amp: float, seed: int):
 def spins_pm1(count: int, N: int, seed: int) -> np.ndarray:
     """Random spin configurations in {-1,+1}, int8, shape (count, N)."""
     return (_rng(seed).integers(0, 2, size=(count, N)) * 2 - 1).astype(np.int8)
+
+
+def square_lattice(L: int) -> np.ndarray:
+    """Edges (u < v) of the periodic L x L square lattice, site x + L*y, L >= 3."""
+    if L < 3:
+        raise ValueError("periodic square lattice needs L >= 3")
+    x, y = np.meshgrid(np.arange(L), np.arange(L), indexing="ij")
+    site = (x + L * y).ravel()
+    right = (((x + 1) % L) + L * y).ravel()
+    up = (x + L * ((y + 1) % L)).ravel()
+    E = np.concatenate([np.stack([site, right], 1), np.stack([site, up], 1)])
+    return np.sort(E, axis=1).astype(np.int64)
+
+
+def cubic_lattice(L: int) -> np.ndarray:
+    """Edges (u < v) of the periodic L x L x L simple cubic lattice, site
+    x + L*y + L*L*z, L >= 3."""
+    if L < 3:
+        raise ValueError("periodic cubic lattice needs L >= 3")
+    x, y, z = np.meshgrid(np.arange(L), np.arange(L), np.arange(L), indexing="ij")
+    site = (x + L * y + L * L * z).ravel()
+    nb = [(((x + 1) % L) + L * y + L * L * z).ravel(),
+          (x + L * ((y + 1) % L) + L * L * z).ravel(),
+          (x + L * y + L * L * ((z + 1) % L)).ravel()]
+    E = np.concatenate([np.stack([site, n], 1) for n in nb])
+    return np.sort(E, axis=1).astype(np.int64)
+
+
+def planted_square(L: int, seed: int, p_frustrated: float = 0.5):
+    """Periodic L x L square lattice (L even, >= 4) with a planted ground state.
+
+    The faces with x + y even (a checkerboard) cover every bond exactly once.
+    Each such plaquette gets integer bond magnitudes in {1, 2, 3}; with
+    probability p_frustrated its weakest bond (first minimum) is made
+    antiferromagnetic. A frustrated 4-cycle must violate at least one bond and
+    at best violates only its weakest one, which is what the all-up state does,
+    so all-up minimises every plaquette at once and is a ground state of the
+    sum. A random gauge s* (J_uv -> s*_u s*_v J_uv) then hides it.
+
+    Returns (edges (n, 2) int64 with u < v, weights float64, planted spins s*
+    int8, E0): E0 is the energy -sum_edges J_uv s_u s_v of s* (Eq. 2 at the
+    corners with h = 0), the sum of the plaquette minima."""
+    if L < 4 or L % 2:
+        raise ValueError("planted_square needs an even L >= 4")
+    rng = _rng(seed)
+    edges, w = [], []
+    E0 = 0.0
+    for x in range(L):
+        for y in range(L):
+            if (x + y) % 2:
+                continue
+            a, b = x + L * y, (x + 1) % L + L * y
+            c, d = (x + 1) % L + L * ((y + 1) % L), x + L * ((y + 1) % L)
+            mags = rng.integers(1, 4, size=4).astype(np.float64)
+            J = mags.copy()
+            if rng.random() < p_frustrated:
+                J[int(np.argmin(mags))] *= -1.0
+            E0 += -J.sum()
+            for (u, v), j in zip(((a, b), (b, c), (c, d), (d, a)), J):
+                edges.append((min(u, v), max(u, v)))
+                w.append(j)
+    edges = np.asarray(edges, dtype=np.int64)
+    w = np.asarray(w)
+    s = (rng.integers(0, 2, size=L * L) * 2 - 1).astype(np.int8)
+    w = w * s[edges[:, 0]] * s[edges[:, 1]]
+    return edges, w, s, float(E0)
