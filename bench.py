@@ -61,6 +61,19 @@ def make_workload(name: str):
         return dict(J=inst.dense_gaussian(N, 4001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32",
                     fmode=2, desc="dense N=8192 J~N(0,1), ballistic, fp32, R=16 x 32 runs, 5000 steps",
                     dtype="f32")
+    if name in ("cubic88", "square800"):
+        # large sparse lattices (Sec. III: cubic and square lattice families up to ~7e5 spins),
+        # many runs batched; Gaussian couplings on the bonds, h ~ N(0, 0.1^2)
+        L = 88 if name == "cubic88" else 800
+        E = inst.cubic_lattice(L) if name == "cubic88" else inst.square_lattice(L)
+        N = L ** 3 if name == "cubic88" else L * L
+        csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 2101))
+        h = inst.gaussian_fields(N, 0.1, 2102)
+        R, runs, S = 16, 8, 1000
+        desc = ("%s lattice L=%d (N=%d), J~N(0,1) on bonds, h~N(0,0.1^2), R=16 x 8 runs, 1000 steps, "
+                "ternary f, fp32 CSR" % ("cubic" if name == "cubic88" else "square", L, N))
+        return dict(csr=csr, h=h, N=N, R=R, runs=runs, S=S, prec=None, fmode=0, desc=desc,
+                    d=6 if name == "cubic88" else 4, dtype="f32")
     if name == "sk64":
         N, R, runs, S = 64, 8, 4, 1000
         return dict(J=inst.sk_pm1(N, 1001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32", fmode=0,

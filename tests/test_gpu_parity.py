@@ -374,6 +374,24 @@ def test_full_size_sparse_regular(sb, orc):
     _full_size_step(sb, orc, csr=csr, h=h, N=N, R=R, runs=runs, nrows=N, S=5000)
 
 
+def test_large_cubic_lattice(sb, orc):
+    """Periodic cubic lattice L = 64 (N = 262144, degree 6), Gaussian bonds,
+    R = 16 x 8 runs: the large-lattice regime of Sec. III on the streaming CSR
+    kernel, sampled rows (the last row included); energies of the returned
+    spins agree with the oracle's."""
+    L, R, runs = 64, 16, 8
+    N = L ** 3
+    _log("large cubic lattice N=%d R=%d runs=%d" % (N, R, runs))
+    E = inst.cubic_lattice(L)
+    csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 2201))
+    h = inst.gaussian_fields(N, 0.1, 2202)
+    _full_size_step(sb, orc, csr=csr, h=h, N=N, R=R, runs=runs, nrows=48, S=1000)
+    ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=200, seed=9)
+    sb.sbqa_step(ctx, 200)
+    Eb, sp = sb.sbqa_best(ctx)
+    np.testing.assert_allclose(orc.energy(sp, csr=csr, h=h), Eb, rtol=1e-12, atol=1e-9)
+
+
 def test_full_size_fp8_sk(sb, orc):
     """SK N = 16384, J = +-1 as e4m3, R = 16 x 16 runs: sampled rows, fields exact."""
     N, R, runs = 16384, 16, 16
