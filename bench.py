@@ -221,36 +221,40 @@ def serve_instances(n, seed):
     return out
 
 
-def serve_run(sb, srv, items, arrivals, R, runs, S, seed):
-    """Submit items at their arrival times (seconds from start), poll until all
-    are done. Returns per-item latency (completion - arrival), the makespan and
-    the library's own latencies."""
-    tickets = {}
-    done = {}
-    lib_lat = {}
+def serve_run(sb, srv, items, arrivals, R, runs, S, seed, workers=8):
+    """Submit items at their arrival times (seconds from start) from a pool of
+    client threads (a submission validates and copies the instance, so one
+    client thread would delay later arrivals), poll until all are done.
+    Returns per-item latency (completion - arrival time), the makespan and the
+    library's own latencies (submit call -> result)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def submit(q):
+        it = items[q]
+        prec = dict(precision=sb.PREC_FP8) if it["kind"] == "dense" else {}
+        return sb.sbqa_submit(srv, J=it["J"], csr=it["csr"], R=R, runs=runs, steps=S, fmode=0,
+                              jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0, seed=seed + q, **prec)
+
+    pool = ThreadPoolExecutor(max_workers=workers)
+    futs, done, lib_lat = {}, {}, {}
     t0 = time.perf_counter()
-    nxt = 0
-    n = len(items)
-    while len(done) < n:
-        now = time.perf_counter() - t0
-        while nxt < n and arrivals[nxt] <= now:
-            it = items[nxt]
-            prec = dict(precision=sb.PREC_FP8) if it["kind"] == "dense" else {}
-            tickets[nxt] = sb.sbqa_submit(srv, J=it["J"], csr=it["csr"], R=R, runs=runs, steps=S, fmode=0,
-                                          jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0, seed=seed + nxt, **prec)
-            nxt += 1
+    nxt, n = 0, len(items)
+    try:
+        while len(done) < n:
             now = time.perf_counter() - t0
-        for q, t in list(tickets.items()):
-            if q in done:
-                continue
-            r = sb.sbqa_poll(srv, t)
-            if r is not None:
-                done[q] = time.perf_counter() - t0 - arrivals[q]
-                lib_lat[q] = r[2]
-        if nxt < n and len(tickets) - len(done) == 0:
-            time.sleep(max(0.0, min(0.002, arrivals[nxt] - (time.perf_counter() - t0))))
-        else:
+            while nxt < n and arrivals[nxt] <= now:
+                futs[nxt] = pool.submit(submit, nxt)
+                nxt += 1
+            for q, f in list(futs.items()):
+                if q in done or not f.done():
+                    continue
+                r = sb.sbqa_poll(srv, f.result())
+                if r is not None:
+                    done[q] = time.perf_counter() - t0 - arrivals[q]
+                    lib_lat[q] = r[2]
             time.sleep(0.0005)
+    finally:
+        pool.shutdown(wait=True)
     makespan = time.perf_counter() - t0
     lat = np.array([done[q] for q in range(n)])
     return lat, makespan, np.array([lib_lat[q] for q in range(n)])

@@ -110,15 +110,14 @@ __device__ __forceinline__ float4 gather_fields(int i, int c, int Cs, const int3
 // lane's 4 columns come from the adjacent lane of the same run by a cross-lane
 // read. Otherwise they are read from the row in memory.
 template <bool BALLISTIC, bool RING_SHFL>
-__global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, int nchunk,
-                                                  const int32_t *__restrict__ row_ptr,
-                                                  const int32_t *__restrict__ col,
-                                                  const float *__restrict__ val, const float *__restrict__ h,
-                                                  const float *__restrict__ x_in, float *__restrict__ x_out,
-                                                  float *__restrict__ y, const int8_t *__restrict__ g_in,
-                                                  int8_t *__restrict__ g_out, const float *__restrict__ jp,
-                                                  int64_t jp_stride, StepCoef k, int fmode) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ void csr_step_body(int b, int N, int Cs, int C, int R, int nchunk,
+                                              const int32_t *__restrict__ row_ptr,
+                                              const int32_t *__restrict__ col,
+                                              const float *__restrict__ val, const float *__restrict__ h,
+                                              const float *__restrict__ x_in, float *__restrict__ x_out,
+                                              float *__restrict__ y, const int8_t *__restrict__ g_in,
+                                              int8_t *__restrict__ g_out, const float *__restrict__ jp,
+                                              int64_t jp_stride, StepCoef k, int fmode) {
     const int chunk = b % nchunk, rg = b / nchunk;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = rg * WAVES + wave;
@@ -171,6 +170,46 @@ __global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, i
         *reinterpret_cast<uint32_t *>(g_out + o) = pack_ternary(fo[0], fo[1], fo[2], fo[3]);
 }
 #pragma clang fp contract(on)
+
+template <bool BALLISTIC, bool RING_SHFL>
+__global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, int nchunk,
+                                                  const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col,
+                                                  const float *__restrict__ val, const float *__restrict__ h,
+                                                  const float *__restrict__ x_in, float *__restrict__ x_out,
+                                                  float *__restrict__ y, const int8_t *__restrict__ g_in,
+                                                  int8_t *__restrict__ g_out, const float *__restrict__ jp,
+                                                  int64_t jp_stride, StepCoef k, int fmode) {
+    csr_step_body<BALLISTIC, RING_SHFL>(blockIdx.x, N, Cs, C, R, nchunk, row_ptr, col, val, h, x_in, x_out, y, g_in,
+                                        g_out, jp, jp_stride, k, fmode);
+}
+
+// Grouped step of every CSR instance of one serving group: a grid-stride loop
+// over the virtual blocks of all tasks (task q owns blocks [first, first +
+// nblocks)), each running exactly the block of the standalone kernel for the
+// task's step n = n_base + offset; tasks past their last step skip.
+template <bool BALLISTIC, bool RING_SHFL>
+__global__ __launch_bounds__(256) void k_group_csr(const GroupHeader *__restrict__ hdr,
+                                                   const GroupTask *__restrict__ tasks, int offset) {
+    const int ntask = hdr->ntask, total = hdr->total_blocks;
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        int q = 0;
+        while (q + 1 < ntask && tasks[q + 1].first_block <= vb) ++q;
+        const GroupTask &t = tasks[q];
+        const int n = t.n_base + offset;
+        if (n >= t.n_end) continue;
+        const int in = n & 1;
+        StepCoef k;
+        k.kA = t.coefA[n];
+        k.kB = t.kB;
+        k.dt = t.dt;
+        k.kD = t.kD;
+        k.delta_next = t.delta[n + 1];
+        csr_step_body<BALLISTIC, RING_SHFL>(vb - t.first_block, t.N, t.ld, t.C, t.R, t.nchunk, t.row_ptr, t.col,
+                                            t.val, t.h, t.x[in], t.x[1 - in], t.y, (const int8_t *)t.g[in],
+                                            (int8_t *)t.g[1 - in], t.jp + n, t.S, k, t.fmode);
+    }
+}
 
 __global__ __launch_bounds__(256) void k_csr_operand(int N, int Cs, int C, const float *__restrict__ x,
                                                      int8_t *__restrict__ g, float delta, int fmode) {
@@ -423,10 +462,9 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
                            int64_t jp_stride, StepCoef k, hipStream_t st) {
     const int C = R * runs;
     if (Cs % 4 || Cs < C) return hipErrorInvalidValue;
-    const int nchunk = (C + COLS_PER_WAVE - 1) / COLS_PER_WAVE;
-    const int nrg = (N + WAVES - 1) / WAVES;
-    dim3 grid(nchunk * nrg), block(WAVES * 64);
-    const bool shfl = (R % 4 == 0) && (COLS_PER_WAVE % R == 0);
+    const int nchunk = csr_step_chunks(C);
+    dim3 grid(csr_step_blocks(N, C)), block(WAVES * 64);
+    const bool shfl = csr_ring_shfl(R);
 #define SBQA_CSR_LAUNCH(B, S)                                                                                  \
     hipLaunchKernelGGL((k_csr_step<B, S>), grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, h, x_in, \
                        x_out, y, g_in, g_out, jp, jp_stride, k, fmode)
@@ -438,6 +476,29 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
         else SBQA_CSR_LAUNCH(false, false);
     }
 #undef SBQA_CSR_LAUNCH
+    return hipGetLastError();
+}
+
+int csr_step_blocks(int N, int C) {
+    return ((C + COLS_PER_WAVE - 1) / COLS_PER_WAVE) * ((N + WAVES - 1) / WAVES);
+}
+
+int csr_step_chunks(int C) { return (C + COLS_PER_WAVE - 1) / COLS_PER_WAVE; }
+
+bool csr_ring_shfl(int R) { return (R % 4 == 0) && (COLS_PER_WAVE % R == 0); }
+
+hipError_t launch_group_csr(bool ballistic, bool shfl, const GroupHeader *hdr, const GroupTask *tasks, int grid,
+                            int offset, hipStream_t st) {
+    if (grid < 1) return hipErrorInvalidValue;
+#define SBQA_GCSR(B, S) hipLaunchKernelGGL((k_group_csr<B, S>), dim3(grid), dim3(WAVES * 64), 0, st, hdr, tasks, offset)
+    if (ballistic) {
+        if (shfl) SBQA_GCSR(true, true);
+        else SBQA_GCSR(true, false);
+    } else {
+        if (shfl) SBQA_GCSR(false, true);
+        else SBQA_GCSR(false, false);
+    }
+#undef SBQA_GCSR
     return hipGetLastError();
 }
 

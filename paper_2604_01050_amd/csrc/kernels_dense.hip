@@ -299,7 +299,7 @@ __device__ __forceinline__ void update_store(const DenseStepArgs &a, int c, int 
 // the J chunks the previous one touched last.
 // ---------------------------------------------------------------------------
 template <int PATH, int MBW, int EPI>
-__global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArgs a) {
+__device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, int mchunk) {
     constexpr int PL = Pipe<PATH>::planes;
     constexpr int PD = Pipe<PATH>::depth;
     constexpr int NT = Terms<PATH>::n;
@@ -311,8 +311,8 @@ __global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArg
     __shared__ __align__(16) uint8_t lds[LDS_BYTES];
 
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int nt = blockIdx.x, n0 = nt * DENSE_TN;
-    const int mb0 = (blockIdx.y * 4 + w) * MBW;   // first m-block of this wave
+    const int n0 = nt * DENSE_TN;
+    const int mb0 = (mchunk * 4 + w) * MBW;       // first m-block of this wave
     const int nkc = a.nkc;
     const int l16 = lane * 16;
     constexpr int JCH = RBT * FRAG_BYTES;   // J bytes of one tile and K chunk
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArg
     // this wave stages J row block w of tile nt (both planes); its operand
     // group is m-blocks mb0..mb0+MBW-1
     const int64_t jgrp = (int64_t)nt * nkc * JCH + w * FRAG_BYTES + l16;
-    const int64_t xgrp = (int64_t)(blockIdx.y * 4 + w) * nkc * XCH + l16;
+    const int64_t xgrp = (int64_t)(mchunk * 4 + w) * nkc * XCH + l16;
     const uint8_t *jsrc = a.J + jgrp;
     const uint8_t *jsrc_lo = (PL == 2) ? a.J_lo + jgrp : jsrc;
     const uint8_t *xsrc = a.g + xgrp;
@@ -463,6 +463,93 @@ __global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArg
     }
 }
 
+template <int PATH, int MBW, int EPI>
+__global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArgs a) {
+    dense_step_body<PATH, MBW, EPI>(a, blockIdx.x, blockIdx.y);
+}
+
+// Grouped step of every dense instance of one serving group (same path and
+// m-blocks per wave): a grid-stride loop over the tiles of all tasks (task q
+// owns virtual blocks [first, first + nblocks), nchunk spin tiles per column
+// chunk), each running exactly the workgroup of the standalone kernel for the
+// task's step n = n_base + offset; tasks past their last step skip.
+// J in the contraction precision, fragment-tiled (groups of DENSE_TN/16 row
+// blocks), from the zero-padded row-major float64 copy: one thread per 4
+// consecutive K elements of a row. e4m3 for ternary J (validated on the host),
+// float32 round-to-nearest, or bf16 hi = rne(J), lo = rne(J - hi) in float64.
+template <int PATH>
+__global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J64, int Np, int nkc,
+                                                   uint8_t *__restrict__ Jd, uint8_t *__restrict__ Jd_lo) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nq = (int64_t)Np * (Np / 4);
+    if (q >= nq) return;
+    const int row = (int)(q / (Np / 4)), k4 = (int)(q % (Np / 4)) * 4;
+    const double *src = J64 + (int64_t)row * Np + k4;
+    constexpr int eb = (PATH == PATH_F32) ? 4 : (PATH == PATH_FP8) ? 1 : 2;
+    const int64_t o = tf_offset(row, k4, nkc, eb, DENSE_TN / 16);
+    if constexpr (PATH == PATH_F32) {
+        *reinterpret_cast<float4 *>(Jd + o) = make_float4((float)src[0], (float)src[1], (float)src[2], (float)src[3]);
+    } else if constexpr (PATH == PATH_FP8) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t b = src[e] > 0.0 ? FP8_P1 : (src[e] < 0.0 ? FP8_M1 : 0u);
+            w |= b << (8 * e);
+        }
+        *reinterpret_cast<uint32_t *>(Jd + o) = w;
+    } else {
+        uint16_t hi[4], lo[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            hi[e] = bf16_rne((float)src[e]);
+            lo[e] = bf16_rne((float)(src[e] - (double)bf16_to_f32(hi[e])));
+        }
+        *reinterpret_cast<uint2 *>(Jd + o) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
+        *reinterpret_cast<uint2 *>(Jd_lo + o) = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
+    }
+}
+
+template <int PATH, int MBW>
+__global__ __launch_bounds__(DENSE_THREADS) void k_group_dense(const GroupHeader *__restrict__ hdr,
+                                                               const GroupTask *__restrict__ tasks, int offset) {
+    const int ntask = hdr->ntask, total = hdr->total_blocks;
+    for (int vb = blockIdx.x; vb < total; vb += gridDim.x) {
+        int q = 0;
+        while (q + 1 < ntask && tasks[q + 1].first_block <= vb) ++q;
+        const GroupTask &t = tasks[q];
+        const int n = t.n_base + offset;
+        if (n >= t.n_end) continue;
+        const int in = n & 1, lt = vb - t.first_block;
+        DenseStepArgs a;
+        a.N = t.N;
+        a.Np = t.ld;
+        a.R = t.R;
+        a.C = t.C;
+        a.nkc = t.nkc;
+        a.reverse = in;
+        a.J = static_cast<const uint8_t *>(t.J);
+        a.J_lo = static_cast<const uint8_t *>(t.J_lo);
+        a.g = static_cast<const uint8_t *>(t.g[in]);
+        a.g_lo = static_cast<const uint8_t *>(t.g_lo[in]);
+        a.g_next = static_cast<uint8_t *>(t.g[1 - in]);
+        a.g_next_lo = static_cast<uint8_t *>(t.g_lo[1 - in]);
+        a.h = t.h;
+        a.x_in = t.x[in];
+        a.x_out = t.x[1 - in];
+        a.y = t.y;
+        a.phi = nullptr;
+        a.jp = t.jp + n;
+        a.jp_stride = t.S;
+        a.k.kA = t.coefA[n];
+        a.k.kB = t.kB;
+        a.k.dt = t.dt;
+        a.k.kD = t.kD;
+        a.k.delta_next = t.delta[n + 1];
+        a.fmode = t.fmode;
+        dense_step_body<PATH, MBW, EPI_UPDATE>(a, lt % t.nchunk, lt / t.nchunk);
+    }
+}
+
 // Operand f(X) from the state: one thread per 4 consecutive spins of column c.
 template <int PATH>
 __global__ __launch_bounds__(256) void k_dense_operand(int Np, int nkc, int mbw, const float *__restrict__ x, void *g,
@@ -521,6 +608,42 @@ hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, cons
         case PATH_BF16X3: return launch_step_path<PATH_BF16X3>(epi, mbw, grid, a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void *Jd, void *Jd_lo, hipStream_t st) {
+    if (Np % 128 || nkc != Np * path_ebytes(path) / 128) return hipErrorInvalidValue;
+    const int64_t nq = (int64_t)Np * (Np / 4);
+    const dim3 grid((unsigned)((nq + 255) / 256)), block(256);
+    uint8_t *d = static_cast<uint8_t *>(Jd), *dl = static_cast<uint8_t *>(Jd_lo);
+    switch (path) {
+        case PATH_F32: hipLaunchKernelGGL(k_convert_j<PATH_F32>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
+        case PATH_FP8: hipLaunchKernelGGL(k_convert_j<PATH_FP8>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
+        case PATH_BF16X3: hipLaunchKernelGGL(k_convert_j<PATH_BF16X3>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_group_dense(Path path, int mbw, const GroupHeader *hdr, const GroupTask *tasks, int grid,
+                              int offset, hipStream_t st) {
+    if (grid < 1) return hipErrorInvalidValue;
+#define SBQA_GD(P, M) hipLaunchKernelGGL((k_group_dense<P, M>), dim3(grid), dim3(DENSE_THREADS), 0, st, hdr, tasks, offset)
+#define SBQA_GD_PATH(P)                 \
+    switch (mbw) {                      \
+        case 1: SBQA_GD(P, 1); break;   \
+        case 2: SBQA_GD(P, 2); break;   \
+        case 4: SBQA_GD(P, 4); break;   \
+        default: return hipErrorInvalidValue; \
+    }
+    switch (path) {
+        case PATH_F32: SBQA_GD_PATH(PATH_F32); break;
+        case PATH_FP8: SBQA_GD_PATH(PATH_FP8); break;
+        case PATH_BF16X3: SBQA_GD_PATH(PATH_BF16X3); break;
+        default: return hipErrorInvalidValue;
+    }
+#undef SBQA_GD_PATH
+#undef SBQA_GD
+    return hipGetLastError();
 }
 
 hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int nkc, int mbw, const float *x, void *g,

@@ -4,12 +4,14 @@
 #include "sbqa_ctx.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace sbqa {
@@ -48,30 +50,72 @@ static uint64_t splitmix64(uint64_t &s) {
 }
 static double unit_double(uint64_t &s) { return (double)(splitmix64(s) >> 11) * (1.0 / 9007199254740992.0); }
 
-static uint16_t bf16_rne_host(float v) {
-    uint32_t u;
-    std::memcpy(&u, &v, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-static float bf16_to_float_host(uint16_t b) {
-    uint32_t u = (uint32_t)b << 16;
-    float f;
-    std::memcpy(&f, &u, 4);
-    return f;
-}
-
-// Byte offset of element (row, k) of a fragment-tiled matrix with groups of
-// G row blocks (layout of the dense contraction operands, described in
-// sbqa_internal.h).
-static size_t tf_offset_host(int row, int k, int nkc, int eb, int G) {
-    const int kbyte = k * eb, kc = kbyte >> 7, kb = kbyte & 127, rb = row >> 4;
-    const int l = ((kb >> 5) << 4) | (row & 15);
-    return (((size_t)(rb / G) * nkc + kc) * G + rb % G) * FRAG_BYTES + (size_t)((kb >> 4) & 1) * 1024 +
-           (size_t)l * 16 + (kb & 15);
-}
-
 // ---------------------------------------------------------------- validation
+// One pass over a dense J: diagonal, finiteness, symmetry (64 x 64 tiles of
+// the upper triangle against their transposes, so both stay in cache), the
+// integral / ternary flags and the sum of squares of the entries. Row blocks
+// are scanned in parallel; their sums of squares are added in block order, so
+// the result does not depend on the number of threads.
+struct DenseScan {
+    int bad = 0;              // 1 diagonal, 2 not finite, 3 not symmetric
+    int64_t i = 0, j = 0;
+    bool integral = true, ternary = true;
+    double ss = 0.0;
+};
+
+static DenseScan scan_dense(const double *A, int64_t N) {
+    constexpr int64_t TB = 64;
+    const int64_t nb = (N + TB - 1) / TB;
+    std::vector<DenseScan> part((size_t)nb);
+    auto scan_block = [&](int64_t bi) {
+        DenseScan &r = part[(size_t)bi];
+        const int64_t i0 = bi * TB, i1 = std::min(N, i0 + TB);
+        for (int64_t i = i0; i < i1; ++i) {
+            if (A[i * N + i] != 0.0 && !r.bad) { r.bad = 1; r.i = i; r.j = i; }
+            double srow = 0.0;
+            for (int64_t j = 0; j < N; ++j) {
+                const double v = A[i * N + j];
+                if (!std::isfinite(v)) {
+                    if (!r.bad) { r.bad = 2; r.i = i; r.j = j; }
+                    continue;
+                }
+                if (v != std::floor(v) || std::fabs(v) > 2147483647.0) r.integral = false;
+                if (!(v == 0.0 || v == 1.0 || v == -1.0)) r.ternary = false;
+                srow += v * v;
+            }
+            r.ss += srow;
+        }
+        for (int64_t bj = bi; bj < nb; ++bj) {
+            const int64_t j0 = bj * TB, j1 = std::min(N, j0 + TB);
+            for (int64_t i = i0; i < i1; ++i)
+                for (int64_t j = std::max(j0, i + 1); j < j1; ++j)
+                    if (A[i * N + j] != A[j * N + i] && !(std::isnan(A[i * N + j]) && std::isnan(A[j * N + i])) && !r.bad) {
+                        r.bad = 3; r.i = i; r.j = j;
+                    }
+        }
+    };
+    const int nt = (int)std::min<int64_t>(nb, std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    if (nt <= 1 || N < 512) {
+        for (int64_t bi = 0; bi < nb; ++bi) scan_block(bi);
+    } else {
+        std::vector<std::thread> pool;
+        std::atomic<int64_t> next{0};
+        for (int t = 0; t < nt; ++t)
+            pool.emplace_back([&] {
+                for (int64_t bi; (bi = next.fetch_add(1)) < nb;) scan_block(bi);
+            });
+        for (std::thread &t : pool) t.join();
+    }
+    DenseScan out;
+    for (const DenseScan &r : part) {
+        if (r.bad && !out.bad) { out.bad = r.bad; out.i = r.i; out.j = r.j; }
+        out.integral = out.integral && r.integral;
+        out.ternary = out.ternary && r.ternary;
+        out.ss += r.ss;
+    }
+    return out;
+}
+
 sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                               const sbqa_schedule *s, InstanceFacts *facts) {
     if (!J || !s) return fail(SBQA_EINVAL, "J and schedule must be non-NULL");
@@ -122,17 +166,17 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     };
     if (dense) {
         if ((int64_t)N * N > (int64_t)1 << 32) return fail(SBQA_EINVAL, "dense N too large");
-        const double *A = J->dense;
-        for (int64_t i = 0; i < N; ++i) {
-            if (A[i * N + i] != 0.0) return fail(SBQA_EINVAL, "J has a non-zero diagonal at %lld", (long long)i);
-            for (int64_t j = 0; j < N; ++j) {
-                const double v = A[i * N + j];
-                if (!std::isfinite(v)) return fail(SBQA_EINVAL, "J[%lld][%lld] is not finite", (long long)i, (long long)j);
-                if (j > i && v != A[j * N + i]) return fail(SBQA_EINVAL, "J is not symmetric at (%lld,%lld)", (long long)i, (long long)j);
-                note(v);
-                ss += v * v;
+        const DenseScan d = scan_dense(J->dense, N);
+        if (d.bad) {
+            switch (d.bad) {
+                case 1: return fail(SBQA_EINVAL, "J has a non-zero diagonal at %lld", (long long)d.i);
+                case 2: return fail(SBQA_EINVAL, "J[%lld][%lld] is not finite", (long long)d.i, (long long)d.j);
+                default: return fail(SBQA_EINVAL, "J is not symmetric at (%lld,%lld)", (long long)d.i, (long long)d.j);
             }
         }
+        integral = d.integral;
+        ternary = d.ternary;
+        ss = d.ss;
         facts->nnz = 0;
     } else {
         if (!J->row_ptr || !J->col || !J->val) return fail(SBQA_EINVAL, "CSR needs row_ptr, col and val");
@@ -233,7 +277,7 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
 size_t instance_bytes(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, uint32_t steps) {
     Layout L;
     plan_layout(N, R, runs, f, &L);
-    return L.bytes + (size_t)runs * steps * 4;
+    return L.bytes + ((size_t)runs + 2) * steps * 4 + 4;   // + J_perp table, per-step a_n and Delta_n tables
 }
 
 // ----------------------------------------------------------------- schedules
@@ -336,6 +380,18 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     const uint32_t S = c->s.steps;
     HIP_TRY(dalloc(c, &c->jp, (size_t)runs * S));
     HIP_TRY(hipMemcpyAsync(c->jp, c->jp_host.data(), sizeof(float) * runs * S, hipMemcpyHostToDevice, c->stream));
+    {
+        // per-step pump and threshold tables (a_n term and Delta_n of Eq. 8),
+        // read on the device by the resident loops and the grouped steps
+        std::vector<float> ca(S), dtab((size_t)S + 1);
+        for (uint32_t n = 0; n < S; ++n) ca[n] = step_coef(&c->s, c->c0, c->R, n).kA;
+        for (uint32_t n = 0; n <= S; ++n) dtab[n] = delta_at(&c->s, n);
+        HIP_TRY(dalloc(c, &c->coefA, ca.size()));
+        HIP_TRY(dalloc(c, &c->delta_tab, dtab.size()));
+        HIP_TRY(hipMemcpyAsync(c->coefA, ca.data(), sizeof(float) * ca.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipMemcpyAsync(c->delta_tab, dtab.data(), sizeof(float) * dtab.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
+    }
     HIP_TRY(dalloc(c, &c->E, (size_t)std::max(C, Cp)));
     HIP_TRY(dalloc(c, &c->bestE, (size_t)runs));
     HIP_TRY(dalloc(c, &c->bestStep, (size_t)runs));
@@ -380,11 +436,11 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         HIP_TRY(hipMemcpyAsync(c->val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(c->val64, J->val, sizeof(double) * nnz, hipMemcpyHostToDevice, c->stream));
         std::vector<int32_t> cp;
-        std::vector<float> vp, ca, dtab;
+        std::vector<float> vp;
         if (c->resident) {
             // padded neighbour lists (CSR order, then index 0 with weight 0),
-            // per-step pump and threshold tables, ring exchange buffers
-            const int D = c->res_D, NR = c->res_rows, S = (int)c->s.steps;
+            // ring exchange buffers
+            const int D = c->res_D, NR = c->res_rows;
             cp.assign((size_t)NR * D, 0);
             vp.assign((size_t)D * NR, 0.0f);
             for (int i = 0; i < N; ++i)
@@ -392,14 +448,8 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
                     cp[(size_t)i * D + q] = J->col[J->row_ptr[i] + q];
                     vp[(size_t)q * NR + i] = (float)J->val[J->row_ptr[i] + q];
                 }
-            ca.resize(S);
-            dtab.resize((size_t)S + 1);
-            for (int n = 0; n < S; ++n) ca[n] = step_coef(&c->s, c->c0, c->R, (uint32_t)n).kA;
-            for (int n = 0; n <= S; ++n) dtab[n] = delta_at(&c->s, (uint32_t)n);
             HIP_TRY(dalloc(c, &c->colpad, cp.size()));
             HIP_TRY(dalloc(c, &c->valpad, vp.size()));
-            HIP_TRY(dalloc(c, &c->coefA, ca.size()));
-            HIP_TRY(dalloc(c, &c->delta_tab, dtab.size()));
             HIP_TRY(dalloc(c, &c->xpub, (size_t)2 * c->res_nwg * 2 * NR));
             HIP_TRY(dalloc(c, &c->flags, (size_t)c->res_nwg));
             HIP_TRY(dalloc(c, &c->epoch_cnt, (size_t)c->res_nwg));
@@ -408,8 +458,6 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
             *c->err_host = 0;
             HIP_TRY(hipMemcpyAsync(c->colpad, cp.data(), sizeof(int32_t) * cp.size(), hipMemcpyHostToDevice, c->stream));
             HIP_TRY(hipMemcpyAsync(c->valpad, vp.data(), sizeof(float) * vp.size(), hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(hipMemcpyAsync(c->coefA, ca.data(), sizeof(float) * ca.size(), hipMemcpyHostToDevice, c->stream));
-            HIP_TRY(hipMemcpyAsync(c->delta_tab, dtab.data(), sizeof(float) * dtab.size(), hipMemcpyHostToDevice, c->stream));
         }
         HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
         return SBQA_OK;
@@ -429,18 +477,11 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     HIP_TRY(dalloc(c, &c->S64, (size_t)Cp * Np));
     HIP_TRY(dalloc(c, &c->phis64, (size_t)c->L.esplits * Cp * Np));
     if (c->resident) {
-        // small dense loop: J float32 [N][N], per-step pump and threshold tables
-        const int S = (int)c->s.steps;
-        std::vector<float> jsm((size_t)N * N), ca(S), dtab((size_t)S + 1);
+        // small dense loop: J float32 [N][N]
+        std::vector<float> jsm((size_t)N * N);
         for (size_t q = 0; q < jsm.size(); ++q) jsm[q] = (float)J->dense[q];
-        for (int n = 0; n < S; ++n) ca[n] = step_coef(&c->s, c->c0, c->R, (uint32_t)n).kA;
-        for (int n = 0; n <= S; ++n) dtab[n] = delta_at(&c->s, (uint32_t)n);
         HIP_TRY(dalloc(c, &c->Jsm, jsm.size()));
-        HIP_TRY(dalloc(c, &c->coefA, ca.size()));
-        HIP_TRY(dalloc(c, &c->delta_tab, dtab.size()));
         HIP_TRY(hipMemcpyAsync(c->Jsm, jsm.data(), sizeof(float) * jsm.size(), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipMemcpyAsync(c->coefA, ca.data(), sizeof(float) * ca.size(), hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipMemcpyAsync(c->delta_tab, dtab.data(), sizeof(float) * dtab.size(), hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
     }
 
@@ -455,43 +496,12 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     c->Jd = jd;
     c->Jd_lo = jlo;
     c->J64 = j64;
-    // Upload blocks of RB rows (whole groups of DENSE_TN rows, contiguous in
-    // the tiled layout) through bounded host staging buffers.
-    const int RB = 4 * DENSE_TN;
-    const size_t blk = (size_t)RB * Np * eb;   // RB rows, fragment-tiled, contiguous
-    std::vector<uint8_t> stage(blk), stage_lo(path == PATH_BF16X3 ? blk : 0);
-    std::vector<double> stage64((size_t)RB * Np);
-    for (int i0 = 0; i0 < N; i0 += RB) {
-        const int nr = std::min(RB, N - i0), nrg = (int)round_up(nr, DENSE_TN);
-        std::fill(stage.begin(), stage.end(), 0);
-        std::fill(stage_lo.begin(), stage_lo.end(), 0);
-        std::fill(stage64.begin(), stage64.end(), 0.0);
-        for (int ii = 0; ii < nr; ++ii) {
-            const double *row = A + (int64_t)(i0 + ii) * N;
-            for (int j = 0; j < N; ++j) {
-                const double v = row[j];
-                stage64[(size_t)ii * Np + j] = v;
-                const size_t o = tf_offset_host(ii, j, nkc, eb, DENSE_TN / 16);
-                if (path == PATH_F32) {
-                    const float f = (float)v;
-                    std::memcpy(&stage[o], &f, 4);
-                } else if (path == PATH_FP8) {
-                    stage[o] = v > 0 ? 0x38 : (v < 0 ? 0xB8 : 0x00);
-                } else {
-                    const uint16_t hi = bf16_rne_host((float)v);
-                    const uint16_t lo = bf16_rne_host((float)(v - (double)bf16_to_float_host(hi)));
-                    std::memcpy(&stage[o], &hi, 2);
-                    std::memcpy(&stage_lo[o], &lo, 2);
-                }
-            }
-        }
-        const size_t dst = (size_t)i0 * Np * eb, nbytes = (size_t)nrg * Np * eb;
-        HIP_TRY(hipMemcpyAsync(jd + dst, stage.data(), nbytes, hipMemcpyHostToDevice, c->stream));
-        if (path == PATH_BF16X3)
-            HIP_TRY(hipMemcpyAsync(jlo + dst, stage_lo.data(), nbytes, hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipMemcpyAsync(j64 + (size_t)i0 * Np, stage64.data(), sizeof(double) * nr * Np, hipMemcpyHostToDevice, c->stream));
-        HIP_TRY(hipStreamSynchronize(c->stream));  // staging buffers are reused
-    }
+    // float64 rows straight into the zero-padded row-major copy (energies),
+    // then the contraction copy is derived from it on the device
+    HIP_TRY(hipMemcpy2DAsync(j64, sizeof(double) * Np, A, sizeof(double) * N, sizeof(double) * N, N,
+                             hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_convert_j(path, j64, Np, nkc, jd, jlo, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));   // the caller may free J on return
     return SBQA_OK;
 }
 

@@ -53,6 +53,7 @@ sbqa_status ctx_step(sbqa_ctx *c, uint32_t n);
 sbqa_status ctx_step_once(sbqa_ctx *c);
 sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins);
 sbqa_status ctx_check_async(sbqa_ctx *c);  // after a stream synchronisation
+sbqa_status ctx_evaluate(sbqa_ctx *c);     // energies of the current state -> best tracking
 
 }  // namespace sbqa
 

@@ -89,6 +89,44 @@ struct DenseStepArgs {
 hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, const DenseStepArgs &a,
                              hipStream_t st);
 
+// ---- grouped steps of the serving loop ----------------------------------------
+// One task per resident instance; the tasks of a group (same kernel
+// specialisation) are stepped together by one grouped launch per step, a
+// grid-stride loop over the virtual blocks of all tasks (task q owns blocks
+// [first_block, first_block + nblocks)). Step n = n_base + offset runs while
+// n < n_end; the state buffers ping-pong on the parity of n (x[n & 1] in).
+struct GroupTask {
+    int first_block, nblocks;
+    int n_base, n_end;
+    int S;                   // schedule length (J_perp row stride)
+    int N, ld;               // spins; state row stride (CSR: Cs, dense: Np)
+    int R, C;
+    int nchunk;              // CSR: column chunks of the step; dense: spin tiles (Np / DENSE_TN)
+    int nkc, fmode;
+    float kB, dt, kD;
+    float *x[2];
+    float *y;
+    void *g[2], *g_lo[2];
+    const void *J, *J_lo;    // dense, fragment-tiled
+    const int32_t *row_ptr, *col;
+    const float *val;        // CSR
+    const float *h, *jp, *coefA, *delta;   // jp: [runs][S]; coefA [S]; delta [S+1]
+};
+struct GroupHeader {
+    int ntask, total_blocks;
+};
+int csr_step_blocks(int N, int C);
+int csr_step_chunks(int C);
+bool csr_ring_shfl(int R);
+hipError_t launch_group_csr(bool ballistic, bool shfl, const GroupHeader *hdr, const GroupTask *tasks, int grid,
+                            int offset, hipStream_t st);
+hipError_t launch_group_dense(Path path, int mbw, const GroupHeader *hdr, const GroupTask *tasks, int grid,
+                              int offset, hipStream_t st);
+
+// J in the contraction precision (fragment-tiled, groups of DENSE_TN/16 row
+// blocks) from the zero-padded row-major float64 J64 [Np][Np].
+hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void *Jd, void *Jd_lo, hipStream_t st);
+
 // Operand f(X) (fragment-tiled, groups of mbw row blocks) from state [C][Np]
 // with threshold delta.
 hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int nkc, int mbw, const float *x,

@@ -3,14 +3,19 @@
 //
 // A scheduler thread owns every device call. Requests queue in arrival order;
 // the head of the queue is admitted as soon as a slot is free and its device
-// footprint fits the remaining budget. Every resident instance then advances
-// in step blocks of STEP_BLOCK steps on its slot's own stream, so the kernels
-// of different instances overlap on the device; at each block boundary the
-// finished instances are read out (best over replicas, Sec. II.B), retired,
-// and queued requests take their place. Each instance runs exactly the
-// kernels it would run alone, so its result does not depend on the mix.
+// footprint fits the remaining budget. All resident instances then advance
+// together in step blocks of up to STEP_BLOCK steps: every step is one
+// grouped launch per kernel specialisation (dense path x m-blocks per wave,
+// CSR ballistic x ring by lane reads), a grid-stride loop over the workgroups
+// of all instances of the group, driven by a device task table that the
+// scheduler rewrites between blocks. Each instance runs exactly the
+// workgroups its standalone kernel would run, so its result does not depend
+// on the mix. At block boundaries finished instances are read out (best over
+// replicas, Sec. II.B) and retired, tracked energies are evaluated, and queued
+// requests take their place.
 #include "sbqa_ctx.h"
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -27,7 +32,70 @@ using namespace sbqa;
 namespace {
 
 constexpr uint32_t STEP_BLOCK = 64;
+// Task-table groups: 9 dense (path x m-blocks per wave 1/2/4) and 4 CSR
+// (ballistic x ring by lane reads).
+constexpr int NGROUPS = 13;
+constexpr int DENSE_GRID_CAP = 512;   // workgroups of one grouped dense launch at most
+constexpr int CSR_GRID_CAP = 2048;
 typedef std::chrono::steady_clock Clock;
+
+int group_of(const sbqa_ctx *c) {
+    if (c->facts.path == PATH_CSR)
+        return 9 + 2 * (c->s.fmode == SBQA_F_BALLISTIC ? 1 : 0) + (csr_ring_shfl(c->R) ? 1 : 0);
+    const int mi = c->L.mbw == 1 ? 0 : c->L.mbw == 2 ? 1 : 2;
+    return (int)c->facts.path * 3 + mi;
+}
+
+// Table entry of context c for steps [c->step, n_end).
+GroupTask make_task(const sbqa_ctx *c, int first_block, uint32_t n_end) {
+    GroupTask t;
+    std::memset(&t, 0, sizeof t);
+    const StepCoef k = step_coef(&c->s, c->c0, c->R, c->step);
+    t.first_block = first_block;
+    t.n_base = (int)c->step;
+    t.n_end = (int)n_end;
+    t.S = (int)c->s.steps;
+    t.N = c->N;
+    t.R = c->R;
+    t.C = c->L.C;
+    t.fmode = c->s.fmode;
+    t.kB = k.kB;
+    t.dt = k.dt;
+    t.kD = k.kD;
+    t.x[0] = c->x[0];
+    t.x[1] = c->x[1];
+    t.y = c->y;
+    t.g[0] = c->g[0];
+    t.g[1] = c->g[1];
+    t.g_lo[0] = c->g_lo[0];
+    t.g_lo[1] = c->g_lo[1];
+    t.h = c->h32;
+    t.jp = c->jp;
+    t.coefA = c->coefA;
+    t.delta = c->delta_tab;
+    if (c->facts.path == PATH_CSR) {
+        t.ld = c->L.Cs;
+        t.nchunk = csr_step_chunks(c->L.C);
+        t.nblocks = csr_step_blocks(c->N, c->L.C);
+        t.row_ptr = c->rp;
+        t.col = c->col;
+        t.val = c->val;
+    } else {
+        t.ld = c->L.Np;
+        t.nkc = c->L.nkc;
+        t.nchunk = c->L.Np / DENSE_TN;
+        t.nblocks = t.nchunk * (c->L.Cg / (64 * c->L.mbw));
+        t.J = c->Jd;
+        t.J_lo = c->Jd_lo;
+    }
+    return t;
+}
+
+#define HIP_CHECK_SERVE(expr)                                                                 \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return fail(SBQA_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
 
 struct Request {
     uint64_t ticket = 0;
@@ -39,6 +107,8 @@ struct Request {
     InstanceFacts facts;
     size_t bytes = 0;
     Clock::time_point t_submit;
+    sbqa_status create_status = SBQA_OK;   // set by the creator thread on failure
+    std::string error;
 };
 
 struct Result {
@@ -52,7 +122,6 @@ struct Result {
 struct Slot {
     std::unique_ptr<Request> req;
     sbqa_ctx *ctx = nullptr;
-    hipStream_t stream = nullptr;
     size_t bytes = 0;
 };
 
@@ -69,7 +138,21 @@ struct sbqa_server {
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread worker;
-    std::vector<hipStream_t> streams;
+    hipStream_t stream = nullptr;
+    // context creation off the scheduler thread: admitted requests wait in
+    // `create` until the creator thread has built their context (on its own
+    // stream, so uploads overlap the grouped steps) and moved them to `ready`
+    std::thread creator;
+    hipStream_t create_stream = nullptr;
+    std::deque<std::unique_ptr<Slot>> create, ready;   // guarded by mu
+    std::condition_variable cv_create;
+    bool stop_creator = false;   // set once the scheduler has drained all admitted work
+    // task tables: pinned host copies (two, alternating between blocks) and the device table
+    GroupTask *h_tasks[2] = {nullptr, nullptr};
+    GroupHeader *h_hdr[2] = {nullptr, nullptr};
+    hipEvent_t h_free[2] = {nullptr, nullptr};   // the copy out of host table q has completed
+    GroupTask *d_tasks = nullptr;
+    GroupHeader *d_hdr = nullptr;
     // stats (guarded by mu)
     uint64_t completed = 0;
     double updates = 0.0;
@@ -101,73 +184,167 @@ static void finish(sbqa_server *srv, Slot &sl, sbqa_status st, const char *msg) 
     srv->results[sl.req->ticket] = std::move(res);
 }
 
+// One step block for every resident instance: rewrite the task table, then
+// per step one grouped launch per group present. Returns the first failure.
+static sbqa_status step_block(sbqa_server *srv, std::vector<Slot> &slots, int parity) {
+    GroupTask *ht = srv->h_tasks[parity];
+    GroupHeader *hh = srv->h_hdr[parity];
+    HIP_CHECK_SERVE(hipEventSynchronize(srv->h_free[parity]));   // host table q no longer read by a copy
+    int cnt[NGROUPS] = {0}, total[NGROUPS] = {0};
+    uint32_t steps = 0;
+    for (Slot &sl : slots) {
+        sbqa_ctx *c = sl.ctx;
+        if (!c || c->step >= c->s.steps) continue;
+        uint32_t n_end = std::min(c->s.steps, c->step + STEP_BLOCK);
+        if (c->s.energy_every) n_end = std::min(n_end, (c->step / c->s.energy_every + 1) * c->s.energy_every);
+        const int g = group_of(c);
+        ht[g * srv->max_slots + cnt[g]] = make_task(c, total[g], n_end);
+        total[g] += ht[g * srv->max_slots + cnt[g]].nblocks;
+        ++cnt[g];
+        steps = std::max(steps, n_end - c->step);
+    }
+    if (!steps) return SBQA_OK;
+    for (int g = 0; g < NGROUPS; ++g) hh[g] = GroupHeader{cnt[g], total[g]};
+    HIP_CHECK_SERVE(hipMemcpyAsync(srv->d_hdr, hh, sizeof(GroupHeader) * NGROUPS, hipMemcpyHostToDevice, srv->stream));
+    HIP_CHECK_SERVE(hipMemcpyAsync(srv->d_tasks, ht, sizeof(GroupTask) * NGROUPS * srv->max_slots,
+                                   hipMemcpyHostToDevice, srv->stream));
+    HIP_CHECK_SERVE(hipEventRecord(srv->h_free[parity], srv->stream));
+    for (uint32_t off = 0; off < steps; ++off)
+        for (int g = 0; g < NGROUPS; ++g) {
+            if (!cnt[g]) continue;
+            const GroupHeader *dh = srv->d_hdr + g;
+            const GroupTask *dt = srv->d_tasks + (size_t)g * srv->max_slots;
+            if (g < 9) {
+                const int mbw = (g % 3 == 0) ? 1 : (g % 3 == 1) ? 2 : 4;
+                HIP_CHECK_SERVE(launch_group_dense((Path)(g / 3), mbw, dh, dt, std::min(total[g], DENSE_GRID_CAP),
+                                                   (int)off, srv->stream));
+            } else {
+                const int q = g - 9;
+                HIP_CHECK_SERVE(launch_group_csr(q >= 2, q & 1, dh, dt, std::min(total[g], CSR_GRID_CAP), (int)off,
+                                                 srv->stream));
+            }
+        }
+    for (Slot &sl : slots) {
+        sbqa_ctx *c = sl.ctx;
+        if (!c || c->step >= c->s.steps) continue;
+        uint32_t n_end = std::min(c->s.steps, c->step + STEP_BLOCK);
+        if (c->s.energy_every) n_end = std::min(n_end, (c->step / c->s.energy_every + 1) * c->s.energy_every);
+        c->step = n_end;
+        c->cur = (int)(n_end & 1u);
+        if (c->s.energy_every && c->step % c->s.energy_every == 0) {
+            const sbqa_status st = ctx_evaluate(c);
+            if (st != SBQA_OK) return st;
+        }
+    }
+    return SBQA_OK;
+}
+
+// Creator thread: builds the contexts of admitted requests on its own stream
+// and hands them to the scheduler once their device state is complete.
+static void creator(sbqa_server *srv) {
+    (void)hipSetDevice(srv->device);
+    for (;;) {
+        std::unique_ptr<Slot> sl;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            srv->cv_create.wait(lk, [&] { return srv->stop_creator || !srv->create.empty(); });
+            if (srv->create.empty()) break;
+            sl = std::move(srv->create.front());
+            srv->create.pop_front();
+        }
+        Request &r = *sl->req;
+        sbqa_coupling J{};
+        if (r.facts.dense) J.dense = r.dense.data();
+        else {
+            J.row_ptr = r.row_ptr.data();
+            J.col = r.col.data();
+            J.val = r.val.data();
+            J.nnz = (int64_t)r.col.size();
+        }
+        sbqa_schedule s = r.s;
+        s.beta = r.beta.empty() ? nullptr : r.beta.data();
+        s.alpha = r.alpha.empty() ? nullptr : r.alpha.data();
+        s.jp_table = r.jp_table.empty() ? nullptr : r.jp_table.data();
+        sbqa_status st = ctx_create(&J, r.h.empty() ? nullptr : r.h.data(), r.N, r.R, r.runs, &s, r.facts,
+                                    srv->create_stream, &sl->ctx, false);
+        if (st == SBQA_OK && hipStreamSynchronize(srv->create_stream) != hipSuccess)
+            st = fail(SBQA_EDEVICE, "context set-up did not complete");
+        if (st == SBQA_OK) {
+            sl->ctx->stream = srv->stream;   // later work is ordered with the grouped steps
+        } else {
+            if (sl->ctx) sbqa_destroy(sl->ctx);
+            sl->ctx = nullptr;
+            r.error = last_error();
+            r.create_status = st;
+        }
+        r.dense.clear();
+        r.dense.shrink_to_fit();
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->ready.push_back(std::move(sl));
+        }
+        srv->cv.notify_one();
+    }
+}
+
 static void scheduler(sbqa_server *srv) {
     (void)hipSetDevice(srv->device);
     std::vector<Slot> slots(srv->max_slots);
-    for (int q = 0; q < srv->max_slots; ++q) slots[q].stream = srv->streams[q];
     size_t used = 0;
-    int resident = 0;
+    int admitted = 0, active = 0, parity = 0;
     for (;;) {
-        // ---- admission (FIFO, budget and slots)
+        // ---- admission (FIFO, budget and slots) and hand-over of built contexts
+        std::deque<std::unique_ptr<Slot>> got;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
-            if (resident == 0) {
-                srv->cv.wait(lk, [&] { return srv->stop || !srv->queue.empty(); });
-                if (srv->stop && srv->queue.empty()) break;
+            if (active == 0) {
+                srv->cv.wait(lk, [&] {
+                    return srv->stop || !srv->ready.empty() ||
+                           (!srv->queue.empty() && admitted < srv->max_slots &&
+                            used + srv->queue.front()->bytes <= srv->budget);
+                });
+                if (srv->stop && srv->queue.empty() && admitted == 0) break;
             }
             if (srv->stop) srv->queue.clear();
-            while (!srv->queue.empty() && resident < srv->max_slots && used + srv->queue.front()->bytes <= srv->budget) {
-                std::unique_ptr<Request> rq = std::move(srv->queue.front());
+            bool pushed = false;
+            while (!srv->queue.empty() && admitted < srv->max_slots && used + srv->queue.front()->bytes <= srv->budget) {
+                std::unique_ptr<Slot> sl(new Slot());
+                sl->req = std::move(srv->queue.front());
                 srv->queue.pop_front();
-                int q = 0;
-                while (slots[q].req) ++q;
-                slots[q].req = std::move(rq);
-                slots[q].bytes = slots[q].req->bytes;
-                used += slots[q].bytes;
-                ++resident;
+                sl->bytes = sl->req->bytes;
+                used += sl->bytes;
+                ++admitted;
+                srv->create.push_back(std::move(sl));
+                pushed = true;
             }
+            if (pushed) srv->cv_create.notify_one();
+            got.swap(srv->ready);
         }
         auto t0 = Clock::now();
-        // ---- create newly admitted contexts
-        for (Slot &sl : slots) {
-            if (!sl.req || sl.ctx) continue;
-            Request &r = *sl.req;
-            sbqa_coupling J{};
-            if (r.facts.dense) J.dense = r.dense.data();
-            else {
-                J.row_ptr = r.row_ptr.data();
-                J.col = r.col.data();
-                J.val = r.val.data();
-                J.nnz = (int64_t)r.col.size();
-            }
-            sbqa_schedule s = r.s;
-            s.beta = r.beta.empty() ? nullptr : r.beta.data();
-            s.alpha = r.alpha.empty() ? nullptr : r.alpha.data();
-            s.jp_table = r.jp_table.empty() ? nullptr : r.jp_table.data();
-            sbqa_status st = ctx_create(&J, r.h.empty() ? nullptr : r.h.data(), r.N, r.R, r.runs, &s, r.facts, sl.stream,
-                                        &sl.ctx, false);
-            if (st != SBQA_OK) {
-                sl.ctx = nullptr;
-                finish(srv, sl, st, last_error());
-                used -= sl.bytes;
-                sl.req.reset();
-                --resident;
+        for (std::unique_ptr<Slot> &sp : got) {
+            if (!sp->ctx) {
+                finish(srv, *sp, sp->req->create_status, sp->req->error.c_str());
+                used -= sp->bytes;
+                --admitted;
                 continue;
             }
-            // free what the estimate did not cover
-            r.dense.clear(); r.dense.shrink_to_fit();
+            int q = 0;
+            while (slots[q].req) ++q;
+            slots[q] = std::move(*sp);
+            ++active;
         }
-        // ---- one step block for every resident instance (overlapping streams)
-        for (Slot &sl : slots) {
-            if (!sl.ctx) continue;
-            const uint32_t left = sl.ctx->s.steps - sl.ctx->step;
-            const uint32_t n = left < STEP_BLOCK ? left : STEP_BLOCK;
-            sbqa_status st = ctx_step(sl.ctx, n);
-            if (st != SBQA_OK) {
-                finish(srv, sl, st, last_error());
+        // ---- one step block for every resident instance (grouped launches)
+        const sbqa_status st = step_block(srv, slots, parity);
+        parity ^= 1;
+        if (st != SBQA_OK) {
+            const std::string msg = last_error();
+            for (Slot &sl : slots) {
+                if (!sl.req) continue;
+                finish(srv, sl, st, msg.c_str());
                 used -= sl.bytes;
                 sl.req.reset();
-                --resident;
+                --admitted;
+                --active;
             }
         }
         // ---- retire finished instances
@@ -176,7 +353,8 @@ static void scheduler(sbqa_server *srv) {
             finish(srv, sl, SBQA_OK, nullptr);
             used -= sl.bytes;
             sl.req.reset();
-            --resident;
+            --admitted;
+            --active;
         }
         {
             std::lock_guard<std::mutex> lk(srv->mu);
@@ -185,6 +363,20 @@ static void scheduler(sbqa_server *srv) {
     }
     for (Slot &sl : slots)
         if (sl.ctx) sbqa_destroy(sl.ctx);
+}
+
+static void release(sbqa_server *srv) {
+    if (srv->stream) (void)hipStreamSynchronize(srv->stream);
+    for (int q = 0; q < 2; ++q) {
+        if (srv->h_tasks[q]) (void)hipHostFree(srv->h_tasks[q]);
+        if (srv->h_hdr[q]) (void)hipHostFree(srv->h_hdr[q]);
+        if (srv->h_free[q]) (void)hipEventDestroy(srv->h_free[q]);
+    }
+    if (srv->d_tasks) (void)hipFree(srv->d_tasks);
+    if (srv->d_hdr) (void)hipFree(srv->d_hdr);
+    if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    if (srv->create_stream) (void)hipStreamDestroy(srv->create_stream);
+    delete srv;
 }
 
 extern "C" {
@@ -200,17 +392,22 @@ sbqa_status sbqa_server_create(size_t hbm_budget_bytes, int32_t max_slots, sbqa_
     srv->max_slots = max_slots;
     hipError_t e = hipGetDevice(&srv->device);
     if (e != hipSuccess) { delete srv; return fail(SBQA_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e)); }
-    for (int q = 0; q < max_slots; ++q) {
-        hipStream_t st;
-        e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-        if (e != hipSuccess) {
-            for (hipStream_t x : srv->streams) (void)hipStreamDestroy(x);
-            delete srv;
-            return fail(SBQA_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e));
-        }
-        srv->streams.push_back(st);
+    const size_t ntask = (size_t)NGROUPS * max_slots;
+    e = hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->create_stream, hipStreamNonBlocking);
+    for (int q = 0; q < 2 && e == hipSuccess; ++q) {
+        e = hipHostMalloc((void **)&srv->h_tasks[q], sizeof(GroupTask) * ntask, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipHostMalloc((void **)&srv->h_hdr[q], sizeof(GroupHeader) * NGROUPS, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->h_free[q], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipMalloc(&srv->d_tasks, sizeof(GroupTask) * ntask);
+    if (e == hipSuccess) e = hipMalloc(&srv->d_hdr, sizeof(GroupHeader) * NGROUPS);
+    if (e != hipSuccess) {
+        release(srv);
+        return fail(e == hipErrorOutOfMemory ? SBQA_ENOMEM : SBQA_EDEVICE, "server set-up: %s", hipGetErrorString(e));
     }
     srv->worker = std::thread(scheduler, srv);
+    srv->creator = std::thread(creator, srv);
     *out = srv;
     return SBQA_OK;
 }
@@ -291,9 +488,16 @@ void sbqa_server_destroy(sbqa_server *srv) {
         srv->stop = true;
     }
     srv->cv.notify_all();
+    // the scheduler finishes every admitted instance (the creator keeps
+    // building the admitted ones meanwhile), then the creator stops
     if (srv->worker.joinable()) srv->worker.join();
-    for (hipStream_t st : srv->streams) (void)hipStreamDestroy(st);
-    delete srv;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop_creator = true;
+    }
+    srv->cv_create.notify_all();
+    if (srv->creator.joinable()) srv->creator.join();
+    release(srv);
 }
 
 }  // extern "C"
