@@ -153,6 +153,9 @@ struct sbqa_server {
     hipEvent_t h_free[2] = {nullptr, nullptr};   // the copy out of host table q has completed
     GroupTask *d_tasks = nullptr;
     GroupHeader *d_hdr = nullptr;
+    // full step blocks are replayed from HIP graphs, one per set of groups
+    // present (the kernels read membership from the task table)
+    std::map<uint32_t, hipGraphExec_t> graphs;
     // stats (guarded by mu)
     uint64_t completed = 0;
     double updates = 0.0;
@@ -209,21 +212,51 @@ static sbqa_status step_block(sbqa_server *srv, std::vector<Slot> &slots, int pa
     HIP_CHECK_SERVE(hipMemcpyAsync(srv->d_tasks, ht, sizeof(GroupTask) * NGROUPS * srv->max_slots,
                                    hipMemcpyHostToDevice, srv->stream));
     HIP_CHECK_SERVE(hipEventRecord(srv->h_free[parity], srv->stream));
-    for (uint32_t off = 0; off < steps; ++off)
-        for (int g = 0; g < NGROUPS; ++g) {
-            if (!cnt[g]) continue;
-            const GroupHeader *dh = srv->d_hdr + g;
-            const GroupTask *dt = srv->d_tasks + (size_t)g * srv->max_slots;
-            if (g < 9) {
-                const int mbw = (g % 3 == 0) ? 1 : (g % 3 == 1) ? 2 : 4;
-                HIP_CHECK_SERVE(launch_group_dense((Path)(g / 3), mbw, dh, dt, std::min(total[g], DENSE_GRID_CAP),
-                                                   (int)off, srv->stream));
-            } else {
-                const int q = g - 9;
-                HIP_CHECK_SERVE(launch_group_csr(q >= 2, q & 1, dh, dt, std::min(total[g], CSR_GRID_CAP), (int)off,
-                                                 srv->stream));
+    uint32_t mask = 0;
+    for (int g = 0; g < NGROUPS; ++g)
+        if (cnt[g]) mask |= 1u << g;
+    // full grids (capped) inside graphs, so that a graph serves any membership
+    auto launch_all = [&](uint32_t nsteps, bool full_grid) -> sbqa_status {
+        for (uint32_t off = 0; off < nsteps; ++off)
+            for (int g = 0; g < NGROUPS; ++g) {
+                if (!(mask & (1u << g))) continue;
+                const GroupHeader *dh = srv->d_hdr + g;
+                const GroupTask *dt = srv->d_tasks + (size_t)g * srv->max_slots;
+                if (g < 9) {
+                    const int mbw = (g % 3 == 0) ? 1 : (g % 3 == 1) ? 2 : 4;
+                    const int grid = full_grid ? DENSE_GRID_CAP : std::min(total[g], DENSE_GRID_CAP);
+                    HIP_CHECK_SERVE(launch_group_dense((Path)(g / 3), mbw, dh, dt, grid, (int)off, srv->stream));
+                } else {
+                    const int q = g - 9;
+                    const int grid = full_grid ? CSR_GRID_CAP : std::min(total[g], CSR_GRID_CAP);
+                    HIP_CHECK_SERVE(launch_group_csr(q >= 2, q & 1, dh, dt, grid, (int)off, srv->stream));
+                }
             }
+        return SBQA_OK;
+    };
+    if (steps == STEP_BLOCK) {
+        auto it = srv->graphs.find(mask);
+        if (it == srv->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            HIP_CHECK_SERVE(hipStreamBeginCapture(srv->stream, hipStreamCaptureModeThreadLocal));
+            const sbqa_status st = launch_all(STEP_BLOCK, true);
+            const hipError_t e = hipStreamEndCapture(srv->stream, &graph);
+            if (st != SBQA_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            HIP_CHECK_SERVE(e);
+            const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIP_CHECK_SERVE(ei);
+            it = srv->graphs.emplace(mask, exec).first;
         }
+        HIP_CHECK_SERVE(hipGraphLaunch(it->second, srv->stream));
+    } else {
+        const sbqa_status st = launch_all(steps, false);
+        if (st != SBQA_OK) return st;
+    }
     for (Slot &sl : slots) {
         sbqa_ctx *c = sl.ctx;
         if (!c || c->step >= c->s.steps) continue;
@@ -367,6 +400,7 @@ static void scheduler(sbqa_server *srv) {
 
 static void release(sbqa_server *srv) {
     if (srv->stream) (void)hipStreamSynchronize(srv->stream);
+    for (auto &kv : srv->graphs) (void)hipGraphExecDestroy(kv.second);
     for (int q = 0; q < 2; ++q) {
         if (srv->h_tasks[q]) (void)hipHostFree(srv->h_tasks[q]);
         if (srv->h_hdr[q]) (void)hipHostFree(srv->h_hdr[q]);

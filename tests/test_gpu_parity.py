@@ -439,6 +439,50 @@ def test_best_energy_statistics_256_seeds(sb, orc):
 
 
 # -------------------------------------------------------------------- serving
+def test_serving_graph_blocks_alone_equals_mix(sb):
+    """Longer schedules (several full step blocks, replayed from a captured
+    graph while membership changes as instances finish at different steps,
+    plus partial blocks and energy tracking): every result equals the
+    instance's standalone run bit-for-bit."""
+    rng = np.random.default_rng(80)
+    items = []
+    for q in range(7):
+        N = int(rng.choice([200, 300, 512]))
+        steps = int(rng.choice([150, 200, 333]))
+        ee = 0 if q % 3 else 50
+        if q % 2 == 0:
+            J, csr = inst.sk_pm1(N, 800 + q), None
+        else:
+            N -= N % 2
+            E = inst.regular_graph(N, int(rng.integers(3, 7)), 810 + q)
+            J, csr = None, inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 820 + q))
+        items.append((J, csr, dict(R=8, runs=2, steps=steps, seed=830 + q, jp_kind=sb.JP_PAPER, energy_every=ee)))
+    alone = []
+    for J, csr, kw in items:
+        ctx = sb.sbqa_create(J=J, csr=csr, loop_kernel=sb.LOOP_STREAM, **kw)
+        sb.sbqa_step(ctx, kw["steps"])
+        alone.append(sb.sbqa_best(ctx))
+        sb.sbqa_destroy(ctx)
+    srv = sb.sbqa_server_create(1 << 30, 4)
+    import time
+    for rep in range(2):      # the second round replays the graphs captured in the first
+        tickets = [sb.sbqa_submit(srv, J=J, csr=csr, **kw) for J, csr, kw in items]
+        got = {}
+        t0 = time.time()
+        while len(got) < len(tickets) and time.time() - t0 < 120:
+            for t in tickets:
+                if t not in got:
+                    r = sb.sbqa_poll(srv, t)
+                    if r is not None:
+                        got[t] = r
+            time.sleep(0.005)
+        assert len(got) == len(tickets)
+        for t, (Ea, sa) in zip(tickets, alone):
+            Em, sm, _ = got[t]
+            assert np.array_equal(Ea, Em) and np.array_equal(sa, sm)
+    sb.sbqa_server_destroy(srv)
+
+
 def test_serving_alone_equals_mix(sb):
     """Continuous batching: instances of mixed size and density submitted to a
     server (small budget, 3 slots, so some wait) give exactly the results they
