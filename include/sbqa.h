@@ -127,12 +127,17 @@ typedef struct {
     uint32_t energy_every;   /* 0: best over the final state only; K > 0: also
                                 track the best after every K-th step              */
     int32_t loop_kernel;     /* sbqa_loop_kernel                                   */
+    int32_t dense_tile;      /* dense path: replica columns per workgroup tile,
+                                64, 128 or 256; 0 = autotuned (each candidate's
+                                step timed once per process on scratch buffers
+                                of the instance's shape; every tile gives the
+                                same bits)                                        */
 } sbqa_schedule;
 
 /* Defaults: steps 1000, dt 0.5, a0 1, c0 auto, ternary f, delta_max 0.7,
  * PAPER schedule with gamma0_over_R 1, beta in [0.5,1.5], alpha in [0.5,1.0]
  * (Sec. II.B), seed 0, init_amp 0.1, precision AUTO, energy_every 0,
- * loop_kernel AUTO. */
+ * loop_kernel AUTO, dense_tile 0 (autotuned). */
 sbqa_schedule sbqa_schedule_default(void);
 
 /* Context information (sbqa_info). */
@@ -147,6 +152,7 @@ typedef struct {
     size_t device_bytes;     /* device memory held by the context                  */
     int32_t resident;        /* 1 when steps run in a resident loop
                                 (sbqa_loop_kernel), 0 otherwise                   */
+    int32_t tile_cols;       /* dense path: replica columns per workgroup tile   */
 } sbqa_info_t;
 
 /*

@@ -42,13 +42,15 @@ class Schedule(ct.Structure):
                 ("beta_lo", ct.c_double), ("beta_hi", ct.c_double), ("alpha_lo", ct.c_double),
                 ("alpha_hi", ct.c_double), ("beta", ct.c_void_p), ("alpha", ct.c_void_p),
                 ("jp_table", ct.c_void_p), ("seed", ct.c_uint64), ("init_amp", ct.c_double),
-                ("precision", ct.c_int32), ("energy_every", ct.c_uint32), ("loop_kernel", ct.c_int32)]
+                ("precision", ct.c_int32), ("energy_every", ct.c_uint32), ("loop_kernel", ct.c_int32),
+                ("dense_tile", ct.c_int32)]
 
 
 class Info(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("R", ct.c_int32), ("runs", ct.c_int32), ("steps", ct.c_uint32),
                 ("step", ct.c_uint32), ("path", ct.c_int32), ("fmode", ct.c_int32), ("c0", ct.c_double),
-                ("j_integral", ct.c_int32), ("device_bytes", ct.c_size_t), ("resident", ct.c_int32)]
+                ("j_integral", ct.c_int32), ("device_bytes", ct.c_size_t), ("resident", ct.c_int32),
+                ("tile_cols", ct.c_int32)]
 
 
 def _load() -> ct.CDLL:
@@ -240,7 +242,7 @@ def sbqa_info(ctx: Context) -> dict:
     _check(lib.sbqa_info(ctx.ptr, ct.byref(i)))
     return {"N": i.N, "R": i.R, "runs": i.runs, "steps": i.steps, "step": i.step,
             "path": PATHS[i.path], "fmode": i.fmode, "c0": i.c0, "j_integral": bool(i.j_integral),
-            "device_bytes": i.device_bytes, "resident": bool(i.resident)}
+            "device_bytes": i.device_bytes, "resident": bool(i.resident), "tile_cols": i.tile_cols}
 
 
 def sbqa_sync(ctx: Context) -> None:

@@ -9,7 +9,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <thread>
 #include <vector>
@@ -129,6 +132,8 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     if (!std::isfinite(s->delta_max) || s->delta_max < 0) return fail(SBQA_EINVAL, "delta_max must be finite and >= 0");
     if (s->precision < 0 || s->precision > 3) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
     if (s->loop_kernel < 0 || s->loop_kernel > 2) return fail(SBQA_EINVAL, "unknown loop_kernel %d", s->loop_kernel);
+    if (s->dense_tile != 0 && s->dense_tile != 64 && s->dense_tile != 128 && s->dense_tile != 256)
+        return fail(SBQA_EINVAL, "dense_tile must be 0 (autotuned), 64, 128 or 256 (got %d)", s->dense_tile);
     if (!(s->init_amp >= 0) || !std::isfinite(s->init_amp)) return fail(SBQA_EINVAL, "init_amp must be finite and >= 0");
     switch (s->jp_kind) {
         case SBQA_JP_LINEAR:
@@ -239,7 +244,8 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
     const int64_t C = (int64_t)R * runs;
     L->C = (int)C;
     L->Cp = (int)round_up(C, GEMM_BM);
-    L->mbw = dense_mbw((int)C);
+    // the operand is sized for the widest tile the autotuner may pick
+    L->mbw = 4;
     L->Cg = (int)round_up(C, 64 * L->mbw);
     L->Np = (int)round_up(N, f.path == PATH_CSR ? GEMM_BN : dense_pad(f.path));
     L->Cs = (int)round_up(C, 4);
@@ -272,6 +278,95 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
     b += (int64_t)runs * (int64_t)0;  // schedule tables counted by the caller (steps known there)
     b += C * 8 + (int64_t)runs * (16 + N);                                // E, best
     L->bytes = (size_t)b;
+}
+
+void set_tile(Layout *L, int mbw) {
+    L->mbw = mbw;
+    L->Cg = (int)round_up(L->C, 64 * mbw);
+}
+
+// ------------------------------------------------------------ tile autotuner
+// Dense workgroup tile: 64 * mbw replica columns (mbw m-blocks per wave).
+// Candidates that pad C by at most 2x are timed once per (path, C, Np rounded
+// up to a power of two) and process, on scratch buffers of the instance's
+// shape (the MFMA step's time does not depend on the values); the fastest is
+// kept. Every tile sums each field in the same K order, so the choice never
+// changes results.
+static int tune_dense_mbw(Path path, int C, int Np, hipStream_t st) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, int> cache;
+    int npb = 128;
+    while (npb < Np) npb *= 2;
+    const auto key = std::make_tuple((int)path, C, npb);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) return it->second;
+    }
+    const int fallback = dense_mbw(C);
+    std::vector<int> cand;
+    for (int m : {1, 2, 4})
+        if (m == fallback || round_up(C, 64 * m) <= 2 * round_up(C, 64)) cand.push_back(m);
+    int best = fallback;
+    if (cand.size() > 1) {
+        const int eb = path_ebytes(path), planes = path == PATH_BF16X3 ? 2 : 1;
+        const int Cgm = (int)round_up(C, 256), nkc = Np * eb / 128;
+        std::vector<void *> bufs;
+        auto grab = [&](size_t bytes) -> void * {
+            void *p = nullptr;
+            if (hipMalloc(&p, std::max<size_t>(bytes, 256)) != hipSuccess) return nullptr;
+            bufs.push_back(p);
+            (void)hipMemsetAsync(p, 0, std::max<size_t>(bytes, 256), st);
+            return p;
+        };
+        const size_t jb = (size_t)Np * Np * eb, gb = (size_t)Cgm * Np * eb, sb = (size_t)C * Np * 4;
+        DenseStepArgs a{};
+        a.N = Np;
+        a.Np = Np;
+        a.R = 1;
+        a.C = C;
+        a.nkc = nkc;
+        a.J = (const uint8_t *)grab(jb);
+        a.J_lo = planes == 2 ? (const uint8_t *)grab(jb) : nullptr;
+        a.g = (const uint8_t *)grab(gb);
+        a.g_lo = planes == 2 ? (const uint8_t *)grab(gb) : nullptr;
+        a.g_next = (uint8_t *)grab(gb);
+        a.g_next_lo = planes == 2 ? (uint8_t *)grab(gb) : nullptr;
+        a.h = (const float *)grab((size_t)Np * 4);
+        a.x_in = (const float *)grab(sb);
+        a.x_out = (float *)grab(sb);
+        a.y = (float *)grab(sb);
+        a.jp = (const float *)grab((size_t)C * 4);
+        a.jp_stride = 1;
+        a.fmode = 0;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        bool ok = a.J && a.g && a.g_next && a.h && a.x_in && a.x_out && a.y && a.jp && (planes == 1 || (a.J_lo && a.g_lo && a.g_next_lo)) &&
+                  hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess;
+        float best_ms = 0.0f;
+        for (int m : cand) {
+            if (!ok) break;
+            const int Cg = (int)round_up(C, 64 * m);
+            ok = launch_dense_step(path, EPI_UPDATE, m, Cg, a, st) == hipSuccess;   // warm-up
+            ok = ok && hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < 3 && ok; ++r) ok = launch_dense_step(path, EPI_UPDATE, m, Cg, a, st) == hipSuccess;
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.0f;
+            ok = ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            if (ok && (m == cand.front() || ms < best_ms)) {
+                best_ms = ms;
+                best = m;
+            }
+        }
+        (void)hipStreamSynchronize(st);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        for (void *p : bufs) (void)hipFree(p);
+        if (!ok) best = fallback;
+        (void)hipGetLastError();
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    cache[key] = best;
+    return best;
 }
 
 size_t instance_bytes(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, uint32_t steps) {
@@ -652,6 +747,8 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
                         allow_resident ? why.c_str() : "contexts of the serving loop step one launch at a time");
         }
     }
+    if (facts.path != PATH_CSR)
+        set_tile(&c->L, s->dense_tile ? s->dense_tile / 64 : tune_dense_mbw(facts.path, c->L.C, c->L.Np, c->stream));
     st = ctx_upload(c, J, h);
     if (st == SBQA_OK) {
         const bool sm = facts.path == PATH_CSR;
@@ -1002,6 +1099,7 @@ sbqa_status sbqa_info(sbqa_ctx *c, sbqa_info_t *info) {
     info->j_integral = c->facts.integral ? 1 : 0;
     info->device_bytes = c->bytes;
     info->resident = c->resident ? 1 : 0;
+    info->tile_cols = c->facts.path == PATH_CSR ? 0 : 64 * c->L.mbw;
     return SBQA_OK;
 }
 

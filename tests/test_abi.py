@@ -49,6 +49,7 @@ def test_schedule_default_matches_paper_ranges(abi):
     assert (s.beta_lo, s.beta_hi) == (0.5, 1.5)      # Sec. II.B
     assert (s.alpha_lo, s.alpha_hi) == (0.5, 1.0)
     assert s.jp_kind == abi.JP_PAPER and s.fmode == abi.F_TERNARY
+    assert s.loop_kernel == abi.LOOP_AUTO and s.dense_tile == 0   # resident loops and tiles chosen by the library
 
 
 def _expect(abi, status, **kw):
@@ -76,6 +77,8 @@ def test_validation_errors(abi):
     # FP8 needs J in {-1,0,1} and a discrete f
     _expect(abi, abi.EINVAL, J=J * 2, R=2, runs=2, precision=abi.PREC_FP8)
     _expect(abi, abi.EINVAL, J=J, R=2, runs=2, precision=abi.PREC_FP8, fmode=abi.F_BALLISTIC)
+    assert "dense_tile" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, dense_tile=96)
+    assert "loop_kernel" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, loop_kernel=7)
     # CSR: asymmetric, out of range, unsorted, bf16 precision
     E = inst.regular_graph(20, 3, 2)
     rp, col, val = inst.edges_to_csr(20, E, inst.gaussian_edges(len(E), 3))

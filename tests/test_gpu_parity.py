@@ -228,6 +228,31 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
     _log("  %s: wall-boundary elements excluded: %d" % (name, excluded))
 
 
+@pytest.mark.parametrize("prec,fmode,coup", [("PREC_FP32", 2, "gauss"), ("PREC_BF16X3", 2, "gauss"),
+                                              ("PREC_FP8", 0, "sk")])
+def test_dense_tiles_identical(sb, prec, fmode, coup):
+    """Every dense workgroup tile (64, 128 or 256 replica columns; the
+    autotuner picks one) sums each field in the same K order, so trajectories
+    agree bit-for-bit, real-valued couplings included."""
+    N, R, runs, S = 300, 8, 20, 30
+    J = inst.dense_gaussian(N, 41) if coup == "gauss" else inst.sk_pm1(N, 41)
+    h = inst.gaussian_fields(N, 0.3, 42)
+    _log("dense tiles %s N=%d C=%d" % (prec, N, R * runs))
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.2, 43)
+    out = []
+    for tile in (64, 128, 256, 0):
+        ctx = _ctx(sb, J=J, h=h, R=R, runs=runs, steps=S, fmode=fmode, precision=getattr(sb, prec), dense_tile=tile,
+                   loop_kernel=sb.LOOP_STREAM)
+        info = sb.sbqa_info(ctx)
+        assert info["tile_cols"] == tile or (tile == 0 and info["tile_cols"] in (64, 128, 256))
+        sb.sbqa_set_state(ctx, X0, Y0)
+        sb.sbqa_step(ctx, S)
+        out.append(sb.sbqa_get_state(ctx) + (sb.sbqa_fields(ctx),))
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
+
+
 def test_fp8_and_fp32_trajectories_identical(sb):
     """J in {-1,+1} with ternary f: fields are exact integers in fp8 and fp32,
     so whole trajectories agree bit-for-bit."""
