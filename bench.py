@@ -11,7 +11,8 @@ contraction, update). The timed region is K steps of a fresh solve followed by
 the readout (energies of all replicas and the best per run). value =
 N*R*runs*K / seconds. The dominant kernel's average duration comes from HIP
 events around every step on the context's stream; its roofline uses the
-algorithmic bytes per launch stated in the design doc.
+algorithmic bytes (HBM-bound kernels) or operations (MFMA and VALU-bound
+kernels) per launch computed below.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
                        [--no-cpu-baseline]
@@ -30,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PEAK = {"fp8": 5030.0, "bf16": 2520.0, "fp32": 157.3, "fp64": 78.6}  # TFLOP/s dense MFMA
+PEAK = {"fp8": 5030.0, "int8": 5030.0, "bf16": 2520.0, "fp32": 157.3, "fp64": 78.6}  # T(FL)OP/s dense MFMA
 
 
 def make_workload(name: str):
@@ -47,6 +48,14 @@ def make_workload(name: str):
         N, R, runs, S = 16384, 16, 16, 10000
         return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP8", fmode=0,
                     desc="SK N=16384 J=+-1 (e4m3), R=16 x 16 runs, 10000 steps, ternary f", dtype="fp8")
+    if name in ("sidon_i8", "sidon_fp32"):
+        # integer couplings of the QAC benchmarks (Sidon28 set x 28), dense at the SK size
+        N, R, runs, S = 16384, 16, 16, 10000
+        i8 = name == "sidon_i8"
+        return dict(J=inst.sidon28_dense(N, 3101), h=None, N=N, R=R, runs=runs, S=S,
+                    prec="PREC_INT8" if i8 else "PREC_FP32", fmode=0,
+                    desc="dense N=16384 J in 28 x Sidon28 = {+-8,+-13,+-19,+-28} (%s), R=16 x 16 runs, "
+                         "10000 steps, ternary f" % ("int8" if i8 else "fp32 path"), dtype="int8" if i8 else "f32")
     if name == "sk_fp32":
         N, R, runs, S = 16384, 16, 16, 10000
         return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32", fmode=0,
@@ -97,7 +106,7 @@ def algorithmic_bytes(w, info):
         nnz = len(w["csr"][1])
         # x, y read + write (fp32) + int8 operand written once and read once
         return N * C * (16 + 2) + 4 * (N + 1) + 8 * nnz + 4 * N
-    eb = {"dense_fp8": 1, "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
+    eb = {"dense_fp8": 1, "dense_int8": 1, "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
     # GEMM: J streamed once + operand read once + fp32 field partial written
     return N * N * eb + C * N * eb + C * N * 4
 
@@ -128,6 +137,7 @@ def algorithmic_flops(w):
 KERNEL_SOURCES = {"csr_fp32": "paper_2604_01050_amd/csrc/kernels_csr.hip",
                   "csr_resident": "paper_2604_01050_amd/csrc/kernels_csr.hip",
                   "dense_fp8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
+                  "dense_int8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
                   "dense_fp32": "paper_2604_01050_amd/csrc/kernels_dense.hip",
                   "dense_bf16x3": "paper_2604_01050_amd/csrc/kernels_dense.hip"}
 
@@ -457,8 +467,10 @@ def main():
                                "algorithmic_bytes_per_launch": ab}
         else:
             fl = algorithmic_flops(w)
-            peak = PEAK[{"dense_fp8": "fp8", "dense_fp32": "fp32", "dense_bf16x3": "bf16"}[info["path"]]]
-            out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
+            peak = PEAK[{"dense_fp8": "fp8", "dense_int8": "int8", "dense_fp32": "fp32",
+                         "dense_bf16x3": "bf16"}[info["path"]]]
+            unit = "TOP/s" if info["path"] == "dense_int8" else "TFLOP/s"
+            out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": unit,
                                "frac": fl / avg_s / 1e12 / peak,
                                "traffic": measured_traffic(a.workload, info["path"]), "kernel": "k_dense_step",
                                "avg_step_us": avg_s * 1e6, "algorithmic_flops_per_step": fl}

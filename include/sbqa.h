@@ -63,11 +63,17 @@ typedef enum { SBQA_F_TERNARY = 0, SBQA_F_SIGN = 1, SBQA_F_BALLISTIC = 2 } sbqa_
  *   FP32   fp32 J, fp32 operand, fp32 accumulation (MFMA f32).
  *   FP8    J and f(X) in e4m3, fp32 accumulation. Exact when J is in
  *          {-1,0,+1} and f is ternary or sign; rejected otherwise.
+ *   INT8   J and f(X) in int8, int32 accumulation, each field rounded once to
+ *          fp32. Exact integer sums for integer J with |J| <= 127 (e.g. the
+ *          Sidon28 couplings of the QAC benchmarks, Sec. III, scaled by 28 to
+ *          {8, 13, 19, 28}: 19 has no e4m3 encoding) and f ternary or sign;
+ *          rejected otherwise.
  *   BF16X3 J and f(X) split into bf16 hi + lo; J_hi f_hi + J_hi f_lo + J_lo f_hi
  *          accumulated in fp32 (ballistic / real-valued contraction).
- *   AUTO   FP8 when exact, else FP32. */
+ *   AUTO   with f ternary or sign: FP8 for J in {-1,0,+1}, else INT8 for
+ *          integer J with |J| <= 127, else FP32; with f ballistic: FP32. */
 typedef enum {
-    SBQA_PREC_AUTO = 0, SBQA_PREC_FP32 = 1, SBQA_PREC_FP8 = 2, SBQA_PREC_BF16X3 = 3
+    SBQA_PREC_AUTO = 0, SBQA_PREC_FP32 = 1, SBQA_PREC_FP8 = 2, SBQA_PREC_BF16X3 = 3, SBQA_PREC_INT8 = 4
 } sbqa_prec;
 
 /* Inter-replica coupling schedule J_perp[r][n]:
@@ -145,7 +151,8 @@ typedef struct {
     int32_t N, R, runs;
     uint32_t steps;          /* S                                                  */
     uint32_t step;           /* steps already taken                                */
-    int32_t path;            /* 0 dense fp32, 1 dense fp8, 2 dense bf16x3, 3 csr   */
+    int32_t path;            /* 0 dense fp32, 1 dense fp8, 2 dense bf16x3, 3 csr,
+                                4 dense int8                                     */
     int32_t fmode;
     double c0;               /* c0 actually used                                   */
     int32_t j_integral;      /* 1 when every J_ij and h_i is an integer            */

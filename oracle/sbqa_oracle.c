@@ -10,7 +10,7 @@
  * Source: arXiv 2604.01050, Sec. II.A (Eqs. 1-8), Sec. II.B (auto-tuning),
  * Supplement S1 (Eq. S12, periodic Trotter ring).
  *
- * Conventions (readings where the paper is silent; all listed in the design doc):
+ * Conventions (readings where the paper is silent):
  *  - State X, Y are N x C row-major, C = runs*R, column c = r*R + k holds
  *    replica k of run r.
  *  - Step n (n = 0..S-1) integrates t_n = n*dt -> t_{n+1}; T = S*dt, so the

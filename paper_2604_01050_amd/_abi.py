@@ -16,10 +16,10 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsbqa.so"
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 F_TERNARY, F_SIGN, F_BALLISTIC = 0, 1, 2
-PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3 = 0, 1, 2, 3
+PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8 = 0, 1, 2, 3, 4
 JP_LINEAR, JP_PAPER, JP_TABLE = 0, 1, 2
 LOOP_AUTO, LOOP_STREAM, LOOP_RESIDENT = 0, 1, 2
-PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32"}
+PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32", 4: "dense_int8"}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EBUDGET", -6: "EAGAIN"}
 
 

@@ -1,7 +1,8 @@
 // Dense SBQA kernels for gfx950 (CDNA4, wave64):
 //   * one step of the dense path: the coupling sum of Eq. 7 over all runs and
 //     replicas, Phi^T[c][i] = sum_j f(X)^T[c][j] J[i][j] (J symmetric, zero
-//     diagonal), on MFMA in fp32, e4m3 fp8 or bf16 hi+lo (three products),
+//     diagonal), on MFMA in fp32, e4m3 fp8, int8 (integer J) or bf16 hi+lo
+//     (three products),
 //     with the update of Eqs. 6-7 (pump, Trotter ring, kick, drift, wall) and
 //     the next operand f(X) (Eq. 8) fused into its epilogue;
 //   * the fp64 GEMM of the energies (Eq. 2 at the corners).
@@ -18,10 +19,12 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef int i8v __attribute__((ext_vector_type(8)));
+typedef int i4v __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 
-// e4m3 encodings of the ternary values.
+// e4m3 and int8 encodings of the ternary values.
 constexpr uint8_t FP8_P1 = 0x38, FP8_M1 = 0xB8;
+constexpr uint8_t I8_P1 = 0x01, I8_M1 = 0xFF;
 // E8M0 block scale 2^(127-127) = 1 for the scaled fp8 MFMA.
 constexpr int E8M0_ONE = 127;
 
@@ -152,12 +155,13 @@ __device__ __forceinline__ void store_operand(void *g, void *g_lo, int64_t o, fl
     uint8_t *gb = reinterpret_cast<uint8_t *>(g);
     if constexpr (PATH == PATH_F32) {
         *reinterpret_cast<float4 *>(gb + o) = f;
-    } else if constexpr (PATH == PATH_FP8) {
+    } else if constexpr (PATH == PATH_FP8 || PATH == PATH_I8) {
+        constexpr uint32_t P1 = PATH == PATH_FP8 ? FP8_P1 : I8_P1, M1 = PATH == PATH_FP8 ? FP8_M1 : I8_M1;
         const float v[4] = {f.x, f.y, f.z, f.w};
         uint32_t w = 0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            const uint32_t b = v[e] > 0.0f ? FP8_P1 : (v[e] < 0.0f ? FP8_M1 : 0u);
+            const uint32_t b = v[e] > 0.0f ? P1 : (v[e] < 0.0f ? M1 : 0u);
             w |= b << (8 * e);
         }
         *reinterpret_cast<uint32_t *>(gb + o) = w;
@@ -188,6 +192,7 @@ template <int PATH> struct Terms;
 template <> struct Terms<PATH_F32> { static constexpr int n = 8; };     // 8 x 16x16x4 f32
 template <> struct Terms<PATH_FP8> { static constexpr int n = 1; };     // 1 x 16x16x128 f8f6f4
 template <> struct Terms<PATH_BF16X3> { static constexpr int n = 6; };  // lo*hi, hi*lo, hi*hi x 2 halves
+template <> struct Terms<PATH_I8> { static constexpr int n = 2; };      // 2 x 16x16x64 i8 (K halves)
 
 template <int PATH, int T>
 __device__ __forceinline__ void mma_term(f4 &acc, const Frag32 &a, const Frag32 &b, const Frag32 &a2,
@@ -201,6 +206,17 @@ __device__ __forceinline__ void mma_term(f4 &acc, const Frag32 &a, const Frag32 
         __builtin_memcpy(&av, &a, 32);
         __builtin_memcpy(&bv, &b, 32);
         acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, E8M0_ONE, 0, E8M0_ONE);
+    } else if constexpr (PATH == PATH_I8) {
+        // int32 accumulation, carried in the float accumulator's bits; term T
+        // takes the lane's K bytes of half T (each 16x16x64 product pairs the
+        // same lane bytes of both operands, so the two halves cover the
+        // chunk's 128 K exactly once)
+        const uint4 &xs = T ? a.hi : a.lo;
+        const uint4 &ys = T ? b.hi : b.lo;
+        i4v xv, yv;
+        __builtin_memcpy(&xv, &xs, 16);
+        __builtin_memcpy(&yv, &ys, 16);
+        acc = __builtin_bit_cast(f4, __builtin_amdgcn_mfma_i32_16x16x64_i8(xv, yv, __builtin_bit_cast(i4v, acc), 0, 0, 0));
     } else {
         // small products first: lo*hi, hi*lo, then hi*hi; each over both halves
         const Frag32 &x = (T < 2) ? a2 : a;
@@ -220,6 +236,14 @@ template <int PATH> struct Pipe {
 };
 
 __device__ __forceinline__ uint4 ld16(const uint8_t *p) { return *reinterpret_cast<const uint4 *>(p); }
+
+// Field value of one accumulator element (int8 path: the exact int32 sum,
+// rounded once to float32).
+template <int PATH>
+__device__ __forceinline__ float acc_field(float v) {
+    if constexpr (PATH == PATH_I8) return (float)__builtin_bit_cast(int, v);
+    else return v;
+}
 
 // f(integral_constant<int, I>) for I = B..E-1, unrolled at compile time.
 template <int B, int E, class F>
@@ -282,7 +306,7 @@ __device__ __forceinline__ void update_store(const DenseStepArgs &a, int c, int 
     const int64_t o = (int64_t)c * a.Np + i4;
     *reinterpret_cast<float4 *>(a.x_out + o) = make_float4(xo[0], xo[1], xo[2], xo[3]);
     *reinterpret_cast<float4 *>(a.y + o) = make_float4(yo[0], yo[1], yo[2], yo[3]);
-    constexpr int eb = (PATH == PATH_F32) ? 4 : (PATH == PATH_FP8) ? 1 : 2;
+    constexpr int eb = path_ebytes(Path(PATH));
     store_operand<PATH>(a.g_next, a.g_next_lo, tf_offset(c, i4, a.nkc, eb, MBW),
                         make_float4(fo[0], fo[1], fo[2], fo[3]), a.fmode);
 }
@@ -435,7 +459,7 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
 #pragma unroll
         for (int p = 0; p < RBT; ++p)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) T[(4 * g + r) * TS + 16 * p + r16] = acc[mb][p][r];
+            for (int r = 0; r < 4; ++r) T[(4 * g + r) * TS + 16 * p + r16] = acc_field<PATH>(acc[mb][p][r]);
         __syncthreads();
         float4 ph[ITEMS];
         int cc[ITEMS], ii[ITEMS];
@@ -475,8 +499,9 @@ __global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArg
 // task's step n = n_base + offset; tasks past their last step skip.
 // J in the contraction precision, fragment-tiled (groups of DENSE_TN/16 row
 // blocks), from the zero-padded row-major float64 copy: one thread per 4
-// consecutive K elements of a row. e4m3 for ternary J (validated on the host),
-// float32 round-to-nearest, or bf16 hi = rne(J), lo = rne(J - hi) in float64.
+// consecutive K elements of a row. e4m3 for ternary J, int8 for integer J
+// with |J| <= 127 (both validated on the host), float32 round-to-nearest, or
+// bf16 hi = rne(J), lo = rne(J - hi) in float64.
 template <int PATH>
 __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J64, int Np, int nkc,
                                                    uint8_t *__restrict__ Jd, uint8_t *__restrict__ Jd_lo) {
@@ -485,7 +510,7 @@ __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J6
     if (q >= nq) return;
     const int row = (int)(q / (Np / 4)), k4 = (int)(q % (Np / 4)) * 4;
     const double *src = J64 + (int64_t)row * Np + k4;
-    constexpr int eb = (PATH == PATH_F32) ? 4 : (PATH == PATH_FP8) ? 1 : 2;
+    constexpr int eb = path_ebytes(Path(PATH));
     const int64_t o = tf_offset(row, k4, nkc, eb, DENSE_TN / 16);
     if constexpr (PATH == PATH_F32) {
         *reinterpret_cast<float4 *>(Jd + o) = make_float4((float)src[0], (float)src[1], (float)src[2], (float)src[3]);
@@ -496,6 +521,11 @@ __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J6
             const uint32_t b = src[e] > 0.0 ? FP8_P1 : (src[e] < 0.0 ? FP8_M1 : 0u);
             w |= b << (8 * e);
         }
+        *reinterpret_cast<uint32_t *>(Jd + o) = w;
+    } else if constexpr (PATH == PATH_I8) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= ((uint32_t)(int32_t)src[e] & 0xFFu) << (8 * e);
         *reinterpret_cast<uint32_t *>(Jd + o) = w;
     } else {
         uint16_t hi[4], lo[4];
@@ -560,7 +590,7 @@ __global__ __launch_bounds__(256) void k_dense_operand(int Np, int nkc, int mbw,
     const float4 v = *reinterpret_cast<const float4 *>(x + (int64_t)c * Np + i4);
     const float4 f = make_float4(f_value(fmode, v.x, delta), f_value(fmode, v.y, delta),
                                  f_value(fmode, v.z, delta), f_value(fmode, v.w, delta));
-    constexpr int eb = (PATH == PATH_F32) ? 4 : (PATH == PATH_FP8) ? 1 : 2;
+    constexpr int eb = path_ebytes(Path(PATH));
     store_operand<PATH>(g, g_lo, tf_offset(c, i4, nkc, eb, mbw), f, fmode);
 }
 
@@ -606,6 +636,7 @@ hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, cons
         case PATH_F32: return launch_step_path<PATH_F32>(epi, mbw, grid, a, st);
         case PATH_FP8: return launch_step_path<PATH_FP8>(epi, mbw, grid, a, st);
         case PATH_BF16X3: return launch_step_path<PATH_BF16X3>(epi, mbw, grid, a, st);
+        case PATH_I8: return launch_step_path<PATH_I8>(epi, mbw, grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }
@@ -619,6 +650,7 @@ hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void 
         case PATH_F32: hipLaunchKernelGGL(k_convert_j<PATH_F32>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
         case PATH_FP8: hipLaunchKernelGGL(k_convert_j<PATH_FP8>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
         case PATH_BF16X3: hipLaunchKernelGGL(k_convert_j<PATH_BF16X3>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
+        case PATH_I8: hipLaunchKernelGGL(k_convert_j<PATH_I8>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -639,6 +671,7 @@ hipError_t launch_group_dense(Path path, int mbw, const GroupHeader *hdr, const 
         case PATH_F32: SBQA_GD_PATH(PATH_F32); break;
         case PATH_FP8: SBQA_GD_PATH(PATH_FP8); break;
         case PATH_BF16X3: SBQA_GD_PATH(PATH_BF16X3); break;
+        case PATH_I8: SBQA_GD_PATH(PATH_I8); break;
         default: return hipErrorInvalidValue;
     }
 #undef SBQA_GD_PATH
@@ -654,6 +687,7 @@ hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int 
         case PATH_F32: hipLaunchKernelGGL(k_dense_operand<PATH_F32>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_FP8: hipLaunchKernelGGL(k_dense_operand<PATH_FP8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_BF16X3: hipLaunchKernelGGL(k_dense_operand<PATH_BF16X3>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
+        case PATH_I8: hipLaunchKernelGGL(k_dense_operand<PATH_I8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -63,7 +63,7 @@ struct DenseScan {
     int bad = 0;              // 1 diagonal, 2 not finite, 3 not symmetric
     int64_t i = 0, j = 0;
     bool integral = true, ternary = true;
-    double ss = 0.0;
+    double ss = 0.0, maxabs = 0.0;
 };
 
 static DenseScan scan_dense(const double *A, int64_t N) {
@@ -84,6 +84,7 @@ static DenseScan scan_dense(const double *A, int64_t N) {
                 }
                 if (v != std::floor(v) || std::fabs(v) > 2147483647.0) r.integral = false;
                 if (!(v == 0.0 || v == 1.0 || v == -1.0)) r.ternary = false;
+                r.maxabs = std::max(r.maxabs, std::fabs(v));
                 srow += v * v;
             }
             r.ss += srow;
@@ -114,6 +115,7 @@ static DenseScan scan_dense(const double *A, int64_t N) {
         if (r.bad && !out.bad) { out.bad = r.bad; out.i = r.i; out.j = r.j; }
         out.integral = out.integral && r.integral;
         out.ternary = out.ternary && r.ternary;
+        out.maxabs = std::max(out.maxabs, r.maxabs);
         out.ss += r.ss;
     }
     return out;
@@ -130,7 +132,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     if (!std::isfinite(s->c0)) return fail(SBQA_EINVAL, "c0 must be finite");
     if (s->fmode < 0 || s->fmode > 2) return fail(SBQA_EINVAL, "unknown fmode %d", s->fmode);
     if (!std::isfinite(s->delta_max) || s->delta_max < 0) return fail(SBQA_EINVAL, "delta_max must be finite and >= 0");
-    if (s->precision < 0 || s->precision > 3) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
+    if (s->precision < SBQA_PREC_AUTO || s->precision > SBQA_PREC_INT8) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
     if (s->loop_kernel < 0 || s->loop_kernel > 2) return fail(SBQA_EINVAL, "unknown loop_kernel %d", s->loop_kernel);
     if (s->dense_tile != 0 && s->dense_tile != 64 && s->dense_tile != 128 && s->dense_tile != 256)
         return fail(SBQA_EINVAL, "dense_tile must be 0 (autotuned), 64, 128 or 256 (got %d)", s->dense_tile);
@@ -164,10 +166,11 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     const bool csr = J->row_ptr || J->col || J->val;
     if (dense == csr) return fail(SBQA_EINVAL, "exactly one of J.dense or the CSR arrays must be given");
     bool integral = true, ternary = true;
-    double ss = 0.0;
+    double ss = 0.0, maxabs = 0.0;
     auto note = [&](double v) {
         if (v != std::floor(v) || std::fabs(v) > 2147483647.0) integral = false;
         if (!(v == 0.0 || v == 1.0 || v == -1.0)) ternary = false;
+        maxabs = std::max(maxabs, std::fabs(v));
     };
     if (dense) {
         if ((int64_t)N * N > (int64_t)1 << 32) return fail(SBQA_EINVAL, "dense N too large");
@@ -181,6 +184,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
         }
         integral = d.integral;
         ternary = d.ternary;
+        maxabs = d.maxabs;
         ss = d.ss;
         facts->nnz = 0;
     } else {
@@ -212,6 +216,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
         }
         facts->nnz = J->nnz;
     }
+    facts->int8 = integral && maxabs <= 127.0;   // J only: h enters in fp32
     if (h)
         for (int32_t i = 0; i < N; ++i) {
             if (!std::isfinite(h[i])) return fail(SBQA_EINVAL, "h[%d] not finite", i);
@@ -229,12 +234,23 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
             return fail(SBQA_EINVAL, "CSR couplings support only fp32 precision");
         facts->path = PATH_CSR;
     } else {
-        if (prec == SBQA_PREC_AUTO) prec = (ternary && s->fmode != SBQA_F_BALLISTIC) ? SBQA_PREC_FP8 : SBQA_PREC_FP32;
+        if (prec == SBQA_PREC_AUTO)
+            prec = s->fmode == SBQA_F_BALLISTIC ? SBQA_PREC_FP32
+                   : ternary                    ? SBQA_PREC_FP8
+                   : facts->int8                ? SBQA_PREC_INT8
+                                                : SBQA_PREC_FP32;
         if (prec == SBQA_PREC_FP8) {
             if (s->fmode == SBQA_F_BALLISTIC) return fail(SBQA_EINVAL, "FP8 precision needs ternary or sign f (ballistic operands are not exact in e4m3)");
             if (!ternary) return fail(SBQA_EINVAL, "FP8 precision needs J in {-1,0,+1}");
         }
-        facts->path = prec == SBQA_PREC_FP8 ? PATH_FP8 : prec == SBQA_PREC_BF16X3 ? PATH_BF16X3 : PATH_F32;
+        if (prec == SBQA_PREC_INT8) {
+            if (s->fmode == SBQA_F_BALLISTIC) return fail(SBQA_EINVAL, "INT8 precision needs ternary or sign f (ballistic operands are not integers)");
+            if (!facts->int8) return fail(SBQA_EINVAL, "INT8 precision needs integer J with |J| <= 127");
+        }
+        facts->path = prec == SBQA_PREC_FP8      ? PATH_FP8
+                      : prec == SBQA_PREC_INT8   ? PATH_I8
+                      : prec == SBQA_PREC_BF16X3 ? PATH_BF16X3
+                                                 : PATH_F32;
     }
     return SBQA_OK;
 }
@@ -707,7 +723,7 @@ static bool resident_plan(sbqa_ctx *c, const sbqa_coupling *J, std::string *why)
 
 // Whether the small dense resident loop fits this instance.
 static bool small_plan(sbqa_ctx *c, std::string *why) {
-    if (c->facts.path != PATH_F32 && c->facts.path != PATH_FP8) { *why = "the small dense loop computes in float32 (FP32 or FP8 precision only)"; return false; }
+    if (c->facts.path == PATH_BF16X3) { *why = "the small dense loop computes in float32 (FP32, FP8 or INT8 precision only)"; return false; }
     if (c->N > SMALL_MAX_N) { *why = "N is above the small dense loop's limit"; return false; }
     if ((int64_t)c->R * c->N > SMALL_MAX_ELEMS) { *why = "R*N is above the small dense loop's limit"; return false; }
     if (small_lds_bytes(c->N, c->R) > 160 * 1024) { *why = "J and the run state do not fit in LDS"; return false; }

@@ -15,6 +15,7 @@ struct InstanceFacts {
     bool dense = true;
     bool integral = false;   // every J_ij and h_i is an integer
     bool ternary = false;    // every J_ij in {-1, 0, +1}
+    bool int8 = false;       // every J_ij an integer in [-127, 127]
     double rms = 0.0;        // rms of the N(N-1) off-diagonal couplings
     int64_t nnz = 0;
     Path path = PATH_F32;

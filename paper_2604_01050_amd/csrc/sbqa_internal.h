@@ -9,7 +9,7 @@
 namespace sbqa {
 
 // Contraction path of a context.
-enum Path : int32_t { PATH_F32 = 0, PATH_FP8 = 1, PATH_BF16X3 = 2, PATH_CSR = 3 };
+enum Path : int32_t { PATH_F32 = 0, PATH_FP8 = 1, PATH_BF16X3 = 2, PATH_CSR = 3, PATH_I8 = 4 };
 
 // Tiling of the fp64 energy GEMM (row-major operands).
 // Output tile: GEMM_BM columns c (replicas) x GEMM_BN rows i (spins);
@@ -51,10 +51,10 @@ constexpr int DENSE_TN = 64;        // J rows (spins) per workgroup: 4 row block
 constexpr int DENSE_THREADS = 256;  // 4 waves
 
 // Element bytes of the contraction operands.
-constexpr int path_ebytes(Path p) { return p == PATH_F32 ? 4 : p == PATH_FP8 ? 1 : 2; }
+constexpr int path_ebytes(Path p) { return p == PATH_F32 ? 4 : (p == PATH_FP8 || p == PATH_I8) ? 1 : 2; }
 // K chunks in flight per wave (prefetch depth); a row's K chunk count must be a
 // multiple of it.
-constexpr int dense_depth(Path p) { return p == PATH_FP8 ? 4 : 2; }
+constexpr int dense_depth(Path p) { return path_ebytes(p) == 1 ? 4 : 2; }
 // Spin padding of the dense paths: a multiple of 128 and of depth K chunks.
 constexpr int dense_pad(Path p) {
     return 128 / path_ebytes(p) * dense_depth(p) > 128 ? 128 / path_ebytes(p) * dense_depth(p) : 128;

@@ -32,18 +32,22 @@ using namespace sbqa;
 namespace {
 
 constexpr uint32_t STEP_BLOCK = 64;
-// Task-table groups: 9 dense (path x m-blocks per wave 1/2/4) and 4 CSR
-// (ballistic x ring by lane reads).
-constexpr int NGROUPS = 13;
+// Task-table groups: 12 dense (4 contraction paths x m-blocks per wave
+// 1/2/4) and 4 CSR (ballistic x ring by lane reads).
+constexpr Path DENSE_PATHS[4] = {PATH_F32, PATH_FP8, PATH_BF16X3, PATH_I8};
+constexpr int NDENSE_GROUPS = 12;
+constexpr int NGROUPS = NDENSE_GROUPS + 4;
 constexpr int DENSE_GRID_CAP = 512;   // workgroups of one grouped dense launch at most
 constexpr int CSR_GRID_CAP = 2048;
 typedef std::chrono::steady_clock Clock;
 
 int group_of(const sbqa_ctx *c) {
     if (c->facts.path == PATH_CSR)
-        return 9 + 2 * (c->s.fmode == SBQA_F_BALLISTIC ? 1 : 0) + (csr_ring_shfl(c->R) ? 1 : 0);
+        return NDENSE_GROUPS + 2 * (c->s.fmode == SBQA_F_BALLISTIC ? 1 : 0) + (csr_ring_shfl(c->R) ? 1 : 0);
     const int mi = c->L.mbw == 1 ? 0 : c->L.mbw == 2 ? 1 : 2;
-    return (int)c->facts.path * 3 + mi;
+    int pi = 0;
+    while (DENSE_PATHS[pi] != c->facts.path) ++pi;
+    return pi * 3 + mi;
 }
 
 // Table entry of context c for steps [c->step, n_end).
@@ -222,12 +226,12 @@ static sbqa_status step_block(sbqa_server *srv, std::vector<Slot> &slots, int pa
                 if (!(mask & (1u << g))) continue;
                 const GroupHeader *dh = srv->d_hdr + g;
                 const GroupTask *dt = srv->d_tasks + (size_t)g * srv->max_slots;
-                if (g < 9) {
+                if (g < NDENSE_GROUPS) {
                     const int mbw = (g % 3 == 0) ? 1 : (g % 3 == 1) ? 2 : 4;
                     const int grid = full_grid ? DENSE_GRID_CAP : std::min(total[g], DENSE_GRID_CAP);
-                    HIP_CHECK_SERVE(launch_group_dense((Path)(g / 3), mbw, dh, dt, grid, (int)off, srv->stream));
+                    HIP_CHECK_SERVE(launch_group_dense(DENSE_PATHS[g / 3], mbw, dh, dt, grid, (int)off, srv->stream));
                 } else {
-                    const int q = g - 9;
+                    const int q = g - NDENSE_GROUPS;
                     const int grid = full_grid ? CSR_GRID_CAP : std::min(total[g], CSR_GRID_CAP);
                     HIP_CHECK_SERVE(launch_group_csr(q >= 2, q & 1, dh, dt, grid, (int)off, srv->stream));
                 }

@@ -13,6 +13,9 @@ Instance families stand in for the paper's (whose data are not available):
                       weights; the sparse, rugged families of Sec. III (cubic
                       lattices have degree 6).
 * ``dense_gaussian``  dense J_ij ~ N(0,1), real-valued couplings.
+* ``sidon28_dense``   dense couplings drawn from the Sidon28 set of the QAC
+                      benchmarks of Sec. III, scaled by 28 to the integers
+                      {+-8, +-13, +-19, +-28}.
 * ``square_lattice``, ``cubic_lattice``  periodic lattices (degree 4 and 6) for
                       the large sparse lattice instances of Sec. III.
 * ``planted_square``  square-lattice instances with a planted ground state of
@@ -29,7 +32,7 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = [
-    "sk_pm1", "dense_gaussian", "regular_graph", "gaussian_edges",
+    "sk_pm1", "dense_gaussian", "sidon28_dense", "SIDON28", "regular_graph", "gaussian_edges",
     "edges_to_csr", "csr_to_dense", "dense_to_csr", "gaussian_fields",
     "uniform_state", "spins_pm1", "square_lattice", "cubic_lattice", "planted_square",
 ]
@@ -54,6 +57,21 @@ def dense_gaussian(N: int, seed: int) -> np.ndarray:
     J = np.zeros((N, N), dtype=np.float64)
     iu = np.triu_indices(N, k=1)
     J[iu] = rng.standard_normal(iu[0].size)
+    return J + J.T
+
+
+# Magnitudes of the Sidon28 couplings {8/28, 13/28, 19/28, 1}, times 28.
+SIDON28 = (8, 13, 19, 28)
+
+
+def sidon28_dense(N: int, seed: int) -> np.ndarray:
+    """Dense integer couplings: J_ij = J_ji uniform over {+-8, +-13, +-19, +-28}
+    for i<j, J_ii = 0 (28 x the Sidon28 set)."""
+    rng = _rng(seed)
+    J = np.zeros((N, N), dtype=np.float64)
+    iu = np.triu_indices(N, k=1)
+    mag = np.asarray(SIDON28, dtype=np.float64)[rng.integers(0, 4, size=iu[0].size)]
+    J[iu] = mag * (rng.integers(0, 2, size=iu[0].size) * 2.0 - 1.0)
     return J + J.T
 
 

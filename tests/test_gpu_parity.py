@@ -152,6 +152,8 @@ CASES = [
     ("fp32_ballistic", "PREC_FP32", 2, "gauss"),
     ("fp8_ternary", "PREC_FP8", 0, "sk"),
     ("fp8_sign", "PREC_FP8", 1, "sk"),
+    ("int8_ternary", "PREC_INT8", 0, "sidon"),
+    ("int8_sign", "PREC_INT8", 1, "sidon"),
     ("bf16x3_ballistic", "PREC_BF16X3", 2, "gauss"),
     ("bf16x3_ternary", "PREC_BF16X3", 0, "gauss"),
     ("csr_ternary", None, 0, "csr"),
@@ -163,6 +165,7 @@ CASES = [
     ("small_fp32_ternary", "PREC_FP32", 0, "gauss_small"),
     ("small_fp32_ballistic", "PREC_FP32", 2, "gauss_small"),
     ("small_fp8_sign", "PREC_FP8", 1, "sk_small"),
+    ("small_int8_ternary", "PREC_INT8", 0, "sidon_small"),
 ]
 
 
@@ -179,6 +182,10 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
         N = 100 if small else 300
         J = inst.sk_pm1(N, 21)
         h = np.round(inst.gaussian_fields(N, 1.0, 22))
+    elif coup.startswith("sidon"):
+        N = 100 if small else 300
+        J = inst.sidon28_dense(N, 21)
+        h = np.round(inst.gaussian_fields(N, 20.0, 22))
     elif coup.startswith("gauss"):
         N = 100 if small else 300
         J = inst.dense_gaussian(N, 23)
@@ -216,8 +223,8 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
             ex, phi_o, phi_abs = _check_step(orc, P, ctx, sb, X, Y, n, S, jr, xg, yg, J=J, csr=csr, h=h,
                                              field_tol=BF16X3_TOL if prec == "PREC_BF16X3" else TOL)
             excluded += ex
-            if prec == "PREC_FP8" or coup.startswith("sk"):
-                assert np.array_equal(phi_g, phi_o.astype(np.float32)), "fp8 fields must be exact integers"
+            if prec in ("PREC_FP8", "PREC_INT8") or coup.startswith(("sk", "sidon")):
+                assert np.array_equal(phi_g, phi_o.astype(np.float32)), "integer-J fields must be exact"
             else:
                 ftol = BF16X3_TOL if prec == "PREC_BF16X3" else TOL
                 err = np.abs(phi_g - phi_o)
@@ -229,13 +236,13 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
 
 
 @pytest.mark.parametrize("prec,fmode,coup", [("PREC_FP32", 2, "gauss"), ("PREC_BF16X3", 2, "gauss"),
-                                              ("PREC_FP8", 0, "sk")])
+                                              ("PREC_FP8", 0, "sk"), ("PREC_INT8", 1, "sidon")])
 def test_dense_tiles_identical(sb, prec, fmode, coup):
     """Every dense workgroup tile (64, 128 or 256 replica columns; the
     autotuner picks one) sums each field in the same K order, so trajectories
     agree bit-for-bit, real-valued couplings included."""
     N, R, runs, S = 300, 8, 20, 30
-    J = inst.dense_gaussian(N, 41) if coup == "gauss" else inst.sk_pm1(N, 41)
+    J = {"gauss": inst.dense_gaussian, "sk": inst.sk_pm1, "sidon": inst.sidon28_dense}[coup](N, 41)
     h = inst.gaussian_fields(N, 0.3, 42)
     _log("dense tiles %s N=%d C=%d" % (prec, N, R * runs))
     X0, Y0 = inst.uniform_state(N, R * runs, 0.2, 43)
@@ -263,6 +270,26 @@ def test_fp8_and_fp32_trajectories_identical(sb):
     out = []
     for prec in (sb.PREC_FP8, sb.PREC_FP32):
         ctx = _ctx(sb, J=J, R=R, runs=runs, steps=S, precision=prec)
+        sb.sbqa_set_state(ctx, X0, Y0)
+        sb.sbqa_step(ctx, S)
+        out.append(sb.sbqa_get_state(ctx) + sb.sbqa_best(ctx))
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_int8_and_fp32_trajectories_identical(sb):
+    """Integer J from the Sidon28 set (x 28) with ternary f: the int8 path's
+    int32 sums and the fp32 path's sums are the same exact integers (|field| <
+    2^24), so whole trajectories agree bit-for-bit; AUTO picks int8."""
+    N, R, runs, S = 700, 8, 6, 150
+    J = inst.sidon28_dense(N, 31)
+    h = np.round(inst.gaussian_fields(N, 30.0, 30))
+    _log("int8 vs fp32 trajectory N=%d S=%d" % (N, S))
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.1, 32)
+    out = []
+    for prec in (sb.PREC_AUTO, sb.PREC_FP32):
+        ctx = _ctx(sb, J=J, h=h, R=R, runs=runs, steps=S, precision=prec, loop_kernel=sb.LOOP_STREAM)
+        assert sb.sbqa_info(ctx)["path"] == ("dense_int8" if prec == sb.PREC_AUTO else "dense_fp32")
         sb.sbqa_set_state(ctx, X0, Y0)
         sb.sbqa_step(ctx, S)
         out.append(sb.sbqa_get_state(ctx) + sb.sbqa_best(ctx))
@@ -425,6 +452,15 @@ def test_full_size_fp8_sk(sb, orc):
     _full_size_step(sb, orc, J=J, N=N, R=R, runs=runs, prec=sb.PREC_FP8, S=10000, exact_fields=True, nrows=24)
 
 
+def test_full_size_int8_sidon(sb, orc):
+    """N = 16384, integer J from the Sidon28 set (x 28) as int8, R = 16 x 16
+    runs: sampled rows, fields exact."""
+    N, R, runs = 16384, 16, 16
+    _log("full-size int8 Sidon28 N=%d" % N)
+    J = inst.sidon28_dense(N, 3101)
+    _full_size_step(sb, orc, J=J, N=N, R=R, runs=runs, prec=sb.PREC_INT8, S=10000, exact_fields=True, nrows=24)
+
+
 def test_full_size_bf16x3_gaussian(sb, orc):
     """N = 8192 Gaussian J, ballistic f, bf16 hi+lo, R = 16 x 32 runs: sampled rows
     within the derived split-bf16 bound; normwise error reported."""
@@ -467,16 +503,16 @@ def test_best_energy_statistics_256_seeds(sb, orc):
 def test_serving_graph_blocks_alone_equals_mix(sb):
     """Longer schedules (several full step blocks, replayed from a captured
     graph while membership changes as instances finish at different steps,
-    plus partial blocks and energy tracking): every result equals the
-    instance's standalone run bit-for-bit."""
+    plus partial blocks and energy tracking; fp8, int8 and CSR groups): every
+    result equals the instance's standalone run bit-for-bit."""
     rng = np.random.default_rng(80)
     items = []
     for q in range(7):
         N = int(rng.choice([200, 300, 512]))
         steps = int(rng.choice([150, 200, 333]))
         ee = 0 if q % 3 else 50
-        if q % 2 == 0:
-            J, csr = inst.sk_pm1(N, 800 + q), None
+        if q % 2 == 0:   # q = 6: integer Sidon28 couplings (int8 path)
+            J, csr = (inst.sidon28_dense if q == 6 else inst.sk_pm1)(N, 800 + q), None
         else:
             N -= N % 2
             E = inst.regular_graph(N, int(rng.integers(3, 7)), 810 + q)
