@@ -44,10 +44,13 @@ def make_workload(name: str):
         desc = ("random 6-regular N=4096, J~N(0,1) on edges, h~N(0,0.1^2), R=32 x 64 runs, "
                 "5000 steps, dt=0.5, ternary f, J_perp linear 0.5->0, fp32 CSR")
         return dict(csr=csr, h=h, N=N, R=R, runs=runs, S=S, prec=None, fmode=0, desc=desc, d=d, dtype="f32")
-    if name == "sk_fp8":
+    if name in ("sk_fp8", "sk_fp8_bytes"):
         N, R, runs, S = 16384, 16, 16, 10000
+        packed = name == "sk_fp8"
         return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP8", fmode=0,
-                    desc="SK N=16384 J=+-1 (e4m3), R=16 x 16 runs, 10000 steps, ternary f", dtype="fp8")
+                    j_packing=None if packed else "JPACK_BYTES",
+                    desc="SK N=16384 J=+-1 (%s), R=16 x 16 runs, 10000 steps, ternary f"
+                         % ("1 bit per coupling, e4m3 MFMA" if packed else "e4m3 bytes"), dtype="fp8")
     if name in ("sidon_i8", "sidon_fp32"):
         # integer couplings of the QAC benchmarks (Sidon28 set x 28), dense at the SK size
         N, R, runs, S = 16384, 16, 16, 10000
@@ -96,6 +99,8 @@ def create(sb, w, seed, loop_kernel="auto"):
               loop_kernel={"auto": sb.LOOP_AUTO, "stream": sb.LOOP_STREAM, "resident": sb.LOOP_RESIDENT}[loop_kernel])
     if w["prec"]:
         kw["precision"] = getattr(sb, w["prec"])
+    if w.get("j_packing"):
+        kw["j_packing"] = getattr(sb, w["j_packing"])
     return sb.sbqa_create(J=w.get("J"), csr=w.get("csr"), h=w.get("h"), **kw)
 
 
@@ -106,9 +111,10 @@ def algorithmic_bytes(w, info):
         nnz = len(w["csr"][1])
         # x, y read + write (fp32) + int8 operand written once and read once
         return N * C * (16 + 2) + 4 * (N + 1) + 8 * nnz + 4 * N
-    eb = {"dense_fp8": 1, "dense_int8": 1, "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
+    eb = {"dense_fp8": 1, "dense_fp8_packed": 1, "dense_int8": 1, "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
+    jb = N * N / 8 if info["path"] == "dense_fp8_packed" else N * N * eb
     # GEMM: J streamed once + operand read once + fp32 field partial written
-    return N * N * eb + C * N * eb + C * N * 4
+    return jb + C * N * eb + C * N * 4
 
 
 # VALU peak of MI355X in fp32 lane operations: 256 CUs x 4 SIMDs x 16 lanes x
@@ -138,6 +144,7 @@ KERNEL_SOURCES = {"csr_fp32": "paper_2604_01050_amd/csrc/kernels_csr.hip",
                   "csr_resident": "paper_2604_01050_amd/csrc/kernels_csr.hip",
                   "dense_fp8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
                   "dense_int8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
+                  "dense_fp8_packed": "paper_2604_01050_amd/csrc/kernels_dense.hip",
                   "dense_fp32": "paper_2604_01050_amd/csrc/kernels_dense.hip",
                   "dense_bf16x3": "paper_2604_01050_amd/csrc/kernels_dense.hip"}
 
@@ -467,7 +474,7 @@ def main():
                                "algorithmic_bytes_per_launch": ab}
         else:
             fl = algorithmic_flops(w)
-            peak = PEAK[{"dense_fp8": "fp8", "dense_int8": "int8", "dense_fp32": "fp32",
+            peak = PEAK[{"dense_fp8": "fp8", "dense_fp8_packed": "fp8", "dense_int8": "int8", "dense_fp32": "fp32",
                          "dense_bf16x3": "bf16"}[info["path"]]]
             unit = "TOP/s" if info["path"] == "dense_int8" else "TFLOP/s"
             out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": unit,

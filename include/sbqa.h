@@ -98,6 +98,13 @@ typedef enum { SBQA_JP_LINEAR = 0, SBQA_JP_PAPER = 1, SBQA_JP_TABLE = 2 } sbqa_j
  *             sbqa_create fails with EINVAL when the instance does not fit. */
 typedef enum { SBQA_LOOP_AUTO = 0, SBQA_LOOP_STREAM = 1, SBQA_LOOP_RESIDENT = 2 } sbqa_loop_kernel;
 
+/* Storage of J for the dense FP8 contraction:
+ *   AUTO   one bit per coupling when every off-diagonal J_ij is +-1 (SK-type
+ *          instances: 8x fewer J bytes to stream per step); expanded to e4m3
+ *          in registers, so the fields are the same exact integers.
+ *   BYTES  one e4m3 byte per coupling. */
+typedef enum { SBQA_JPACK_AUTO = 0, SBQA_JPACK_BYTES = 1 } sbqa_j_packing;
+
 /* Couplings: exactly one of `dense` or the CSR triple is non-NULL.
  * J must be symmetric with a zero diagonal and finite entries.
  *   dense    N*N float64, row-major.
@@ -138,12 +145,13 @@ typedef struct {
                                 step timed once per process on scratch buffers
                                 of the instance's shape; every tile gives the
                                 same bits)                                        */
+    int32_t j_packing;       /* sbqa_j_packing (dense FP8 only)                    */
 } sbqa_schedule;
 
 /* Defaults: steps 1000, dt 0.5, a0 1, c0 auto, ternary f, delta_max 0.7,
  * PAPER schedule with gamma0_over_R 1, beta in [0.5,1.5], alpha in [0.5,1.0]
  * (Sec. II.B), seed 0, init_amp 0.1, precision AUTO, energy_every 0,
- * loop_kernel AUTO, dense_tile 0 (autotuned). */
+ * loop_kernel AUTO, dense_tile 0 (autotuned), j_packing AUTO. */
 sbqa_schedule sbqa_schedule_default(void);
 
 /* Context information (sbqa_info). */
@@ -152,7 +160,7 @@ typedef struct {
     uint32_t steps;          /* S                                                  */
     uint32_t step;           /* steps already taken                                */
     int32_t path;            /* 0 dense fp32, 1 dense fp8, 2 dense bf16x3, 3 csr,
-                                4 dense int8                                     */
+                                4 dense int8, 5 dense fp8 with bit-packed J     */
     int32_t fmode;
     double c0;               /* c0 actually used                                   */
     int32_t j_integral;      /* 1 when every J_ij and h_i is an integer            */

@@ -19,7 +19,8 @@ F_TERNARY, F_SIGN, F_BALLISTIC = 0, 1, 2
 PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8 = 0, 1, 2, 3, 4
 JP_LINEAR, JP_PAPER, JP_TABLE = 0, 1, 2
 LOOP_AUTO, LOOP_STREAM, LOOP_RESIDENT = 0, 1, 2
-PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32", 4: "dense_int8"}
+JPACK_AUTO, JPACK_BYTES = 0, 1
+PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32", 4: "dense_int8", 5: "dense_fp8_packed"}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EBUDGET", -6: "EAGAIN"}
 
 
@@ -43,7 +44,7 @@ class Schedule(ct.Structure):
                 ("alpha_hi", ct.c_double), ("beta", ct.c_void_p), ("alpha", ct.c_void_p),
                 ("jp_table", ct.c_void_p), ("seed", ct.c_uint64), ("init_amp", ct.c_double),
                 ("precision", ct.c_int32), ("energy_every", ct.c_uint32), ("loop_kernel", ct.c_int32),
-                ("dense_tile", ct.c_int32)]
+                ("dense_tile", ct.c_int32), ("j_packing", ct.c_int32)]
 
 
 class Info(ct.Structure):

@@ -1,8 +1,8 @@
 // Dense SBQA kernels for gfx950 (CDNA4, wave64):
 //   * one step of the dense path: the coupling sum of Eq. 7 over all runs and
 //     replicas, Phi^T[c][i] = sum_j f(X)^T[c][j] J[i][j] (J symmetric, zero
-//     diagonal), on MFMA in fp32, e4m3 fp8, int8 (integer J) or bf16 hi+lo
-//     (three products),
+//     diagonal), on MFMA in fp32, e4m3 fp8 (J as bytes or, for J = +-1, one
+//     bit per coupling), int8 (integer J) or bf16 hi+lo (three products),
 //     with the update of Eqs. 6-7 (pump, Trotter ring, kick, drift, wall) and
 //     the next operand f(X) (Eq. 8) fused into its epilogue;
 //   * the fp64 GEMM of the energies (Eq. 2 at the corners).
@@ -29,6 +29,16 @@ constexpr uint8_t I8_P1 = 0x01, I8_M1 = 0xFF;
 constexpr int E8M0_ONE = 127;
 
 struct Frag32 { uint4 lo, hi; };  // the 32 K bytes of one lane for a 16x16 block
+
+template <int PATH> constexpr bool is_fp8 = PATH == PATH_FP8 || PATH == PATH_FP8PK;
+
+// Bit-packed +-1 J: lane l of a fragment owns the dword at 4*l; its bit
+// 8*i + k encodes byte i of dword k (k = 0..7) of the lane's 32 fp8 K bytes,
+// set for -1. Dword k is then ((w << (7 - k)) & 0x80808080) | e4m3(+1) x 4.
+__device__ __forceinline__ Frag32 unpack_pm1(uint32_t w) {
+    auto d = [w](int k) { return ((w << (7 - k)) & 0x80808080u) | 0x38383838u; };
+    return Frag32{make_uint4(d(0), d(1), d(2), d(3)), make_uint4(d(4), d(5), d(6), d(7))};
+}
 
 // ---------------------------------------------------------------------------
 // fp64 energy GEMM (row-major operands staged through LDS).
@@ -155,8 +165,8 @@ __device__ __forceinline__ void store_operand(void *g, void *g_lo, int64_t o, fl
     uint8_t *gb = reinterpret_cast<uint8_t *>(g);
     if constexpr (PATH == PATH_F32) {
         *reinterpret_cast<float4 *>(gb + o) = f;
-    } else if constexpr (PATH == PATH_FP8 || PATH == PATH_I8) {
-        constexpr uint32_t P1 = PATH == PATH_FP8 ? FP8_P1 : I8_P1, M1 = PATH == PATH_FP8 ? FP8_M1 : I8_M1;
+    } else if constexpr (is_fp8<PATH> || PATH == PATH_I8) {
+        constexpr uint32_t P1 = is_fp8<PATH> ? FP8_P1 : I8_P1, M1 = is_fp8<PATH> ? FP8_M1 : I8_M1;
         const float v[4] = {f.x, f.y, f.z, f.w};
         uint32_t w = 0;
 #pragma unroll
@@ -191,6 +201,7 @@ __device__ __forceinline__ void store_operand(void *g, void *g_lo, int64_t o, fl
 template <int PATH> struct Terms;
 template <> struct Terms<PATH_F32> { static constexpr int n = 8; };     // 8 x 16x16x4 f32
 template <> struct Terms<PATH_FP8> { static constexpr int n = 1; };     // 1 x 16x16x128 f8f6f4
+template <> struct Terms<PATH_FP8PK> { static constexpr int n = 1; };
 template <> struct Terms<PATH_BF16X3> { static constexpr int n = 6; };  // lo*hi, hi*lo, hi*hi x 2 halves
 template <> struct Terms<PATH_I8> { static constexpr int n = 2; };      // 2 x 16x16x64 i8 (K halves)
 
@@ -201,7 +212,7 @@ __device__ __forceinline__ void mma_term(f4 &acc, const Frag32 &a, const Frag32 
         const float *af = reinterpret_cast<const float *>(&a);
         const float *bf = reinterpret_cast<const float *>(&b);
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(af[T], bf[T], acc, 0, 0, 0);
-    } else if constexpr (PATH == PATH_FP8) {
+    } else if constexpr (is_fp8<PATH>) {
         i8v av, bv;
         __builtin_memcpy(&av, &a, 32);
         __builtin_memcpy(&bv, &b, 32);
@@ -339,19 +350,22 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
     const int mb0 = (mchunk * 4 + w) * MBW;       // first m-block of this wave
     const int nkc = a.nkc;
     const int l16 = lane * 16;
-    constexpr int JCH = RBT * FRAG_BYTES;   // J bytes of one tile and K chunk
+    constexpr bool JPK = PATH == PATH_FP8PK;     // J as one bit per coupling
+    constexpr int JFRAG = JPK ? PK_FRAG_BYTES : FRAG_BYTES;
+    constexpr int JCH = RBT * JFRAG;        // J bytes of one tile and K chunk
     constexpr int XCH = MBW * FRAG_BYTES;   // operand bytes of one wave and K chunk
 
     // this wave stages J row block w of tile nt (both planes); its operand
     // group is m-blocks mb0..mb0+MBW-1
-    const int64_t jgrp = (int64_t)nt * nkc * JCH + w * FRAG_BYTES + l16;
+    const int64_t jgrp = (int64_t)nt * nkc * JCH + w * JFRAG + (JPK ? lane * 4 : l16);
     const int64_t xgrp = (int64_t)(mchunk * 4 + w) * nkc * XCH + l16;
     const uint8_t *jsrc = a.J + jgrp;
     const uint8_t *jsrc_lo = (PL == 2) ? a.J_lo + jgrp : jsrc;
     const uint8_t *xsrc = a.g + xgrp;
     const uint8_t *xsrc_lo = (PL == 2) ? a.g_lo + xgrp : xsrc;
 
-    uint4 jr[PD][PL][2];
+    uint4 jr[JPK ? 1 : PD][PL][2];
+    uint32_t jw[JPK ? PD : 1];
     uint4 xr[PD][MBW][PL][2];
     f4 acc[MBW][RBT];
 #pragma unroll
@@ -361,13 +375,17 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
 
     const int rev = a.reverse;
     auto chunk_at = [&](int kc) -> int64_t { return rev ? nkc - 1 - kc : kc; };
-    auto load_j = [&](uint4 (&d)[PL][2], int kc) {
+    auto load_j = [&](int s, int kc) {
         const int64_t o = chunk_at(kc) * JCH;
-        d[0][0] = ld16(jsrc + o);
-        d[0][1] = ld16(jsrc + o + 1024);
-        if constexpr (PL == 2) {
-            d[PL - 1][0] = ld16(jsrc_lo + o);
-            d[PL - 1][1] = ld16(jsrc_lo + o + 1024);
+        if constexpr (JPK) {
+            jw[s] = *reinterpret_cast<const uint32_t *>(jsrc + o);
+        } else {
+            jr[s][0][0] = ld16(jsrc + o);
+            jr[s][0][1] = ld16(jsrc + o + 1024);
+            if constexpr (PL == 2) {
+                jr[s][PL - 1][0] = ld16(jsrc_lo + o);
+                jr[s][PL - 1][1] = ld16(jsrc_lo + o + 1024);
+            }
         }
     };
     auto load_x = [&](uint4 (&d)[MBW][PL][2], int kc) {
@@ -390,7 +408,7 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
     // prologue issues its loads in the loop's order, J then operand per chunk.
 #pragma unroll
     for (int s = 0; s < PD; ++s) {
-        load_j(jr[s], s);
+        load_j(s, s);
         __builtin_amdgcn_sched_barrier(0);
         load_x(xr[s], s);
         __builtin_amdgcn_sched_barrier(0);
@@ -403,16 +421,24 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
             const int kc = kc0 + s;
             const int kn = (kc + PD < nkc) ? kc + PD : kc;
             uint8_t *slot = lds + (kc & 1) * SLOT;
-            // publish this wave's J fragment of chunk kc; slot (kc & 1) was
-            // last read in chunk kc - 2, which every wave finished before the
-            // barrier of chunk kc - 1
+            // publish this wave's J fragment of chunk kc (bit-packed J is
+            // expanded to e4m3 bytes here); slot (kc & 1) was last read in
+            // chunk kc - 2, which every wave finished before the barrier of
+            // chunk kc - 1
+            if constexpr (JPK) {
+                const Frag32 f = unpack_pm1(jw[s]);
+                uint8_t *dst = slot + w * FRAG_BYTES + l16;
+                *reinterpret_cast<uint4 *>(dst) = f.lo;
+                *reinterpret_cast<uint4 *>(dst + 1024) = f.hi;
+            } else {
 #pragma unroll
-            for (int pl = 0; pl < PL; ++pl) {
-                uint8_t *dst = slot + (pl * RBT + w) * FRAG_BYTES + l16;
-                *reinterpret_cast<uint4 *>(dst) = jr[s][pl][0];
-                *reinterpret_cast<uint4 *>(dst + 1024) = jr[s][pl][1];
+                for (int pl = 0; pl < PL; ++pl) {
+                    uint8_t *dst = slot + (pl * RBT + w) * FRAG_BYTES + l16;
+                    *reinterpret_cast<uint4 *>(dst) = jr[s][pl][0];
+                    *reinterpret_cast<uint4 *>(dst + 1024) = jr[s][pl][1];
+                }
             }
-            load_j(jr[s], kn);
+            load_j(s, kn);
             __syncthreads();
             // J fragments of the 4 row blocks, two in registers at a time
             Frag32 bjb[2][PL];
@@ -469,6 +495,25 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
             ph[it] = *reinterpret_cast<const float4 *>(T + row * TS + 4 * q);
             cc[it] = 16 * (mb0 + mb) + row;
             ii[it] = n0 + 4 * q;
+        }
+        if constexpr (JPK) {
+            // bit-packed J holds +1 on the diagonal and in the padding: take
+            // the diagonal term J'_ii f_i = f_i (the operand byte this step
+            // read) back out, and zero the fields of padded spins so that
+            // their x and f stay 0
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                if (cc[it] >= a.C) continue;
+                const uint32_t fb = *reinterpret_cast<const uint32_t *>(a.g + tf_offset(cc[it], ii[it], nkc, 1, MBW));
+                float v[4] = {ph[it].x, ph[it].y, ph[it].z, ph[it].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t b = (fb >> (8 * e)) & 0xFFu;
+                    const float f = b == 0u ? 0.0f : ((b & 0x80u) ? -1.0f : 1.0f);
+                    v[e] = (ii[it] + e < a.N) ? v[e] - f : 0.0f;
+                }
+                ph[it] = make_float4(v[0], v[1], v[2], v[3]);
+            }
         }
         if constexpr (EPI == EPI_UPDATE) {
             UpdIn u[ITEMS];
@@ -537,6 +582,33 @@ __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J6
         *reinterpret_cast<uint2 *>(Jd + o) = make_uint2(hi[0] | ((uint32_t)hi[1] << 16), hi[2] | ((uint32_t)hi[3] << 16));
         *reinterpret_cast<uint2 *>(Jd_lo + o) = make_uint2(lo[0] | ((uint32_t)lo[1] << 16), lo[2] | ((uint32_t)lo[3] << 16));
     }
+}
+
+// Bit-packed +-1 J (layout of unpack_pm1), fragment-tiled like the byte
+// copy (groups of DENSE_TN/16 row blocks): one thread per (fragment, lane)
+// dword, consecutive threads write consecutive dwords. A bit is set where
+// J_ij < 0; the diagonal and the padding read 0 and so hold +1 (the step's
+// epilogue removes both).
+__global__ __launch_bounds__(256) void k_convert_j_pk(const double *__restrict__ J64, int Np, int nkc,
+                                                     uint32_t *__restrict__ Jd) {
+    constexpr int RBT = DENSE_TN / 16;
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= (int64_t)(Np / 16) * nkc * 64) return;
+    const int lane = (int)(q & 63);
+    const int64_t frag = q >> 6;
+    const int w = (int)(frag % RBT);
+    const int64_t t = frag / RBT;
+    const int kc = (int)(t % nkc), rb = (int)(t / nkc) * RBT + w;
+    const double *src = J64 + (int64_t)(16 * rb + (lane & 15)) * Np + 128 * kc + 32 * (lane >> 4);
+    uint32_t bits = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int b = 4 * k + i;               // byte of the lane's 32: half b/16, byte b%16
+            if (src[16 * (b >> 4) + (b & 15)] < 0.0) bits |= 1u << (8 * i + k);
+        }
+    Jd[q] = bits;
 }
 
 template <int PATH, int MBW>
@@ -637,12 +709,19 @@ hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, cons
         case PATH_FP8: return launch_step_path<PATH_FP8>(epi, mbw, grid, a, st);
         case PATH_BF16X3: return launch_step_path<PATH_BF16X3>(epi, mbw, grid, a, st);
         case PATH_I8: return launch_step_path<PATH_I8>(epi, mbw, grid, a, st);
+        case PATH_FP8PK: return launch_step_path<PATH_FP8PK>(epi, mbw, grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void *Jd, void *Jd_lo, hipStream_t st) {
     if (Np % 128 || nkc != Np * path_ebytes(path) / 128) return hipErrorInvalidValue;
+    if (path == PATH_FP8PK) {
+        const int64_t nq = (int64_t)(Np / 16) * nkc * 64;
+        hipLaunchKernelGGL(k_convert_j_pk, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, J64, Np, nkc,
+                           static_cast<uint32_t *>(Jd));
+        return hipGetLastError();
+    }
     const int64_t nq = (int64_t)Np * (Np / 4);
     const dim3 grid((unsigned)((nq + 255) / 256)), block(256);
     uint8_t *d = static_cast<uint8_t *>(Jd), *dl = static_cast<uint8_t *>(Jd_lo);
@@ -672,6 +751,7 @@ hipError_t launch_group_dense(Path path, int mbw, const GroupHeader *hdr, const 
         case PATH_FP8: SBQA_GD_PATH(PATH_FP8); break;
         case PATH_BF16X3: SBQA_GD_PATH(PATH_BF16X3); break;
         case PATH_I8: SBQA_GD_PATH(PATH_I8); break;
+        case PATH_FP8PK: SBQA_GD_PATH(PATH_FP8PK); break;
         default: return hipErrorInvalidValue;
     }
 #undef SBQA_GD_PATH
@@ -688,6 +768,7 @@ hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int 
         case PATH_FP8: hipLaunchKernelGGL(k_dense_operand<PATH_FP8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_BF16X3: hipLaunchKernelGGL(k_dense_operand<PATH_BF16X3>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_I8: hipLaunchKernelGGL(k_dense_operand<PATH_I8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
+        case PATH_FP8PK: hipLaunchKernelGGL(k_dense_operand<PATH_FP8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -62,7 +62,7 @@ static double unit_double(uint64_t &s) { return (double)(splitmix64(s) >> 11) * 
 struct DenseScan {
     int bad = 0;              // 1 diagonal, 2 not finite, 3 not symmetric
     int64_t i = 0, j = 0;
-    bool integral = true, ternary = true;
+    bool integral = true, ternary = true, pm1 = true;
     double ss = 0.0, maxabs = 0.0;
 };
 
@@ -84,6 +84,7 @@ static DenseScan scan_dense(const double *A, int64_t N) {
                 }
                 if (v != std::floor(v) || std::fabs(v) > 2147483647.0) r.integral = false;
                 if (!(v == 0.0 || v == 1.0 || v == -1.0)) r.ternary = false;
+                if (j != i && !(v == 1.0 || v == -1.0)) r.pm1 = false;
                 r.maxabs = std::max(r.maxabs, std::fabs(v));
                 srow += v * v;
             }
@@ -115,6 +116,7 @@ static DenseScan scan_dense(const double *A, int64_t N) {
         if (r.bad && !out.bad) { out.bad = r.bad; out.i = r.i; out.j = r.j; }
         out.integral = out.integral && r.integral;
         out.ternary = out.ternary && r.ternary;
+        out.pm1 = out.pm1 && r.pm1;
         out.maxabs = std::max(out.maxabs, r.maxabs);
         out.ss += r.ss;
     }
@@ -134,6 +136,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     if (!std::isfinite(s->delta_max) || s->delta_max < 0) return fail(SBQA_EINVAL, "delta_max must be finite and >= 0");
     if (s->precision < SBQA_PREC_AUTO || s->precision > SBQA_PREC_INT8) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
     if (s->loop_kernel < 0 || s->loop_kernel > 2) return fail(SBQA_EINVAL, "unknown loop_kernel %d", s->loop_kernel);
+    if (s->j_packing < SBQA_JPACK_AUTO || s->j_packing > SBQA_JPACK_BYTES) return fail(SBQA_EINVAL, "unknown j_packing %d", s->j_packing);
     if (s->dense_tile != 0 && s->dense_tile != 64 && s->dense_tile != 128 && s->dense_tile != 256)
         return fail(SBQA_EINVAL, "dense_tile must be 0 (autotuned), 64, 128 or 256 (got %d)", s->dense_tile);
     if (!(s->init_amp >= 0) || !std::isfinite(s->init_amp)) return fail(SBQA_EINVAL, "init_amp must be finite and >= 0");
@@ -184,6 +187,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
         }
         integral = d.integral;
         ternary = d.ternary;
+        facts->pm1 = d.pm1 && N > 1;
         maxabs = d.maxabs;
         ss = d.ss;
         facts->nnz = 0;
@@ -247,7 +251,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
             if (s->fmode == SBQA_F_BALLISTIC) return fail(SBQA_EINVAL, "INT8 precision needs ternary or sign f (ballistic operands are not integers)");
             if (!facts->int8) return fail(SBQA_EINVAL, "INT8 precision needs integer J with |J| <= 127");
         }
-        facts->path = prec == SBQA_PREC_FP8      ? PATH_FP8
+        facts->path = prec == SBQA_PREC_FP8      ? (facts->pm1 && s->j_packing == SBQA_JPACK_AUTO ? PATH_FP8PK : PATH_FP8)
                       : prec == SBQA_PREC_INT8   ? PATH_I8
                       : prec == SBQA_PREC_BF16X3 ? PATH_BF16X3
                                                  : PATH_F32;
@@ -285,7 +289,7 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         L->esplits = es;
         b += 3 * C * (int64_t)L->Np * 4;                                  // x ping-pong, y
         b += 2 * (int64_t)L->Cg * L->Np * eb * planes;                    // operand ping-pong
-        b += (int64_t)L->Np * L->Np * eb * planes;                        // J
+        b += dense_j_bytes(f.path, L->Np) * planes;                       // J
         b += (int64_t)L->Np * L->Np * 8;                                  // J fp64 (energies)
         b += (int64_t)L->Np * 12;                                         // h
         b += (int64_t)L->Cp * L->Np * 8 * (1 + es);                      // readout + energy partials
@@ -335,7 +339,7 @@ static int tune_dense_mbw(Path path, int C, int Np, hipStream_t st) {
             (void)hipMemsetAsync(p, 0, std::max<size_t>(bytes, 256), st);
             return p;
         };
-        const size_t jb = (size_t)Np * Np * eb, gb = (size_t)Cgm * Np * eb, sb = (size_t)C * Np * 4;
+        const size_t jb = (size_t)dense_j_bytes(path, Np), gb = (size_t)Cgm * Np * eb, sb = (size_t)C * Np * 4;
         DenseStepArgs a{};
         a.N = Np;
         a.Np = Np;
@@ -601,7 +605,7 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     const double *A = J->dense;
     uint8_t *jd, *jlo = nullptr;
     double *j64;
-    HIP_TRY(dalloc(c, &jd, (size_t)Np * Np * eb));
+    HIP_TRY(dalloc(c, &jd, (size_t)dense_j_bytes(path, Np)));
     if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &jlo, (size_t)Np * Np * eb));
     HIP_TRY(dalloc(c, &j64, (size_t)Np * Np));
     c->Jd = jd;
@@ -922,6 +926,8 @@ sbqa_schedule sbqa_schedule_default(void) {
     s.precision = SBQA_PREC_AUTO;
     s.energy_every = 0;
     s.loop_kernel = SBQA_LOOP_AUTO;
+    s.dense_tile = 0;
+    s.j_packing = SBQA_JPACK_AUTO;
     return s;
 }
 

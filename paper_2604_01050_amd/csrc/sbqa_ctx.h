@@ -16,6 +16,7 @@ struct InstanceFacts {
     bool integral = false;   // every J_ij and h_i is an integer
     bool ternary = false;    // every J_ij in {-1, 0, +1}
     bool int8 = false;       // every J_ij an integer in [-127, 127]
+    bool pm1 = false;        // every off-diagonal J_ij in {-1, +1} (dense)
     double rms = 0.0;        // rms of the N(N-1) off-diagonal couplings
     int64_t nnz = 0;
     Path path = PATH_F32;

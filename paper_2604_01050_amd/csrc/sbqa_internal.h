@@ -9,7 +9,8 @@
 namespace sbqa {
 
 // Contraction path of a context.
-enum Path : int32_t { PATH_F32 = 0, PATH_FP8 = 1, PATH_BF16X3 = 2, PATH_CSR = 3, PATH_I8 = 4 };
+// PATH_FP8PK: the fp8 contraction with J = +-1 stored as one bit per coupling.
+enum Path : int32_t { PATH_F32 = 0, PATH_FP8 = 1, PATH_BF16X3 = 2, PATH_CSR = 3, PATH_I8 = 4, PATH_FP8PK = 5 };
 
 // Tiling of the fp64 energy GEMM (row-major operands).
 // Output tile: GEMM_BM columns c (replicas) x GEMM_BN rows i (spins);
@@ -51,7 +52,13 @@ constexpr int DENSE_TN = 64;        // J rows (spins) per workgroup: 4 row block
 constexpr int DENSE_THREADS = 256;  // 4 waves
 
 // Element bytes of the contraction operands.
-constexpr int path_ebytes(Path p) { return p == PATH_F32 ? 4 : (p == PATH_FP8 || p == PATH_I8) ? 1 : 2; }
+constexpr int path_ebytes(Path p) { return p == PATH_F32 ? 4 : p == PATH_BF16X3 ? 2 : 1; }
+// Bit-packed J: a 16 x 128 fragment in 256 bytes (one dword per lane).
+constexpr int PK_FRAG_BYTES = 256;
+// Device bytes of the contraction copy of J (one plane).
+inline int64_t dense_j_bytes(Path p, int Np) {
+    return p == PATH_FP8PK ? (int64_t)Np * Np / 8 : (int64_t)Np * Np * path_ebytes(p);
+}
 // K chunks in flight per wave (prefetch depth); a row's K chunk count must be a
 // multiple of it.
 constexpr int dense_depth(Path p) { return path_ebytes(p) == 1 ? 4 : 2; }

@@ -83,6 +83,7 @@ def test_validation_errors(abi):
     assert "precision" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, precision=5)
     assert "dense_tile" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, dense_tile=96)
     assert "loop_kernel" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, loop_kernel=7)
+    assert "j_packing" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, j_packing=2)
     # CSR: asymmetric, out of range, unsorted, bf16 precision
     E = inst.regular_graph(20, 3, 2)
     rp, col, val = inst.edges_to_csr(20, E, inst.gaussian_edges(len(E), 3))

@@ -152,6 +152,8 @@ CASES = [
     ("fp32_ballistic", "PREC_FP32", 2, "gauss"),
     ("fp8_ternary", "PREC_FP8", 0, "sk"),
     ("fp8_sign", "PREC_FP8", 1, "sk"),
+    ("fp8_bytes_ternary", "PREC_FP8", 0, "sk"),
+    ("fp8_ternary_zeros", "PREC_FP8", 0, "sk0"),
     ("int8_ternary", "PREC_INT8", 0, "sidon"),
     ("int8_sign", "PREC_INT8", 1, "sidon"),
     ("bf16x3_ballistic", "PREC_BF16X3", 2, "gauss"),
@@ -181,6 +183,9 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
     if coup.startswith("sk"):
         N = 100 if small else 300
         J = inst.sk_pm1(N, 21)
+        if coup == "sk0":   # J in {-1, 0, +1}: one byte per coupling
+            keep = np.triu(np.random.default_rng(20).random((N, N)) < 0.6, 1)
+            J = J * (keep | keep.T)
         h = np.round(inst.gaussian_fields(N, 1.0, 22))
     elif coup.startswith("sidon"):
         N = 100 if small else 300
@@ -200,11 +205,16 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
     _log("single-step parity %s N=%d R=%d runs=%d" % (name, N, R, runs))
     kw = {} if prec is None else {"precision": getattr(sb, prec)}
     kw["loop_kernel"] = sb.LOOP_RESIDENT if small else sb.LOOP_STREAM
+    if "_bytes" in name:
+        kw["j_packing"] = sb.JPACK_BYTES
     rng = np.random.default_rng(28)
     beta, alpha = rng.uniform(0.5, 1.5, runs), rng.uniform(0.5, 1.0, runs)
     ctx = _ctx(sb, J=J, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, jp_kind=sb.JP_PAPER,
                beta=beta, alpha=alpha, gamma0_over_R=0.7, **kw)
-    assert sb.sbqa_info(ctx)["resident"] == small
+    info = sb.sbqa_info(ctx)
+    assert info["resident"] == small
+    if prec == "PREC_FP8" and not small:
+        assert info["path"] == ("dense_fp8_packed" if coup == "sk" and "_bytes" not in name else "dense_fp8")
     P = _orc_problem(orc, sb, ctx, J=J, csr=csr, h=h, fmode=fmode)
     jt = np.stack([orc.jperp_paper_table(b, a, 0.7, S) for b, a in zip(beta, alpha)])
     # schedule table of the library equals the oracle's, rounded to float32
@@ -236,20 +246,22 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
 
 
 @pytest.mark.parametrize("prec,fmode,coup", [("PREC_FP32", 2, "gauss"), ("PREC_BF16X3", 2, "gauss"),
-                                              ("PREC_FP8", 0, "sk"), ("PREC_INT8", 1, "sidon")])
+                                              ("PREC_FP8", 0, "sk"), ("PREC_FP8", 0, "sk_bytes"),
+                                              ("PREC_INT8", 1, "sidon")])
 def test_dense_tiles_identical(sb, prec, fmode, coup):
     """Every dense workgroup tile (64, 128 or 256 replica columns; the
     autotuner picks one) sums each field in the same K order, so trajectories
     agree bit-for-bit, real-valued couplings included."""
     N, R, runs, S = 300, 8, 20, 30
-    J = {"gauss": inst.dense_gaussian, "sk": inst.sk_pm1, "sidon": inst.sidon28_dense}[coup](N, 41)
+    J = {"gauss": inst.dense_gaussian, "sidon": inst.sidon28_dense}.get(coup, inst.sk_pm1)(N, 41)
+    pk = {"j_packing": sb.JPACK_BYTES} if coup == "sk_bytes" else {}
     h = inst.gaussian_fields(N, 0.3, 42)
     _log("dense tiles %s N=%d C=%d" % (prec, N, R * runs))
     X0, Y0 = inst.uniform_state(N, R * runs, 0.2, 43)
     out = []
     for tile in (64, 128, 256, 0):
         ctx = _ctx(sb, J=J, h=h, R=R, runs=runs, steps=S, fmode=fmode, precision=getattr(sb, prec), dense_tile=tile,
-                   loop_kernel=sb.LOOP_STREAM)
+                   loop_kernel=sb.LOOP_STREAM, **pk)
         info = sb.sbqa_info(ctx)
         assert info["tile_cols"] == tile or (tile == 0 and info["tile_cols"] in (64, 128, 256))
         sb.sbqa_set_state(ctx, X0, Y0)
@@ -261,20 +273,24 @@ def test_dense_tiles_identical(sb, prec, fmode, coup):
 
 
 def test_fp8_and_fp32_trajectories_identical(sb):
-    """J in {-1,+1} with ternary f: fields are exact integers in fp8 and fp32,
-    so whole trajectories agree bit-for-bit."""
+    """J in {-1,+1} with ternary f: fields are exact integers in fp8 (J
+    bit-packed or as e4m3 bytes) and fp32, so whole trajectories agree
+    bit-for-bit."""
     N, R, runs, S = 700, 8, 6, 150
     J = inst.sk_pm1(N, 31)
     _log("fp8 vs fp32 trajectory N=%d S=%d" % (N, S))
     X0, Y0 = inst.uniform_state(N, R * runs, 0.1, 32)
     out = []
-    for prec in (sb.PREC_FP8, sb.PREC_FP32):
-        ctx = _ctx(sb, J=J, R=R, runs=runs, steps=S, precision=prec)
+    for prec, pk, path in ((sb.PREC_FP8, sb.JPACK_AUTO, "dense_fp8_packed"), (sb.PREC_FP8, sb.JPACK_BYTES, "dense_fp8"),
+                           (sb.PREC_FP32, sb.JPACK_AUTO, "dense_fp32")):
+        ctx = _ctx(sb, J=J, R=R, runs=runs, steps=S, precision=prec, j_packing=pk, loop_kernel=sb.LOOP_STREAM)
+        assert sb.sbqa_info(ctx)["path"] == path
         sb.sbqa_set_state(ctx, X0, Y0)
         sb.sbqa_step(ctx, S)
         out.append(sb.sbqa_get_state(ctx) + sb.sbqa_best(ctx))
-    for a, b in zip(out[0], out[1]):
-        assert np.array_equal(a, b)
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
 
 
 def test_int8_and_fp32_trajectories_identical(sb):
@@ -394,8 +410,9 @@ def test_energy_tracking_matches_oracle(sb, orc):
 
 # ----------------------------------------------------- full-size, sampled rows
 def _full_size_step(sb, orc, J=None, csr=None, h=None, N=None, R=None, runs=None, prec=None, fmode=0,
-                    nrows=48, steps_before=3, S=1000, field_tol=TOL, exact_fields=False):
+                    nrows=48, steps_before=3, S=1000, field_tol=TOL, exact_fields=False, **extra):
     kw = {} if prec is None else {"precision": prec}
+    kw.update(extra)
     ctx = _ctx(sb, J=J, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, seed=7, **kw)
     sb.sbqa_step(ctx, steps_before)
     X, Y = sb.sbqa_get_state(ctx)
@@ -444,12 +461,15 @@ def test_large_cubic_lattice(sb, orc):
     np.testing.assert_allclose(orc.energy(sp, csr=csr, h=h), Eb, rtol=1e-12, atol=1e-9)
 
 
-def test_full_size_fp8_sk(sb, orc):
-    """SK N = 16384, J = +-1 as e4m3, R = 16 x 16 runs: sampled rows, fields exact."""
+@pytest.mark.parametrize("packing", ["packed", "bytes"])
+def test_full_size_fp8_sk(sb, orc, packing):
+    """SK N = 16384, J = +-1 bit-packed or as e4m3 bytes, R = 16 x 16 runs:
+    sampled rows, fields exact."""
     N, R, runs = 16384, 16, 16
-    _log("full-size fp8 SK N=%d" % N)
+    _log("full-size fp8 SK N=%d J %s" % (N, packing))
     J = inst.sk_pm1(N, 3001)
-    _full_size_step(sb, orc, J=J, N=N, R=R, runs=runs, prec=sb.PREC_FP8, S=10000, exact_fields=True, nrows=24)
+    _full_size_step(sb, orc, J=J, N=N, R=R, runs=runs, prec=sb.PREC_FP8, S=10000, exact_fields=True, nrows=24,
+                    j_packing=sb.JPACK_AUTO if packing == "packed" else sb.JPACK_BYTES)
 
 
 def test_full_size_int8_sidon(sb, orc):
