@@ -52,7 +52,7 @@ class _Problem(ct.Structure):
                 ("dense", ct.c_void_p), ("row_ptr", ct.c_void_p), ("col", ct.c_void_p),
                 ("val", ct.c_void_p), ("h", ct.c_void_p),
                 ("dt", ct.c_double), ("a0", ct.c_double), ("c0", ct.c_double),
-                ("fmode", ct.c_int32)]
+                ("fmode", ct.c_int32), ("n3", ct.c_int64), ("tri", ct.c_void_p), ("K", ct.c_void_p)]
 
 
 def _declare(L):
@@ -77,6 +77,10 @@ def _declare(L):
     L.orc_run.restype = i32
     L.orc_auto_c0_dense.argtypes, L.orc_auto_c0_dense.restype = [i32, vp], d
     L.orc_auto_c0_csr.argtypes, L.orc_auto_c0_csr.restype = [i32, vp, vp, vp], d
+    L.orc_energy3.argtypes = [i32, i64, vp, vp, vp, i32, vp]
+    L.orc_bruteforce_hubo.argtypes, L.orc_bruteforce_hubo.restype = [i32, vp, vp, i64, vp, vp, vp], d
+    L.orc_fields3.argtypes = [i32, i32, i64, vp, vp, vp, vp]
+    L.orc_auto_c0_hubo.argtypes, L.orc_auto_c0_hubo.restype = [i32, vp, vp, vp, i64, vp], d
 
 
 def _p(a):
@@ -133,8 +137,9 @@ def jperp_linear_table(start: float, end: float, S: int) -> np.ndarray:
 
 
 # ------------------------------------------------------------------ energies
-def energy(spins, J=None, h=None, csr=None) -> np.ndarray:
-    """E(s) = -1/2 s^T J s - h^T s for each row of spins (count, N)."""
+def energy(spins, J=None, h=None, csr=None, tri=None, K=None) -> np.ndarray:
+    """E(s) = -1/2 s^T J s - h^T s - sum_t K_t s_l s_m s_n for each row of
+    spins (count, N); tri (n3, 3) lists each triple once."""
     s = np.ascontiguousarray(np.atleast_2d(spins), dtype=np.int8)
     count, N = s.shape
     E = np.empty(count)
@@ -145,7 +150,23 @@ def energy(spins, J=None, h=None, csr=None) -> np.ndarray:
     else:
         J = _f64(J)
         lib().orc_energy_dense(N, _p(J), _p(h), _p(s), count, _p(E))
+    if tri is not None and len(tri):
+        tri, K = _i32(tri), _f64(K)
+        E3 = np.empty(count)
+        lib().orc_energy3(N, len(K), _p(tri), _p(K), _p(s), count, _p(E3))
+        E = E + E3
     return E
+
+
+def bruteforce_hubo(J, h=None, tri=None, K=None):
+    """Exhaustive minimum with three-body terms (N <= 24). Returns (E_min, spins)."""
+    J = _f64(J)
+    N = J.shape[0]
+    tri = _i32(np.zeros((0, 3)) if tri is None else tri)
+    K = _f64(np.zeros(0) if K is None else K)
+    best = np.empty(N, dtype=np.int8)
+    E = lib().orc_bruteforce_hubo(N, _p(J), _p(_f64(h)), len(K), _p(tri), _p(K), _p(best))
+    return E, best
 
 
 def bruteforce(J, h=None):
@@ -157,8 +178,13 @@ def bruteforce(J, h=None):
     return E, best
 
 
-def auto_c0(J=None, csr=None) -> float:
-    """c0 = 0.5 / (sqrt(N) * rms of off-diagonal J)."""
+def auto_c0(J=None, csr=None, K=None) -> float:
+    """c0 = 0.5 / (sqrt(N) * rms of off-diagonal J); with three-body weights K
+    (CSR two-body part) the field-variance rule of orc_auto_c0_hubo."""
+    if K is not None and len(K):
+        rp, col, val = _i32(csr[0]), _i32(csr[1]), _f64(csr[2])
+        K = _f64(K)
+        return lib().orc_auto_c0_hubo(rp.size - 1, _p(rp), _p(col), _p(val), len(K), _p(K))
     if csr is not None:
         rp, col, val = _i32(csr[0]), _i32(csr[1]), _f64(csr[2])
         return lib().orc_auto_c0_csr(rp.size - 1, _p(rp), _p(col), _p(val))
@@ -174,8 +200,8 @@ def apply_f(fmode: int, delta, x) -> np.ndarray:
     return g
 
 
-def fields(G, J=None, csr=None) -> np.ndarray:
-    """Phi = J G for G of shape (N, C)."""
+def fields(G, J=None, csr=None, tri=None, K=None) -> np.ndarray:
+    """Phi = J G (+ the three-body sums) for G of shape (N, C)."""
     G = _f64(G)
     N, C = G.shape
     Phi = np.empty_like(G)
@@ -185,6 +211,9 @@ def fields(G, J=None, csr=None) -> np.ndarray:
     else:
         J = _f64(J)
         lib().orc_fields_dense(N, C, _p(J), _p(G), _p(Phi))
+    if tri is not None and len(tri):
+        tri, K = _i32(tri), _f64(K)
+        lib().orc_fields3(N, C, len(K), _p(tri), _p(K), _p(G), _p(Phi))
     return Phi
 
 
@@ -193,20 +222,23 @@ class Problem:
     """An SBQA problem for the oracle: couplings, fields and constants."""
 
     def __init__(self, N, R, runs, J=None, csr=None, h=None, dt=0.5, a0=1.0, c0=None,
-                 fmode=F_TERNARY):
+                 fmode=F_TERNARY, tri=None, K=None):
         self.N, self.R, self.runs = int(N), int(R), int(runs)
         self.C = self.R * self.runs
         self.J = _f64(J)
         self.csr = None if csr is None else (_i32(csr[0]), _i32(csr[1]), _f64(csr[2]))
         self.h = _f64(h)
+        self.tri = _i32(np.zeros((0, 3)) if tri is None else tri)
+        self.K = _f64(np.zeros(0) if K is None else K)
         self.dt, self.a0 = float(dt), float(a0)
-        self.c0 = float(auto_c0(J=self.J, csr=self.csr) if c0 is None else c0)
+        self.c0 = float(auto_c0(J=self.J, csr=self.csr, K=self.K) if c0 is None else c0)
         self.fmode = int(fmode)
         self._s = _Problem(self.N, self.R, self.runs, _p(self.J),
                            _p(self.csr[0]) if self.csr else None,
                            _p(self.csr[1]) if self.csr else None,
                            _p(self.csr[2]) if self.csr else None,
-                           _p(self.h), self.dt, self.a0, self.c0, self.fmode)
+                           _p(self.h), self.dt, self.a0, self.c0, self.fmode,
+                           len(self.K), _p(self.tri) if len(self.K) else None, _p(self.K) if len(self.K) else None)
 
     def step(self, X, Y, a_n, delta_n, jperp_r, want_phi=False):
         """One step (Eqs. 6-7 + wall) from (X, Y); returns new (X, Y[, Phi])."""

@@ -23,6 +23,13 @@
  *    GPU state, on the binary32-rounded value.
  *  - Energy: E(s) = -1/2 s^T J s - h^T s (the SBM potential of Eq. 2 at the
  *    hypercube corners), readout s_i = sign(x_i) with sign(0) = +1.
+ *  - Three-body terms (the HUBO Hamiltonian of Eq. 11, Sec. III.B, native rather than
+ *    reduced to QUBO form): a list of triples (l, m, n) of distinct spins with
+ *    weights K, each triple once, adds -K s_l s_m s_n to the energy (the sign
+ *    convention of the two-body part: pass -J, -K for the paper's
+ *    H = sum J s s + sum K s s s). Its coupling sum is minus the derivative of
+ *    that energy with the other two spins replaced by f: spin l receives
+ *    K f_m f_n, and likewise m and n.
  *
  * Parity pins: every function here is pinned by tests against closed forms,
  * brute force, Hamilton's equations for Eq. 4 and special cases (Eq. 3).
@@ -129,6 +136,43 @@ void orc_energy_csr(int32_t N, const int32_t *row_ptr, const int32_t *col,
     }
 }
 
+/* Three-body part of the energy, -sum_t K_t s_l s_m s_n, for count
+ * configurations (count x N, int8 +-1); tri is n3 x 3 (each triple once). */
+void orc_energy3(int32_t N, int64_t n3, const int32_t *tri, const double *K,
+                 const int8_t *s, int32_t count, double *E) {
+    #pragma omp parallel for schedule(static)
+    for (int32_t m = 0; m < count; ++m) {
+        const int8_t *sm = s + (int64_t)m * N;
+        double cub = 0.0;
+        for (int64_t t = 0; t < n3; ++t)
+            cub += K[t] * (double)sm[tri[3 * t]] * (double)sm[tri[3 * t + 1]] * (double)sm[tri[3 * t + 2]];
+        E[m] = -cub;
+    }
+}
+
+/* Exhaustive minimum of the full energy (two-body dense J, h, three-body
+ * triples) for N <= 24 by direct evaluation of every configuration, in
+ * binary counting order (bit i of the counter set = spin i is -1; ties keep
+ * the first minimum met). */
+double orc_bruteforce_hubo(int32_t N, const double *J, const double *h, int64_t n3,
+                           const int32_t *tri, const double *K, int8_t *best) {
+    if (N < 1 || N > 24) return NAN;
+    int8_t *s = (int8_t *)malloc((size_t)N);
+    double Emin = INFINITY;
+    for (uint64_t g = 0; g < (1ull << N); ++g) {
+        for (int32_t i = 0; i < N; ++i) s[i] = ((g >> i) & 1u) ? -1 : 1;
+        double E = 0.0;
+        for (int32_t i = 0; i < N; ++i) {
+            for (int32_t j = 0; j < N; ++j) E += -0.5 * J[(int64_t)i * N + j] * s[i] * s[j];
+            if (h) E -= h[i] * s[i];
+        }
+        for (int64_t t = 0; t < n3; ++t) E -= K[t] * s[tri[3 * t]] * s[tri[3 * t + 1]] * s[tri[3 * t + 2]];
+        if (E < Emin) { Emin = E; memcpy(best, s, (size_t)N); }
+    }
+    free(s);
+    return Emin;
+}
+
 /* Exhaustive ground state for N <= 30 (Gray-code order; ties keep the first
  * minimum met). Returns the minimum energy and writes one minimiser. */
 double orc_bruteforce_dense(int32_t N, const double *J, const double *h, int8_t *best) {
@@ -221,6 +265,9 @@ typedef struct {
     const double *h;                           /* N, or NULL */
     double dt, a0, c0;
     int32_t fmode;
+    int64_t n3;                                /* three-body triples (may be 0) */
+    const int32_t *tri;                        /* n3 x 3 spin indices */
+    const double *K;                           /* n3 weights */
 } orc_problem;
 
 /* Coupling sum of row i for all C columns: phi[c] = sum_j J_ij G[j][c]. */
@@ -238,6 +285,35 @@ static void field_row(const orc_problem *P, int32_t i, const double *G, double *
             const double w = P->val[p];
             const double *g = G + (int64_t)P->col[p] * C;
             for (int32_t c = 0; c < C; ++c) phi[c] += w * g[c];
+        }
+    }
+}
+
+/* Three-body coupling sums added to Phi (N x C): for every triple t in list
+ * order, spin l gains K_t G[m] G[n], spin m gains K_t G[l] G[n] and spin n
+ * gains K_t G[l] G[m]. */
+void orc_fields3(int32_t N, int32_t C, int64_t n3, const int32_t *tri, const double *K,
+                 const double *G, double *Phi) {
+    (void)N;
+    for (int64_t t = 0; t < n3; ++t) {
+        const int32_t v[3] = {tri[3 * t], tri[3 * t + 1], tri[3 * t + 2]};
+        for (int e = 0; e < 3; ++e) {
+            const double *ga = G + (int64_t)v[(e + 1) % 3] * C, *gb = G + (int64_t)v[(e + 2) % 3] * C;
+            double *out = Phi + (int64_t)v[e] * C;
+            for (int32_t c = 0; c < C; ++c) out[c] += K[t] * (ga[c] * gb[c]);
+        }
+    }
+}
+
+/* The three-body part of the coupling sum of one row i (list order). */
+static void field3_row(const orc_problem *P, int32_t i, const double *G, double *phi) {
+    const int32_t C = P->R * P->runs;
+    for (int64_t t = 0; t < P->n3; ++t) {
+        const int32_t *v = P->tri + 3 * t;
+        for (int e = 0; e < 3; ++e) {
+            if (v[e] != i) continue;
+            const double *ga = G + (int64_t)v[(e + 1) % 3] * C, *gb = G + (int64_t)v[(e + 2) % 3] * C;
+            for (int32_t c = 0; c < C; ++c) phi[c] += P->K[t] * (ga[c] * gb[c]);
         }
     }
 }
@@ -289,11 +365,12 @@ void orc_step(const orc_problem *P, double *X, double *Y, double a_n, float delt
     memcpy(X0, X, sizeof(double) * (size_t)NC);
     orc_apply_f(P->fmode, delta_n, NC, X0, G);
     #pragma omp parallel for schedule(static)
-    for (int32_t i = 0; i < N; ++i) {
-        field_row(P, i, G, Phi + (int64_t)i * C);
+    for (int32_t i = 0; i < N; ++i) field_row(P, i, G, Phi + (int64_t)i * C);
+    if (P->n3) orc_fields3(N, C, P->n3, P->tri, P->K, G, Phi);
+    #pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < N; ++i)
         update_row(P, i, X0, Y, Phi + (int64_t)i * C, a_n, jperp_r,
                    X + (int64_t)i * C, Y + (int64_t)i * C);
-    }
     if (Phi_out) memcpy(Phi_out, Phi, sizeof(double) * (size_t)NC);
 }
 
@@ -311,6 +388,7 @@ void orc_step_rows(const orc_problem *P, const double *X, const double *Y, doubl
     #pragma omp parallel for schedule(static)
     for (int32_t q = 0; q < nrows; ++q) {
         field_row(P, rows[q], G, Phio + (int64_t)q * C);
+        if (P->n3) field3_row(P, rows[q], G, Phio + (int64_t)q * C);
         update_row(P, rows[q], X, Y, Phio + (int64_t)q * C, a_n, jperp_r,
                    Xo + (int64_t)q * C, Yo + (int64_t)q * C);
     }
@@ -324,6 +402,12 @@ static void readout_energies(const orc_problem *P, const double *X, int8_t *S, d
             S[(int64_t)c * N + i] = X[(int64_t)i * C + c] >= 0.0 ? 1 : -1;
     if (P->dense) orc_energy_dense(N, P->dense, P->h, S, C, E);
     else orc_energy_csr(N, P->row_ptr, P->col, P->val, P->h, S, C, E);
+    if (P->n3) {
+        double *E3 = (double *)malloc(sizeof(double) * (size_t)C);
+        orc_energy3(N, P->n3, P->tri, P->K, S, C, E3);
+        for (int32_t c = 0; c < C; ++c) E[c] += E3[c];
+        free(E3);
+    }
 }
 
 /*
@@ -393,4 +477,21 @@ double orc_auto_c0_csr(int32_t N, const int32_t *row_ptr, const int32_t *col, co
             if (col[p] != i) ss += val[p] * val[p];
     if (ss == 0.0 || N < 2) return 0.0;
     return 0.5 / (sqrt((double)N) * sqrt(ss / ((double)N * (double)(N - 1))));
+}
+
+/*
+ * c0 with three-body terms: 0.5 / sqrt(mean_i Var(Phi_i) * N/(N-1)) where, for
+ * independent uniform random spins, Var(Phi_i) = sum_j J_ij^2 + sum_{t ni i}
+ * K_t^2; without triples this is the two-body rule above. Two-body part from
+ * CSR (diagonal excluded); the triples count once per member spin.
+ */
+double orc_auto_c0_hubo(int32_t N, const int32_t *row_ptr, const int32_t *col, const double *val,
+                        int64_t n3, const double *K) {
+    double ss = 0.0;
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+            if (col[p] != i) ss += val[p] * val[p];
+    for (int64_t t = 0; t < n3; ++t) ss += 3.0 * K[t] * K[t];
+    if (ss == 0.0 || N < 2) return 0.0;
+    return 0.5 / sqrt(ss / (double)(N - 1));
 }

@@ -22,6 +22,14 @@ Instance families stand in for the paper's (whose data are not available):
                       known energy (frustrated plaquettes, hidden by a gauge), for
                       optimality gaps and time-to-epsilon without a reference
                       solver.
+* ``heavy_hex`` + ``hubo_heavy_hex``  native higher-order (3-body) instances on a
+                      heavy-hexagon graph, shaped like the HUBO benchmark of
+                      Sec. III.B: one set of vertex-disjoint 2-body edges and
+                      several sets of vertex-disjoint 3-body paths, weights from
+                      a normal, Cauchy or symmetrised Pareto law (the SWAP layers
+                      of the original construction are not reproduced).
+* ``random_hubo``     small random 2-body + 3-body instances with integer
+                      weights (exhaustive checks).
 
 Coupling convention everywhere: J is symmetric with a zero diagonal, stored
 row-major as float64 (dense) or as CSR (row_ptr int32[N+1], col int32[nnz]
@@ -35,6 +43,7 @@ __all__ = [
     "sk_pm1", "dense_gaussian", "sidon28_dense", "SIDON28", "regular_graph", "gaussian_edges",
     "edges_to_csr", "csr_to_dense", "dense_to_csr", "gaussian_fields",
     "uniform_state", "spins_pm1", "square_lattice", "cubic_lattice", "planted_square",
+    "heavy_hex", "hubo_heavy_hex", "random_hubo",
 ]
 
 
@@ -264,3 +273,94 @@ def planted_square(L: int, seed: int, p_frustrated: float = 0.5):
     s = (rng.integers(0, 2, size=L * L) * 2 - 1).astype(np.int8)
     w = w * s[edges[:, 0]] * s[edges[:, 1]]
     return edges, w, s, float(E0)
+
+
+def heavy_hex(rows: int, cols: int) -> tuple:
+    """Heavy-hexagon graph: a brick-wall honeycomb of rows x cols degree-<=3
+    sites (horizontal bonds along each row, vertical bonds where row + column
+    is even) with one extra degree-2 site on every bond. Returns (N, edges
+    (n, 2) int64 with u < v); honeycomb site (i, j) is i*cols + j, the bond
+    sites follow in bond order."""
+    if rows < 2 or cols < 2:
+        raise ValueError("heavy_hex needs rows, cols >= 2")
+    site = lambda i, j: i * cols + j
+    bonds = [(site(i, j), site(i, j + 1)) for i in range(rows) for j in range(cols - 1)]
+    bonds += [(site(i, j), site(i + 1, j)) for i in range(rows - 1) for j in range(cols) if (i + j) % 2 == 0]
+    n0 = rows * cols
+    E = []
+    for q, (u, v) in enumerate(bonds):
+        m = n0 + q
+        E.append((u, m))
+        E.append((v, m))
+    E = np.sort(np.asarray(E, dtype=np.int64), axis=1)
+    return n0 + len(bonds), E
+
+
+def _weights(rng, n: int, dist: str) -> np.ndarray:
+    if dist == "normal":
+        return rng.standard_normal(n)
+    if dist == "cauchy":
+        return rng.standard_cauchy(n)
+    if dist == "pareto":   # symmetrised Pareto: shape 2, scale 1, random sign
+        return (1.0 + rng.pareto(2.0, n)) * (rng.integers(0, 2, n) * 2.0 - 1.0)
+    if dist == "int":      # integers in {-5..-1, 1..5}
+        return rng.integers(1, 6, n) * (rng.integers(0, 2, n) * 2.0 - 1.0)
+    raise ValueError("unknown weight law " + dist)
+
+
+def hubo_heavy_hex(rows: int, cols: int, seed: int, dist: str = "normal", n2_sets: int = 1, n3_sets: int = 6):
+    """Native 3-body instance on heavy_hex(rows, cols).
+
+    2-body terms: n2_sets greedy maximal matchings of the edges (each a set of
+    vertex-disjoint pairs, drawn in random edge order, later sets among the
+    edges not yet taken). 3-body terms: n3_sets sets of vertex-disjoint paths
+    l - m - n (m adjacent to both), each set a greedy maximal selection in
+    random order, a path used at most once. Weights from `dist` (normal,
+    cauchy, pareto, int), one per term.
+
+    Returns (N, edges (n2, 2), w2 (n2,), triples (n3, 3) int64 sorted within
+    each triple, K (n3,)); the energy is -sum w2 s_u s_v - sum K s_l s_m s_n
+    (the library's sign convention)."""
+    rng = _rng(seed)
+    N, E = heavy_hex(rows, cols)
+    adj = [[] for _ in range(N)]
+    for u, v in E:
+        adj[u].append(int(v))
+        adj[v].append(int(u))
+    taken = np.zeros(len(E), dtype=bool)
+    pairs = []
+    for _ in range(n2_sets):
+        used = np.zeros(N, dtype=bool)
+        for q in rng.permutation(len(E)):
+            u, v = E[q]
+            if taken[q] or used[u] or used[v]:
+                continue
+            taken[q] = used[u] = used[v] = True
+            pairs.append((u, v))
+    paths = [(a, m, b) for m in range(N) for x, a in enumerate(adj[m]) for b in adj[m][x + 1:]]
+    ptaken = np.zeros(len(paths), dtype=bool)
+    tris = []
+    for _ in range(n3_sets):
+        used = np.zeros(N, dtype=bool)
+        for q in rng.permutation(len(paths)):
+            t = paths[q]
+            if ptaken[q] or used[t[0]] or used[t[1]] or used[t[2]]:
+                continue
+            ptaken[q] = True
+            used[list(t)] = True
+            tris.append(sorted(t))
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    tris = np.asarray(tris, dtype=np.int64).reshape(-1, 3)
+    return N, pairs, _weights(rng, len(pairs), dist), tris, _weights(rng, len(tris), dist)
+
+
+def random_hubo(N: int, n2: int, n3: int, seed: int):
+    """Random instance on N spins: n2 distinct pairs and n3 distinct triples
+    (uniform), integer weights in {-5..-1, 1..5}, and integer h in [-2, 2].
+    Returns (edges (n2, 2), w2, triples (n3, 3), K, h)."""
+    rng = _rng(seed)
+    allp = [(u, v) for u in range(N) for v in range(u + 1, N)]
+    allt = [(a, b, c) for a in range(N) for b in range(a + 1, N) for c in range(b + 1, N)]
+    P = np.asarray([allp[q] for q in rng.choice(len(allp), n2, replace=False)], dtype=np.int64).reshape(-1, 2)
+    T = np.asarray([allt[q] for q in rng.choice(len(allt), n3, replace=False)], dtype=np.int64).reshape(-1, 3)
+    return P, _weights(rng, n2, "int"), T, _weights(rng, n3, "int"), rng.integers(-2, 3, N).astype(np.float64)

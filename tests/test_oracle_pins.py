@@ -421,3 +421,129 @@ def test_regular_graph_generator():
     assert np.all(np.diff(rp) == d)
     D = inst.csr_to_dense(N, rp, col, val)
     assert np.array_equal(D, D.T) and np.all(np.diag(D) == 0)
+
+
+# ------------------------------------------------- three-body terms (HUBO)
+def _hubo_csr(N, pairs, w2):
+    pairs = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    return inst.edges_to_csr(N, pairs, np.asarray(w2, dtype=float))
+
+
+def test_hubo_energy_hand_fixture(orc):
+    """Hand-computed energies with native three-body terms (Eq. 11 in the sign
+    convention of Eq. 2); dense and CSR two-body parts agree; exhaustive
+    minimum where given."""
+    with open(os.path.join(GOLD, "hubo_hand.json")) as f:
+        cases = json.load(f)["cases"]
+    for case in cases:
+        N = case["N"]
+        csr = _hubo_csr(N, case["pairs"], case["w2"])
+        J = inst.csr_to_dense(N, *csr)
+        h = np.array(case["h"], dtype=float)
+        T, K = np.array(case["triples"]), np.array(case["K"], dtype=float)
+        s = np.array(case["spins"], dtype=np.int8)
+        want = np.array(case["E"], dtype=float)
+        assert np.array_equal(orc.energy(s, csr=csr, h=h, tri=T, K=K), want), case["name"]
+        assert np.array_equal(orc.energy(s, J=J, h=h, tri=T, K=K), want), case["name"]
+        if "ground_E" in case:
+            assert orc.bruteforce_hubo(J, h, T, K)[0] == case["ground_E"]
+
+
+def test_hubo_flip_identity_pins_three_body_fields(orc):
+    """The energy is linear in each s_i, so flipping s_i changes it by
+    2 s_i (phi_i + h_i), phi the coupling sum at f = s. With three-body terms
+    this pins the oracle's three-body coupling sum (each triple feeds all three
+    members with the product of the other two) against its energy."""
+    N = 14
+    P, w2, T, K, h = inst.random_hubo(N, 20, 30, 61)
+    K = K + 0.25 * inst.gaussian_fields(len(K), 1.0, 62)   # non-integer weights too
+    csr = _hubo_csr(N, P, w2)
+    s = inst.spins_pm1(25, N, 63)
+    phi = orc.fields(s.T.astype(float), csr=csr, tri=T, K=K)          # (N, count)
+    E0 = orc.energy(s, csr=csr, h=h, tri=T, K=K)
+    for i in range(N):
+        t = s.copy()
+        t[:, i] = -t[:, i]
+        dE = orc.energy(t, csr=csr, h=h, tri=T, K=K) - E0
+        np.testing.assert_allclose(dE, 2.0 * s[:, i] * (phi[i] + h[i]), rtol=1e-12, atol=1e-12)
+
+
+def test_hubo_bruteforce_cross_checks(orc):
+    """Plain enumeration (bruteforce_hubo) equals the Gray-code search without
+    triples, and a numpy enumeration over all 2^N states with triples."""
+    N = 11
+    P, w2, T, K, h = inst.random_hubo(N, 18, 25, 71)
+    J = inst.csr_to_dense(N, *_hubo_csr(N, P, w2))
+    Eg, _ = orc.bruteforce(J, h)
+    assert orc.bruteforce_hubo(J, h)[0] == Eg
+    states = np.array(list(itertools.product([1, -1], repeat=N)), dtype=np.int8)
+    Sd = states.astype(float)
+    E_all = -0.5 * np.einsum("ci,ij,cj->c", Sd, J, Sd) - Sd @ h - (Sd[:, T[:, 0]] * Sd[:, T[:, 1]] * Sd[:, T[:, 2]]) @ K
+    Eh, sh = orc.bruteforce_hubo(J, h, T, K)
+    assert Eh == E_all.min()
+    assert orc.energy(sh[None], J=J, h=h, tri=T, K=K)[0] == Eh
+
+
+def test_hubo_special_cases(orc):
+    """No triples: the three-body run is bit-identical to the Ising run.
+    Reordering the triple list or the members inside a triple changes nothing
+    (integer weights, ternary f: exact sums). c0 with triples follows the
+    field-variance rule and reduces to the two-body rule."""
+    N, R, runs, S = 16, 4, 3, 120
+    P, w2, T, K, h = inst.random_hubo(N, 24, 30, 81)
+    csr = _hubo_csr(N, P, w2)
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.2, 82)
+    jt = np.tile(orc.jperp_linear_table(0.5, 0.0, S), (runs, 1))
+    c0 = 0.07
+    a = orc.Problem(N, R, runs, csr=csr, h=h, c0=c0).run(X0, Y0, S, jt)
+    b = orc.Problem(N, R, runs, csr=csr, h=h, c0=c0, tri=T[:0], K=K[:0]).run(X0, Y0, S, jt)
+    assert np.array_equal(a["X"], b["X"]) and np.array_equal(a["best_E"], b["best_E"])
+    perm = np.random.default_rng(83).permutation(len(K))
+    T2 = T[perm][:, [2, 0, 1]]
+    r1 = orc.Problem(N, R, runs, csr=csr, h=h, c0=c0, tri=T, K=K).run(X0, Y0, S, jt)
+    r2 = orc.Problem(N, R, runs, csr=csr, h=h, c0=c0, tri=T2, K=K[perm]).run(X0, Y0, S, jt)
+    assert np.array_equal(r1["X"], r2["X"]) and np.array_equal(r1["best_E"], r2["best_E"])
+    assert not np.array_equal(r1["X"], a["X"])
+    # c0: 0.5 / sqrt((sum_{i!=j} J_ij^2 + 3 sum K^2) / (N - 1))
+    ss = 2.0 * np.sum(w2 ** 2) + 3.0 * np.sum(K ** 2)
+    assert orc.auto_c0(csr=csr, K=K) == pytest.approx(0.5 / math.sqrt(ss / (N - 1)), rel=1e-14)
+    assert orc.auto_c0(csr=csr, K=K[:0]) == orc.auto_c0(csr=csr)
+
+
+def test_hubo_reaches_bruteforce_ground_state(orc):
+    """The SBQA iteration with native three-body coupling sums (ternary f,
+    auto-tuned J_perp of Sec. II.B) finds the exhaustive minimum of small
+    random instances."""
+    N, R, runs, S = 14, 8, 16, 800
+    for seed in (91, 92):
+        P, w2, T, K, h = inst.random_hubo(N, 20, 24, seed)
+        csr = _hubo_csr(N, P, w2)
+        J = inst.csr_to_dense(N, *csr)
+        Eg, _ = orc.bruteforce_hubo(J, h, T, K)
+        Pb = orc.Problem(N, R, runs, csr=csr, h=h, tri=T, K=K, fmode=orc.F_TERNARY)
+        rng = np.random.default_rng(seed + 100)
+        betas, alphas = rng.uniform(0.5, 1.5, runs), rng.uniform(0.5, 1.0, runs)
+        jt = np.stack([orc.jperp_paper_table(b, a, 1.0, S) for b, a in zip(betas, alphas)])
+        X0, Y0 = inst.uniform_state(N, R * runs, 0.1, seed + 200)
+        res = Pb.run(X0, Y0, S, jt)
+        assert res["best_E"].min() == Eg, (seed, res["best_E"].min(), Eg)
+        for r in range(runs):
+            assert orc.energy(res["best_s"][r][None], csr=csr, h=h, tri=T, K=K)[0] == res["best_E"][r]
+
+
+def test_heavy_hex_generator():
+    """Heavy-hex graph: honeycomb sites of degree <= 3, bond sites of degree 2,
+    bipartite between the two; HUBO terms are vertex-disjoint inside each set
+    and every triple is a path of the graph."""
+    N, E = inst.heavy_hex(6, 7)
+    n0 = 42
+    deg = np.bincount(E.ravel(), minlength=N)
+    assert np.all(deg[n0:] == 2) and np.all(deg[:n0] <= 3) and np.all(deg[:n0] >= 2)
+    assert np.all((E[:, 0] < n0) & (E[:, 1] >= n0))
+    N2, P, w2, T, K = inst.hubo_heavy_hex(6, 7, 5, n2_sets=1, n3_sets=6)
+    assert N2 == N and len(set(map(tuple, P))) == len(P) and len(set(map(tuple, T))) == len(T)
+    assert len(np.unique(P.ravel())) == P.size          # one matching
+    es = set(map(tuple, E))
+    for a, b, c in T:
+        links = sum((min(u, v), max(u, v)) in es for u, v in ((a, b), (b, c), (a, c)))
+        assert links == 2                                # a path l - m - n
