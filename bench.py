@@ -86,6 +86,16 @@ def make_workload(name: str):
                 "ternary f, fp32 CSR" % ("cubic" if name == "cubic88" else "square", L, N))
         return dict(csr=csr, h=h, N=N, R=R, runs=runs, S=S, prec=None, fmode=0, desc=desc,
                     d=6 if name == "cubic88" else 4, dtype="f32")
+    if name == "hubo_hh":
+        # native three-body instance on a heavy-hex graph (Sec. III.B HUBO family, scaled up):
+        # 200 x 200 honeycomb with a site on every bond, one matching of 2-body terms and six
+        # sets of vertex-disjoint 3-body paths, N(0,1) weights
+        N, P2, w2, T, K = inst.hubo_heavy_hex(200, 200, 2301, dist="normal")
+        R, runs, S = 16, 8, 1000
+        desc = ("heavy-hex HUBO N=%d (%d 2-body, %d 3-body terms, N(0,1)), R=16 x 8 runs, 1000 steps, "
+                "ternary f, fp32 CSR + 3-body lists" % (N, len(P2), len(T)))
+        return dict(csr=inst.edges_to_csr(N, P2, w2), tri=T, K=K, h=None, N=N, R=R, runs=runs, S=S, prec=None,
+                    fmode=0, desc=desc, d=2, dtype="f32")
     if name == "sk64":
         N, R, runs, S = 64, 8, 4, 1000
         return dict(J=inst.sk_pm1(N, 1001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32", fmode=0,
@@ -101,7 +111,7 @@ def create(sb, w, seed, loop_kernel="auto"):
         kw["precision"] = getattr(sb, w["prec"])
     if w.get("j_packing"):
         kw["j_packing"] = getattr(sb, w["j_packing"])
-    return sb.sbqa_create(J=w.get("J"), csr=w.get("csr"), h=w.get("h"), **kw)
+    return sb.sbqa_create(J=w.get("J"), csr=w.get("csr"), h=w.get("h"), tri=w.get("tri"), K=w.get("K"), **kw)
 
 
 def algorithmic_bytes(w, info):
@@ -110,7 +120,10 @@ def algorithmic_bytes(w, info):
     if info["path"] == "csr_fp32":
         nnz = len(w["csr"][1])
         # x, y read + write (fp32) + int8 operand written once and read once
-        return N * C * (16 + 2) + 4 * (N + 1) + 8 * nnz + 4 * N
+        b = N * C * (16 + 2) + 4 * (N + 1) + 8 * nnz + 4 * N
+        if w.get("K") is not None:   # three-body lists: per member entry two indices and a weight
+            b += 4 * (N + 1) + 3 * len(w["K"]) * 12
+        return b
     eb = {"dense_fp8": 1, "dense_fp8_packed": 1, "dense_int8": 1, "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
     jb = N * N / 8 if info["path"] == "dense_fp8_packed" else N * N * eb
     # GEMM: J streamed once + operand read once + fp32 field partial written
@@ -196,7 +209,7 @@ def cpu_baseline(w, target_s=15.0):
     oracle.build()
     N, R, runs, S = w["N"], w["R"], w["runs"], w["S"]
     P = oracle.Problem(N, R, runs, J=w.get("J"), csr=w.get("csr"), h=w.get("h"), dt=0.5, a0=1.0, c0=None,
-                       fmode=w["fmode"])
+                       fmode=w["fmode"], tri=w.get("tri"), K=w.get("K"))
     jt = oracle.jperp_linear_table(0.5, 0.0, S)
     X0, Y0 = inst.uniform_state(N, R * runs, 0.1, 99)
     X, Y = X0.astype(np.float64), Y0.astype(np.float64)

@@ -109,13 +109,27 @@ typedef enum { SBQA_JPACK_AUTO = 0, SBQA_JPACK_BYTES = 1 } sbqa_j_packing;
  * J must be symmetric with a zero diagonal and finite entries.
  *   dense    N*N float64, row-major.
  *   row_ptr  N+1 int32, col nnz int32 (0 <= col < N), val nnz float64;
- *            both (i,j) and (j,i) stored; duplicate entries are rejected. */
+ *            both (i,j) and (j,i) stored; duplicate entries are rejected.
+ * Optional native three-body terms (the cubic part of the HUBO Hamiltonian,
+ * Eq. 11; CSR couplings only, nnz may be 0):
+ *   n3       number of triples (0: none)
+ *   tri      n3*3 int32 spin indices, three distinct per triple, each triple
+ *            listed once
+ *   K        n3 float64 finite weights
+ * Energy E(s) = -1/2 s^T J s - h^T s - sum_t K_t s_l s_m s_n, so the paper's
+ * H = sum J s s + sum K s s s is J -> -J (both entries of each pair) and
+ * K -> -K. In the equations of motion spin l receives K f(x_m) f(x_n) in its
+ * coupling sum (likewise m and n). Three-body instances run on the streaming
+ * CSR kernel (no resident loop). */
 typedef struct {
     const double *dense;
     const int32_t *row_ptr;
     const int32_t *col;
     const double *val;
     int64_t nnz;
+    int64_t n3;
+    const int32_t *tri;
+    const double *K;
 } sbqa_coupling;
 
 /* Hyper-parameters of one solve. Start from sbqa_schedule_default(). */
@@ -123,7 +137,9 @@ typedef struct {
     uint32_t steps;          /* S >= 1 (total evolution T = steps*dt)              */
     double dt;               /* > 0                                                */
     double a0;               /* > 0, Eq. 3 / Eq. 6                                 */
-    double c0;               /* > 0; <= 0 selects 0.5/(sqrt(N) rms(J_offdiag))     */
+    double c0;               /* > 0; <= 0 selects 0.5/(sqrt(N) rms(J_offdiag)); with
+                                three-body terms 0.5/sqrt(v/(N-1)), v = sum of
+                                J_ij^2 over i != j plus 3 sum K_t^2            */
     int32_t fmode;           /* sbqa_fmode                                         */
     double delta_max;        /* Eq. 8 threshold factor (paper: 0.7)                */
     int32_t jp_kind;         /* sbqa_jpkind                                        */

@@ -33,7 +33,8 @@ class SbqaError(RuntimeError):
 
 class Coupling(ct.Structure):
     _fields_ = [("dense", ct.c_void_p), ("row_ptr", ct.c_void_p), ("col", ct.c_void_p),
-                ("val", ct.c_void_p), ("nnz", ct.c_int64)]
+                ("val", ct.c_void_p), ("nnz", ct.c_int64), ("n3", ct.c_int64), ("tri", ct.c_void_p),
+                ("K", ct.c_void_p)]
 
 
 class Schedule(ct.Structure):
@@ -129,9 +130,17 @@ def make_schedule(**kw):
     return s, keep
 
 
-def _coupling(J=None, csr=None):
+def _coupling(J=None, csr=None, tri=None, K=None):
+    """tri (n3, 3) and K (n3,): optional three-body terms (CSR couplings)."""
     keep = []
     c = Coupling()
+    if tri is not None:
+        T = np.ascontiguousarray(tri, dtype=np.int32).reshape(-1, 3)
+        Kd = np.ascontiguousarray(K, dtype=np.float64).reshape(-1)
+        if Kd.size != T.shape[0]:
+            raise ValueError("tri and K differ in length")
+        keep += [T, Kd]
+        c.n3, c.tri, c.K = Kd.size, T.ctypes.data, Kd.ctypes.data
     if J is not None:
         Jd = np.ascontiguousarray(J, dtype=np.float64)
         keep.append(Jd)
@@ -160,10 +169,11 @@ class Context:
             self.ptr = None
 
 
-def sbqa_create(J=None, h=None, N=None, R=1, runs=1, schedule=None, csr=None, **sched_kw) -> Context:
+def sbqa_create(J=None, h=None, N=None, R=1, runs=1, schedule=None, csr=None, tri=None, K=None,
+                **sched_kw) -> Context:
     if (J is None) == (csr is None):
         raise ValueError("give exactly one of J (dense) or csr=(row_ptr, col, val)")
-    c, keep, n = _coupling(J, csr)
+    c, keep, n = _coupling(J, csr, tri, K)
     N = n if N is None else N
     if schedule is None:
         schedule, keep2 = make_schedule(**sched_kw)
@@ -274,8 +284,9 @@ def sbqa_server_create(hbm_budget_bytes: int, max_slots: int) -> Server:
     return Server(out.value)
 
 
-def sbqa_submit(srv: Server, J=None, h=None, R=1, runs=1, schedule=None, csr=None, **sched_kw) -> int:
-    c, keep, N = _coupling(J, csr)
+def sbqa_submit(srv: Server, J=None, h=None, R=1, runs=1, schedule=None, csr=None, tri=None, K=None,
+                **sched_kw) -> int:
+    c, keep, N = _coupling(J, csr, tri, K)
     if schedule is None:
         schedule, keep2 = make_schedule(**sched_kw)
         keep += keep2

@@ -104,6 +104,68 @@ __device__ __forceinline__ float4 gather_fields(int i, int c, int Cs, const int3
     return make_float4(a0, a1, a2, a3);
 }
 
+// Three-body coupling sums of the 4 columns c..c+3 of row i (the cubic term
+// of Eq. 11), continuing the accumulators acc: for each triple containing i,
+// in list order, acc += K f_a f_b with the other two members' operands (the
+// product f_a f_b is exact for ternary operands).
+template <bool BALLISTIC>
+__device__ __forceinline__ float4 gather_fields3(int i, int c, int Cs, const Tri3 &t3, const float *__restrict__ x_in,
+                                                 const int8_t *__restrict__ g_in, float4 acc) {
+    const int p0 = __builtin_amdgcn_readfirstlane(t3.ptr[i]);
+    const int p1 = __builtin_amdgcn_readfirstlane(t3.ptr[i + 1]);
+    constexpr int B = GATHER_BATCH / 2;
+    float a[4] = {acc.x, acc.y, acc.z, acc.w};
+    for (int p = p0; p < p1; p += B) {
+        const int cnt = min(B, p1 - p);
+        int ja[B], jb[B];
+        float ws[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            ja[q] = q < cnt ? t3.ab[2 * (p + q)] : 0;
+            jb[q] = q < cnt ? t3.ab[2 * (p + q) + 1] : 0;
+            ws[q] = q < cnt ? t3.k[p + q] : 0.f;
+        }
+        if constexpr (BALLISTIC) {
+            float4 va[B], vb[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+                if (q < cnt) {
+                    va[q] = *reinterpret_cast<const float4 *>(x_in + (int64_t)ja[q] * Cs + c);
+                    vb[q] = *reinterpret_cast<const float4 *>(x_in + (int64_t)jb[q] * Cs + c);
+                }
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+                if (q < cnt) {
+                    const float pa[4] = {va[q].x, va[q].y, va[q].z, va[q].w};
+                    const float pb[4] = {vb[q].x, vb[q].y, vb[q].z, vb[q].w};
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float prod = pa[e] * pb[e];
+                        a[e] = __builtin_fmaf(ws[q], prod, a[e]);
+                    }
+                }
+        } else {
+            uint32_t va[B], vb[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+                if (q < cnt) {
+                    va[q] = *reinterpret_cast<const uint32_t *>(g_in + (int64_t)ja[q] * Cs + c);
+                    vb[q] = *reinterpret_cast<const uint32_t *>(g_in + (int64_t)jb[q] * Cs + c);
+                }
+#pragma unroll
+            for (int q = 0; q < B; ++q)
+                if (q < cnt) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int prod = (int)(int8_t)(va[q] >> (8 * e)) * (int)(int8_t)(vb[q] >> (8 * e));
+                        a[e] = __builtin_fmaf(ws[q], (float)prod, a[e]);
+                    }
+                }
+        }
+    }
+    return make_float4(a[0], a[1], a[2], a[3]);
+}
+
 #pragma clang fp contract(off)
 // RING_SHFL: R divides 256 and is a multiple of 4, so every run lies inside
 // one wavefront's 256 columns and its R/4 lanes; the ring neighbours outside a
@@ -113,7 +175,8 @@ template <bool BALLISTIC, bool RING_SHFL>
 __device__ __forceinline__ void csr_step_body(int b, int N, int Cs, int C, int R, int nchunk,
                                               const int32_t *__restrict__ row_ptr,
                                               const int32_t *__restrict__ col,
-                                              const float *__restrict__ val, const float *__restrict__ h,
+                                              const float *__restrict__ val, const Tri3 &t3,
+                                              const float *__restrict__ h,
                                               const float *__restrict__ x_in, float *__restrict__ x_out,
                                               float *__restrict__ y, const int8_t *__restrict__ g_in,
                                               int8_t *__restrict__ g_out, const float *__restrict__ jp,
@@ -127,7 +190,8 @@ __device__ __forceinline__ void csr_step_body(int b, int N, int Cs, int C, int R
     const int64_t o = (int64_t)i * Cs + c;
     const float4 x = *reinterpret_cast<const float4 *>(x_in + o);
     const float4 yv = *reinterpret_cast<const float4 *>(y + o);
-    const float4 phi = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x_in, g_in);
+    float4 phi = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x_in, g_in);
+    if (t3.ptr) phi = gather_fields3<BALLISTIC>(i, c, Cs, t3, x_in, g_in, phi);
     const float hi = h[i];
     const float xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
     const float ps[4] = {phi.x, phi.y, phi.z, phi.w};
@@ -175,13 +239,14 @@ template <bool BALLISTIC, bool RING_SHFL>
 __global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, int nchunk,
                                                   const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
-                                                  const float *__restrict__ val, const float *__restrict__ h,
+                                                  const float *__restrict__ val, const Tri3 t3,
+                                                  const float *__restrict__ h,
                                                   const float *__restrict__ x_in, float *__restrict__ x_out,
                                                   float *__restrict__ y, const int8_t *__restrict__ g_in,
                                                   int8_t *__restrict__ g_out, const float *__restrict__ jp,
                                                   int64_t jp_stride, StepCoef k, int fmode) {
-    csr_step_body<BALLISTIC, RING_SHFL>(blockIdx.x, N, Cs, C, R, nchunk, row_ptr, col, val, h, x_in, x_out, y, g_in,
-                                        g_out, jp, jp_stride, k, fmode);
+    csr_step_body<BALLISTIC, RING_SHFL>(blockIdx.x, N, Cs, C, R, nchunk, row_ptr, col, val, t3, h, x_in, x_out, y,
+                                        g_in, g_out, jp, jp_stride, k, fmode);
 }
 
 // Grouped step of every CSR instance of one serving group: a grid-stride loop
@@ -206,7 +271,7 @@ __global__ __launch_bounds__(256) void k_group_csr(const GroupHeader *__restrict
         k.kD = t.kD;
         k.delta_next = t.delta[n + 1];
         csr_step_body<BALLISTIC, RING_SHFL>(vb - t.first_block, t.N, t.ld, t.C, t.R, t.nchunk, t.row_ptr, t.col,
-                                            t.val, t.h, t.x[in], t.x[1 - in], t.y, (const int8_t *)t.g[in],
+                                            t.val, t.t3, t.h, t.x[in], t.x[1 - in], t.y, (const int8_t *)t.g[in],
                                             (int8_t *)t.g[1 - in], t.jp + n, t.S, k, t.fmode);
     }
 }
@@ -228,15 +293,17 @@ template <bool BALLISTIC>
 __global__ __launch_bounds__(256) void k_csr_fields(int N, int Cs, int C, int nchunk,
                                                     const int32_t *__restrict__ row_ptr,
                                                     const int32_t *__restrict__ col,
-                                                    const float *__restrict__ val, const float *__restrict__ x,
-                                                    const int8_t *__restrict__ g, float *__restrict__ phi) {
+                                                    const float *__restrict__ val, const Tri3 t3,
+                                                    const float *__restrict__ x, const int8_t *__restrict__ g,
+                                                    float *__restrict__ phi) {
     const int b = blockIdx.x;
     const int chunk = b % nchunk, rg = b / nchunk;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = rg * WAVES + wave;
     const int c = chunk * COLS_PER_WAVE + lane * 4;
     if (i >= N || c >= C) return;
-    const float4 v = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x, g);
+    float4 v = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x, g);
+    if (t3.ptr) v = gather_fields3<BALLISTIC>(i, c, Cs, t3, x, g, v);
     *reinterpret_cast<float4 *>(phi + (int64_t)i * Cs + c) = v;
 }
 
@@ -457,7 +524,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
 }  // namespace
 
 hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int32_t *row_ptr,
-                           const int32_t *col, const float *val, const float *h, const float *x_in,
+                           const int32_t *col, const float *val, const Tri3 &t3, const float *h, const float *x_in,
                            float *x_out, float *y, const int8_t *g_in, int8_t *g_out, const float *jp,
                            int64_t jp_stride, StepCoef k, hipStream_t st) {
     const int C = R * runs;
@@ -466,7 +533,7 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
     dim3 grid(csr_step_blocks(N, C)), block(WAVES * 64);
     const bool shfl = csr_ring_shfl(R);
 #define SBQA_CSR_LAUNCH(B, S)                                                                                  \
-    hipLaunchKernelGGL((k_csr_step<B, S>), grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, h, x_in, \
+    hipLaunchKernelGGL((k_csr_step<B, S>), grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, t3, h, x_in, \
                        x_out, y, g_in, g_out, jp, jp_stride, k, fmode)
     if (fmode == 2) {
         if (shfl) SBQA_CSR_LAUNCH(true, true);
@@ -511,14 +578,15 @@ hipError_t launch_csr_operand(int fmode, int N, int Cs, int C, const float *x, i
 }
 
 hipError_t launch_csr_fields(int fmode, int N, int Cs, int C, const int32_t *row_ptr, const int32_t *col,
-                             const float *val, const float *x, const int8_t *g, float *phi, hipStream_t st) {
+                             const float *val, const Tri3 &t3, const float *x, const int8_t *g, float *phi,
+                             hipStream_t st) {
     const int nchunk = (C + COLS_PER_WAVE - 1) / COLS_PER_WAVE;
     const int nrg = (N + WAVES - 1) / WAVES;
     dim3 grid(nchunk * nrg), block(WAVES * 64);
     if (fmode == 2)
-        hipLaunchKernelGGL(k_csr_fields<true>, grid, block, 0, st, N, Cs, C, nchunk, row_ptr, col, val, x, g, phi);
+        hipLaunchKernelGGL(k_csr_fields<true>, grid, block, 0, st, N, Cs, C, nchunk, row_ptr, col, val, t3, x, g, phi);
     else
-        hipLaunchKernelGGL(k_csr_fields<false>, grid, block, 0, st, N, Cs, C, nchunk, row_ptr, col, val, x, g, phi);
+        hipLaunchKernelGGL(k_csr_fields<false>, grid, block, 0, st, N, Cs, C, nchunk, row_ptr, col, val, t3, x, g, phi);
     return hipGetLastError();
 }
 

@@ -96,19 +96,30 @@ __global__ __launch_bounds__(256) void k_energy_reduce(int N, int Np, int Cp, in
     if (t == 0) E[c] = -0.5 * sq[0] - sl[0];
 }
 
+// Three-body part of the energy of one spin i, as s_i psi_i with psi_i the
+// sum over the triples containing i of K s_a s_b; summed over i this counts
+// every triple three times (E3 = -1/3 sum_i s_i psi_i, exact for integer K).
+template <class SpinOf>
+__device__ __forceinline__ double tri_psi(const Tri3 &t3, int i, SpinOf spin) {
+    double psi = 0.0;
+    for (int p = t3.ptr[i]; p < t3.ptr[i + 1]; ++p) psi += t3.k64[p] * (spin(t3.ab[2 * p]) * spin(t3.ab[2 * p + 1]));
+    return psi;
+}
+
 // CSR energies of the readout of a spin-major state. Stage 1: block (row
 // block rb, 256 columns) accumulates per column over its rows in row order.
 __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int Cs, int C, int rows_per_blk,
                                                             const int32_t *__restrict__ row_ptr,
                                                             const int32_t *__restrict__ col,
-                                                            const double *__restrict__ val,
+                                                            const double *__restrict__ val, const Tri3 t3,
                                                             const double *__restrict__ h,
                                                             const float *__restrict__ x,
                                                             double *__restrict__ partial) {
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int rb = blockIdx.y;
     if (c >= C) return;
-    double q = 0.0, l = 0.0;
+    double q = 0.0, l = 0.0, q3 = 0.0;
+    auto spin = [&](int j) { return x[(int64_t)j * Cs + c] >= 0.0f ? 1.0 : -1.0; };
     const int i0 = rb * rows_per_blk, i1 = min(N, i0 + rows_per_blk);
     for (int i = i0; i < i1; ++i) {
         double phi = 0.0;
@@ -119,48 +130,55 @@ __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int Cs, int C
         const double s = x[(int64_t)i * Cs + c] >= 0.0f ? 1.0 : -1.0;
         q += s * phi;
         if (h) l += h[i] * s;
+        if (t3.ptr) q3 += s * tri_psi(t3, i, spin);
     }
-    partial[((int64_t)rb * C + c) * 2] = q;
-    partial[((int64_t)rb * C + c) * 2 + 1] = l;
+    partial[((int64_t)rb * C + c) * 3] = q;
+    partial[((int64_t)rb * C + c) * 3 + 1] = l;
+    partial[((int64_t)rb * C + c) * 3 + 2] = q3;
 }
 
 __global__ void k_csr_energy_final(int C, int nrb, const double *__restrict__ partial, double *__restrict__ E) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C) return;
-    double q = 0.0, l = 0.0;
+    double q = 0.0, l = 0.0, q3 = 0.0;
     for (int rb = 0; rb < nrb; ++rb) {
-        q += partial[((int64_t)rb * C + c) * 2];
-        l += partial[((int64_t)rb * C + c) * 2 + 1];
+        q += partial[((int64_t)rb * C + c) * 3];
+        l += partial[((int64_t)rb * C + c) * 3 + 1];
+        q3 += partial[((int64_t)rb * C + c) * 3 + 2];
     }
-    E[c] = -0.5 * q - l;
+    E[c] = -0.5 * q - l - q3 / 3.0;
 }
 
 __global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
-                                                          const double *__restrict__ val,
+                                                          const double *__restrict__ val, const Tri3 t3,
                                                           const double *__restrict__ h,
                                                           const int8_t *__restrict__ spins, double *__restrict__ E) {
-    __shared__ double sq[256], sl[256];
+    __shared__ double sq[256], sl[256], s3[256];
     const int m = blockIdx.x, t = threadIdx.x;
     const int8_t *s = spins + (int64_t)m * N;
-    double q = 0.0, l = 0.0;
+    auto spin = [&](int j) { return (double)s[j]; };
+    double q = 0.0, l = 0.0, q3 = 0.0;
     for (int i = t; i < N; i += 256) {
         double phi = 0.0;
         for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) phi += val[p] * (double)s[col[p]];
         q += (double)s[i] * phi;
         if (h) l += h[i] * (double)s[i];
+        if (t3.ptr) q3 += (double)s[i] * tri_psi(t3, i, spin);
     }
     sq[t] = q;
     sl[t] = l;
+    s3[t] = q3;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (t < w) {
             sq[t] += sq[t + w];
             sl[t] += sl[t + w];
+            s3[t] += s3[t + w];
         }
         __syncthreads();
     }
-    if (t == 0) E[m] = -0.5 * sq[0] - sl[0];
+    if (t == 0) E[m] = -0.5 * sq[0] - sl[0] - s3[0] / 3.0;
 }
 
 // One wavefront per run: argmin over the run's replicas (tie -> lowest k)
@@ -235,19 +253,19 @@ hipError_t launch_energy_reduce(int N, int Np, int count, int Cp, int splits, co
 }
 
 hipError_t launch_csr_energy_state(int N, int Cs, int C, const int32_t *row_ptr, const int32_t *col,
-                                   const double *val, const double *h, const float *x, double *partial,
-                                   int nblk_rows, double *E, hipStream_t st) {
+                                   const double *val, const Tri3 &t3, const double *h, const float *x,
+                                   double *partial, int nblk_rows, double *E, hipStream_t st) {
     const int rows_per_blk = (N + nblk_rows - 1) / nblk_rows;
     dim3 grid((C + 255) / 256, nblk_rows), block(256);
-    hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, Cs, C, rows_per_blk, row_ptr, col, val, h, x,
+    hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, Cs, C, rows_per_blk, row_ptr, col, val, t3, h, x,
                        partial);
     hipLaunchKernelGGL(k_csr_energy_final, dim3((C + 255) / 256), dim3(256), 0, st, C, nblk_rows, partial, E);
     return hipGetLastError();
 }
 
 hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col, const double *val,
-                                   const double *h, const int8_t *spins, double *E, hipStream_t st) {
-    hipLaunchKernelGGL(k_csr_energy_spins, dim3(count), dim3(256), 0, st, N, row_ptr, col, val, h, spins, E);
+                                   const Tri3 &t3, const double *h, const int8_t *spins, double *E, hipStream_t st) {
+    hipLaunchKernelGGL(k_csr_energy_spins, dim3(count), dim3(256), 0, st, N, row_ptr, col, val, t3, h, spins, E);
     return hipGetLastError();
 }
 

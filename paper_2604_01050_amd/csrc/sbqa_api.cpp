@@ -221,6 +221,22 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
         facts->nnz = J->nnz;
     }
     facts->int8 = integral && maxabs <= 127.0;   // J only: h enters in fp32
+    if (J->n3 < 0) return fail(SBQA_EINVAL, "n3 must be >= 0");
+    if (J->n3 > 0) {
+        if (dense) return fail(SBQA_EINVAL, "three-body terms need CSR two-body couplings (nnz may be 0)");
+        if (!J->tri || !J->K) return fail(SBQA_EINVAL, "three-body terms need tri and K");
+        if (J->n3 > (int64_t)1 << 28) return fail(SBQA_EINVAL, "too many three-body terms");
+        for (int64_t t = 0; t < J->n3; ++t) {
+            const int32_t a = J->tri[3 * t], b = J->tri[3 * t + 1], d = J->tri[3 * t + 2];
+            if (a < 0 || a >= N || b < 0 || b >= N || d < 0 || d >= N)
+                return fail(SBQA_EINVAL, "triple %lld has a spin index out of range", (long long)t);
+            if (a == b || a == d || b == d) return fail(SBQA_EINVAL, "triple %lld repeats a spin", (long long)t);
+            if (!std::isfinite(J->K[t])) return fail(SBQA_EINVAL, "K[%lld] not finite", (long long)t);
+            if (J->K[t] != std::floor(J->K[t])) integral = false;
+            ss += 3.0 * J->K[t] * J->K[t];   // field variance of random spins (c0)
+        }
+    }
+    facts->n3 = J->n3 > 0 ? J->n3 : 0;
     if (h)
         for (int32_t i = 0; i < N; ++i) {
             if (!std::isfinite(h[i])) return fail(SBQA_EINVAL, "h[%d] not finite", i);
@@ -277,7 +293,8 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         b += (int64_t)(N + 1) * 4 + f.nnz * (4 + 4 + 8);                 // CSR
         b += (int64_t)N * 12;                                             // h32, h64
         L->csr_nrb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (N + 63) / 64));
-        b += (int64_t)L->csr_nrb * C * 16;
+        b += (int64_t)L->csr_nrb * C * 24;
+        if (f.n3) b += (int64_t)(N + 1) * 4 + 3 * f.n3 * (8 + 4 + 8);    // three-body lists
         b += (int64_t)N * L->Cs * 4;                                      // phi (fields hook)
     } else {
         const int eb = path_ebytes(f.path), planes = f.path == PATH_BF16X3 ? 2 : 1;
@@ -542,7 +559,37 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         HIP_TRY(dalloc(c, &c->col, (size_t)nnz + 8));
         HIP_TRY(dalloc(c, &c->val, (size_t)nnz + 8));
         HIP_TRY(dalloc(c, &c->val64, (size_t)nnz));
-        HIP_TRY(dalloc(c, &c->csr_partial, (size_t)c->L.csr_nrb * C * 2));
+        HIP_TRY(dalloc(c, &c->csr_partial, (size_t)c->L.csr_nrb * C * 3));
+        if (J->n3 > 0) {
+            // three-body terms listed per member spin, triples in the given
+            // order; +4 entries: the step reads them in batches of up to 4
+            std::vector<int32_t> tp((size_t)N + 1, 0);
+            for (int64_t t = 0; t < J->n3; ++t)
+                for (int e = 0; e < 3; ++e) ++tp[(size_t)J->tri[3 * t + e] + 1];
+            for (int32_t i = 0; i < N; ++i) tp[(size_t)i + 1] += tp[(size_t)i];
+            const int64_t ne = 3 * J->n3;
+            std::vector<int32_t> ab((size_t)2 * (ne + 4), 0), fill(tp.begin(), tp.end() - 1);
+            std::vector<float> k32((size_t)ne + 4, 0.0f);
+            std::vector<double> k64((size_t)ne, 0.0);
+            for (int64_t t = 0; t < J->n3; ++t)
+                for (int e = 0; e < 3; ++e) {
+                    const int32_t *v = J->tri + 3 * t;
+                    const int64_t q = fill[(size_t)v[e]]++;
+                    ab[(size_t)2 * q] = v[(e + 1) % 3];
+                    ab[(size_t)2 * q + 1] = v[(e + 2) % 3];
+                    k32[(size_t)q] = (float)J->K[t];
+                    k64[(size_t)q] = J->K[t];
+                }
+            HIP_TRY(dalloc(c, &c->t3ptr, tp.size()));
+            HIP_TRY(dalloc(c, &c->t3ab, ab.size()));
+            HIP_TRY(dalloc(c, &c->t3k, k32.size()));
+            HIP_TRY(dalloc(c, &c->t3k64, k64.size()));
+            HIP_TRY(hipMemcpyAsync(c->t3ptr, tp.data(), sizeof(int32_t) * tp.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->t3ab, ab.data(), sizeof(int32_t) * ab.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->t3k, k32.data(), sizeof(float) * k32.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->t3k64, k64.data(), sizeof(double) * k64.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
+        }
         HIP_TRY(dalloc(c, &c->phi, (size_t)N * Cs));
         std::vector<float> v32((size_t)nnz);
         for (int64_t p = 0; p < nnz; ++p) v32[p] = (float)J->val[p];
@@ -655,7 +702,7 @@ sbqa_status ctx_step_once(sbqa_ctx *c) {
     const int64_t jp_stride = c->s.steps;
     const int in = c->cur, out = 1 - c->cur;
     if (c->facts.path == PATH_CSR) {
-        HIP_TRY(launch_csr_step(c->s.fmode, c->N, c->L.Cs, c->R, c->runs, c->rp, c->col, c->val, c->h32, c->x[in],
+        HIP_TRY(launch_csr_step(c->s.fmode, c->N, c->L.Cs, c->R, c->runs, c->rp, c->col, c->val, c->tri3(), c->h32, c->x[in],
                                 c->x[out], c->y, (const int8_t *)c->g[in], (int8_t *)c->g[out], jp, jp_stride, k,
                                 c->stream));
     } else {
@@ -672,7 +719,7 @@ sbqa_status ctx_state_energies(sbqa_ctx *c) {
     const bool sm = c->facts.path == PATH_CSR;
     const double *h64 = c->has_h ? c->h64 : nullptr;
     if (sm) {
-        HIP_TRY(launch_csr_energy_state(c->N, c->L.Cs, c->L.C, c->rp, c->col, c->val64, h64, c->x[c->cur], c->csr_partial,
+        HIP_TRY(launch_csr_energy_state(c->N, c->L.Cs, c->L.C, c->rp, c->col, c->val64, c->tri3(), h64, c->x[c->cur], c->csr_partial,
                                         c->L.csr_nrb, c->E, c->stream));
     } else {
         HIP_TRY(launch_readout_f64(c->N, c->L.Np, c->L.C, c->L.Np, false, c->x[c->cur], c->S64, c->stream));
@@ -704,6 +751,7 @@ sbqa_status ctx_reset_best(sbqa_ctx *c) {
 // Whether the register-resident CSR loop fits this instance on this device.
 static bool resident_plan(sbqa_ctx *c, const sbqa_coupling *J, std::string *why) {
     if (c->s.fmode == SBQA_F_BALLISTIC) { *why = "ballistic f needs a float32 operand"; return false; }
+    if (c->facts.n3) { *why = "three-body terms run on the streaming kernel"; return false; }
     if (c->R % resident_cols()) { *why = "R is not a multiple of 8"; return false; }
     const int rpt = resident_rpt(c->N);
     if (rpt < 0 || c->N > 65535) { *why = "N above 4096"; return false; }
@@ -981,7 +1029,7 @@ sbqa_status sbqa_energy(sbqa_ctx *c, const int8_t *spins, int32_t count, double 
     struct Guard { void *a, *b, *c2, *d; ~Guard() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c2); (void)hipFree(d); } } gd{ds, E, nullptr, nullptr};
     HIP_TRY(hipMemcpyAsync(ds, spins, (size_t)count * N, hipMemcpyHostToDevice, c->stream));
     if (c->facts.path == PATH_CSR) {
-        HIP_TRY(launch_csr_energy_spins(N, count, c->rp, c->col, c->val64, h64, ds, E, c->stream));
+        HIP_TRY(launch_csr_energy_spins(N, count, c->rp, c->col, c->val64, c->tri3(), h64, ds, E, c->stream));
     } else {
         const int Np = c->L.Np;
         const int cp = (int)round_up(count, GEMM_BM);
@@ -1010,7 +1058,7 @@ sbqa_status sbqa_fields(sbqa_ctx *c, float *phi) {
     std::vector<float> buf;
     if (c->facts.path == PATH_CSR) {
         const int Cs = c->L.Cs;
-        HIP_TRY(launch_csr_fields(c->s.fmode, N, Cs, C, c->rp, c->col, c->val, c->x[c->cur], (const int8_t *)c->g[c->cur],
+        HIP_TRY(launch_csr_fields(c->s.fmode, N, Cs, C, c->rp, c->col, c->val, c->tri3(), c->x[c->cur], (const int8_t *)c->g[c->cur],
                                   c->phi, c->stream));
         buf.resize((size_t)N * Cs);
         HIP_TRY(hipMemcpyAsync(buf.data(), c->phi, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, c->stream));

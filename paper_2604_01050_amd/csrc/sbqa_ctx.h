@@ -17,6 +17,7 @@ struct InstanceFacts {
     bool ternary = false;    // every J_ij in {-1, 0, +1}
     bool int8 = false;       // every J_ij an integer in [-127, 127]
     bool pm1 = false;        // every off-diagonal J_ij in {-1, +1} (dense)
+    int64_t n3 = 0;          // three-body terms (CSR)
     double rms = 0.0;        // rms of the N(N-1) off-diagonal couplings
     int64_t nnz = 0;
     Path path = PATH_F32;
@@ -87,6 +88,14 @@ struct sbqa_ctx {
     int32_t *rp = nullptr, *col = nullptr;
     float *val = nullptr;
     double *val64 = nullptr;
+    int32_t *t3ptr = nullptr, *t3ab = nullptr;   // three-body terms per member spin (Tri3)
+    float *t3k = nullptr;
+    double *t3k64 = nullptr;
+    sbqa::Tri3 tri3() const {
+        sbqa::Tri3 t;
+        if (t3ptr) { t.ptr = t3ptr; t.ab = t3ab; t.k = t3k; t.k64 = t3k64; }
+        return t;
+    }
     float *h32 = nullptr;
     double *h64 = nullptr;
     float *jp = nullptr;                // device J_perp table [runs][steps]

@@ -97,6 +97,18 @@ hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, cons
                              hipStream_t st);
 
 // ---- grouped steps of the serving loop ----------------------------------------
+// Three-body terms (the cubic part of Eq. 11) of a CSR instance, listed per
+// member spin: entries ptr[i]..ptr[i+1]-1 of spin i hold the other two
+// members ab[2e], ab[2e+1] of each triple containing i (in the order the
+// triples were given) and its weight k (float32; float64 copy k64 for the
+// energies). ptr == nullptr: no three-body terms.
+struct Tri3 {
+    const int32_t *ptr = nullptr;
+    const int32_t *ab = nullptr;
+    const float *k = nullptr;
+    const double *k64 = nullptr;
+};
+
 // One task per resident instance; the tasks of a group (same kernel
 // specialisation) are stepped together by one grouped launch per step, a
 // grid-stride loop over the virtual blocks of all tasks (task q owns blocks
@@ -117,6 +129,7 @@ struct GroupTask {
     const void *J, *J_lo;    // dense, fragment-tiled
     const int32_t *row_ptr, *col;
     const float *val;        // CSR
+    Tri3 t3;                 // CSR three-body terms
     const float *h, *jp, *coefA, *delta;   // jp: [runs][S]; coefA [S]; delta [S+1]
 };
 struct GroupHeader {
@@ -143,7 +156,7 @@ hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int 
 // (int8 f values, or x itself for ballistic f), pump/ring/kick/drift/wall,
 // next operand with delta_next.
 hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int32_t *row_ptr,
-                           const int32_t *col, const float *val, const float *h,
+                           const int32_t *col, const float *val, const Tri3 &t3, const float *h,
                            const float *x_in, float *x_out, float *y, const int8_t *g_in,
                            int8_t *g_out, const float *jp, int64_t jp_stride, StepCoef k,
                            hipStream_t st);
@@ -201,7 +214,7 @@ hipError_t launch_csr_operand(int fmode, int N, int Cs, int C, const float *x, i
 
 // CSR coupling sum phi[N][Cs] = J f(X) (test hook).
 hipError_t launch_csr_fields(int fmode, int N, int Cs, int C, const int32_t *row_ptr,
-                             const int32_t *col, const float *val, const float *x,
+                             const int32_t *col, const float *val, const Tri3 &t3, const float *x,
                              const int8_t *g, float *phi, hipStream_t st);
 
 // Counter-based initial state: x, y ~ U[-amp, amp] from Philox4x32-10 keyed by
@@ -225,11 +238,11 @@ hipError_t launch_energy_reduce(int N, int Np, int count, int Cp, int splits,
 
 // CSR energies of the readout of x ([N][Cs]) or of given spins.
 hipError_t launch_csr_energy_state(int N, int Cs, int C, const int32_t *row_ptr,
-                                   const int32_t *col, const double *val, const double *h,
+                                   const int32_t *col, const double *val, const Tri3 &t3, const double *h,
                                    const float *x, double *partial, int nblk_rows, double *E,
                                    hipStream_t st);
 hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col,
-                                   const double *val, const double *h, const int8_t *spins,
+                                   const double *val, const Tri3 &t3, const double *h, const int8_t *spins,
                                    double *E, hipStream_t st);
 
 // Per-run best over replicas with tie -> lowest k; updates best_E/best_step

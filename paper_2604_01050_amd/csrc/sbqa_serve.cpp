@@ -84,6 +84,7 @@ GroupTask make_task(const sbqa_ctx *c, int first_block, uint32_t n_end) {
         t.row_ptr = c->rp;
         t.col = c->col;
         t.val = c->val;
+        t.t3 = c->tri3();
     } else {
         t.ld = c->L.Np;
         t.nkc = c->L.nkc;
@@ -106,7 +107,8 @@ struct Request {
     int32_t N = 0, R = 0, runs = 0;
     sbqa_schedule s{};
     std::vector<double> dense, val, h, beta, alpha;
-    std::vector<int32_t> row_ptr, col;
+    std::vector<int32_t> row_ptr, col, tri;
+    std::vector<double> K;
     std::vector<float> jp_table;
     InstanceFacts facts;
     size_t bytes = 0;
@@ -297,6 +299,9 @@ static void creator(sbqa_server *srv) {
             J.col = r.col.data();
             J.val = r.val.data();
             J.nnz = (int64_t)r.col.size();
+            J.n3 = (int64_t)r.K.size();
+            J.tri = r.tri.empty() ? nullptr : r.tri.data();
+            J.K = r.K.empty() ? nullptr : r.K.data();
         }
         sbqa_schedule s = r.s;
         s.beta = r.beta.empty() ? nullptr : r.beta.data();
@@ -471,6 +476,10 @@ sbqa_status sbqa_submit(sbqa_server *srv, const sbqa_coupling *J, const double *
         r->row_ptr.assign(J->row_ptr, J->row_ptr + N + 1);
         r->col.assign(J->col, J->col + J->nnz);
         r->val.assign(J->val, J->val + J->nnz);
+        if (J->n3 > 0) {
+            r->tri.assign(J->tri, J->tri + 3 * J->n3);
+            r->K.assign(J->K, J->K + J->n3);
+        }
     }
     if (h) r->h.assign(h, h + N);
     if (s->beta) r->beta.assign(s->beta, s->beta + runs);

@@ -97,6 +97,13 @@ def test_validation_errors(abi):
     c3[0], c3[1] = c3[1], c3[0]
     _expect(abi, abi.EINVAL, csr=(rp, c3, val), R=2, runs=2)
     _expect(abi, abi.EINVAL, csr=(rp, col, val), R=2, runs=2, precision=abi.PREC_BF16X3)
+    # three-body terms: CSR only, indices in range and distinct, finite weights
+    T = np.array([[0, 1, 2], [3, 4, 5]])
+    Kw = np.array([1.0, -2.0])
+    assert "CSR" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, tri=T, K=Kw)
+    assert "range" in _expect(abi, abi.EINVAL, csr=(rp, col, val), R=2, runs=2, tri=T + 17, K=Kw)
+    assert "repeats" in _expect(abi, abi.EINVAL, csr=(rp, col, val), R=2, runs=2, tri=[[0, 1, 1]], K=[1.0])
+    assert "finite" in _expect(abi, abi.EINVAL, csr=(rp, col, val), R=2, runs=2, tri=T, K=[1.0, np.inf])
     # schedule table must be given for JP_TABLE
     _expect(abi, abi.EINVAL, J=J, R=2, runs=2, jp_kind=abi.JP_TABLE)
 

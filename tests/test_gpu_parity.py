@@ -56,13 +56,14 @@ def _ctx(sb, J=None, csr=None, h=None, R=4, runs=3, steps=50, **kw):
     return sb.sbqa_create(J=J, csr=csr, h=h, R=R, runs=runs, steps=steps, **kw)
 
 
-def _orc_problem(orc, sb, ctx, J=None, csr=None, h=None, fmode=0, dt=0.5, a0=1.0):
+def _orc_problem(orc, sb, ctx, J=None, csr=None, h=None, fmode=0, dt=0.5, a0=1.0, tri=None, K=None):
     info = sb.sbqa_info(ctx)
-    return orc.Problem(ctx.N, ctx.R, ctx.runs, J=J, csr=csr, h=h, dt=dt, a0=a0, c0=info["c0"], fmode=fmode)
+    return orc.Problem(ctx.N, ctx.R, ctx.runs, J=J, csr=csr, h=h, dt=dt, a0=a0, c0=info["c0"], fmode=fmode,
+                       tri=tri, K=K)
 
 
 def _check_step(orc, P, ctx, sb, X, Y, n, S, jp_r, xg, yg, J=None, csr=None, h=None, rows=None,
-                field_tol=TOL, delta_max=0.7):
+                field_tol=TOL, delta_max=0.7, tri=None, K=None):
     """Compare the GPU's one step (xg, yg) from float32 (X, Y) with the oracle
     (all rows, or the sampled rows). Returns the number of wall-boundary
     elements excluded."""
@@ -73,10 +74,11 @@ def _check_step(orc, P, ctx, sb, X, Y, n, S, jp_r, xg, yg, J=None, csr=None, h=N
     else:
         xo, yo, phi = P.step_rows(X, Y, an, dn, jp_r, rows)
         xg, yg = xg[rows], yg[rows]
-    # magnitude of the coupling sum: sum_j |J_ij f_j|
+    # magnitude of the coupling sum: sum_j |J_ij f_j| (+ sum |K f_a f_b|)
     G = orc.apply_f(P.fmode, dn, X.astype(np.float64))
     if csr is not None:
-        absP = orc.Problem(P.N, P.R, P.runs, csr=(csr[0], csr[1], np.abs(csr[2])), c0=1.0, fmode=2)
+        absP = orc.Problem(P.N, P.R, P.runs, csr=(csr[0], csr[1], np.abs(csr[2])), c0=1.0, fmode=2, tri=tri,
+                           K=None if K is None else np.abs(K))
     else:
         absP = orc.Problem(P.N, P.R, P.runs, J=np.abs(J), c0=1.0, fmode=2)
     _, _, phi_abs = absP.step_rows(np.abs(G), np.zeros_like(G), 0.0, 0.0, np.zeros(P.runs), rows)
@@ -108,13 +110,19 @@ def _check_step(orc, P, ctx, sb, X, Y, n, S, jp_r, xg, yg, J=None, csr=None, h=N
 
 
 # ------------------------------------------------------------------ energies
-@pytest.mark.parametrize("kind", ["sk_dense", "int_dense_h", "int_csr_h", "gauss_dense", "gauss_csr"])
+@pytest.mark.parametrize("kind", ["sk_dense", "int_dense_h", "int_csr_h", "gauss_dense", "gauss_csr",
+                                  "int_hubo_h", "normal_hubo"])
 def test_energy_of_given_spins(sb, orc, kind):
-    """Ising energy (Eq. 2 at the corners) of given spins: bit-exact for integer J, h."""
+    """Ising energy (Eq. 2 at the corners; with three-body terms the cubic part
+    of Eq. 11) of given spins: bit-exact for integer J, K, h."""
     N = 300
     _log("energy parity %s N=%d" % (kind, N))
-    csr = J = h = None
-    if kind == "sk_dense":
+    csr = J = h = T = K = None
+    if kind.endswith("hubo_h") or kind.endswith("hubo"):
+        N, P2, w2, T, K = inst.hubo_heavy_hex(9, 10, 15, dist="int" if kind.startswith("int") else "normal")
+        csr = inst.edges_to_csr(N, P2, w2)
+        h = np.random.default_rng(16).integers(-2, 3, size=N).astype(float) if kind.endswith("_h") else None
+    elif kind == "sk_dense":
         J = inst.sk_pm1(N, 1)
     elif kind == "int_dense_h":
         rng = np.random.default_rng(2)
@@ -133,10 +141,10 @@ def test_energy_of_given_spins(sb, orc, kind):
         E = inst.regular_graph(N, 6, 8)
         csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 9))
         h = inst.gaussian_fields(N, 0.1, 10)
-    ctx = _ctx(sb, J=J, csr=csr, h=h, R=2, runs=3, precision=sb.PREC_FP32 if J is not None else 0)
+    ctx = _ctx(sb, J=J, csr=csr, h=h, R=2, runs=3, precision=sb.PREC_FP32 if J is not None else 0, tri=T, K=K)
     s = inst.spins_pm1(70, N, 11)
     Eg = sb.sbqa_energy(ctx, s)
-    Eo = orc.energy(s, J=J, h=h, csr=csr)
+    Eo = orc.energy(s, J=J, h=h, csr=csr, tri=T, K=K)
     if kind.startswith(("sk", "int")):
         assert np.array_equal(Eg, Eo)
         assert sb.sbqa_info(ctx)["j_integral"]
@@ -313,6 +321,77 @@ def test_int8_and_fp32_trajectories_identical(sb):
         assert np.array_equal(a, b)
 
 
+# ----------------------------------------------- native three-body (HUBO) terms
+@pytest.mark.parametrize("fmode,law,R", [(0, "int", 5), (1, "int", 8), (2, "normal", 5), (0, "normal", 8),
+                                         (0, "cauchy", 5)])
+def test_hubo_single_step_parity(sb, orc, fmode, law, R):
+    """Heavy-hex instance with native three-body terms (Eq. 11): one step of
+    Eqs. 6-7 from identical float32 states at several step indices; integer
+    weights with ternary or sign f give exact fields; c0 follows the
+    field-variance rule (R = 5: ring from memory, C = 35 ragged; R = 8: ring
+    by lane reads)."""
+    runs, S = 7, 40
+    N, P2, w2, T, K = inst.hubo_heavy_hex(7, 8, 51, dist=law)
+    csr = inst.edges_to_csr(N, P2, w2)
+    h = np.round(inst.gaussian_fields(N, 1.0, 52)) if law == "int" else inst.gaussian_fields(N, 0.2, 52)
+    _log("hubo single-step parity f=%d %s N=%d triples=%d R=%d" % (fmode, law, N, len(K), R))
+    rng = np.random.default_rng(53)
+    beta, alpha = rng.uniform(0.5, 1.5, runs), rng.uniform(0.5, 1.0, runs)
+    ctx = _ctx(sb, csr=csr, h=h, tri=T, K=K, R=R, runs=runs, steps=S, fmode=fmode, jp_kind=sb.JP_PAPER,
+               beta=beta, alpha=alpha, gamma0_over_R=0.7)
+    info = sb.sbqa_info(ctx)
+    assert info["path"] == "csr_fp32" and not info["resident"]
+    assert info["c0"] == pytest.approx(orc.auto_c0(csr=csr, K=K), rel=1e-12)
+    P = _orc_problem(orc, sb, ctx, csr=csr, h=h, fmode=fmode, tri=T, K=K)
+    jt = np.stack([orc.jperp_paper_table(b, a, 0.7, S) for b, a in zip(beta, alpha)])
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.3, 54)
+    sb.sbqa_set_state(ctx, X0, Y0)
+    for n in range(S):
+        X, Y = sb.sbqa_get_state(ctx)
+        if n in (0, 1, 7, 20, 39):
+            phi_g = sb.sbqa_fields(ctx)
+        sb.sbqa_step(ctx, 1)
+        xg, yg = sb.sbqa_get_state(ctx)
+        if n in (0, 1, 7, 20, 39):
+            jr = jt[:, n].astype(np.float32).astype(np.float64)
+            _, phi_o, phi_abs = _check_step(orc, P, ctx, sb, X, Y, n, S, jr, xg, yg, csr=csr, h=h, tri=T, K=K)
+            if law == "int" and fmode != 2:
+                assert np.array_equal(phi_g, phi_o.astype(np.float32)), "integer three-body fields must be exact"
+            else:
+                assert np.all(np.abs(phi_g - phi_o) <= TOL * phi_abs + 1e-30)
+
+
+def test_hubo_reaches_bruteforce_minimum(sb, orc):
+    """End to end on the GPU: small random instances with three-body terms
+    reach the exhaustive minimum of the oracle, and the returned energies are
+    the oracle's energies of the returned spins (bit-exact, integer weights)."""
+    N, R, runs, S = 14, 8, 16, 800
+    for seed in (91, 92, 93):
+        P2, w2, T, K, h = inst.random_hubo(N, 20, 24, seed)
+        csr = inst.edges_to_csr(N, P2, w2)
+        Eg, _ = orc.bruteforce_hubo(inst.csr_to_dense(N, *csr), h, T, K)
+        ctx = _ctx(sb, csr=csr, h=h, tri=T, K=K, R=R, runs=runs, steps=S, jp_kind=sb.JP_PAPER, seed=seed)
+        sb.sbqa_step(ctx, S)
+        Eb, sp = sb.sbqa_best(ctx)
+        assert np.array_equal(orc.energy(sp, csr=csr, h=h, tri=T, K=K), Eb)
+        assert Eb.min() == Eg, (seed, Eb.min(), Eg)
+
+
+def test_hubo_large_heavy_hex(sb, orc):
+    """Heavy-hex HUBO with about 1e5 spins (200 x 200 honeycomb, one matching
+    of 2-body terms, six sets of 3-body paths), R = 16 x 8 runs: sampled rows
+    of one step, and the energies of the returned spins."""
+    N, P2, w2, T, K = inst.hubo_heavy_hex(200, 200, 61, dist="normal")
+    csr = inst.edges_to_csr(N, P2, w2)
+    R, runs = 16, 8
+    _log("large heavy-hex hubo N=%d triples=%d" % (N, len(K)))
+    _full_size_step(sb, orc, csr=csr, N=N, R=R, runs=runs, nrows=48, S=1000, tri=T, K=K)
+    ctx = _ctx(sb, csr=csr, tri=T, K=K, R=R, runs=runs, steps=100, seed=3)
+    sb.sbqa_step(ctx, 100)
+    Eb, sp = sb.sbqa_best(ctx)
+    np.testing.assert_allclose(orc.energy(sp, csr=csr, tri=T, K=K), Eb, rtol=1e-12, atol=1e-9)
+
+
 def test_negation_symmetry_and_column_independence(sb):
     """h = 0: negated start -> negated trajectory (bit-exact). With J_perp = 0
     a run alone equals the same run inside a batch (CSR path: per-element
@@ -413,18 +492,19 @@ def _full_size_step(sb, orc, J=None, csr=None, h=None, N=None, R=None, runs=None
                     nrows=48, steps_before=3, S=1000, field_tol=TOL, exact_fields=False, **extra):
     kw = {} if prec is None else {"precision": prec}
     kw.update(extra)
+    tri, K = extra.get("tri"), extra.get("K")
     ctx = _ctx(sb, J=J, csr=csr, h=h, R=R, runs=runs, steps=S, fmode=fmode, seed=7, **kw)
     sb.sbqa_step(ctx, steps_before)
     X, Y = sb.sbqa_get_state(ctx)
     phi_g = sb.sbqa_fields(ctx)
     sb.sbqa_step(ctx, 1)
     xg, yg = sb.sbqa_get_state(ctx)
-    P = _orc_problem(orc, sb, ctx, J=J, csr=csr, h=h, fmode=fmode)
+    P = _orc_problem(orc, sb, ctx, J=J, csr=csr, h=h, fmode=fmode, tri=tri, K=K)
     rows = np.sort(np.random.default_rng(3).choice(N, nrows, replace=False))
     rows[-1] = N - 1
     jr = sb.sbqa_jperp_table(ctx)[:, steps_before].astype(np.float64)
     ex, phi_o, phi_abs = _check_step(orc, P, ctx, sb, X, Y, steps_before, S, jr, xg, yg, J=J, csr=csr, h=h,
-                                     rows=rows, field_tol=field_tol)
+                                     rows=rows, field_tol=field_tol, tri=tri, K=K)
     if exact_fields:
         assert np.array_equal(phi_g[rows], phi_o.astype(np.float32))
     else:
@@ -523,21 +603,27 @@ def test_best_energy_statistics_256_seeds(sb, orc):
 def test_serving_graph_blocks_alone_equals_mix(sb):
     """Longer schedules (several full step blocks, replayed from a captured
     graph while membership changes as instances finish at different steps,
-    plus partial blocks and energy tracking; fp8, int8 and CSR groups): every
-    result equals the instance's standalone run bit-for-bit."""
+    plus partial blocks and energy tracking; fp8, int8, CSR and three-body CSR
+    instances): every result equals the instance's standalone run bit-for-bit."""
     rng = np.random.default_rng(80)
     items = []
     for q in range(7):
         N = int(rng.choice([200, 300, 512]))
         steps = int(rng.choice([150, 200, 333]))
         ee = 0 if q % 3 else 50
+        extra = {}
         if q % 2 == 0:   # q = 6: integer Sidon28 couplings (int8 path)
             J, csr = (inst.sidon28_dense if q == 6 else inst.sk_pm1)(N, 800 + q), None
+        elif q == 5:     # native three-body terms on a heavy-hex graph
+            Nh, P2, w2, T, K = inst.hubo_heavy_hex(8, 9, 815, dist="normal")
+            J, csr = None, inst.edges_to_csr(Nh, P2, w2)
+            extra = dict(tri=T, K=K)
         else:
             N -= N % 2
             E = inst.regular_graph(N, int(rng.integers(3, 7)), 810 + q)
             J, csr = None, inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 820 + q))
-        items.append((J, csr, dict(R=8, runs=2, steps=steps, seed=830 + q, jp_kind=sb.JP_PAPER, energy_every=ee)))
+        items.append((J, csr, dict(R=8, runs=2, steps=steps, seed=830 + q, jp_kind=sb.JP_PAPER, energy_every=ee,
+                                   **extra)))
     alone = []
     for J, csr, kw in items:
         ctx = sb.sbqa_create(J=J, csr=csr, loop_kernel=sb.LOOP_STREAM, **kw)
@@ -729,7 +815,9 @@ def test_resident_rejects_unfit_instances(sb):
     AUTO then falls back to the streaming kernel."""
     E = inst.regular_graph(300, 4, 5101)
     csr = inst.edges_to_csr(300, E, inst.gaussian_edges(len(E), 5102))
-    for kw, why in ((dict(R=5, runs=4), "multiple of 8"), (dict(R=8, runs=2, fmode=sb.F_BALLISTIC), "ballistic")):
+    tri3 = dict(tri=np.array([[0, 1, 2], [5, 9, 200]]), K=np.array([1.0, -0.5]))
+    for kw, why in ((dict(R=5, runs=4), "multiple of 8"), (dict(R=8, runs=2, fmode=sb.F_BALLISTIC), "ballistic"),
+                    (dict(R=8, runs=2, **tri3), "three-body")):
         with pytest.raises(sb.SbqaError) as ei:
             _ctx(sb, csr=csr, loop_kernel=sb.LOOP_RESIDENT, **kw)
         assert ei.value.status == sb.EINVAL and why in ei.value.message
