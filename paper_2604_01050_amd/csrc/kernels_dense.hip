@@ -666,6 +666,21 @@ __global__ __launch_bounds__(256) void k_dense_operand(int Np, int nkc, int mbw,
     store_operand<PATH>(g, g_lo, tf_offset(c, i4, nkc, eb, mbw), f, fmode);
 }
 
+// Readout operand s = sign(x) with sign(0) = +1 (the energy convention of
+// Eq. 2 at the corners), 0 for padded spins i >= N: the dense contraction of
+// it gives J s exactly (integer J in fp8 / int8, |J s| < 2^24).
+template <int PATH>
+__global__ __launch_bounds__(256) void k_readout_operand(int N, int Np, int nkc, int mbw, const float *__restrict__ x,
+                                                         void *g) {
+    const int c = blockIdx.y;
+    const int i4 = (blockIdx.x * blockDim.x + threadIdx.x) * 4;
+    if (i4 >= Np) return;
+    const float4 v = *reinterpret_cast<const float4 *>(x + (int64_t)c * Np + i4);
+    auto s = [N](float xv, int i) { return i < N ? (xv >= 0.0f ? 1.0f : -1.0f) : 0.0f; };
+    const float4 f = make_float4(s(v.x, i4), s(v.y, i4 + 1), s(v.z, i4 + 2), s(v.w, i4 + 3));
+    store_operand<PATH>(g, nullptr, tf_offset(c, i4, nkc, 1, mbw), f, 0);
+}
+
 template <int PATH, int EPI>
 hipError_t launch_step_mbw(int mbw, dim3 grid, const DenseStepArgs &a, hipStream_t st) {
     switch (mbw) {
@@ -769,6 +784,22 @@ hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int 
         case PATH_BF16X3: hipLaunchKernelGGL(k_dense_operand<PATH_BF16X3>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_I8: hipLaunchKernelGGL(k_dense_operand<PATH_I8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_FP8PK: hipLaunchKernelGGL(k_dense_operand<PATH_FP8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace sbqa
+
+namespace sbqa {
+
+hipError_t launch_readout_operand(Path path, int N, int Np, int C, int nkc, int mbw, const float *x, void *g,
+                                  hipStream_t st) {
+    dim3 grid((Np / 4 + 255) / 256, C), block(256);
+    switch (path) {
+        case PATH_FP8:
+        case PATH_FP8PK: hipLaunchKernelGGL(k_readout_operand<PATH_FP8>, grid, block, 0, st, N, Np, nkc, mbw, x, g); break;
+        case PATH_I8: hipLaunchKernelGGL(k_readout_operand<PATH_I8>, grid, block, 0, st, N, Np, nkc, mbw, x, g); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -96,6 +96,34 @@ __global__ __launch_bounds__(256) void k_energy_reduce(int N, int Np, int Cp, in
     if (t == 0) E[c] = -0.5 * sq[0] - sl[0];
 }
 
+// Energies from exact integer fields Phi = J s of the readout s = sign(x)
+// (sign(0) = +1), replica-major [C][Np]: E_c = -1/2 sum_i s_ci Phi_ci -
+// sum_i h_i s_ci, block per column, the same fixed-order reduction as
+// k_energy_reduce (every partial sum an integer for integer J and h).
+__global__ __launch_bounds__(256) void k_energy_fields(int N, int Np, const float *__restrict__ x,
+                                                       const float *__restrict__ phi, const double *__restrict__ h,
+                                                       double *__restrict__ E) {
+    __shared__ double sq[256], sl[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    double q = 0.0, l = 0.0;
+    for (int i = t; i < N; i += 256) {
+        const double s = x[(int64_t)c * Np + i] >= 0.0f ? 1.0 : -1.0;
+        q += s * (double)phi[(int64_t)c * Np + i];
+        if (h) l += h[i] * s;
+    }
+    sq[t] = q;
+    sl[t] = l;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sq[t] += sq[t + w];
+            sl[t] += sl[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) E[c] = -0.5 * sq[0] - sl[0];
+}
+
 // Three-body part of the energy of one spin i, as s_i psi_i with psi_i the
 // sum over the triples containing i of K s_a s_b; summed over i this counts
 // every triple three times (E3 = -1/3 sum_i s_i psi_i, exact for integer K).
@@ -266,6 +294,12 @@ hipError_t launch_csr_energy_state(int N, int Cs, int C, const int32_t *row_ptr,
 hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col, const double *val,
                                    const Tri3 &t3, const double *h, const int8_t *spins, double *E, hipStream_t st) {
     hipLaunchKernelGGL(k_csr_energy_spins, dim3(count), dim3(256), 0, st, N, row_ptr, col, val, t3, h, spins, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const float *phi, const double *h, double *E,
+                                hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_fields, dim3(C), dim3(256), 0, st, N, Np, x, phi, h, E);
     return hipGetLastError();
 }
 

@@ -721,6 +721,19 @@ sbqa_status ctx_state_energies(sbqa_ctx *c) {
     if (sm) {
         HIP_TRY(launch_csr_energy_state(c->N, c->L.Cs, c->L.C, c->rp, c->col, c->val64, c->tri3(), h64, c->x[c->cur], c->csr_partial,
                                         c->L.csr_nrb, c->E, c->stream));
+    } else if (c->facts.path == PATH_FP8 || c->facts.path == PATH_FP8PK || c->facts.path == PATH_I8) {
+        // integer J: J s on MFMA is exact, so the energies equal the float64
+        // ones bit for bit; the free halves of the ping-pong buffers (written
+        // in full by the next step before they are read) hold the readout
+        // operand and its fields
+        const int in = c->cur, sc = 1 - c->cur;
+        HIP_TRY(launch_readout_operand(c->facts.path, c->N, c->L.Np, c->L.C, c->L.nkc, c->L.mbw, c->x[in], c->g[sc],
+                                       c->stream));
+        DenseStepArgs a = dense_args(c, c->step, in);
+        a.g = static_cast<const uint8_t *>(c->g[sc]);
+        a.phi = c->x[sc];
+        HIP_TRY(launch_dense_step(c->facts.path, EPI_FIELDS, c->L.mbw, c->L.Cg, a, c->stream));
+        HIP_TRY(launch_energy_fields(c->N, c->L.Np, c->L.C, c->x[in], c->x[sc], h64, c->E, c->stream));
     } else {
         HIP_TRY(launch_readout_f64(c->N, c->L.Np, c->L.C, c->L.Np, false, c->x[c->cur], c->S64, c->stream));
         HIP_TRY(launch_gemm_f64(c->S64, c->J64, c->phis64, c->L.Np, c->L.Cp, c->L.esplits, c->stream));

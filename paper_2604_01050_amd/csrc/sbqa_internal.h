@@ -245,6 +245,15 @@ hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, con
                                    const double *val, const Tri3 &t3, const double *h, const int8_t *spins,
                                    double *E, hipStream_t st);
 
+// Exact energies of the readout of a dense state [C][Np] whose J is integral
+// (fp8 / int8 paths): the readout operand sign(x) (sign(0) = +1, padded spins
+// 0) in the fragment-tiled layout, contracted by the dense step's fields
+// epilogue into phi [C][Np], then E_c = -1/2 s.phi - h.s in float64.
+hipError_t launch_readout_operand(Path path, int N, int Np, int C, int nkc, int mbw, const float *x, void *g,
+                                  hipStream_t st);
+hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const float *phi, const double *h, double *E,
+                                hipStream_t st);
+
 // Per-run best over replicas with tie -> lowest k; updates best_E/best_step
 // when strictly lower and copies the winning readout spins.
 hipError_t launch_best_update(int N, int R, int runs, int ld, bool spin_major, const float *x,

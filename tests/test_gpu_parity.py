@@ -321,6 +321,29 @@ def test_int8_and_fp32_trajectories_identical(sb):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec,coup,packing", [("PREC_FP8", "sk", "auto"), ("PREC_FP8", "sk", "bytes"),
+                                               ("PREC_FP8", "sk0", "auto"), ("PREC_INT8", "sidon", "auto")])
+def test_integer_j_energies_on_mfma(sb, orc, prec, coup, packing):
+    """Integer J on the fp8 / int8 paths: the readout energies come from the
+    MFMA contraction of sign(x) (exact integers), and equal the oracle's
+    float64 energies of the same spins bit for bit (N = 300 ragged, integer h)."""
+    N, R, runs, S = 300, 4, 5, 37
+    J = inst.sidon28_dense(N, 71) if coup == "sidon" else inst.sk_pm1(N, 71)
+    if coup == "sk0":
+        keep = np.triu(np.random.default_rng(72).random((N, N)) < 0.5, 1)
+        J = J * (keep | keep.T)
+    h = np.round(inst.gaussian_fields(N, 3.0, 73))
+    ctx = _ctx(sb, J=J, h=h, R=R, runs=runs, steps=S, precision=getattr(sb, prec), loop_kernel=sb.LOOP_STREAM,
+               j_packing=sb.JPACK_BYTES if packing == "bytes" else sb.JPACK_AUTO)
+    sb.sbqa_step(ctx, S)
+    X, _ = sb.sbqa_get_state(ctx)
+    spins = np.where(X >= 0, 1, -1).astype(np.int8).T          # (C, N)
+    Eo = orc.energy(spins, J=J, h=h).reshape(runs, R)
+    Eb, sp = sb.sbqa_best(ctx)
+    assert np.array_equal(Eb, Eo.min(axis=1))
+    assert np.array_equal(orc.energy(sp, J=J, h=h), Eb)
+
+
 # ----------------------------------------------- native three-body (HUBO) terms
 @pytest.mark.parametrize("fmode,law,R", [(0, "int", 5), (1, "int", 8), (2, "normal", 5), (0, "normal", 8),
                                          (0, "cauchy", 5)])
