@@ -153,19 +153,23 @@ def algorithmic_flops(w):
     return 2.0 * N * N * C
 
 
-KERNEL_SOURCES = {"csr_fp32": "paper_2604_01050_amd/csrc/kernels_csr.hip",
-                  "csr_resident": "paper_2604_01050_amd/csrc/kernels_csr.hip",
-                  "dense_fp8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
-                  "dense_int8": "paper_2604_01050_amd/csrc/kernels_dense.hip",
-                  "dense_fp8_packed": "paper_2604_01050_amd/csrc/kernels_dense.hip",
-                  "dense_fp32": "paper_2604_01050_amd/csrc/kernels_dense.hip",
-                  "dense_bf16x3": "paper_2604_01050_amd/csrc/kernels_dense.hip"}
+_CS = "paper_2604_01050_amd/csrc/"
+# Source files that define each dominant kernel (the kernel file and the
+# headers it includes from csrc/); counter summaries record their hash.
+KERNEL_SOURCES = {"csr_fp32": [_CS + "kernels_csr.hip", _CS + "csr_common.h", _CS + "sbqa_internal.h"],
+                  "csr_resident": [_CS + "kernels_resident.hip", _CS + "csr_common.h", _CS + "sbqa_internal.h"]}
+for _p in ("dense_fp8", "dense_fp8_packed", "dense_int8", "dense_fp32", "dense_bf16x3"):
+    KERNEL_SOURCES[_p] = [_CS + "kernels_dense.hip", _CS + "sbqa_internal.h"]
 
 
-def source_hash(path):
+def source_hash(paths):
+    """First 16 hex digits of the sha256 of the concatenated files."""
     import hashlib
-    with open(os.path.join(ROOT, path), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in paths:
+        with open(os.path.join(ROOT, path), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, path):
