@@ -154,12 +154,12 @@ def algorithmic_flops(w):
 
 
 _CS = "paper_2604_01050_amd/csrc/"
-# Source files that define each dominant kernel (the kernel file and the
-# headers it includes from csrc/); counter summaries record their hash.
-KERNEL_SOURCES = {"csr_fp32": [_CS + "kernels_csr.hip", _CS + "csr_common.h", _CS + "sbqa_internal.h"],
-                  "csr_resident": [_CS + "kernels_resident.hip", _CS + "csr_common.h", _CS + "sbqa_internal.h"]}
+# Source files that hold each dominant kernel's code (the kernel file and the
+# device helpers it includes); counter summaries record their hash.
+KERNEL_SOURCES = {"csr_fp32": [_CS + "kernels_csr.hip", _CS + "csr_common.h"],
+                  "csr_resident": [_CS + "kernels_resident.hip", _CS + "csr_common.h"]}
 for _p in ("dense_fp8", "dense_fp8_packed", "dense_int8", "dense_fp32", "dense_bf16x3"):
-    KERNEL_SOURCES[_p] = [_CS + "kernels_dense.hip", _CS + "sbqa_internal.h"]
+    KERNEL_SOURCES[_p] = [_CS + "kernels_dense.hip"]
 
 
 def source_hash(paths):

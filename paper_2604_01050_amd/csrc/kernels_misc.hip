@@ -214,10 +214,9 @@ __global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *
 // lower and the winner's readout spins are copied. The comparison is kept in
 // vector registers on purpose: a wave-uniform float64 compare feeding a scalar
 // select was observed to be lowered with a stale condition code on gfx950.
-__global__ __launch_bounds__(64) void k_best_update(int N, int R, int ld, int spin_major,
-                                                    const float *__restrict__ x, const double *__restrict__ E,
-                                                    double *__restrict__ best_E, int64_t *__restrict__ best_step,
-                                                    int8_t *__restrict__ best_spins, int64_t step) {
+__global__ __launch_bounds__(64) void k_best_select(int R, const double *__restrict__ E, double *__restrict__ best_E,
+                                                    int64_t *__restrict__ best_step, int *__restrict__ sel,
+                                                    int64_t step) {
     const int r = blockIdx.x, lane = threadIdx.x;
     double eb = INFINITY;
     int kb = 0x7FFFFFFF;
@@ -235,16 +234,28 @@ __global__ __launch_bounds__(64) void k_best_update(int N, int R, int ld, int sp
     }
     const double cur = best_E[r];
     const int better = (eb < cur) ? 1 : 0;
-    if (!better) return;
     if (lane == 0) {
-        best_E[r] = eb;
-        best_step[r] = step;
+        sel[r] = better ? kb : -1;
+        if (better) {
+            best_E[r] = eb;
+            best_step[r] = step;
+        }
     }
-    const int c = r * R + kb;
-    for (int i = lane; i < N; i += 64) {
-        const float v = spin_major ? x[(int64_t)i * ld + c] : x[(int64_t)c * ld + i];
-        best_spins[(int64_t)r * N + i] = v >= 0.0f ? 1 : -1;
-    }
+}
+
+// Copy of the winning replica's readout spins (sign(0) = +1) for the runs
+// whose best improved: block (chunk, run), one spin per thread.
+__global__ __launch_bounds__(256) void k_best_copy(int N, int R, int ld, int spin_major,
+                                                   const float *__restrict__ x, const int *__restrict__ sel,
+                                                   int8_t *__restrict__ best_spins) {
+    const int r = blockIdx.y;
+    const int k = sel[r];
+    if (k < 0) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    const int c = r * R + k;
+    const float v = spin_major ? x[(int64_t)i * ld + c] : x[(int64_t)c * ld + i];
+    best_spins[(int64_t)r * N + i] = v >= 0.0f ? 1 : -1;
 }
 
 }  // namespace
@@ -304,10 +315,11 @@ hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const floa
 }
 
 hipError_t launch_best_update(int N, int R, int runs, int ld, bool spin_major, const float *x, const double *E,
-                              double *best_E, int64_t *best_step, int8_t *best_spins, int64_t step,
+                              double *best_E, int64_t *best_step, int8_t *best_spins, int *sel, int64_t step,
                               hipStream_t st) {
-    hipLaunchKernelGGL(k_best_update, dim3(runs), dim3(64), 0, st, N, R, ld, spin_major ? 1 : 0, x, E, best_E,
-                       best_step, best_spins, step);
+    hipLaunchKernelGGL(k_best_select, dim3(runs), dim3(64), 0, st, R, E, best_E, best_step, sel, step);
+    hipLaunchKernelGGL(k_best_copy, dim3((N + 255) / 256, runs), dim3(256), 0, st, N, R, ld, spin_major ? 1 : 0, x,
+                       sel, best_spins);
     return hipGetLastError();
 }
 

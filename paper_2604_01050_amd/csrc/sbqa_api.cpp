@@ -292,7 +292,9 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         b += 2 * (int64_t)N * L->Cs;                                      // int8 operand ping-pong
         b += (int64_t)(N + 1) * 4 + f.nnz * (4 + 4 + 8);                 // CSR
         b += (int64_t)N * 12;                                             // h32, h64
-        L->csr_nrb = (int)std::max<int64_t>(1, std::min<int64_t>(64, (N + 63) / 64));
+        // energy row blocks: about 2048 blocks over the column chunks, >= 16 rows each
+        const int64_t ncb = (C + 255) / 256;
+        L->csr_nrb = (int)std::max<int64_t>(1, std::min<int64_t>((N + 15) / 16, (2048 + ncb - 1) / ncb));
         b += (int64_t)L->csr_nrb * C * 24;
         if (f.n3) b += (int64_t)(N + 1) * 4 + 3 * f.n3 * (8 + 4 + 8);    // three-body lists
         b += (int64_t)N * L->Cs * 4;                                      // phi (fields hook)
@@ -528,6 +530,7 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     HIP_TRY(dalloc(c, &c->bestE, (size_t)runs));
     HIP_TRY(dalloc(c, &c->bestStep, (size_t)runs));
     HIP_TRY(dalloc(c, &c->bestSpins, (size_t)runs * N));
+    HIP_TRY(dalloc(c, &c->bestSel, (size_t)runs));
 
     const int hrows = std::max(Np, c->resident ? c->res_rows : 0);
     std::vector<float> h32((size_t)hrows, 0.0f);
@@ -747,7 +750,7 @@ sbqa_status ctx_evaluate(sbqa_ctx *c) {
     if (st != SBQA_OK) return st;
     const bool sm = c->facts.path == PATH_CSR;
     const int ld = sm ? c->L.Cs : c->L.Np;
-    HIP_TRY(launch_best_update(c->N, c->R, c->runs, ld, sm, c->x[c->cur], c->E, c->bestE, c->bestStep, c->bestSpins,
+    HIP_TRY(launch_best_update(c->N, c->R, c->runs, ld, sm, c->x[c->cur], c->E, c->bestE, c->bestStep, c->bestSpins, c->bestSel,
                                (int64_t)c->step, c->stream));
     c->last_eval_step = c->step;
     return SBQA_OK;

@@ -105,6 +105,7 @@ struct sbqa_ctx {
     double *bestE = nullptr;
     int64_t *bestStep = nullptr;
     int8_t *bestSpins = nullptr;
+    int *bestSel = nullptr;             // [runs] scratch of the best update
 
     // resident loops: register-resident CSR loop (kernels_csr.hip) or the
     // small dense loop (kernels_small.hip)

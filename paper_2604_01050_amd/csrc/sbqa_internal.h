@@ -255,9 +255,10 @@ hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const floa
                                 hipStream_t st);
 
 // Per-run best over replicas with tie -> lowest k; updates best_E/best_step
-// when strictly lower and copies the winning readout spins.
+// when strictly lower and copies the winning readout spins. sel: [runs]
+// scratch (the winning replica, or -1).
 hipError_t launch_best_update(int N, int R, int runs, int ld, bool spin_major, const float *x,
                               const double *E, double *best_E, int64_t *best_step,
-                              int8_t *best_spins, int64_t step, hipStream_t st);
+                              int8_t *best_spins, int *sel, int64_t step, hipStream_t st);
 
 }  // namespace sbqa
