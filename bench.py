@@ -31,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PEAK = {"fp8": 5030.0, "int8": 5030.0, "bf16": 2520.0, "fp32": 157.3, "fp64": 78.6}  # T(FL)OP/s dense MFMA
+PEAK = {"fp4": 10060.0, "fp8": 5030.0, "int8": 5030.0, "bf16": 2520.0, "fp32": 157.3, "fp64": 78.6}  # T(FL)OP/s dense MFMA
 
 
 def make_workload(name: str):
@@ -44,6 +44,13 @@ def make_workload(name: str):
         desc = ("random 6-regular N=4096, J~N(0,1) on edges, h~N(0,0.1^2), R=32 x 64 runs, "
                 "5000 steps, dt=0.5, ternary f, J_perp linear 0.5->0, fp32 CSR")
         return dict(csr=csr, h=h, N=N, R=R, runs=runs, S=S, prec=None, fmode=0, desc=desc, d=d, dtype="f32")
+    if name in ("sk_fp4", "sk_fp4_bytes"):
+        N, R, runs, S = 16384, 16, 16, 10000
+        packed = name == "sk_fp4"
+        return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP4", fmode=0,
+                    j_packing=None if packed else "JPACK_BYTES",
+                    desc="SK N=16384 J=+-1 (%s), R=16 x 16 runs, 10000 steps, ternary f"
+                         % ("1 bit per coupling, e2m1 fp4 MFMA" if packed else "e2m1 nibbles"), dtype="fp4")
     if name in ("sk_fp8", "sk_fp8_bytes"):
         N, R, runs, S = 16384, 16, 16, 10000
         packed = name == "sk_fp8"
@@ -124,8 +131,9 @@ def algorithmic_bytes(w, info):
         if w.get("K") is not None:   # three-body lists: per member entry two indices and a weight
             b += 4 * (N + 1) + 3 * len(w["K"]) * 12
         return b
-    eb = {"dense_fp8": 1, "dense_fp8_packed": 1, "dense_int8": 1, "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
-    jb = N * N / 8 if info["path"] == "dense_fp8_packed" else N * N * eb
+    eb = {"dense_fp8": 1, "dense_fp8_packed": 1, "dense_int8": 1, "dense_fp4": 0.5, "dense_fp4_packed": 0.5,
+          "dense_fp32": 4, "dense_bf16x3": 4}[info["path"]]
+    jb = N * N / 8 if info["path"].endswith("_packed") else N * N * eb
     # GEMM: J streamed once + operand read once + fp32 field partial written
     return jb + C * N * eb + C * N * 4
 
@@ -158,7 +166,8 @@ _CS = "paper_2604_01050_amd/csrc/"
 # device helpers it includes); counter summaries record their hash.
 KERNEL_SOURCES = {"csr_fp32": [_CS + "kernels_csr.hip", _CS + "csr_common.h"],
                   "csr_resident": [_CS + "kernels_resident.hip", _CS + "csr_common.h"]}
-for _p in ("dense_fp8", "dense_fp8_packed", "dense_int8", "dense_fp32", "dense_bf16x3"):
+for _p in ("dense_fp8", "dense_fp8_packed", "dense_int8", "dense_fp4", "dense_fp4_packed", "dense_fp32",
+           "dense_bf16x3"):
     KERNEL_SOURCES[_p] = [_CS + "kernels_dense.hip"]
 
 
@@ -491,7 +500,8 @@ def main():
                                "algorithmic_bytes_per_launch": ab}
         else:
             fl = algorithmic_flops(w)
-            peak = PEAK[{"dense_fp8": "fp8", "dense_fp8_packed": "fp8", "dense_int8": "int8", "dense_fp32": "fp32",
+            peak = PEAK[{"dense_fp8": "fp8", "dense_fp8_packed": "fp8", "dense_int8": "int8", "dense_fp4": "fp4",
+                         "dense_fp4_packed": "fp4", "dense_fp32": "fp32",
                          "dense_bf16x3": "bf16"}[info["path"]]]
             unit = "TOP/s" if info["path"] == "dense_int8" else "TFLOP/s"
             out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": unit,

@@ -68,12 +68,18 @@ typedef enum { SBQA_F_TERNARY = 0, SBQA_F_SIGN = 1, SBQA_F_BALLISTIC = 2 } sbqa_
  *          Sidon28 couplings of the QAC benchmarks, Sec. III, scaled by 28 to
  *          {8, 13, 19, 28}: 19 has no e4m3 encoding) and f ternary or sign;
  *          rejected otherwise.
+ *   FP4    J and f(X) in e2m1 fp4 (4 bits, the CDNA4 matrix cores' fastest
+ *          format), fp32 accumulation. +-1 and 0 are exact in e2m1, so it is
+ *          exact where FP8 is (J in {-1,0,+1}, f ternary or sign) and gives
+ *          the same bits; rejected otherwise.
  *   BF16X3 J and f(X) split into bf16 hi + lo; J_hi f_hi + J_hi f_lo + J_lo f_hi
  *          accumulated in fp32 (ballistic / real-valued contraction).
- *   AUTO   with f ternary or sign: FP8 for J in {-1,0,+1}, else INT8 for
- *          integer J with |J| <= 127, else FP32; with f ballistic: FP32. */
+ *   AUTO   with f ternary or sign: FP4 for J in {-1,0,+1} (the fastest exact
+ *          form), else INT8 for integer J with |J| <= 127, else FP32; with f
+ *          ballistic: FP32. */
 typedef enum {
-    SBQA_PREC_AUTO = 0, SBQA_PREC_FP32 = 1, SBQA_PREC_FP8 = 2, SBQA_PREC_BF16X3 = 3, SBQA_PREC_INT8 = 4
+    SBQA_PREC_AUTO = 0, SBQA_PREC_FP32 = 1, SBQA_PREC_FP8 = 2, SBQA_PREC_BF16X3 = 3, SBQA_PREC_INT8 = 4,
+    SBQA_PREC_FP4 = 5
 } sbqa_prec;
 
 /* Inter-replica coupling schedule J_perp[r][n]:
@@ -98,11 +104,12 @@ typedef enum { SBQA_JP_LINEAR = 0, SBQA_JP_PAPER = 1, SBQA_JP_TABLE = 2 } sbqa_j
  *             sbqa_create fails with EINVAL when the instance does not fit. */
 typedef enum { SBQA_LOOP_AUTO = 0, SBQA_LOOP_STREAM = 1, SBQA_LOOP_RESIDENT = 2 } sbqa_loop_kernel;
 
-/* Storage of J for the dense FP8 contraction:
+/* Storage of J for the dense FP8 and FP4 contractions:
  *   AUTO   one bit per coupling when every off-diagonal J_ij is +-1 (SK-type
- *          instances: 8x fewer J bytes to stream per step); expanded to e4m3
- *          in registers, so the fields are the same exact integers.
- *   BYTES  one e4m3 byte per coupling. */
+ *          instances: 8x (FP8) or 4x (FP4) fewer J bytes to stream per
+ *          step); expanded to e4m3 / e2m1 in registers, so the fields are the
+ *          same exact integers.
+ *   BYTES  one e4m3 byte (FP8) or e2m1 nibble (FP4) per coupling. */
 typedef enum { SBQA_JPACK_AUTO = 0, SBQA_JPACK_BYTES = 1 } sbqa_j_packing;
 
 /* Couplings: exactly one of `dense` or the CSR triple is non-NULL.
@@ -161,7 +168,7 @@ typedef struct {
                                 step timed once per process on scratch buffers
                                 of the instance's shape; every tile gives the
                                 same bits)                                        */
-    int32_t j_packing;       /* sbqa_j_packing (dense FP8 only)                    */
+    int32_t j_packing;       /* sbqa_j_packing (dense FP8 / FP4 only)              */
 } sbqa_schedule;
 
 /* Defaults: steps 1000, dt 0.5, a0 1, c0 auto, ternary f, delta_max 0.7,
@@ -176,7 +183,8 @@ typedef struct {
     uint32_t steps;          /* S                                                  */
     uint32_t step;           /* steps already taken                                */
     int32_t path;            /* 0 dense fp32, 1 dense fp8, 2 dense bf16x3, 3 csr,
-                                4 dense int8, 5 dense fp8 with bit-packed J     */
+                                4 dense int8, 5 dense fp8 with bit-packed J,
+                                6 dense fp4, 7 dense fp4 with bit-packed J      */
     int32_t fmode;
     double c0;               /* c0 actually used                                   */
     int32_t j_integral;      /* 1 when every J_ij and h_i is an integer            */

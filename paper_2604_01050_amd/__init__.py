@@ -9,6 +9,6 @@ without it the import fails, there is no CPU fallback.
 from ._abi import *  # noqa: F401,F403
 from ._abi import (Context, SbqaError, Server, make_schedule, lib, LIB_PATH, PATHS,  # noqa: F401
                    OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET, EAGAIN,
-                   F_TERNARY, F_SIGN, F_BALLISTIC, PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8,
+                   F_TERNARY, F_SIGN, F_BALLISTIC, PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8, PREC_FP4,
                    JP_LINEAR, JP_PAPER, JP_TABLE, LOOP_AUTO, LOOP_STREAM, LOOP_RESIDENT,
                    JPACK_AUTO, JPACK_BYTES)

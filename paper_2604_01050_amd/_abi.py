@@ -16,11 +16,12 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsbqa.so"
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET, EAGAIN = 0, -1, -2, -3, -4, -5, -6
 F_TERNARY, F_SIGN, F_BALLISTIC = 0, 1, 2
-PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8 = 0, 1, 2, 3, 4
+PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8, PREC_FP4 = 0, 1, 2, 3, 4, 5
 JP_LINEAR, JP_PAPER, JP_TABLE = 0, 1, 2
 LOOP_AUTO, LOOP_STREAM, LOOP_RESIDENT = 0, 1, 2
 JPACK_AUTO, JPACK_BYTES = 0, 1
-PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32", 4: "dense_int8", 5: "dense_fp8_packed"}
+PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32", 4: "dense_int8", 5: "dense_fp8_packed",
+         6: "dense_fp4", 7: "dense_fp4_packed"}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EBUDGET", -6: "EAGAIN"}
 
 

@@ -1,8 +1,9 @@
 // Dense SBQA kernels for gfx950 (CDNA4, wave64):
 //   * one step of the dense path: the coupling sum of Eq. 7 over all runs and
 //     replicas, Phi^T[c][i] = sum_j f(X)^T[c][j] J[i][j] (J symmetric, zero
-//     diagonal), on MFMA in fp32, e4m3 fp8 (J as bytes or, for J = +-1, one
-//     bit per coupling), int8 (integer J) or bf16 hi+lo (three products),
+//     diagonal), on MFMA in fp32, e4m3 fp8 or e2m1 fp4 (J as bytes / nibbles
+//     or, for J = +-1, one bit per coupling), int8 (integer J) or bf16 hi+lo
+//     (three products),
 //     with the update of Eqs. 6-7 (pump, Trotter ring, kick, drift, wall) and
 //     the next operand f(X) (Eq. 8) fused into its epilogue;
 //   * the fp64 GEMM of the energies (Eq. 2 at the corners).
@@ -25,12 +26,15 @@ typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 // e4m3 and int8 encodings of the ternary values.
 constexpr uint8_t FP8_P1 = 0x38, FP8_M1 = 0xB8;
 constexpr uint8_t I8_P1 = 0x01, I8_M1 = 0xFF;
+// e2m1 (fp4) nibbles of +1 and -1 (sign bit 3, exponent 01, mantissa 0).
+constexpr uint32_t FP4_P1 = 0x2, FP4_M1 = 0xA;
 // E8M0 block scale 2^(127-127) = 1 for the scaled fp8 MFMA.
 constexpr int E8M0_ONE = 127;
 
 struct Frag32 { uint4 lo, hi; };  // the 32 K bytes of one lane for a 16x16 block
 
 template <int PATH> constexpr bool is_fp8 = PATH == PATH_FP8 || PATH == PATH_FP8PK;
+template <int PATH> constexpr bool is_fp4 = PATH == PATH_FP4 || PATH == PATH_FP4PK;
 
 // Bit-packed +-1 J: lane l of a fragment owns the dword at 4*l; its bit
 // 8*i + k encodes byte i of dword k (k = 0..7) of the lane's 32 fp8 K bytes,
@@ -38,6 +42,16 @@ template <int PATH> constexpr bool is_fp8 = PATH == PATH_FP8 || PATH == PATH_FP8
 __device__ __forceinline__ Frag32 unpack_pm1(uint32_t w) {
     auto d = [w](int k) { return ((w << (7 - k)) & 0x80808080u) | 0x38383838u; };
     return Frag32{make_uint4(d(0), d(1), d(2), d(3)), make_uint4(d(4), d(5), d(6), d(7))};
+}
+
+// The same for fp4: a lane owns two dwords (one per 16-byte half of its 32
+// bytes = 64 nibbles); bit 4*i + k of a half's dword encodes nibble i of dword
+// k (k = 0..3) of that half, set for -1, so dword k is
+// ((w << (3 - k)) & 0x88888888) | e2m1(+1) x 8.
+__device__ __forceinline__ Frag32 unpack_pm1_fp4(uint2 w) {
+    auto d = [](uint32_t v, int k) { return ((v << (3 - k)) & 0x88888888u) | 0x22222222u; };
+    return Frag32{make_uint4(d(w.x, 0), d(w.x, 1), d(w.x, 2), d(w.x, 3)),
+                  make_uint4(d(w.y, 0), d(w.y, 1), d(w.y, 2), d(w.y, 3))};
 }
 
 // ---------------------------------------------------------------------------
@@ -142,6 +156,14 @@ __device__ __forceinline__ int64_t tf_offset(int row, int k, int nkc, int eb, in
     return (((int64_t)(rb / G) * nkc + kc) * G + rb % G) * FRAG_BYTES + ((kb >> 4) & 1) * 1024 + l * 16 + (kb & 15);
 }
 
+// Byte offset of element (row, k) of an operand or J in the path's format
+// (fp4: of the byte that holds elements k and k + 1, k even).
+template <int PATH>
+__device__ __forceinline__ int64_t op_offset(int row, int k, int nkc, int G) {
+    if constexpr (is_fp4<PATH>) return tf_offset(row, k >> 1, nkc, 1, G);
+    else return tf_offset(row, k, nkc, path_ebytes(Path(PATH)), G);
+}
+
 __device__ __forceinline__ float f_value(int fmode, float x, float delta) {
     if (fmode == 2) return x;                       // bSB
     const float d = (fmode == 1) ? 0.0f : delta;    // dSB: sign(0) = 0
@@ -175,6 +197,12 @@ __device__ __forceinline__ void store_operand(void *g, void *g_lo, int64_t o, fl
             w |= b << (8 * e);
         }
         *reinterpret_cast<uint32_t *>(gb + o) = w;
+    } else if constexpr (is_fp4<PATH>) {
+        const float v[4] = {f.x, f.y, f.z, f.w};
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= (v[e] > 0.0f ? FP4_P1 : (v[e] < 0.0f ? FP4_M1 : 0u)) << (4 * e);
+        *reinterpret_cast<uint16_t *>(gb + o) = (uint16_t)w;
     } else {  // BF16X3
         const float v[4] = {f.x, f.y, f.z, f.w};
         uint16_t hi[4], lo[4];
@@ -204,6 +232,8 @@ template <> struct Terms<PATH_FP8> { static constexpr int n = 1; };     // 1 x 1
 template <> struct Terms<PATH_FP8PK> { static constexpr int n = 1; };
 template <> struct Terms<PATH_BF16X3> { static constexpr int n = 6; };  // lo*hi, hi*lo, hi*hi x 2 halves
 template <> struct Terms<PATH_I8> { static constexpr int n = 2; };      // 2 x 16x16x64 i8 (K halves)
+template <> struct Terms<PATH_FP4> { static constexpr int n = 2; };     // 2 x 16x16x128 fp4 (K halves)
+template <> struct Terms<PATH_FP4PK> { static constexpr int n = 2; };
 
 template <int PATH, int T>
 __device__ __forceinline__ void mma_term(f4 &acc, const Frag32 &a, const Frag32 &b, const Frag32 &a2,
@@ -228,6 +258,14 @@ __device__ __forceinline__ void mma_term(f4 &acc, const Frag32 &a, const Frag32 
         __builtin_memcpy(&xv, &xs, 16);
         __builtin_memcpy(&yv, &ys, 16);
         acc = __builtin_bit_cast(f4, __builtin_amdgcn_mfma_i32_16x16x64_i8(xv, yv, __builtin_bit_cast(i4v, acc), 0, 0, 0));
+    } else if constexpr (is_fp4<PATH>) {
+        // e2m1 operands (format 4 for A and B): term T takes the lane's 16
+        // bytes of half T (64 lanes x 32 nibbles = one 16x128 K block each)
+        const uint4 &xs = T ? a.hi : a.lo;
+        const uint4 &ys = T ? b.hi : b.lo;
+        const i8v xv = {(int)xs.x, (int)xs.y, (int)xs.z, (int)xs.w, 0, 0, 0, 0};
+        const i8v yv = {(int)ys.x, (int)ys.y, (int)ys.z, (int)ys.w, 0, 0, 0, 0};
+        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(xv, yv, acc, 4, 4, 0, E8M0_ONE, 0, E8M0_ONE);
     } else {
         // small products first: lo*hi, hi*lo, then hi*hi; each over both halves
         const Frag32 &x = (T < 2) ? a2 : a;
@@ -317,8 +355,7 @@ __device__ __forceinline__ void update_store(const DenseStepArgs &a, int c, int 
     const int64_t o = (int64_t)c * a.Np + i4;
     *reinterpret_cast<float4 *>(a.x_out + o) = make_float4(xo[0], xo[1], xo[2], xo[3]);
     *reinterpret_cast<float4 *>(a.y + o) = make_float4(yo[0], yo[1], yo[2], yo[3]);
-    constexpr int eb = path_ebytes(Path(PATH));
-    store_operand<PATH>(a.g_next, a.g_next_lo, tf_offset(c, i4, a.nkc, eb, MBW),
+    store_operand<PATH>(a.g_next, a.g_next_lo, op_offset<PATH>(c, i4, a.nkc, MBW),
                         make_float4(fo[0], fo[1], fo[2], fo[3]), a.fmode);
 }
 #pragma clang fp contract(on)
@@ -350,14 +387,15 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
     const int mb0 = (mchunk * 4 + w) * MBW;       // first m-block of this wave
     const int nkc = a.nkc;
     const int l16 = lane * 16;
-    constexpr bool JPK = PATH == PATH_FP8PK;     // J as one bit per coupling
-    constexpr int JFRAG = JPK ? PK_FRAG_BYTES : FRAG_BYTES;
+    constexpr bool JPK = path_packed(Path(PATH));   // J as one bit per coupling
+    constexpr int JFRAG = JPK ? pk_frag_bytes(Path(PATH)) : FRAG_BYTES;
+    using JWord = std::conditional_t<is_fp4<PATH>, uint2, uint32_t>;   // a lane's packed J of one chunk
     constexpr int JCH = RBT * JFRAG;        // J bytes of one tile and K chunk
     constexpr int XCH = MBW * FRAG_BYTES;   // operand bytes of one wave and K chunk
 
     // this wave stages J row block w of tile nt (both planes); its operand
     // group is m-blocks mb0..mb0+MBW-1
-    const int64_t jgrp = (int64_t)nt * nkc * JCH + w * JFRAG + (JPK ? lane * 4 : l16);
+    const int64_t jgrp = (int64_t)nt * nkc * JCH + w * JFRAG + (JPK ? lane * (int)sizeof(JWord) : l16);
     const int64_t xgrp = (int64_t)(mchunk * 4 + w) * nkc * XCH + l16;
     const uint8_t *jsrc = a.J + jgrp;
     const uint8_t *jsrc_lo = (PL == 2) ? a.J_lo + jgrp : jsrc;
@@ -365,7 +403,7 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
     const uint8_t *xsrc_lo = (PL == 2) ? a.g_lo + xgrp : xsrc;
 
     uint4 jr[JPK ? 1 : PD][PL][2];
-    uint32_t jw[JPK ? PD : 1];
+    JWord jw[JPK ? PD : 1];
     uint4 xr[PD][MBW][PL][2];
     f4 acc[MBW][RBT];
 #pragma unroll
@@ -378,7 +416,7 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
     auto load_j = [&](int s, int kc) {
         const int64_t o = chunk_at(kc) * JCH;
         if constexpr (JPK) {
-            jw[s] = *reinterpret_cast<const uint32_t *>(jsrc + o);
+            jw[s] = *reinterpret_cast<const JWord *>(jsrc + o);
         } else {
             jr[s][0][0] = ld16(jsrc + o);
             jr[s][0][1] = ld16(jsrc + o + 1024);
@@ -426,7 +464,9 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
             // chunk kc - 2, which every wave finished before the barrier of
             // chunk kc - 1
             if constexpr (JPK) {
-                const Frag32 f = unpack_pm1(jw[s]);
+                Frag32 f;
+                if constexpr (is_fp4<PATH>) f = unpack_pm1_fp4(jw[s]);
+                else f = unpack_pm1(jw[s]);
                 uint8_t *dst = slot + w * FRAG_BYTES + l16;
                 *reinterpret_cast<uint4 *>(dst) = f.lo;
                 *reinterpret_cast<uint4 *>(dst + 1024) = f.hi;
@@ -504,12 +544,16 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
 #pragma unroll
             for (int it = 0; it < ITEMS; ++it) {
                 if (cc[it] >= a.C) continue;
-                const uint32_t fb = *reinterpret_cast<const uint32_t *>(a.g + tf_offset(cc[it], ii[it], nkc, 1, MBW));
+                const uint8_t *fp = a.g + op_offset<PATH>(cc[it], ii[it], nkc, MBW);
+                constexpr int BITS = is_fp4<PATH> ? 4 : 8;
+                constexpr uint32_t MASK = (1u << BITS) - 1u, SIGN = 1u << (BITS - 1);
+                const uint32_t fb = is_fp4<PATH> ? (uint32_t)*reinterpret_cast<const uint16_t *>(fp)
+                                                 : *reinterpret_cast<const uint32_t *>(fp);
                 float v[4] = {ph[it].x, ph[it].y, ph[it].z, ph[it].w};
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const uint32_t b = (fb >> (8 * e)) & 0xFFu;
-                    const float f = b == 0u ? 0.0f : ((b & 0x80u) ? -1.0f : 1.0f);
+                    const uint32_t b = (fb >> (BITS * e)) & MASK;
+                    const float f = b == 0u ? 0.0f : ((b & SIGN) ? -1.0f : 1.0f);
                     v[e] = (ii[it] + e < a.N) ? v[e] - f : 0.0f;
                 }
                 ph[it] = make_float4(v[0], v[1], v[2], v[3]);
@@ -555,8 +599,7 @@ __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J6
     if (q >= nq) return;
     const int row = (int)(q / (Np / 4)), k4 = (int)(q % (Np / 4)) * 4;
     const double *src = J64 + (int64_t)row * Np + k4;
-    constexpr int eb = path_ebytes(Path(PATH));
-    const int64_t o = tf_offset(row, k4, nkc, eb, DENSE_TN / 16);
+    const int64_t o = op_offset<PATH>(row, k4, nkc, DENSE_TN / 16);
     if constexpr (PATH == PATH_F32) {
         *reinterpret_cast<float4 *>(Jd + o) = make_float4((float)src[0], (float)src[1], (float)src[2], (float)src[3]);
     } else if constexpr (PATH == PATH_FP8) {
@@ -572,6 +615,11 @@ __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J6
 #pragma unroll
         for (int e = 0; e < 4; ++e) w |= ((uint32_t)(int32_t)src[e] & 0xFFu) << (8 * e);
         *reinterpret_cast<uint32_t *>(Jd + o) = w;
+    } else if constexpr (PATH == PATH_FP4) {
+        uint32_t w = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) w |= (src[e] > 0.0 ? FP4_P1 : (src[e] < 0.0 ? FP4_M1 : 0u)) << (4 * e);
+        *reinterpret_cast<uint16_t *>(Jd + o) = (uint16_t)w;
     } else {
         uint16_t hi[4], lo[4];
 #pragma unroll
@@ -584,30 +632,44 @@ __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J6
     }
 }
 
-// Bit-packed +-1 J (layout of unpack_pm1), fragment-tiled like the byte
-// copy (groups of DENSE_TN/16 row blocks): one thread per (fragment, lane)
-// dword, consecutive threads write consecutive dwords. A bit is set where
-// J_ij < 0; the diagonal and the padding read 0 and so hold +1 (the step's
-// epilogue removes both).
+// Bit-packed +-1 J (layouts of unpack_pm1 / unpack_pm1_fp4), fragment-tiled
+// like the byte copy (groups of DENSE_TN/16 row blocks): one thread per
+// (fragment, lane, dword), consecutive threads write consecutive dwords. A bit
+// is set where J_ij < 0; the diagonal and the padding read 0 and so hold +1
+// (the step's epilogue removes both).
+template <bool FP4>
 __global__ __launch_bounds__(256) void k_convert_j_pk(const double *__restrict__ J64, int Np, int nkc,
                                                      uint32_t *__restrict__ Jd) {
-    constexpr int RBT = DENSE_TN / 16;
+    constexpr int RBT = DENSE_TN / 16, DW = FP4 ? 2 : 1;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= (int64_t)(Np / 16) * nkc * 64) return;
-    const int lane = (int)(q & 63);
-    const int64_t frag = q >> 6;
+    if (q >= (int64_t)(Np / 16) * nkc * 64 * DW) return;
+    const int d = (int)(q % DW), lane = (int)((q / DW) & 63);
+    const int64_t frag = q / DW / 64;
     const int w = (int)(frag % RBT);
     const int64_t t = frag / RBT;
     const int kc = (int)(t % nkc), rb = (int)(t / nkc) * RBT + w;
-    const double *src = J64 + (int64_t)(16 * rb + (lane & 15)) * Np + 128 * kc + 32 * (lane >> 4);
+    const int g = lane >> 4;
+    const double *row = J64 + (int64_t)(16 * rb + (lane & 15)) * Np;
     uint32_t bits = 0;
+    if constexpr (FP4) {
+        // half d: K = 256 kc + 64 g + 32 d + 8 k + i for nibble i of dword k
+        const double *src = row + 256 * kc + 64 * g + 32 * d;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+        for (int k = 0; k < 4; ++k)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int b = 4 * k + i;               // byte of the lane's 32: half b/16, byte b%16
-            if (src[16 * (b >> 4) + (b & 15)] < 0.0) bits |= 1u << (8 * i + k);
-        }
+            for (int i = 0; i < 8; ++i)
+                if (src[8 * k + i] < 0.0) bits |= 1u << (4 * i + k);
+    } else {
+        // byte b = 4 k + i of the lane's 32: K = 128 kc + 32 g + 16 (b / 16) + b % 16
+        const double *src = row + 128 * kc + 32 * g;
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int bb = 4 * k + i;
+                if (src[16 * (bb >> 4) + (bb & 15)] < 0.0) bits |= 1u << (8 * i + k);
+            }
+    }
     Jd[q] = bits;
 }
 
@@ -662,8 +724,7 @@ __global__ __launch_bounds__(256) void k_dense_operand(int Np, int nkc, int mbw,
     const float4 v = *reinterpret_cast<const float4 *>(x + (int64_t)c * Np + i4);
     const float4 f = make_float4(f_value(fmode, v.x, delta), f_value(fmode, v.y, delta),
                                  f_value(fmode, v.z, delta), f_value(fmode, v.w, delta));
-    constexpr int eb = path_ebytes(Path(PATH));
-    store_operand<PATH>(g, g_lo, tf_offset(c, i4, nkc, eb, mbw), f, fmode);
+    store_operand<PATH>(g, g_lo, op_offset<PATH>(c, i4, nkc, mbw), f, fmode);
 }
 
 // Readout operand s = sign(x) with sign(0) = +1 (the energy convention of
@@ -678,7 +739,7 @@ __global__ __launch_bounds__(256) void k_readout_operand(int N, int Np, int nkc,
     const float4 v = *reinterpret_cast<const float4 *>(x + (int64_t)c * Np + i4);
     auto s = [N](float xv, int i) { return i < N ? (xv >= 0.0f ? 1.0f : -1.0f) : 0.0f; };
     const float4 f = make_float4(s(v.x, i4), s(v.y, i4 + 1), s(v.z, i4 + 2), s(v.w, i4 + 3));
-    store_operand<PATH>(g, nullptr, tf_offset(c, i4, nkc, 1, mbw), f, 0);
+    store_operand<PATH>(g, nullptr, op_offset<PATH>(c, i4, nkc, mbw), f, 0);
 }
 
 template <int PATH, int EPI>
@@ -715,8 +776,8 @@ hipError_t launch_gemm_f64(const double *A, const double *B, double *out, int Np
 hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, const DenseStepArgs &a,
                              hipStream_t st) {
     const int tm = 64 * mbw;
-    if (a.Np % DENSE_TN || Cg % tm || a.C > Cg || a.nkc != a.Np * path_ebytes(path) / 128 ||
-        (a.Np * path_ebytes(path)) % 128 || a.nkc % dense_depth(path))
+    if (a.Np % DENSE_TN || Cg % tm || a.C > Cg || a.Np % path_kpc(path) || a.nkc != dense_nkc(path, a.Np) ||
+        a.nkc % dense_depth(path))
         return hipErrorInvalidValue;
     const dim3 grid(a.Np / DENSE_TN, Cg / tm);
     switch (path) {
@@ -725,16 +786,20 @@ hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, cons
         case PATH_BF16X3: return launch_step_path<PATH_BF16X3>(epi, mbw, grid, a, st);
         case PATH_I8: return launch_step_path<PATH_I8>(epi, mbw, grid, a, st);
         case PATH_FP8PK: return launch_step_path<PATH_FP8PK>(epi, mbw, grid, a, st);
+        case PATH_FP4: return launch_step_path<PATH_FP4>(epi, mbw, grid, a, st);
+        case PATH_FP4PK: return launch_step_path<PATH_FP4PK>(epi, mbw, grid, a, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void *Jd, void *Jd_lo, hipStream_t st) {
-    if (Np % 128 || nkc != Np * path_ebytes(path) / 128) return hipErrorInvalidValue;
-    if (path == PATH_FP8PK) {
-        const int64_t nq = (int64_t)(Np / 16) * nkc * 64;
-        hipLaunchKernelGGL(k_convert_j_pk, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st, J64, Np, nkc,
-                           static_cast<uint32_t *>(Jd));
+    if (Np % 128 || Np % path_kpc(path) || nkc != dense_nkc(path, Np)) return hipErrorInvalidValue;
+    if (path_packed(path)) {
+        const bool fp4 = path_fp4(path);
+        const int64_t nq = (int64_t)(Np / 16) * nkc * 64 * (fp4 ? 2 : 1);
+        const dim3 grid((unsigned)((nq + 255) / 256));
+        if (fp4) hipLaunchKernelGGL(k_convert_j_pk<true>, grid, dim3(256), 0, st, J64, Np, nkc, static_cast<uint32_t *>(Jd));
+        else hipLaunchKernelGGL(k_convert_j_pk<false>, grid, dim3(256), 0, st, J64, Np, nkc, static_cast<uint32_t *>(Jd));
         return hipGetLastError();
     }
     const int64_t nq = (int64_t)Np * (Np / 4);
@@ -745,6 +810,7 @@ hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void 
         case PATH_FP8: hipLaunchKernelGGL(k_convert_j<PATH_FP8>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
         case PATH_BF16X3: hipLaunchKernelGGL(k_convert_j<PATH_BF16X3>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
         case PATH_I8: hipLaunchKernelGGL(k_convert_j<PATH_I8>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
+        case PATH_FP4: hipLaunchKernelGGL(k_convert_j<PATH_FP4>, grid, block, 0, st, J64, Np, nkc, d, dl); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -767,6 +833,8 @@ hipError_t launch_group_dense(Path path, int mbw, const GroupHeader *hdr, const 
         case PATH_BF16X3: SBQA_GD_PATH(PATH_BF16X3); break;
         case PATH_I8: SBQA_GD_PATH(PATH_I8); break;
         case PATH_FP8PK: SBQA_GD_PATH(PATH_FP8PK); break;
+        case PATH_FP4: SBQA_GD_PATH(PATH_FP4); break;
+        case PATH_FP4PK: SBQA_GD_PATH(PATH_FP4PK); break;
         default: return hipErrorInvalidValue;
     }
 #undef SBQA_GD_PATH
@@ -784,6 +852,8 @@ hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int 
         case PATH_BF16X3: hipLaunchKernelGGL(k_dense_operand<PATH_BF16X3>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_I8: hipLaunchKernelGGL(k_dense_operand<PATH_I8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         case PATH_FP8PK: hipLaunchKernelGGL(k_dense_operand<PATH_FP8>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
+        case PATH_FP4:
+        case PATH_FP4PK: hipLaunchKernelGGL(k_dense_operand<PATH_FP4>, grid, block, 0, st, Np, nkc, mbw, x, g, g_lo, delta, fmode); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -800,6 +870,8 @@ hipError_t launch_readout_operand(Path path, int N, int Np, int C, int nkc, int 
         case PATH_FP8:
         case PATH_FP8PK: hipLaunchKernelGGL(k_readout_operand<PATH_FP8>, grid, block, 0, st, N, Np, nkc, mbw, x, g); break;
         case PATH_I8: hipLaunchKernelGGL(k_readout_operand<PATH_I8>, grid, block, 0, st, N, Np, nkc, mbw, x, g); break;
+        case PATH_FP4:
+        case PATH_FP4PK: hipLaunchKernelGGL(k_readout_operand<PATH_FP4>, grid, block, 0, st, N, Np, nkc, mbw, x, g); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -134,7 +134,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     if (!std::isfinite(s->c0)) return fail(SBQA_EINVAL, "c0 must be finite");
     if (s->fmode < 0 || s->fmode > 2) return fail(SBQA_EINVAL, "unknown fmode %d", s->fmode);
     if (!std::isfinite(s->delta_max) || s->delta_max < 0) return fail(SBQA_EINVAL, "delta_max must be finite and >= 0");
-    if (s->precision < SBQA_PREC_AUTO || s->precision > SBQA_PREC_INT8) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
+    if (s->precision < SBQA_PREC_AUTO || s->precision > SBQA_PREC_FP4) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
     if (s->loop_kernel < 0 || s->loop_kernel > 2) return fail(SBQA_EINVAL, "unknown loop_kernel %d", s->loop_kernel);
     if (s->j_packing < SBQA_JPACK_AUTO || s->j_packing > SBQA_JPACK_BYTES) return fail(SBQA_EINVAL, "unknown j_packing %d", s->j_packing);
     if (s->dense_tile != 0 && s->dense_tile != 64 && s->dense_tile != 128 && s->dense_tile != 256)
@@ -256,18 +256,21 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     } else {
         if (prec == SBQA_PREC_AUTO)
             prec = s->fmode == SBQA_F_BALLISTIC ? SBQA_PREC_FP32
-                   : ternary                    ? SBQA_PREC_FP8
+                   : ternary                    ? SBQA_PREC_FP4
                    : facts->int8                ? SBQA_PREC_INT8
                                                 : SBQA_PREC_FP32;
-        if (prec == SBQA_PREC_FP8) {
-            if (s->fmode == SBQA_F_BALLISTIC) return fail(SBQA_EINVAL, "FP8 precision needs ternary or sign f (ballistic operands are not exact in e4m3)");
-            if (!ternary) return fail(SBQA_EINVAL, "FP8 precision needs J in {-1,0,+1}");
+        if (prec == SBQA_PREC_FP8 || prec == SBQA_PREC_FP4) {
+            const char *nm = prec == SBQA_PREC_FP8 ? "FP8" : "FP4";
+            if (s->fmode == SBQA_F_BALLISTIC) return fail(SBQA_EINVAL, "%s precision needs ternary or sign f (ballistic operands are not exact)", nm);
+            if (!ternary) return fail(SBQA_EINVAL, "%s precision needs J in {-1,0,+1}", nm);
         }
         if (prec == SBQA_PREC_INT8) {
             if (s->fmode == SBQA_F_BALLISTIC) return fail(SBQA_EINVAL, "INT8 precision needs ternary or sign f (ballistic operands are not integers)");
             if (!facts->int8) return fail(SBQA_EINVAL, "INT8 precision needs integer J with |J| <= 127");
         }
-        facts->path = prec == SBQA_PREC_FP8      ? (facts->pm1 && s->j_packing == SBQA_JPACK_AUTO ? PATH_FP8PK : PATH_FP8)
+        const bool pack = facts->pm1 && s->j_packing == SBQA_JPACK_AUTO;
+        facts->path = prec == SBQA_PREC_FP8      ? (pack ? PATH_FP8PK : PATH_FP8)
+                      : prec == SBQA_PREC_FP4    ? (pack ? PATH_FP4PK : PATH_FP4)
                       : prec == SBQA_PREC_INT8   ? PATH_I8
                       : prec == SBQA_PREC_BF16X3 ? PATH_BF16X3
                                                  : PATH_F32;
@@ -299,15 +302,15 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         if (f.n3) b += (int64_t)(N + 1) * 4 + 3 * f.n3 * (8 + 4 + 8);    // three-body lists
         b += (int64_t)N * L->Cs * 4;                                      // phi (fields hook)
     } else {
-        const int eb = path_ebytes(f.path), planes = f.path == PATH_BF16X3 ? 2 : 1;
-        L->nkc = L->Np * eb / 128;
+        const int planes = f.path == PATH_BF16X3 ? 2 : 1;
+        L->nkc = dense_nkc(f.path, L->Np);
         const int64_t tiles = (int64_t)(L->Np / GEMM_BN) * (L->Cp / GEMM_BM);
         const int64_t nke = (int64_t)L->Np * 8 / GEMM_KB;
         int es = 1;
         while (tiles * es < 512 && es < 8 && nke % (2 * es) == 0 && nke / (2 * es) >= 4) es *= 2;
         L->esplits = es;
         b += 3 * C * (int64_t)L->Np * 4;                                  // x ping-pong, y
-        b += 2 * (int64_t)L->Cg * L->Np * eb * planes;                    // operand ping-pong
+        b += 2 * dense_plane_bytes(f.path, L->Cg, L->Np) * planes;        // operand ping-pong
         b += dense_j_bytes(f.path, L->Np) * planes;                       // J
         b += (int64_t)L->Np * L->Np * 8;                                  // J fp64 (energies)
         b += (int64_t)L->Np * 12;                                         // h
@@ -348,8 +351,8 @@ static int tune_dense_mbw(Path path, int C, int Np, hipStream_t st) {
         if (m == fallback || round_up(C, 64 * m) <= 2 * round_up(C, 64)) cand.push_back(m);
     int best = fallback;
     if (cand.size() > 1) {
-        const int eb = path_ebytes(path), planes = path == PATH_BF16X3 ? 2 : 1;
-        const int Cgm = (int)round_up(C, 256), nkc = Np * eb / 128;
+        const int planes = path == PATH_BF16X3 ? 2 : 1;
+        const int Cgm = (int)round_up(C, 256), nkc = dense_nkc(path, Np);
         std::vector<void *> bufs;
         auto grab = [&](size_t bytes) -> void * {
             void *p = nullptr;
@@ -358,7 +361,8 @@ static int tune_dense_mbw(Path path, int C, int Np, hipStream_t st) {
             (void)hipMemsetAsync(p, 0, std::max<size_t>(bytes, 256), st);
             return p;
         };
-        const size_t jb = (size_t)dense_j_bytes(path, Np), gb = (size_t)Cgm * Np * eb, sb = (size_t)C * Np * 4;
+        const size_t jb = (size_t)dense_j_bytes(path, Np), gb = (size_t)dense_plane_bytes(path, Cgm, Np),
+                     sb = (size_t)C * Np * 4;
         DenseStepArgs a{};
         a.N = Np;
         a.Np = Np;
@@ -628,14 +632,15 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         return SBQA_OK;
     }
 
-    const int eb = path_ebytes(path), nkc = c->L.nkc, Cg = c->L.Cg;
+    const int nkc = c->L.nkc, Cg = c->L.Cg;
+    const size_t gbytes = (size_t)dense_plane_bytes(path, Cg, Np);
     HIP_TRY(dalloc(c, &c->x[0], (size_t)C * Np));
     HIP_TRY(dalloc(c, &c->x[1], (size_t)C * Np));
     HIP_TRY(dalloc(c, &c->y, (size_t)C * Np));
     for (int q = 0; q < 2; ++q) {
         uint8_t *gb, *glo = nullptr;
-        HIP_TRY(dalloc(c, &gb, (size_t)Cg * Np * eb));
-        if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &glo, (size_t)Cg * Np * eb));
+        HIP_TRY(dalloc(c, &gb, gbytes));
+        if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &glo, gbytes));
         c->g[q] = gb;
         c->g_lo[q] = glo;
     }
@@ -656,7 +661,7 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     uint8_t *jd, *jlo = nullptr;
     double *j64;
     HIP_TRY(dalloc(c, &jd, (size_t)dense_j_bytes(path, Np)));
-    if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &jlo, (size_t)Np * Np * eb));
+    if (path == PATH_BF16X3) HIP_TRY(dalloc(c, &jlo, (size_t)dense_j_bytes(path, Np)));
     HIP_TRY(dalloc(c, &j64, (size_t)Np * Np));
     c->Jd = jd;
     c->Jd_lo = jlo;
@@ -724,7 +729,8 @@ sbqa_status ctx_state_energies(sbqa_ctx *c) {
     if (sm) {
         HIP_TRY(launch_csr_energy_state(c->N, c->L.Cs, c->L.C, c->rp, c->col, c->val64, c->tri3(), h64, c->x[c->cur], c->csr_partial,
                                         c->L.csr_nrb, c->E, c->stream));
-    } else if (c->facts.path == PATH_FP8 || c->facts.path == PATH_FP8PK || c->facts.path == PATH_I8) {
+    } else if (c->facts.path == PATH_FP8 || c->facts.path == PATH_FP8PK || c->facts.path == PATH_I8 ||
+               path_fp4(c->facts.path)) {
         // integer J: J s on MFMA is exact, so the energies equal the float64
         // ones bit for bit; the free halves of the ping-pong buffers (written
         // in full by the next step before they are read) hold the readout

@@ -9,8 +9,14 @@
 namespace sbqa {
 
 // Contraction path of a context.
-// PATH_FP8PK: the fp8 contraction with J = +-1 stored as one bit per coupling.
-enum Path : int32_t { PATH_F32 = 0, PATH_FP8 = 1, PATH_BF16X3 = 2, PATH_CSR = 3, PATH_I8 = 4, PATH_FP8PK = 5 };
+// PATH_FP8PK / PATH_FP4PK: the fp8 / fp4 contraction with J = +-1 stored as
+// one bit per coupling.
+enum Path : int32_t {
+    PATH_F32 = 0, PATH_FP8 = 1, PATH_BF16X3 = 2, PATH_CSR = 3, PATH_I8 = 4, PATH_FP8PK = 5,
+    PATH_FP4 = 6, PATH_FP4PK = 7
+};
+constexpr bool path_fp4(Path p) { return p == PATH_FP4 || p == PATH_FP4PK; }
+constexpr bool path_packed(Path p) { return p == PATH_FP8PK || p == PATH_FP4PK; }
 
 // Tiling of the fp64 energy GEMM (row-major operands).
 // Output tile: GEMM_BM columns c (replicas) x GEMM_BN rows i (spins);
@@ -51,20 +57,28 @@ constexpr int FRAG_BYTES = 2048;
 constexpr int DENSE_TN = 64;        // J rows (spins) per workgroup: 4 row blocks
 constexpr int DENSE_THREADS = 256;  // 4 waves
 
-// Element bytes of the contraction operands.
+// Element bytes of the contraction operands (fp4: two elements per byte,
+// reported as 1 with path_kpc carrying the difference).
 constexpr int path_ebytes(Path p) { return p == PATH_F32 ? 4 : p == PATH_BF16X3 ? 2 : 1; }
-// Bit-packed J: a 16 x 128 fragment in 256 bytes (one dword per lane).
-constexpr int PK_FRAG_BYTES = 256;
+// K elements per 128-byte fragment row (one K chunk).
+constexpr int path_kpc(Path p) { return path_fp4(p) ? 256 : 128 / path_ebytes(p); }
+// K chunks of a row of Np elements.
+constexpr int dense_nkc(Path p, int Np) { return Np / path_kpc(p); }
+// Bit-packed J: a 16 x kpc fragment in 256 (fp8) or 512 (fp4) bytes, one or
+// two dwords per lane.
+constexpr int pk_frag_bytes(Path p) { return path_kpc(p) * 2; }
+// Device bytes of one plane of a [rows][Np] fragment-tiled matrix.
+inline int64_t dense_plane_bytes(Path p, int64_t rows, int Np) { return rows * (int64_t)dense_nkc(p, Np) * 128; }
 // Device bytes of the contraction copy of J (one plane).
 inline int64_t dense_j_bytes(Path p, int Np) {
-    return p == PATH_FP8PK ? (int64_t)Np * Np / 8 : (int64_t)Np * Np * path_ebytes(p);
+    return path_packed(p) ? (int64_t)Np * Np / 8 : dense_plane_bytes(p, Np, Np);
 }
 // K chunks in flight per wave (prefetch depth); a row's K chunk count must be a
 // multiple of it.
-constexpr int dense_depth(Path p) { return path_ebytes(p) == 1 ? 4 : 2; }
+constexpr int dense_depth(Path p) { return (path_ebytes(p) == 1 && !path_fp4(p)) ? 4 : 2; }
 // Spin padding of the dense paths: a multiple of 128 and of depth K chunks.
 constexpr int dense_pad(Path p) {
-    return 128 / path_ebytes(p) * dense_depth(p) > 128 ? 128 / path_ebytes(p) * dense_depth(p) : 128;
+    return path_kpc(p) * dense_depth(p) > 128 ? path_kpc(p) * dense_depth(p) : 128;
 }
 // m-blocks of 16 replicas per wave for C replica columns (workgroup covers
 // 4 * 16 * mbw columns).
@@ -74,7 +88,7 @@ enum DenseEpilogue : int32_t { EPI_UPDATE = 0, EPI_FIELDS = 1 };
 
 struct DenseStepArgs {
     int N, Np, R, C;
-    int nkc;                        // K chunks of 128 bytes per row: Np * ebytes / 128
+    int nkc;                        // K chunks of 128 bytes per row: dense_nkc(path, Np)
     int reverse;                    // traverse K chunks from the last one
     const uint8_t *J, *J_lo;        // fragment-tiled [Np/16][nkc]; J_lo: bf16 low part
     const uint8_t *g, *g_lo;        // operand f(X_n), fragment-tiled [Cg/16][nkc]

@@ -32,10 +32,10 @@ using namespace sbqa;
 namespace {
 
 constexpr uint32_t STEP_BLOCK = 64;
-// Task-table groups: 15 dense (5 contraction paths x m-blocks per wave
+// Task-table groups: 21 dense (7 contraction paths x m-blocks per wave
 // 1/2/4) and 4 CSR (ballistic x ring by lane reads).
-constexpr Path DENSE_PATHS[5] = {PATH_F32, PATH_FP8, PATH_BF16X3, PATH_I8, PATH_FP8PK};
-constexpr int NDENSE_GROUPS = 15;
+constexpr Path DENSE_PATHS[7] = {PATH_F32, PATH_FP8, PATH_BF16X3, PATH_I8, PATH_FP8PK, PATH_FP4, PATH_FP4PK};
+constexpr int NDENSE_GROUPS = 21;
 constexpr int NGROUPS = NDENSE_GROUPS + 4;
 constexpr int DENSE_GRID_CAP = 512;   // workgroups of one grouped dense launch at most
 constexpr int CSR_GRID_CAP = 2048;

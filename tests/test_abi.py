@@ -78,9 +78,11 @@ def test_validation_errors(abi):
     _expect(abi, abi.EINVAL, J=J * 2, R=2, runs=2, precision=abi.PREC_FP8)
     _expect(abi, abi.EINVAL, J=J, R=2, runs=2, precision=abi.PREC_FP8, fmode=abi.F_BALLISTIC)
     _expect(abi, abi.EINVAL, J=J * 0.5, R=2, runs=2, precision=abi.PREC_INT8)
+    assert "FP4" in _expect(abi, abi.EINVAL, J=J * 2, R=2, runs=2, precision=abi.PREC_FP4)
+    _expect(abi, abi.EINVAL, J=J, R=2, runs=2, precision=abi.PREC_FP4, fmode=abi.F_BALLISTIC)
     assert "127" in _expect(abi, abi.EINVAL, J=J * 128, R=2, runs=2, precision=abi.PREC_INT8)
     _expect(abi, abi.EINVAL, J=J * 28, R=2, runs=2, precision=abi.PREC_INT8, fmode=abi.F_BALLISTIC)
-    assert "precision" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, precision=5)
+    assert "precision" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, precision=6)
     assert "dense_tile" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, dense_tile=96)
     assert "loop_kernel" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, loop_kernel=7)
     assert "j_packing" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, j_packing=2)

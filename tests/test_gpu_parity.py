@@ -162,6 +162,9 @@ CASES = [
     ("fp8_sign", "PREC_FP8", 1, "sk"),
     ("fp8_bytes_ternary", "PREC_FP8", 0, "sk"),
     ("fp8_ternary_zeros", "PREC_FP8", 0, "sk0"),
+    ("fp4_ternary", "PREC_FP4", 0, "sk"),
+    ("fp4_bytes_sign", "PREC_FP4", 1, "sk"),
+    ("fp4_ternary_zeros", "PREC_FP4", 0, "sk0"),
     ("int8_ternary", "PREC_INT8", 0, "sidon"),
     ("int8_sign", "PREC_INT8", 1, "sidon"),
     ("bf16x3_ballistic", "PREC_BF16X3", 2, "gauss"),
@@ -221,8 +224,9 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
                beta=beta, alpha=alpha, gamma0_over_R=0.7, **kw)
     info = sb.sbqa_info(ctx)
     assert info["resident"] == small
-    if prec == "PREC_FP8" and not small:
-        assert info["path"] == ("dense_fp8_packed" if coup == "sk" and "_bytes" not in name else "dense_fp8")
+    if prec in ("PREC_FP8", "PREC_FP4") and not small:
+        base = "dense_fp8" if prec == "PREC_FP8" else "dense_fp4"
+        assert info["path"] == (base + "_packed" if coup == "sk" and "_bytes" not in name else base)
     P = _orc_problem(orc, sb, ctx, J=J, csr=csr, h=h, fmode=fmode)
     jt = np.stack([orc.jperp_paper_table(b, a, 0.7, S) for b, a in zip(beta, alpha)])
     # schedule table of the library equals the oracle's, rounded to float32
@@ -241,7 +245,7 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
             ex, phi_o, phi_abs = _check_step(orc, P, ctx, sb, X, Y, n, S, jr, xg, yg, J=J, csr=csr, h=h,
                                              field_tol=BF16X3_TOL if prec == "PREC_BF16X3" else TOL)
             excluded += ex
-            if prec in ("PREC_FP8", "PREC_INT8") or coup.startswith(("sk", "sidon")):
+            if prec in ("PREC_FP8", "PREC_FP4", "PREC_INT8") or coup.startswith(("sk", "sidon")):
                 assert np.array_equal(phi_g, phi_o.astype(np.float32)), "integer-J fields must be exact"
             else:
                 ftol = BF16X3_TOL if prec == "PREC_BF16X3" else TOL
@@ -255,7 +259,8 @@ def test_single_step_parity(sb, orc, name, prec, fmode, coup):
 
 @pytest.mark.parametrize("prec,fmode,coup", [("PREC_FP32", 2, "gauss"), ("PREC_BF16X3", 2, "gauss"),
                                               ("PREC_FP8", 0, "sk"), ("PREC_FP8", 0, "sk_bytes"),
-                                              ("PREC_INT8", 1, "sidon")])
+                                              ("PREC_INT8", 1, "sidon"), ("PREC_FP4", 0, "sk"),
+                                              ("PREC_FP4", 1, "sk_bytes")])
 def test_dense_tiles_identical(sb, prec, fmode, coup):
     """Every dense workgroup tile (64, 128 or 256 replica columns; the
     autotuner picks one) sums each field in the same K order, so trajectories
@@ -281,15 +286,17 @@ def test_dense_tiles_identical(sb, prec, fmode, coup):
 
 
 def test_fp8_and_fp32_trajectories_identical(sb):
-    """J in {-1,+1} with ternary f: fields are exact integers in fp8 (J
-    bit-packed or as e4m3 bytes) and fp32, so whole trajectories agree
-    bit-for-bit."""
+    """J in {-1,+1} with ternary f: fields are exact integers in fp8 and fp4
+    (J bit-packed, or as e4m3 bytes / e2m1 nibbles) and fp32, so whole
+    trajectories agree bit-for-bit."""
     N, R, runs, S = 700, 8, 6, 150
     J = inst.sk_pm1(N, 31)
     _log("fp8 vs fp32 trajectory N=%d S=%d" % (N, S))
     X0, Y0 = inst.uniform_state(N, R * runs, 0.1, 32)
     out = []
     for prec, pk, path in ((sb.PREC_FP8, sb.JPACK_AUTO, "dense_fp8_packed"), (sb.PREC_FP8, sb.JPACK_BYTES, "dense_fp8"),
+                           (sb.PREC_FP4, sb.JPACK_AUTO, "dense_fp4_packed"), (sb.PREC_FP4, sb.JPACK_BYTES, "dense_fp4"),
+                           (sb.PREC_AUTO, sb.JPACK_AUTO, "dense_fp4_packed"),
                            (sb.PREC_FP32, sb.JPACK_AUTO, "dense_fp32")):
         ctx = _ctx(sb, J=J, R=R, runs=runs, steps=S, precision=prec, j_packing=pk, loop_kernel=sb.LOOP_STREAM)
         assert sb.sbqa_info(ctx)["path"] == path
@@ -322,7 +329,8 @@ def test_int8_and_fp32_trajectories_identical(sb):
 
 
 @pytest.mark.parametrize("prec,coup,packing", [("PREC_FP8", "sk", "auto"), ("PREC_FP8", "sk", "bytes"),
-                                               ("PREC_FP8", "sk0", "auto"), ("PREC_INT8", "sidon", "auto")])
+                                               ("PREC_FP8", "sk0", "auto"), ("PREC_INT8", "sidon", "auto"),
+                                               ("PREC_FP4", "sk", "auto"), ("PREC_FP4", "sk0", "auto")])
 def test_integer_j_energies_on_mfma(sb, orc, prec, coup, packing):
     """Integer J on the fp8 / int8 paths: the readout energies come from the
     MFMA contraction of sign(x) (exact integers), and equal the oracle's
@@ -564,14 +572,14 @@ def test_large_cubic_lattice(sb, orc):
     np.testing.assert_allclose(orc.energy(sp, csr=csr, h=h), Eb, rtol=1e-12, atol=1e-9)
 
 
-@pytest.mark.parametrize("packing", ["packed", "bytes"])
-def test_full_size_fp8_sk(sb, orc, packing):
-    """SK N = 16384, J = +-1 bit-packed or as e4m3 bytes, R = 16 x 16 runs:
-    sampled rows, fields exact."""
+@pytest.mark.parametrize("prec,packing", [("PREC_FP8", "packed"), ("PREC_FP8", "bytes"), ("PREC_FP4", "packed")])
+def test_full_size_fp8_sk(sb, orc, prec, packing):
+    """SK N = 16384, J = +-1 bit-packed or as e4m3 bytes (fp8), bit-packed
+    (fp4), R = 16 x 16 runs: sampled rows, fields exact."""
     N, R, runs = 16384, 16, 16
-    _log("full-size fp8 SK N=%d J %s" % (N, packing))
+    _log("full-size %s SK N=%d J %s" % (prec, N, packing))
     J = inst.sk_pm1(N, 3001)
-    _full_size_step(sb, orc, J=J, N=N, R=R, runs=runs, prec=sb.PREC_FP8, S=10000, exact_fields=True, nrows=24,
+    _full_size_step(sb, orc, J=J, N=N, R=R, runs=runs, prec=getattr(sb, prec), S=10000, exact_fields=True, nrows=24,
                     j_packing=sb.JPACK_AUTO if packing == "packed" else sb.JPACK_BYTES)
 
 
@@ -635,8 +643,10 @@ def test_serving_graph_blocks_alone_equals_mix(sb):
         steps = int(rng.choice([150, 200, 333]))
         ee = 0 if q % 3 else 50
         extra = {}
-        if q % 2 == 0:   # q = 6: integer Sidon28 couplings (int8 path)
+        if q % 2 == 0:   # q = 6: integer Sidon28 couplings (int8 path); q = 2: fp4
             J, csr = (inst.sidon28_dense if q == 6 else inst.sk_pm1)(N, 800 + q), None
+            if q == 2:
+                extra = dict(precision=sb.PREC_FP4)
         elif q == 5:     # native three-body terms on a heavy-hex graph
             Nh, P2, w2, T, K = inst.hubo_heavy_hex(8, 9, 815, dist="normal")
             J, csr = None, inst.edges_to_csr(Nh, P2, w2)
