@@ -17,18 +17,39 @@ constexpr int COLS_PER_WAVE = 256;
 constexpr int WAVES = 4;
 using namespace csr;
 
+// Rows per wavefront, as a shift: a wave of 64 lanes x 4 columns covers 256
+// replica columns; for C <= 128 it takes 2 rows (C <= 64: 4, C <= 32: 8), one
+// per group of 64 >> s lanes, so that every lane carries data.
+__device__ __host__ __forceinline__ int csr_rpw_shift(int C) {
+    int s = 0;
+    while (s < 3 && (COLS_PER_WAVE >> (s + 1)) >= C) ++s;
+    return s;
+}
+
+// Row and first column of a lane of block b (nchunk column chunks).
+struct CsrPos {
+    int i, c;
+};
+__device__ __forceinline__ CsrPos csr_pos(int b, int C, int nchunk) {
+    const int s = csr_rpw_shift(C), lpr = 64 >> s;
+    const int chunk = b % nchunk, rg = b / nchunk;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    return CsrPos{((rg * WAVES + wave) << s) + (lane >> (6 - s)), chunk * COLS_PER_WAVE + 4 * (lane & (lpr - 1))};
+}
+
 // Coupling sum of the 4 columns c..c+3 of row i, accumulated in CSR order in
-// fp32 with explicit fused multiply-adds. The row's neighbours are taken GATHER_BATCH at a time: their indices
-// and weights are wave-uniform (scalar loads), and all gathers of a batch are
-// issued before the first is consumed so their latencies overlap.
+// fp32 with explicit fused multiply-adds. The row's neighbours are taken
+// GATHER_BATCH at a time (UNI: the row is wave-uniform, so its indices and
+// weights come from scalar loads), and all gathers of a batch are issued
+// before the first is consumed so their latencies overlap.
 constexpr int GATHER_BATCH = 8;
 
-template <bool BALLISTIC>
+template <bool BALLISTIC, bool UNI = true>
 __device__ __forceinline__ float4 gather_fields(int i, int c, int Cs, const int32_t *__restrict__ row_ptr,
                                                 const int32_t *__restrict__ col, const float *__restrict__ val,
                                                 const float *__restrict__ x_in, const int8_t *__restrict__ g_in) {
-    const int p0 = __builtin_amdgcn_readfirstlane(row_ptr[i]);
-    const int p1 = __builtin_amdgcn_readfirstlane(row_ptr[i + 1]);
+    const int p0 = UNI ? __builtin_amdgcn_readfirstlane(row_ptr[i]) : row_ptr[i];
+    const int p1 = UNI ? __builtin_amdgcn_readfirstlane(row_ptr[i + 1]) : row_ptr[i + 1];
     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
     for (int p = p0; p < p1; p += GATHER_BATCH) {
         const int cnt = min(GATHER_BATCH, p1 - p);
@@ -74,11 +95,11 @@ __device__ __forceinline__ float4 gather_fields(int i, int c, int Cs, const int3
 // of Eq. 11), continuing the accumulators acc: for each triple containing i,
 // in list order, acc += K f_a f_b with the other two members' operands (the
 // product f_a f_b is exact for ternary operands).
-template <bool BALLISTIC>
+template <bool BALLISTIC, bool UNI = true>
 __device__ __forceinline__ float4 gather_fields3(int i, int c, int Cs, const Tri3 &t3, const float *__restrict__ x_in,
                                                  const int8_t *__restrict__ g_in, float4 acc) {
-    const int p0 = __builtin_amdgcn_readfirstlane(t3.ptr[i]);
-    const int p1 = __builtin_amdgcn_readfirstlane(t3.ptr[i + 1]);
+    const int p0 = UNI ? __builtin_amdgcn_readfirstlane(t3.ptr[i]) : t3.ptr[i];
+    const int p1 = UNI ? __builtin_amdgcn_readfirstlane(t3.ptr[i + 1]) : t3.ptr[i + 1];
     constexpr int B = GATHER_BATCH / 2;
     float a[4] = {acc.x, acc.y, acc.z, acc.w};
     for (int p = p0; p < p1; p += B) {
@@ -147,17 +168,21 @@ __device__ __forceinline__ void csr_step_body(int b, int N, int Cs, int C, int R
                                               float *__restrict__ y, const int8_t *__restrict__ g_in,
                                               int8_t *__restrict__ g_out, const float *__restrict__ jp,
                                               int64_t jp_stride, StepCoef k, int fmode) {
-    const int chunk = b % nchunk, rg = b / nchunk;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = rg * WAVES + wave;
-    const int c = chunk * COLS_PER_WAVE + lane * 4;
+    const CsrPos pos = csr_pos(b, C, nchunk);
+    const int i = pos.i, c = pos.c, lane = threadIdx.x & 63;
     if (i >= N || c >= C) return;
 
     const int64_t o = (int64_t)i * Cs + c;
     const float4 x = *reinterpret_cast<const float4 *>(x_in + o);
     const float4 yv = *reinterpret_cast<const float4 *>(y + o);
-    float4 phi = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x_in, g_in);
-    if (t3.ptr) phi = gather_fields3<BALLISTIC>(i, c, Cs, t3, x_in, g_in, phi);
+    float4 phi;
+    if (csr_rpw_shift(C) == 0) {
+        phi = gather_fields<BALLISTIC, true>(i, c, Cs, row_ptr, col, val, x_in, g_in);
+        if (t3.ptr) phi = gather_fields3<BALLISTIC, true>(i, c, Cs, t3, x_in, g_in, phi);
+    } else {
+        phi = gather_fields<BALLISTIC, false>(i, c, Cs, row_ptr, col, val, x_in, g_in);
+        if (t3.ptr) phi = gather_fields3<BALLISTIC, false>(i, c, Cs, t3, x_in, g_in, phi);
+    }
     const float hi = h[i];
     const float xs[4] = {x.x, x.y, x.z, x.w}, ys[4] = {yv.x, yv.y, yv.z, yv.w};
     const float ps[4] = {phi.x, phi.y, phi.z, phi.w};
@@ -262,14 +287,11 @@ __global__ __launch_bounds__(256) void k_csr_fields(int N, int Cs, int C, int nc
                                                     const float *__restrict__ val, const Tri3 t3,
                                                     const float *__restrict__ x, const int8_t *__restrict__ g,
                                                     float *__restrict__ phi) {
-    const int b = blockIdx.x;
-    const int chunk = b % nchunk, rg = b / nchunk;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int i = rg * WAVES + wave;
-    const int c = chunk * COLS_PER_WAVE + lane * 4;
+    const CsrPos pos = csr_pos(blockIdx.x, C, nchunk);
+    const int i = pos.i, c = pos.c;
     if (i >= N || c >= C) return;
-    float4 v = gather_fields<BALLISTIC>(i, c, Cs, row_ptr, col, val, x, g);
-    if (t3.ptr) v = gather_fields3<BALLISTIC>(i, c, Cs, t3, x, g, v);
+    float4 v = gather_fields<BALLISTIC, false>(i, c, Cs, row_ptr, col, val, x, g);
+    if (t3.ptr) v = gather_fields3<BALLISTIC, false>(i, c, Cs, t3, x, g, v);
     *reinterpret_cast<float4 *>(phi + (int64_t)i * Cs + c) = v;
 }
 
@@ -300,7 +322,8 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
 }
 
 int csr_step_blocks(int N, int C) {
-    return ((C + COLS_PER_WAVE - 1) / COLS_PER_WAVE) * ((N + WAVES - 1) / WAVES);
+    const int rows = WAVES << csr_rpw_shift(C);
+    return csr_step_chunks(C) * ((N + rows - 1) / rows);
 }
 
 int csr_step_chunks(int C) { return (C + COLS_PER_WAVE - 1) / COLS_PER_WAVE; }
@@ -333,9 +356,8 @@ hipError_t launch_csr_operand(int fmode, int N, int Cs, int C, const float *x, i
 hipError_t launch_csr_fields(int fmode, int N, int Cs, int C, const int32_t *row_ptr, const int32_t *col,
                              const float *val, const Tri3 &t3, const float *x, const int8_t *g, float *phi,
                              hipStream_t st) {
-    const int nchunk = (C + COLS_PER_WAVE - 1) / COLS_PER_WAVE;
-    const int nrg = (N + WAVES - 1) / WAVES;
-    dim3 grid(nchunk * nrg), block(WAVES * 64);
+    const int nchunk = csr_step_chunks(C);
+    dim3 grid(csr_step_blocks(N, C)), block(WAVES * 64);
     if (fmode == 2)
         hipLaunchKernelGGL(k_csr_fields<true>, grid, block, 0, st, N, Cs, C, nchunk, row_ptr, col, val, t3, x, g, phi);
     else
