@@ -264,7 +264,7 @@ def serve_instances(n, seed):
     return out
 
 
-def serve_run(sb, srv, items, arrivals, R, runs, S, seed, workers=8):
+def serve_run(sb, srv, items, arrivals, R, runs, S, seed, workers=8, dense_prec="fp8"):
     """Submit items at their arrival times (seconds from start) from a pool of
     client threads (a submission validates and copies the instance, so one
     client thread would delay later arrivals), poll until all are done.
@@ -274,7 +274,7 @@ def serve_run(sb, srv, items, arrivals, R, runs, S, seed, workers=8):
 
     def submit(q):
         it = items[q]
-        prec = dict(precision=sb.PREC_FP8) if it["kind"] == "dense" else {}
+        prec = dict(precision=sb.PREC_FP8 if dense_prec == "fp8" else sb.PREC_FP4) if it["kind"] == "dense" else {}
         return sb.sbqa_submit(srv, J=it["J"], csr=it["csr"], R=R, runs=runs, steps=S, fmode=0,
                               jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0, seed=seed + q, **prec)
 
@@ -313,14 +313,14 @@ def serve_main(a):
     # service rate: a burst of the first n_cal instances, all arriving at t = 0
     n_cal = min(n, max(8, n // 4))
     srv = sb.sbqa_server_create(budget, a.serve_slots)
-    _, t_cal, _ = serve_run(sb, srv, items[:n_cal], np.zeros(n_cal), R, runs, S, 7000)
+    _, t_cal, _ = serve_run(sb, srv, items[:n_cal], np.zeros(n_cal), R, runs, S, 7000, dense_prec=a.serve_dense)
     sb.sbqa_server_destroy(srv)
     mu = n_cal / t_cal
     lam = a.serve_rho * mu
     arrivals = np.cumsum(np.random.default_rng(5002).exponential(1.0 / lam, n))
     arrivals -= arrivals[0]
     srv = sb.sbqa_server_create(budget, a.serve_slots)
-    lat, makespan, lib_lat = serve_run(sb, srv, items, arrivals, R, runs, S, 8000)
+    lat, makespan, lib_lat = serve_run(sb, srv, items, arrivals, R, runs, S, 8000, dense_prec=a.serve_dense)
     st = sb.sbqa_server_stats(srv)
     sb.sbqa_server_destroy(srv)
     kinds = np.array([it["kind"] == "dense" for it in items])
@@ -328,10 +328,11 @@ def serve_main(a):
         "metric": "replica-spin updates/s (N*R*runs*steps/s); p99 solve latency, mixed stream",
         "value": updates / makespan, "unit": "replica-spin updates/s", "n_gpus": 1, "steps": S, "warmup": 0,
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "fp8 (dense) / f32 (sparse)", "data": "synthetic",
+        "dtype": "%s (dense) / f32 (sparse)" % a.serve_dense, "data": "synthetic",
         "config": {"workload": "serving stream: %d instances, Poisson arrivals at %.2f x the measured service "
-                               "rate, N log-uniform in [256, 8192], half dense SK +-1 (FP8), half d-regular "
-                               "d~U{3..12} Gaussian (CSR), R=16 x 8 runs, 2000 steps" % (n, a.serve_rho),
+                               "rate, N log-uniform in [256, 8192], half dense SK +-1 (%s), half d-regular "
+                               "d~U{3..12} Gaussian (CSR), R=16 x 8 runs, 2000 steps"
+                               % (n, a.serve_rho, a.serve_dense.upper()),
                    "instances": n, "rho": a.serve_rho, "hbm_budget_gib": a.serve_budget_gib,
                    "slots": a.serve_slots},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
@@ -408,6 +409,8 @@ def main():
     ap.add_argument("--serve-rho", type=float, default=0.8, help="serve workload: arrival rate / service rate")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="serve workload: HBM budget")
     ap.add_argument("--serve-slots", type=int, default=16, help="serve workload: resident instances at most")
+    ap.add_argument("--serve-dense", default="fp8", choices=["fp8", "fp4"],
+                    help="serve workload: contraction of the dense SK instances (both exact)")
     ap.add_argument("--tte-sizes", default="32,64,128", help="tte workload: lattice sizes L (N = L*L)")
     ap.add_argument("--tte-steps", default="250,1000,4000", help="tte workload: step counts")
     ap.add_argument("--tte-seeds", type=int, default=8, help="tte workload: solves per point")

@@ -360,6 +360,83 @@ __device__ __forceinline__ void update_store(const DenseStepArgs &a, int c, int 
 }
 #pragma clang fp contract(on)
 
+// Epilogue of one workgroup tile: transpose each 16 x DENSE_TN block of Phi
+// through LDS (lds: at least 4 waves x 16 x (DENSE_TN + 4) floats) so that a
+// lane holds 4 consecutive spins of one replica column (f32 MFMA results:
+// register r of a lane is row 4*(lane/16) + r, column lane%16); then load
+// every input of the lane's items before the first store.
+template <int PATH, int MBW, int EPI>
+__device__ __forceinline__ void dense_epilogue(const DenseStepArgs &a, f4 (&acc)[MBW][DENSE_TN / 16], int nt, int mchunk,
+                                               uint8_t *lds) {
+    constexpr int RBT = DENSE_TN / 16;
+    constexpr int TS = DENSE_TN + 4;
+    constexpr bool JPK = path_packed(Path(PATH));
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n0 = nt * DENSE_TN;
+    const int mb0 = (mchunk * 4 + w) * MBW;
+    const int nkc = a.nkc;
+    __syncthreads();
+    float *T = reinterpret_cast<float *>(lds) + w * 16 * TS;
+    const int g = lane >> 4, r16 = lane & 15;
+    constexpr int QPR = DENSE_TN / 4;         // spin quads per row
+    constexpr int ITEMS = 16 * QPR / 64;      // (row, quad) items per lane and m-block
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb) {
+#pragma unroll
+        for (int p = 0; p < RBT; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) T[(4 * g + r) * TS + 16 * p + r16] = acc_field<PATH>(acc[mb][p][r]);
+        __syncthreads();
+        float4 ph[ITEMS];
+        int cc[ITEMS], ii[ITEMS];
+#pragma unroll
+        for (int it = 0; it < ITEMS; ++it) {
+            const int flat = it * 64 + lane, row = flat / QPR, q = flat % QPR;
+            ph[it] = *reinterpret_cast<const float4 *>(T + row * TS + 4 * q);
+            cc[it] = 16 * (mb0 + mb) + row;
+            ii[it] = n0 + 4 * q;
+        }
+        if constexpr (JPK) {
+            // bit-packed J holds +1 on the diagonal and in the padding: take
+            // the diagonal term J'_ii f_i = f_i (the operand byte this step
+            // read) back out, and zero the fields of padded spins so that
+            // their x and f stay 0
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it) {
+                if (cc[it] >= a.C) continue;
+                const uint8_t *fp = a.g + op_offset<PATH>(cc[it], ii[it], nkc, MBW);
+                constexpr int BITS = is_fp4<PATH> ? 4 : 8;
+                constexpr uint32_t MASK = (1u << BITS) - 1u, SIGN = 1u << (BITS - 1);
+                const uint32_t fb = is_fp4<PATH> ? (uint32_t)*reinterpret_cast<const uint16_t *>(fp)
+                                                 : *reinterpret_cast<const uint32_t *>(fp);
+                float v[4] = {ph[it].x, ph[it].y, ph[it].z, ph[it].w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t b = (fb >> (BITS * e)) & MASK;
+                    const float f = b == 0u ? 0.0f : ((b & SIGN) ? -1.0f : 1.0f);
+                    v[e] = (ii[it] + e < a.N) ? v[e] - f : 0.0f;
+                }
+                ph[it] = make_float4(v[0], v[1], v[2], v[3]);
+            }
+        }
+        if constexpr (EPI == EPI_UPDATE) {
+            UpdIn u[ITEMS];
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (cc[it] < a.C) u[it] = update_load(a, cc[it], ii[it]);
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (cc[it] < a.C) update_store<PATH, MBW>(a, cc[it], ii[it], u[it], ph[it]);
+        } else {
+#pragma unroll
+            for (int it = 0; it < ITEMS; ++it)
+                if (cc[it] < a.C) *reinterpret_cast<float4 *>(a.phi + (int64_t)cc[it] * a.Np + ii[it]) = ph[it];
+        }
+        __syncthreads();
+    }
+}
+
+
 // ---------------------------------------------------------------------------
 // One dense step. Workgroup tile: DENSE_TN = 64 spins (4 row blocks of J) x
 // 64*MBW replica columns. Wave w owns m-blocks [w*MBW, (w+1)*MBW) of the
@@ -511,69 +588,7 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
         }
     }
 
-    // Epilogue: transpose each 16 x DENSE_TN block of Phi through LDS so that
-    // a lane holds 4 consecutive spins of one replica column (f32 MFMA
-    // results: register r of a lane is row 4*(lane/16) + r, column lane%16);
-    // then load every input of the lane's items before the first store.
-    __syncthreads();
-    float *T = reinterpret_cast<float *>(lds) + w * 16 * TS;
-    const int g = lane >> 4, r16 = lane & 15;
-    constexpr int QPR = DENSE_TN / 4;         // spin quads per row
-    constexpr int ITEMS = 16 * QPR / 64;      // (row, quad) items per lane and m-block
-#pragma unroll
-    for (int mb = 0; mb < MBW; ++mb) {
-#pragma unroll
-        for (int p = 0; p < RBT; ++p)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) T[(4 * g + r) * TS + 16 * p + r16] = acc_field<PATH>(acc[mb][p][r]);
-        __syncthreads();
-        float4 ph[ITEMS];
-        int cc[ITEMS], ii[ITEMS];
-#pragma unroll
-        for (int it = 0; it < ITEMS; ++it) {
-            const int flat = it * 64 + lane, row = flat / QPR, q = flat % QPR;
-            ph[it] = *reinterpret_cast<const float4 *>(T + row * TS + 4 * q);
-            cc[it] = 16 * (mb0 + mb) + row;
-            ii[it] = n0 + 4 * q;
-        }
-        if constexpr (JPK) {
-            // bit-packed J holds +1 on the diagonal and in the padding: take
-            // the diagonal term J'_ii f_i = f_i (the operand byte this step
-            // read) back out, and zero the fields of padded spins so that
-            // their x and f stay 0
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it) {
-                if (cc[it] >= a.C) continue;
-                const uint8_t *fp = a.g + op_offset<PATH>(cc[it], ii[it], nkc, MBW);
-                constexpr int BITS = is_fp4<PATH> ? 4 : 8;
-                constexpr uint32_t MASK = (1u << BITS) - 1u, SIGN = 1u << (BITS - 1);
-                const uint32_t fb = is_fp4<PATH> ? (uint32_t)*reinterpret_cast<const uint16_t *>(fp)
-                                                 : *reinterpret_cast<const uint32_t *>(fp);
-                float v[4] = {ph[it].x, ph[it].y, ph[it].z, ph[it].w};
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const uint32_t b = (fb >> (BITS * e)) & MASK;
-                    const float f = b == 0u ? 0.0f : ((b & SIGN) ? -1.0f : 1.0f);
-                    v[e] = (ii[it] + e < a.N) ? v[e] - f : 0.0f;
-                }
-                ph[it] = make_float4(v[0], v[1], v[2], v[3]);
-            }
-        }
-        if constexpr (EPI == EPI_UPDATE) {
-            UpdIn u[ITEMS];
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it)
-                if (cc[it] < a.C) u[it] = update_load(a, cc[it], ii[it]);
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it)
-                if (cc[it] < a.C) update_store<PATH, MBW>(a, cc[it], ii[it], u[it], ph[it]);
-        } else {
-#pragma unroll
-            for (int it = 0; it < ITEMS; ++it)
-                if (cc[it] < a.C) *reinterpret_cast<float4 *>(a.phi + (int64_t)cc[it] * a.Np + ii[it]) = ph[it];
-        }
-        __syncthreads();
-    }
+    dense_epilogue<PATH, MBW, EPI>(a, acc, nt, mchunk, lds);
 }
 
 template <int PATH, int MBW, int EPI>
