@@ -38,6 +38,10 @@ constexpr Path DENSE_PATHS[7] = {PATH_F32, PATH_FP8, PATH_BF16X3, PATH_I8, PATH_
 constexpr int NDENSE_GROUPS = 21;
 constexpr int NGROUPS = NDENSE_GROUPS + 4;
 constexpr int DENSE_GRID_CAP = 512;   // workgroups of one grouped dense launch at most
+// Groups present in a step block run as parallel branches (one side stream
+// each, forked from and joined to the server stream): they touch disjoint
+// instances, so the GPU may overlap them.
+constexpr int NBRANCH = 4;
 constexpr int CSR_GRID_CAP = 2048;
 typedef std::chrono::steady_clock Clock;
 
@@ -162,6 +166,8 @@ struct sbqa_server {
     // full step blocks are replayed from HIP graphs, one per set of groups
     // present (the kernels read membership from the task table)
     std::map<uint32_t, hipGraphExec_t> graphs;
+    hipStream_t side[NBRANCH] = {};
+    hipEvent_t fork_ev = nullptr, join_ev[NBRANCH] = {};
     // stats (guarded by mu)
     uint64_t completed = 0;
     double updates = 0.0;
@@ -221,23 +227,35 @@ static sbqa_status step_block(sbqa_server *srv, std::vector<Slot> &slots, int pa
     uint32_t mask = 0;
     for (int g = 0; g < NGROUPS; ++g)
         if (cnt[g]) mask |= 1u << g;
-    // full grids (capped) inside graphs, so that a graph serves any membership
+    // full grids (capped) inside graphs, so that a graph serves any membership;
+    // the k-th group present runs on branch k % NBRANCH, its steps in order
+    int present[NGROUPS], np = 0;
+    for (int g = 0; g < NGROUPS; ++g)
+        if (mask & (1u << g)) present[np++] = g;
+    const int nb = std::min(np, NBRANCH);
     auto launch_all = [&](uint32_t nsteps, bool full_grid) -> sbqa_status {
-        for (uint32_t off = 0; off < nsteps; ++off)
-            for (int g = 0; g < NGROUPS; ++g) {
-                if (!(mask & (1u << g))) continue;
-                const GroupHeader *dh = srv->d_hdr + g;
-                const GroupTask *dt = srv->d_tasks + (size_t)g * srv->max_slots;
-                if (g < NDENSE_GROUPS) {
-                    const int mbw = (g % 3 == 0) ? 1 : (g % 3 == 1) ? 2 : 4;
-                    const int grid = full_grid ? DENSE_GRID_CAP : std::min(total[g], DENSE_GRID_CAP);
-                    HIP_CHECK_SERVE(launch_group_dense(DENSE_PATHS[g / 3], mbw, dh, dt, grid, (int)off, srv->stream));
-                } else {
-                    const int q = g - NDENSE_GROUPS;
-                    const int grid = full_grid ? CSR_GRID_CAP : std::min(total[g], CSR_GRID_CAP);
-                    HIP_CHECK_SERVE(launch_group_csr(q >= 2, q & 1, dh, dt, grid, (int)off, srv->stream));
+        HIP_CHECK_SERVE(hipEventRecord(srv->fork_ev, srv->stream));
+        for (int b = 0; b < nb; ++b) {
+            hipStream_t bs = srv->side[b];
+            HIP_CHECK_SERVE(hipStreamWaitEvent(bs, srv->fork_ev, 0));
+            for (uint32_t off = 0; off < nsteps; ++off)
+                for (int k = b; k < np; k += NBRANCH) {
+                    const int g = present[k];
+                    const GroupHeader *dh = srv->d_hdr + g;
+                    const GroupTask *dt = srv->d_tasks + (size_t)g * srv->max_slots;
+                    if (g < NDENSE_GROUPS) {
+                        const int mbw = (g % 3 == 0) ? 1 : (g % 3 == 1) ? 2 : 4;
+                        const int grid = full_grid ? DENSE_GRID_CAP : std::min(total[g], DENSE_GRID_CAP);
+                        HIP_CHECK_SERVE(launch_group_dense(DENSE_PATHS[g / 3], mbw, dh, dt, grid, (int)off, bs));
+                    } else {
+                        const int q = g - NDENSE_GROUPS;
+                        const int grid = full_grid ? CSR_GRID_CAP : std::min(total[g], CSR_GRID_CAP);
+                        HIP_CHECK_SERVE(launch_group_csr(q >= 2, q & 1, dh, dt, grid, (int)off, bs));
+                    }
                 }
-            }
+            HIP_CHECK_SERVE(hipEventRecord(srv->join_ev[b], bs));
+            HIP_CHECK_SERVE(hipStreamWaitEvent(srv->stream, srv->join_ev[b], 0));
+        }
         return SBQA_OK;
     };
     if (steps == STEP_BLOCK) {
@@ -417,6 +435,12 @@ static void release(sbqa_server *srv) {
     }
     if (srv->d_tasks) (void)hipFree(srv->d_tasks);
     if (srv->d_hdr) (void)hipFree(srv->d_hdr);
+    for (int b = 0; b < NBRANCH; ++b) {
+        if (srv->side[b]) (void)hipStreamSynchronize(srv->side[b]);
+        if (srv->side[b]) (void)hipStreamDestroy(srv->side[b]);
+        if (srv->join_ev[b]) (void)hipEventDestroy(srv->join_ev[b]);
+    }
+    if (srv->fork_ev) (void)hipEventDestroy(srv->fork_ev);
     if (srv->stream) (void)hipStreamDestroy(srv->stream);
     if (srv->create_stream) (void)hipStreamDestroy(srv->create_stream);
     delete srv;
@@ -438,6 +462,11 @@ sbqa_status sbqa_server_create(size_t hbm_budget_bytes, int32_t max_slots, sbqa_
     const size_t ntask = (size_t)NGROUPS * max_slots;
     e = hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&srv->create_stream, hipStreamNonBlocking);
+    for (int b = 0; b < NBRANCH && e == hipSuccess; ++b) {
+        e = hipStreamCreateWithFlags(&srv->side[b], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->join_ev[b], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&srv->fork_ev, hipEventDisableTiming);
     for (int q = 0; q < 2 && e == hipSuccess; ++q) {
         e = hipHostMalloc((void **)&srv->h_tasks[q], sizeof(GroupTask) * ntask, hipHostMallocDefault);
         if (e == hipSuccess) e = hipHostMalloc((void **)&srv->h_hdr[q], sizeof(GroupHeader) * NGROUPS, hipHostMallocDefault);
