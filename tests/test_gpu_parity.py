@@ -423,6 +423,66 @@ def test_hubo_large_heavy_hex(sb, orc):
     np.testing.assert_allclose(orc.energy(sp, csr=csr, tri=T, K=K), Eb, rtol=1e-12, atol=1e-9)
 
 
+# --------------------------------------------------------------- edge cases
+def _edge_instance(kind):
+    """Degenerate shapes: a single spin, one run of one replica, isolated
+    spins, no couplings at all, three-body terms only."""
+    rng = np.random.default_rng(90)
+    if kind == "dense_n1":
+        return dict(J=np.zeros((1, 1)), h=np.array([0.5]), R=3, runs=2, precision="PREC_FP32")
+    if kind == "dense_n2_fp4_c1":
+        return dict(J=np.array([[0.0, -1.0], [-1.0, 0.0]]), h=np.array([1.0, 0.0]), R=1, runs=1, precision="PREC_FP4")
+    if kind == "dense_n2_fp8_bytes":
+        return dict(J=np.array([[0.0, 1.0], [1.0, 0.0]]), h=None, R=2, runs=1, precision="PREC_FP8",
+                    j_packing="JPACK_BYTES")
+    if kind == "csr_isolated":
+        N = 37
+        E = np.array([[0, 1], [1, 2], [2, 3], [5, 9], [9, 30], [30, 36], [0, 36]])
+        return dict(csr=inst.edges_to_csr(N, E, rng.integers(-3, 4, len(E)).astype(float)),
+                    h=rng.integers(-1, 2, N).astype(float), R=1, runs=3)
+    if kind == "csr_empty":
+        N = 10
+        return dict(csr=(np.zeros(N + 1, np.int32), np.zeros(0, np.int32), np.zeros(0)),
+                    h=rng.integers(-2, 3, N).astype(float), R=4, runs=2)
+    if kind == "hubo_pure":
+        N = 12
+        P2, w2, T, K, h = inst.random_hubo(N, 0, 15, 91)
+        return dict(csr=(np.zeros(N + 1, np.int32), np.zeros(0, np.int32), np.zeros(0)), tri=T, K=K, h=h, R=4, runs=2)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["dense_n1", "dense_n2_fp4_c1", "dense_n2_fp8_bytes", "csr_isolated", "csr_empty",
+                                  "hubo_pure"])
+def test_edge_instances_step_parity(sb, orc, kind):
+    """Degenerate instances step for step against the oracle (one step from
+    the GPU's own state, 12 steps, streaming kernels), and the energies of
+    the returned spins."""
+    d = _edge_instance(kind)
+    J, csr, h = d.get("J"), d.get("csr"), d.get("h")
+    R, runs, S = d["R"], d["runs"], 12
+    kw = {}
+    if "precision" in d:
+        kw["precision"] = getattr(sb, d["precision"])
+    if "j_packing" in d:
+        kw["j_packing"] = getattr(sb, d["j_packing"])
+    ctx = _ctx(sb, J=J, csr=csr, h=h, R=R, runs=runs, steps=S, tri=d.get("tri"), K=d.get("K"),
+               loop_kernel=sb.LOOP_STREAM, jp_kind=sb.JP_PAPER, **kw)
+    P = _orc_problem(orc, sb, ctx, J=J, csr=csr, h=h, tri=d.get("tri"), K=d.get("K"))
+    N = ctx.N
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.6, 92)
+    sb.sbqa_set_state(ctx, X0, Y0)
+    jt = sb.sbqa_jperp_table(ctx)
+    for n in range(S):
+        X, Y = sb.sbqa_get_state(ctx)
+        sb.sbqa_step(ctx, 1)
+        xg, yg = sb.sbqa_get_state(ctx)
+        _check_step(orc, P, ctx, sb, X, Y, n, S, jt[:, n].astype(np.float64), xg, yg, J=J, csr=csr, h=h,
+                    tri=d.get("tri"), K=d.get("K"))
+    Eb, sp = sb.sbqa_best(ctx)
+    np.testing.assert_allclose(orc.energy(sp, J=J, csr=csr, h=h, tri=d.get("tri"), K=d.get("K")), Eb,
+                               rtol=1e-12, atol=1e-12)
+
+
 def test_negation_symmetry_and_column_independence(sb):
     """h = 0: negated start -> negated trajectory (bit-exact). With J_perp = 0
     a run alone equals the same run inside a batch (CSR path: per-element
