@@ -9,8 +9,9 @@ dt = 0.5, a0 = 1, c0 = 0.5/(sqrt(N) rms J), ternary f (Eq. 8), J_perp linear
 A bench "step" is one SBQA time step over all runs and replicas (operand,
 contraction, update). The timed region is K steps of a fresh solve followed by
 the readout (energies of all replicas and the best per run). value =
-N*R*runs*K / seconds. The dominant kernel's average duration comes from HIP
-events around every step on the context's stream; its roofline uses the
+N*R*runs*K / seconds. The dominant kernel's average duration comes from one
+HIP event pair around the K steps on the context's stream (each step is one
+launch of that kernel, or all K steps are one resident launch); its roofline uses the
 algorithmic bytes (HBM-bound kernels) or operations (MFMA and VALU-bound
 kernels) per launch computed below.
 
@@ -123,6 +124,8 @@ def create(sb, w, seed, loop_kernel="auto"):
         kw["precision"] = getattr(sb, w["prec"])
     if w.get("j_packing"):
         kw["j_packing"] = getattr(sb, w["j_packing"])
+    if w.get("dense_tile"):
+        kw["dense_tile"] = w["dense_tile"]
     return sb.sbqa_create(J=w.get("J"), csr=w.get("csr"), h=w.get("h"), tri=w.get("tri"), K=w.get("K"), **kw)
 
 
@@ -416,8 +419,11 @@ def main():
                     help="default workload: skip the short mixed serving stream (p50/p99 solve latency)")
     ap.add_argument("--serve-quick", type=int, default=128,
                     help="default workload: instances of the short serving stream reported beside the main line")
-    ap.add_argument("--no-events", action="store_true", help="no per-step events in the timed region")
+    ap.add_argument("--no-events", action="store_true", help="no events in the timed region")
     ap.add_argument("--calibrate", action="store_true", help="also run a copy kernel of known size (counter scaling)")
+    ap.add_argument("--dense-tile", type=int, default=0,
+                    help="dense workloads: replica columns per workgroup tile (64/128/256; 0 = autotuned), "
+                         "e.g. to hold the tile fixed in counter runs")
     ap.add_argument("--loop-kernel", default="auto", choices=["auto", "stream", "resident"],
                     help="step loop: one launch per step (stream) or many steps per launch (resident)")
     ap.add_argument("--serve-instances", type=int, default=512, help="serve workload: number of instances")
@@ -447,6 +453,8 @@ def main():
     if a.calibrate:
         copy_calibration()
     w = make_workload(a.workload)
+    if a.dense_tile:
+        w["dense_tile"] = a.dense_tile
     K = a.steps if a.steps is not None else w["S"]
     if K < 1 or K > w["S"]:
         raise SystemExit("--steps must be in [1, %d] (one solve of the schedule)" % w["S"])
@@ -464,30 +472,26 @@ def main():
     info = sb.sbqa_info(ctx)
     torch.cuda.synchronize()
     resident = info["resident"]
-    # Resident sparse loop: the K steps are one launch, bracketed by one event
-    # pair. Otherwise one event pair per step brackets that step's kernels.
-    nev = 0 if a.no_events else (1 if resident else K)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nev)]
+    # One event pair on the context stream brackets the K steps (one resident
+    # launch, or K back-to-back launches of one kernel each): the average
+    # launch duration is their elapsed time over the launches, gaps included.
+    ev = None if a.no_events else (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
     t0 = time.perf_counter()
+    if ev:
+        ev[0].record(stream)
     if resident:
-        if ev:
-            ev[0][0].record(stream)
         sb.sbqa_step(ctx, K)
-        if ev:
-            ev[0][1].record(stream)
     else:
         for q in range(K):
-            if ev:
-                ev[q][0].record(stream)
             sb.sbqa_step(ctx, 1)
-            if ev:
-                ev[q][1].record(stream)
+    if ev:
+        ev[1].record(stream)
     E, spins = sb.sbqa_best(ctx)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     N, R, runs = w["N"], w["R"], w["runs"]
     value = N * R * runs * K / t
-    launch_ms = [s.elapsed_time(e) for s, e in ev]
+    launch_ms = [ev[0].elapsed_time(ev[1]) / (1 if resident else K)] if ev else []
     out = {
         "metric": "replica-spin updates/s (N*R*runs*steps/s)",
         "value": value, "unit": "replica-spin updates/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,

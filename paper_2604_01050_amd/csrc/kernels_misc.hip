@@ -165,16 +165,31 @@ __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int Cs, int C
     partial[((int64_t)rb * C + c) * 3 + 2] = q3;
 }
 
-__global__ void k_csr_energy_final(int C, int nrb, const double *__restrict__ partial, double *__restrict__ E) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= C) return;
+// Stage 2: block per column, strided per-thread sums over the row blocks,
+// then a fixed LDS tree.
+__global__ __launch_bounds__(256) void k_csr_energy_final(int C, int nrb, const double *__restrict__ partial,
+                                                          double *__restrict__ E) {
+    __shared__ double sq[256], sl[256], s3[256];
+    const int c = blockIdx.x, t = threadIdx.x;
     double q = 0.0, l = 0.0, q3 = 0.0;
-    for (int rb = 0; rb < nrb; ++rb) {
+    for (int rb = t; rb < nrb; rb += 256) {
         q += partial[((int64_t)rb * C + c) * 3];
         l += partial[((int64_t)rb * C + c) * 3 + 1];
         q3 += partial[((int64_t)rb * C + c) * 3 + 2];
     }
-    E[c] = -0.5 * q - l - q3 / 3.0;
+    sq[t] = q;
+    sl[t] = l;
+    s3[t] = q3;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) {
+            sq[t] += sq[t + w];
+            sl[t] += sl[t + w];
+            s3[t] += s3[t + w];
+        }
+        __syncthreads();
+    }
+    if (t == 0) E[c] = -0.5 * sq[0] - sl[0] - s3[0] / 3.0;
 }
 
 __global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *__restrict__ row_ptr,
@@ -298,7 +313,7 @@ hipError_t launch_csr_energy_state(int N, int Cs, int C, const int32_t *row_ptr,
     dim3 grid((C + 255) / 256, nblk_rows), block(256);
     hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, Cs, C, rows_per_blk, row_ptr, col, val, t3, h, x,
                        partial);
-    hipLaunchKernelGGL(k_csr_energy_final, dim3((C + 255) / 256), dim3(256), 0, st, C, nblk_rows, partial, E);
+    hipLaunchKernelGGL(k_csr_energy_final, dim3(C), dim3(256), 0, st, C, nblk_rows, partial, E);
     return hipGetLastError();
 }
 
