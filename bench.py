@@ -154,14 +154,15 @@ PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
 def resident_ops_per_step(w):
-    """Operations one step of a resident loop must perform per replica-spin
-    update. Sparse: per neighbour one int8->fp32 conversion and one FMA (2d);
-    dense (small loop): per coupling one FMA counted as two operations (2N);
-    then 7 for the kick and drift, 3 for the wall, 3 for the ternary decision
-    of Eq. 8 (2d + 13 or 2N + 13)."""
+    """VALU lane operations one step of a resident loop must perform per
+    replica-spin update: one FMA per coupling of the row (d for a sparse row,
+    N for the small dense loop; the operand -1/0/+1 is read by the FMA in a
+    format it takes directly, no conversion), 7 for the kick and drift, 3 for
+    the wall, 3 for the ternary decision of Eq. 8: d + 13 (or N + 13). The
+    peak counts one lane operation per lane per cycle, an FMA being one."""
     N, C = w["N"], w["R"] * w["runs"]
     nnz = len(w["csr"][1]) if "csr" in w else N * N
-    return 2.0 * nnz * C + 13.0 * N * C
+    return 1.0 * nnz * C + 13.0 * N * C
 
 
 def algorithmic_flops(w):

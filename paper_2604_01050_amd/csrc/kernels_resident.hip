@@ -12,8 +12,10 @@ using namespace csr;
 //
 // One workgroup of RES_THREADS threads owns RES_COLS consecutive replica
 // columns of one run (R a multiple of RES_COLS) for all N spins. Its x and y
-// stay in registers for the whole launch; its operand f(X) for every spin and
-// its padded CSR weights stay in LDS; column indices stay in registers. The
+// and the fields h stay in registers for the whole launch; its operand f(X)
+// for every spin (as binary16: -1, 0 and +1 are exact, and the coupling sum
+// reads it with mixed-precision FMAs, no conversions) and its padded CSR
+// weights stay in LDS; column indices stay in registers. The
 // coupling sum of a column only needs that column's operand, so the only data
 // that crosses workgroups is the ring coupling at the edges of the column
 // block: after each step a workgroup publishes its first and last column and
@@ -27,6 +29,53 @@ constexpr int RES_COLS = 8;
 constexpr int RES_THREADS = 512;
 constexpr int RES_MAX_RPT = 8;
 constexpr int RES_SPIN_LIMIT = 1 << 22;
+
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef _Float16 half2v __attribute__((ext_vector_type(2)));
+
+// The next step's operand is held as e4m3 bytes between the update and the
+// barrier (2 registers per row instead of 4) and widened to binary16 when it
+// is written to LDS; -1, 0 and +1 are exact in both formats.
+__device__ __forceinline__ uint2 pack_e4m3(const float (&f)[RES_COLS]) {
+    // the first conversion of each pair writes the low half of a register
+    // whose previous contents (here an input that dies) are overwritten by
+    // the second one
+    int lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[0], f[1], __builtin_bit_cast(int, f[0]), false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(f[2], f[3], lo, true);
+    int hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[4], f[5], __builtin_bit_cast(int, f[4]), false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(f[6], f[7], hi, true);
+    return make_uint2((uint32_t)lo, (uint32_t)hi);
+}
+__device__ __forceinline__ half8 e4m3_to_half(uint2 v) {
+    const half2v a = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(v.x, 1.0f, false);
+    const half2v b = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(v.x, 1.0f, true);
+    const half2v c = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(v.y, 1.0f, false);
+    const half2v d = __builtin_amdgcn_cvt_scalef32_pk_f16_fp8(v.y, 1.0f, true);
+    half8 r;
+    r[0] = a[0]; r[1] = a[1]; r[2] = b[0]; r[3] = b[1];
+    r[4] = c[0]; r[5] = c[1]; r[6] = d[0]; r[7] = d[1];
+    return r;
+}
+
+// int8 operand row (8 columns) <-> binary16 row, at the launch's start and end
+__device__ __forceinline__ half8 operand_to_half(uint2 v) {
+    half8 r;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        r[c] = (_Float16)(float)(int8_t)((v.x >> (8 * c)) & 0xFF);
+        r[c + 4] = (_Float16)(float)(int8_t)((v.y >> (8 * c)) & 0xFF);
+    }
+    return r;
+}
+__device__ __forceinline__ uint2 operand_to_int8(half8 f) {
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        lo |= (uint32_t)(uint8_t)(int8_t)(float)f[c] << (8 * c);
+        hi |= (uint32_t)(uint8_t)(int8_t)(float)f[c + 4] << (8 * c);
+    }
+    return make_uint2(lo, hi);
+}
 
 // Edge columns cross workgroups (possibly on different XCDs) through
 // agent-scope atomic stores and loads: these are performed coherently for the
@@ -63,14 +112,13 @@ template <int RPT, int D>
 __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     // Rows are padded to NR = RPT*RES_THREADS (zero rows: no field, no
-    // couplings, zero state, so they stay zero). LDS: operand of the own
-    // columns for every row, then the weights and fields laid out per thread
-    // (row r = t + q*RES_THREADS) so every thread addresses them from one base
-    // with constant offsets.
+    // couplings, zero state, so they stay zero); thread t owns rows
+    // r = t + q*RES_THREADS. LDS: binary16 operand of the own columns for
+    // every row, then the weights laid out per thread so every thread
+    // addresses them from one base with constant offsets.
     constexpr int NR = RPT * RES_THREADS;
-    uint2 *op = reinterpret_cast<uint2 *>(smem);                                            // [NR]
-    float *wv = reinterpret_cast<float *>(smem + (size_t)NR * 8);                          // [RPT*D][T]
-    float *hs = reinterpret_cast<float *>(smem + (size_t)NR * 8 + (size_t)RPT * D * RES_THREADS * 4);  // [RPT][T]
+    half8 *op = reinterpret_cast<half8 *>(smem);                                            // [NR]
+    float *wv = reinterpret_cast<float *>(smem + (size_t)NR * 16);                         // [RPT*D][T]
     const int t = threadIdx.x, w = blockIdx.x;
     const int P = a.R / RES_COLS;
     const int c0 = w * RES_COLS;
@@ -81,15 +129,15 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
     for (int q = 0; q < RPT; ++q) {
         int r = t + q * RES_THREADS;
         asm volatile("" : "+v"(r));
-        op[r] = *reinterpret_cast<const uint2 *>(a.g + (int64_t)r * a.Cs + c0);
-        hs[q * RES_THREADS + t] = a.h[r];
+        op[r] = operand_to_half(*reinterpret_cast<const uint2 *>(a.g + (int64_t)r * a.Cs + c0));
 #pragma unroll
         for (int p = 0; p < D; ++p) wv[(q * D + p) * RES_THREADS + t] = a.valpad[(int64_t)p * NR + r];
     }
 
     float xs[RPT][RES_COLS], ys[RPT][RES_COLS];
     uint32_t cpk[RPT][(D + 1) / 2];
-    // exchange buffer of parity b, block v, edge e (0: first column, 1: last)
+    // exchange buffer of parity b, block v, edge e (0: first column, 1: last),
+    // indexed by row (consecutive lanes, consecutive addresses)
     auto slot = [&](int b, int v, int e) { return a.xpub + (((int64_t)b * a.nwg + v) * 2 + e) * NR; };
     {
         float *pf = slot(a.n0 & 1, w, 0), *pl = slot(a.n0 & 1, w, 1);
@@ -109,8 +157,9 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
             ys[q][4] = y1.x; ys[q][5] = y1.y; ys[q][6] = y1.z; ys[q][7] = y1.w;
 #pragma unroll
             for (int p = 0; p < D; p += 2) {
-                const uint32_t j0 = (uint32_t)a.colpad[(int64_t)r * D + p];
-                const uint32_t j1 = (p + 1 < D) ? (uint32_t)a.colpad[(int64_t)r * D + p + 1] : 0u;
+                // LDS byte offsets of the neighbours' operand rows (< 2^16)
+                const uint32_t j0 = (uint32_t)a.colpad[(int64_t)r * D + p] * (uint32_t)sizeof(half8);
+                const uint32_t j1 = (p + 1 < D) ? (uint32_t)a.colpad[(int64_t)r * D + p + 1] * (uint32_t)sizeof(half8) : 0u;
                 cpk[q][p / 2] = j0 | (j1 << 16);
             }
             publish(pf + r, xs[q][0]);                   // edges of the starting state
@@ -128,9 +177,15 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
 
     float kA = a.coefA[a.n0], dn = a.delta[a.n0 + 1], jpr = a.jp[(int64_t)run * a.S + a.n0];
     for (int s = 0; s < a.K; ++s) {
-        // compiler-only barrier: the loop-invariant LDS weights and fields are
-        // re-read every step instead of being pinned in registers
+        // compiler-only barriers: the loop-invariant LDS weights are re-read
+        // every step instead of being pinned in registers, and the packed
+        // neighbour offsets are unpacked every step instead of being kept
+        // unpacked (twice the registers)
         asm volatile("" ::: "memory");
+#pragma unroll
+        for (int q = 0; q < RPT; ++q)
+#pragma unroll
+            for (int i = 0; i < (D + 1) / 2; ++i) asm volatile("" : "+v"(cpk[q][i]));
         const int n = a.n0 + s;
         const float d = (a.fmode == 1) ? 0.0f : dn;
         const float kA_n = kA, jp_n = jpr;
@@ -141,58 +196,70 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         }
         const float *publ = slot(n & 1, wl, 1);   // last column of the left block
         const float *pubr = slot(n & 1, wr, 0);   // first column of the right block
+        // this step's edges go out row by row as soon as a row is updated: the
+        // parity-(n+1) slots were last read by the neighbours in step n-1,
+        // which they had finished when this block passed its last wait
+        float *pf = slot((n + 1) & 1, w, 0), *pl = slot((n + 1) & 1, w, 1);
         uint2 fnew[RPT];
+        // one row ahead: the fields h (re-read every step, cache-resident)
+        // and the ring-neighbour edge values (coherent loads, long latency)
+        float hnext = a.h[t], lnext = fetch(publ + t), rnext = fetch(pubr + t);
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int r = t + q * RES_THREADS;
             asm volatile("" : "+v"(r));
+            const float hq = hnext, lq = lnext, rq = rnext;
+            if (q + 1 < RPT) {
+                hnext = a.h[r + RES_THREADS];
+                lnext = fetch(publ + r + RES_THREADS);
+                rnext = fetch(pubr + r + RES_THREADS);
+            }
             float acc[RES_COLS];
 #pragma unroll
             for (int c = 0; c < RES_COLS; ++c) acc[c] = 0.f;
 #pragma unroll
             for (int p = 0; p < D; ++p) {
-                const uint32_t j = (cpk[q][p / 2] >> (16 * (p & 1))) & 0xFFFFu;
-                const uint2 f8 = op[j];
+                const uint32_t jo = (cpk[q][p / 2] >> (16 * (p & 1))) & 0xFFFFu;
+                const half8 f = *reinterpret_cast<const half8 *>(smem + jo);
                 const float wgt = wv[(q * D + p) * RES_THREADS + t];
+                // binary16 -1, 0, +1 widen exactly: the same bits as a float32 operand
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    acc[c] = __builtin_fmaf(wgt, (float)(int8_t)((f8.x >> (8 * c)) & 0xFF), acc[c]);
-                    acc[c + 4] = __builtin_fmaf(wgt, (float)(int8_t)((f8.y >> (8 * c)) & 0xFF), acc[c + 4]);
-                }
+                for (int c = 0; c < RES_COLS; ++c) acc[c] = __builtin_fmaf(wgt, (float)f[c], acc[c]);
             }
-            const float hv = hs[q * RES_THREADS + t];
-            const float br = fetch(pubr + r);
+            const float br = rq;
             // columns left to right, in place: the left ring term reads the
             // step-n value of column c-1 kept in prev, the right one the
             // not yet updated column c+1
-            uint32_t lo = 0, hi = 0;
-            float prev = fetch(publ + r);
+            float prev = lq;
+            float fv[RES_COLS];
 #pragma unroll
             for (int c = 0; c < RES_COLS; ++c) {
                 const float xr = c == RES_COLS - 1 ? br : xs[q][c + 1];
-                float xn, yn;
-                update_elem(xs[q][c], ys[q][c], acc[c], hv, prev, xr, jp_n, kA_n, a.kB, a.dt, a.kD, xn, yn);
-                const uint32_t f = ternary_byte(xn, d);
-                if (c < 4) lo |= f << (8 * c);
-                else hi |= f << (8 * (c - 4));
+                float xn, yn, sg;
+                update_elem(xs[q][c], ys[q][c], acc[c], hq, prev, xr, jp_n, kA_n, a.kB, a.dt, a.kD, xn, yn, sg);
+                // f of Eq. 8 (d = 0 for sign): the value ternary_byte gives
+                fv[c] = fabsf(xn) > d ? sg : 0.0f;
                 prev = xs[q][c];
                 xs[q][c] = xn;
                 ys[q][c] = yn;
             }
-            fnew[q] = make_uint2(lo, hi);
+            // materialise y here: otherwise the wall's selects are sunk to the
+            // next step and their condition masks pile up in scalar registers
+#pragma unroll
+            for (int c = 0; c < RES_COLS; ++c) asm volatile("" : "+v"(ys[q][c]));
+            fnew[q] = pack_e4m3(fv);
+            publish(pf + r, xs[q][0]);
+            publish(pl + r, xs[q][RES_COLS - 1]);
             // keep rows apart in the schedule: hoisting every row's gathers
             // ahead raises the register demand past two waves per SIMD
             __builtin_amdgcn_sched_barrier(0);
         }
         __syncthreads();  // every wave is done reading the step-n operand
-        float *pf = slot((n + 1) & 1, w, 0), *pl = slot((n + 1) & 1, w, 1);
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int r = t + q * RES_THREADS;
             asm volatile("" : "+v"(r));
-            op[r] = fnew[q];
-            publish(pf + r, xs[q][0]);
-            publish(pl + r, xs[q][RES_COLS - 1]);
+            op[r] = e4m3_to_half(fnew[q]);
         }
         __builtin_amdgcn_s_waitcnt(0);  // this wave's edge stores have completed
         __syncthreads();
@@ -216,7 +283,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         *reinterpret_cast<float4 *>(xrow + 4) = make_float4(xs[q][4], xs[q][5], xs[q][6], xs[q][7]);
         *reinterpret_cast<float4 *>(yrow) = make_float4(ys[q][0], ys[q][1], ys[q][2], ys[q][3]);
         *reinterpret_cast<float4 *>(yrow + 4) = make_float4(ys[q][4], ys[q][5], ys[q][6], ys[q][7]);
-        *reinterpret_cast<uint2 *>(a.g + (int64_t)r * a.Cs + c0) = op[r];
+        *reinterpret_cast<uint2 *>(a.g + (int64_t)r * a.Cs + c0) = operand_to_int8(op[r]);
     }
 }
 
@@ -237,7 +304,7 @@ int resident_rows(int N) {
 
 size_t resident_lds_bytes(int N, int D) {
     const int rows = resident_rows(N);
-    return rows < 0 ? 0 : (size_t)rows * (8 + 4 * (D + 1));
+    return rows < 0 ? 0 : (size_t)rows * (16 + 4 * D);
 }
 
 // rows per thread (1, 2, 4 or 8), or -1 when N is too large
