@@ -21,9 +21,13 @@ BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed fp32 instructions are disabled on purpose: hand-written or generated
-# v_pk_{add,mul,fma}_f32 are avoided on this target.
+# v_pk_{add,mul,fma}_f32 are avoided on this target. MFMA accumulators and
+# results are allocated in ordinary VGPRs (gfx950 reads and writes both
+# register halves): with accumulation registers the allocator rotated the
+# dense step's accumulators through copies every loop iteration, each copy
+# waiting on an MFMA.
 COMMON = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=" + ARCH, "-I", INCLUDE, "-I", CSRC,
-          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument"]
 
 
