@@ -1,0 +1,83 @@
+"""Host-side logic of bench.py (no GPU): the one-GPU contract, the algorithmic
+work the roofline figures are computed from, and the committed counter
+summaries being used only for the kernel source they were measured on."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    """--gpus N > 1 exits with status 2 and a message, before touching a GPU."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_sparse_algorithmic_bytes_and_ops():
+    """Random 6-regular N = 4096, R = 32 x 64 runs: per step the streaming
+    kernel must read and write x and y (fp32) and write and read the int8
+    operand once (18 B per replica-spin), plus the CSR arrays and h; the
+    resident loop must do one FMA per neighbour and 13 more operations per
+    update."""
+    import bench
+    w = bench.make_workload("sparse6")
+    N, C = 4096, 32 * 64
+    nnz = N * 6
+    assert len(w["csr"][1]) == nnz
+    expect = N * C * 18 + 4 * (N + 1) + 8 * nnz + 4 * N
+    assert bench.algorithmic_bytes(w, {"path": "csr_fp32"}) == expect == 151224324
+    assert bench.resident_ops_per_step(w) == nnz * C + 13 * N * C
+
+
+def test_dense_algorithmic_flops():
+    import bench
+    w = {"N": 1000, "R": 4, "runs": 3}
+    assert bench.algorithmic_flops(w) == 2.0 * 1000 * 1000 * 12
+
+
+def test_committed_traffic_used_only_for_its_source(tmp_path, monkeypatch):
+    """Every committed traffic summary names the source hash it was measured
+    on; bench.py reports its bytes while the hash matches and null once the
+    kernel source differs (checked on a copy with a changed source)."""
+    import bench
+    seen = 0
+    for name in sorted(os.listdir(os.path.join(ROOT, "profiles"))):
+        if not name.startswith("traffic_"):
+            continue
+        kv = {}
+        for line in open(os.path.join(ROOT, "profiles", name)):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        srcs = kv["source"].split()
+        path = [p for p, files in bench.KERNEL_SOURCES.items() if files == srcs][0]
+        workload = name[len("traffic_"):-len(".txt")]
+        got = bench.measured_traffic(workload, path)
+        if kv["source_sha256_16"] != bench.source_hash(srcs):
+            assert got is None          # measured on another source: reported as null
+            continue
+        assert got == float(kv.get("hbm_bytes_per_launch", kv.get("hbm_bytes_per_step")))
+        seen += 1
+    assert seen >= 1
+    # a changed kernel source invalidates the summary
+    fake = tmp_path / "repo"
+    shutil.copytree(os.path.join(ROOT, "profiles"), fake / "profiles")
+    src = fake / "paper_2604_01050_amd" / "csrc"
+    src.mkdir(parents=True)
+    for f in bench.KERNEL_SOURCES["csr_resident"]:
+        data = open(os.path.join(ROOT, f), "rb").read()
+        (fake / f).write_bytes(data + b"\n// changed\n")
+    monkeypatch.setattr(bench, "ROOT", str(fake))
+    assert bench.measured_traffic("sparse6_resident", "csr_resident") is None
+
+
+def test_unknown_workload_is_rejected():
+    import bench
+    with pytest.raises(SystemExit):
+        bench.make_workload("no_such_workload")
