@@ -153,12 +153,25 @@ __device__ __forceinline__ float4 gather_fields3(int i, int c, int Cs, const Tri
     return make_float4(a[0], a[1], a[2], a[3]);
 }
 
+// Non-temporal 16-byte load and store of four consecutive floats.
+typedef float v4f __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float4 nt_load4(const float *p) {
+    const v4f v = __builtin_nontemporal_load(reinterpret_cast<const v4f *>(p));
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+__device__ __forceinline__ void nt_store4(float *p, const float (&v)[4]) {
+    __builtin_nontemporal_store(v4f{v[0], v[1], v[2], v[3]}, reinterpret_cast<v4f *>(p));
+}
+
 #pragma clang fp contract(off)
 // RING_SHFL: R divides 256 and is a multiple of 4, so every run lies inside
 // one wavefront's 256 columns and its R/4 lanes; the ring neighbours outside a
 // lane's 4 columns come from the adjacent lane of the same run by a cross-lane
-// read. Otherwise they are read from the row in memory.
-template <bool BALLISTIC, bool RING_SHFL>
+// read. Otherwise they are read from the row in memory. NT: the row's own x
+// and y stream through non-temporally, so that the cache keeps the gathered
+// operand rows (instances whose state is far larger than the caches; the
+// ballistic path gathers x itself and never takes it).
+template <bool BALLISTIC, bool RING_SHFL, bool NT = false>
 __device__ __forceinline__ void csr_step_body(int b, int N, int Cs, int C, int R, int nchunk,
                                               const int32_t *__restrict__ row_ptr,
                                               const int32_t *__restrict__ col,
@@ -173,8 +186,9 @@ __device__ __forceinline__ void csr_step_body(int b, int N, int Cs, int C, int R
     if (i >= N || c >= C) return;
 
     const int64_t o = (int64_t)i * Cs + c;
-    const float4 x = *reinterpret_cast<const float4 *>(x_in + o);
-    const float4 yv = *reinterpret_cast<const float4 *>(y + o);
+    constexpr bool STREAM = NT && !BALLISTIC;
+    const float4 x = STREAM ? nt_load4(x_in + o) : *reinterpret_cast<const float4 *>(x_in + o);
+    const float4 yv = STREAM ? nt_load4(y + o) : *reinterpret_cast<const float4 *>(y + o);
     float4 phi;
     if (csr_rpw_shift(C) == 0) {
         phi = gather_fields<BALLISTIC, true>(i, c, Cs, row_ptr, col, val, x_in, g_in);
@@ -219,14 +233,19 @@ __device__ __forceinline__ void csr_step_body(int b, int N, int Cs, int C, int R
         yo[e] = yn;
         fo[e] = f_value(fmode, xn, k.delta_next);
     }
-    *reinterpret_cast<float4 *>(x_out + o) = make_float4(xo[0], xo[1], xo[2], xo[3]);
-    *reinterpret_cast<float4 *>(y + o) = make_float4(yo[0], yo[1], yo[2], yo[3]);
+    if constexpr (STREAM) {
+        nt_store4(x_out + o, xo);
+        nt_store4(y + o, yo);
+    } else {
+        *reinterpret_cast<float4 *>(x_out + o) = make_float4(xo[0], xo[1], xo[2], xo[3]);
+        *reinterpret_cast<float4 *>(y + o) = make_float4(yo[0], yo[1], yo[2], yo[3]);
+    }
     if constexpr (!BALLISTIC)
         *reinterpret_cast<uint32_t *>(g_out + o) = pack_ternary(fo[0], fo[1], fo[2], fo[3]);
 }
 #pragma clang fp contract(on)
 
-template <bool BALLISTIC, bool RING_SHFL>
+template <bool BALLISTIC, bool RING_SHFL, bool NT>
 __global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, int nchunk,
                                                   const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col,
@@ -236,8 +255,8 @@ __global__ __launch_bounds__(256) void k_csr_step(int N, int Cs, int C, int R, i
                                                   float *__restrict__ y, const int8_t *__restrict__ g_in,
                                                   int8_t *__restrict__ g_out, const float *__restrict__ jp,
                                                   int64_t jp_stride, StepCoef k, int fmode) {
-    csr_step_body<BALLISTIC, RING_SHFL>(blockIdx.x, N, Cs, C, R, nchunk, row_ptr, col, val, t3, h, x_in, x_out, y,
-                                        g_in, g_out, jp, jp_stride, k, fmode);
+    csr_step_body<BALLISTIC, RING_SHFL, NT>(blockIdx.x, N, Cs, C, R, nchunk, row_ptr, col, val, t3, h, x_in, x_out,
+                                            y, g_in, g_out, jp, jp_stride, k, fmode);
 }
 
 // Grouped step of every CSR instance of one serving group: a grid-stride loop
@@ -307,15 +326,23 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
     const int nchunk = csr_step_chunks(C);
     dim3 grid(csr_step_blocks(N, C)), block(WAVES * 64);
     const bool shfl = csr_ring_shfl(R);
-#define SBQA_CSR_LAUNCH(B, S)                                                                                  \
-    hipLaunchKernelGGL((k_csr_step<B, S>), grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, t3, h, x_in, \
-                       x_out, y, g_in, g_out, jp, jp_stride, k, fmode)
+    // x in, x out and y stream through once per step; when they are larger
+    // than the last-level cache (256 MiB on MI355X; 192 MiB leaves room for
+    // the operand and the CSR), non-temporal accesses keep them from evicting
+    // the gathered operand rows. Smaller states are better served cached.
+    const bool nt = 3.0 * 4.0 * (double)N * (double)Cs > 192.0 * 1024 * 1024;
+#define SBQA_CSR_LAUNCH(B, S, T)                                                                               \
+    hipLaunchKernelGGL((k_csr_step<B, S, T>), grid, block, 0, st, N, Cs, C, R, nchunk, row_ptr, col, val, t3, h,    \
+                       x_in, x_out, y, g_in, g_out, jp, jp_stride, k, fmode)
     if (fmode == 2) {
-        if (shfl) SBQA_CSR_LAUNCH(true, true);
-        else SBQA_CSR_LAUNCH(true, false);
+        if (shfl) SBQA_CSR_LAUNCH(true, true, false);
+        else SBQA_CSR_LAUNCH(true, false, false);
+    } else if (nt) {
+        if (shfl) SBQA_CSR_LAUNCH(false, true, true);
+        else SBQA_CSR_LAUNCH(false, false, true);
     } else {
-        if (shfl) SBQA_CSR_LAUNCH(false, true);
-        else SBQA_CSR_LAUNCH(false, false);
+        if (shfl) SBQA_CSR_LAUNCH(false, true, false);
+        else SBQA_CSR_LAUNCH(false, false, false);
     }
 #undef SBQA_CSR_LAUNCH
     return hipGetLastError();
