@@ -112,6 +112,23 @@ typedef enum { SBQA_LOOP_AUTO = 0, SBQA_LOOP_STREAM = 1, SBQA_LOOP_RESIDENT = 2 
  *   BYTES  one e4m3 byte (FP8) or e2m1 nibble (FP4) per coupling. */
 typedef enum { SBQA_JPACK_AUTO = 0, SBQA_JPACK_BYTES = 1 } sbqa_j_packing;
 
+/* Spin order inside the library for CSR couplings (the contraction gathers
+ * the operand rows of a spin's neighbours and triple partners, which stay in
+ * cache only when their indices are close):
+ *   AUTO  relabel the spins by reverse Cuthill-McKee (breadth-first over the
+ *         pair and triple adjacency) when N >= 16384, the given numbering
+ *         puts neighbours far apart (mean |i - j| over the adjacency above
+ *         N/64) and the new order cuts that mean at least 4x; else keep it;
+ *   OFF   keep the given order;
+ *   ON    relabel whenever the instance has couplings.
+ * Relabelling is internal: every spin-indexed input and output (state, best
+ * spins, the spins of sbqa_energy, fields) stays in the caller's order, the
+ * initial state is drawn by the caller's spin index, and each spin's
+ * couplings are summed in the given order, so trajectories are the same bit
+ * for bit (real-valued energies up to the order of their FP64 sums). Dense
+ * couplings ignore it. */
+typedef enum { SBQA_REORDER_AUTO = 0, SBQA_REORDER_OFF = 1, SBQA_REORDER_ON = 2 } sbqa_reorder;
+
 /* Couplings: exactly one of `dense` or the CSR triple is non-NULL.
  * J must be symmetric with a zero diagonal and finite entries.
  *   dense    N*N float64, row-major.
@@ -169,12 +186,13 @@ typedef struct {
                                 of the instance's shape; every tile gives the
                                 same bits)                                        */
     int32_t j_packing;       /* sbqa_j_packing (dense FP8 / FP4 only)              */
+    int32_t reorder;         /* sbqa_reorder (CSR couplings only)                  */
 } sbqa_schedule;
 
 /* Defaults: steps 1000, dt 0.5, a0 1, c0 auto, ternary f, delta_max 0.7,
  * PAPER schedule with gamma0_over_R 1, beta in [0.5,1.5], alpha in [0.5,1.0]
  * (Sec. II.B), seed 0, init_amp 0.1, precision AUTO, energy_every 0,
- * loop_kernel AUTO, dense_tile 0 (autotuned), j_packing AUTO. */
+ * loop_kernel AUTO, dense_tile 0 (autotuned), j_packing AUTO, reorder AUTO. */
 sbqa_schedule sbqa_schedule_default(void);
 
 /* Context information (sbqa_info). */
@@ -192,6 +210,8 @@ typedef struct {
     int32_t resident;        /* 1 when steps run in a resident loop
                                 (sbqa_loop_kernel), 0 otherwise                   */
     int32_t tile_cols;       /* dense path: replica columns per workgroup tile   */
+    int32_t reordered;       /* 1 when CSR spins are relabelled internally
+                                (sbqa_reorder), 0 otherwise                       */
 } sbqa_info_t;
 
 /*

@@ -11,4 +11,4 @@ from ._abi import (Context, SbqaError, Server, make_schedule, lib, LIB_PATH, PAT
                    OK, EINVAL, ENOMEM, EDEVICE, ESTATE, EBUDGET, EAGAIN,
                    F_TERNARY, F_SIGN, F_BALLISTIC, PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8, PREC_FP4,
                    JP_LINEAR, JP_PAPER, JP_TABLE, LOOP_AUTO, LOOP_STREAM, LOOP_RESIDENT,
-                   JPACK_AUTO, JPACK_BYTES)
+                   JPACK_AUTO, JPACK_BYTES, REORDER_AUTO, REORDER_OFF, REORDER_ON)

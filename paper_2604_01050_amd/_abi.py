@@ -20,6 +20,7 @@ PREC_AUTO, PREC_FP32, PREC_FP8, PREC_BF16X3, PREC_INT8, PREC_FP4 = 0, 1, 2, 3, 4
 JP_LINEAR, JP_PAPER, JP_TABLE = 0, 1, 2
 LOOP_AUTO, LOOP_STREAM, LOOP_RESIDENT = 0, 1, 2
 JPACK_AUTO, JPACK_BYTES = 0, 1
+REORDER_AUTO, REORDER_OFF, REORDER_ON = 0, 1, 2
 PATHS = {0: "dense_fp32", 1: "dense_fp8", 2: "dense_bf16x3", 3: "csr_fp32", 4: "dense_int8", 5: "dense_fp8_packed",
          6: "dense_fp4", 7: "dense_fp4_packed"}
 _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5: "EBUDGET", -6: "EAGAIN"}
@@ -46,14 +47,14 @@ class Schedule(ct.Structure):
                 ("alpha_hi", ct.c_double), ("beta", ct.c_void_p), ("alpha", ct.c_void_p),
                 ("jp_table", ct.c_void_p), ("seed", ct.c_uint64), ("init_amp", ct.c_double),
                 ("precision", ct.c_int32), ("energy_every", ct.c_uint32), ("loop_kernel", ct.c_int32),
-                ("dense_tile", ct.c_int32), ("j_packing", ct.c_int32)]
+                ("dense_tile", ct.c_int32), ("j_packing", ct.c_int32), ("reorder", ct.c_int32)]
 
 
 class Info(ct.Structure):
     _fields_ = [("N", ct.c_int32), ("R", ct.c_int32), ("runs", ct.c_int32), ("steps", ct.c_uint32),
                 ("step", ct.c_uint32), ("path", ct.c_int32), ("fmode", ct.c_int32), ("c0", ct.c_double),
                 ("j_integral", ct.c_int32), ("device_bytes", ct.c_size_t), ("resident", ct.c_int32),
-                ("tile_cols", ct.c_int32)]
+                ("tile_cols", ct.c_int32), ("reordered", ct.c_int32)]
 
 
 def _load() -> ct.CDLL:
@@ -254,7 +255,8 @@ def sbqa_info(ctx: Context) -> dict:
     _check(lib.sbqa_info(ctx.ptr, ct.byref(i)))
     return {"N": i.N, "R": i.R, "runs": i.runs, "steps": i.steps, "step": i.step,
             "path": PATHS[i.path], "fmode": i.fmode, "c0": i.c0, "j_integral": bool(i.j_integral),
-            "device_bytes": i.device_bytes, "resident": bool(i.resident), "tile_cols": i.tile_cols}
+            "device_bytes": i.device_bytes, "resident": bool(i.resident), "tile_cols": i.tile_cols,
+            "reordered": bool(i.reordered)}
 
 
 def sbqa_sync(ctx: Context) -> None:

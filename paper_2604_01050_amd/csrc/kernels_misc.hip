@@ -38,11 +38,15 @@ __device__ __forceinline__ float uniform_sym(uint32_t bits, double amp) {
 }
 
 __global__ void k_init_state(int N, int C, int ld, int spin_major, uint32_t key_lo, uint32_t key_hi,
-                             double amp, float *__restrict__ x, float *__restrict__ y) {
+                             double amp, const int32_t *__restrict__ orig, float *__restrict__ x,
+                             float *__restrict__ y) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)N * C) return;
     const int i = (int)(e / C), c = (int)(e % C);
-    const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)c, 0u, 0u), make_uint2(key_lo, key_hi));
+    // the counter is the caller's spin index (row i holds spin orig[i] when
+    // the spins are relabelled internally)
+    const uint32_t si = orig ? (uint32_t)orig[i] : (uint32_t)i;
+    const uint4 r = philox4x32_10(make_uint4(si, (uint32_t)c, 0u, 0u), make_uint2(key_lo, key_hi));
     const int64_t o = spin_major ? (int64_t)i * ld + c : (int64_t)c * ld + i;
     x[o] = uniform_sym(r.x, amp);
     y[o] = uniform_sym(r.y, amp);
@@ -275,12 +279,12 @@ __global__ __launch_bounds__(256) void k_best_copy(int N, int R, int ld, int spi
 
 }  // namespace
 
-hipError_t launch_init_state(int N, int C, int ld, bool spin_major, uint64_t seed, double amp, float *x, float *y,
-                             hipStream_t st) {
+hipError_t launch_init_state(int N, int C, int ld, bool spin_major, uint64_t seed, double amp, const int32_t *orig,
+                             float *x, float *y, hipStream_t st) {
     const int64_t n = (int64_t)N * C;
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
     hipLaunchKernelGGL(k_init_state, grid, block, 0, st, N, C, ld, spin_major ? 1 : 0, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), amp, x, y);
+                       (uint32_t)(seed >> 32), amp, orig, x, y);
     return hipGetLastError();
 }
 

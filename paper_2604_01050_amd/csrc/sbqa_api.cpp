@@ -137,6 +137,7 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     if (s->precision < SBQA_PREC_AUTO || s->precision > SBQA_PREC_FP4) return fail(SBQA_EINVAL, "unknown precision %d", s->precision);
     if (s->loop_kernel < 0 || s->loop_kernel > 2) return fail(SBQA_EINVAL, "unknown loop_kernel %d", s->loop_kernel);
     if (s->j_packing < SBQA_JPACK_AUTO || s->j_packing > SBQA_JPACK_BYTES) return fail(SBQA_EINVAL, "unknown j_packing %d", s->j_packing);
+    if (s->reorder < SBQA_REORDER_AUTO || s->reorder > SBQA_REORDER_ON) return fail(SBQA_EINVAL, "unknown reorder %d", s->reorder);
     if (s->dense_tile != 0 && s->dense_tile != 64 && s->dense_tile != 128 && s->dense_tile != 256)
         return fail(SBQA_EINVAL, "dense_tile must be 0 (autotuned), 64, 128 or 256 (got %d)", s->dense_tile);
     if (!(s->init_amp >= 0) || !std::isfinite(s->init_amp)) return fail(SBQA_EINVAL, "init_amp must be finite and >= 0");
@@ -804,6 +805,133 @@ static bool small_plan(sbqa_ctx *c, std::string *why) {
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Internal relabelling of CSR spins for cache locality (sbqa_reorder).
+// ---------------------------------------------------------------------------
+
+// Undirected adjacency of the pairs and of the triples' members, as offsets
+// and neighbour lists (duplicates allowed).
+static void spin_adjacency(const sbqa_coupling *J, int32_t N, std::vector<int64_t> *aptr, std::vector<int32_t> *adj) {
+    std::vector<int64_t> deg((size_t)N + 1, 0);
+    for (int32_t i = 0; i < N; ++i) deg[(size_t)i + 1] += J->row_ptr[i + 1] - J->row_ptr[i];
+    for (int64_t t = 0; t < J->n3; ++t)
+        for (int e = 0; e < 3; ++e) deg[(size_t)J->tri[3 * t + e] + 1] += 2;
+    for (int32_t i = 0; i < N; ++i) deg[(size_t)i + 1] += deg[(size_t)i];
+    adj->assign((size_t)deg[(size_t)N], 0);
+    std::vector<int64_t> fill(deg.begin(), deg.end() - 1);
+    for (int32_t i = 0; i < N; ++i)
+        for (int32_t p = J->row_ptr[i]; p < J->row_ptr[i + 1]; ++p) (*adj)[(size_t)fill[(size_t)i]++] = J->col[p];
+    for (int64_t t = 0; t < J->n3; ++t)
+        for (int e = 0; e < 3; ++e) {
+            const int32_t *v = J->tri + 3 * t;
+            (*adj)[(size_t)fill[(size_t)v[e]]++] = v[(e + 1) % 3];
+            (*adj)[(size_t)fill[(size_t)v[e]]++] = v[(e + 2) % 3];
+        }
+    *aptr = std::move(deg);
+}
+
+// Mean |label(i) - label(j)| over the adjacency (label = identity when pnew
+// is empty).
+static double mean_span(const std::vector<int64_t> &aptr, const std::vector<int32_t> &adj, int32_t N,
+                        const std::vector<int32_t> &pnew) {
+    if (adj.empty()) return 0.0;
+    double sum = 0.0;
+    for (int32_t i = 0; i < N; ++i)
+        for (int64_t p = aptr[(size_t)i]; p < aptr[(size_t)i + 1]; ++p) {
+            const int32_t j = adj[(size_t)p];
+            sum += pnew.empty() ? std::fabs((double)i - j) : std::fabs((double)pnew[(size_t)i] - pnew[(size_t)j]);
+        }
+    return sum / (double)adj.size();
+}
+
+// Reverse Cuthill-McKee order: breadth-first through every connected
+// component, each started at its lowest-degree unvisited spin, neighbours
+// taken by increasing degree; the whole order reversed. pnew[i] = new label.
+static void rcm_order(const std::vector<int64_t> &aptr, const std::vector<int32_t> &adj, int32_t N,
+                      std::vector<int32_t> *pnew) {
+    std::vector<int32_t> byDeg((size_t)N), order;
+    order.reserve((size_t)N);
+    for (int32_t i = 0; i < N; ++i) byDeg[(size_t)i] = i;
+    auto deg = [&](int32_t i) { return aptr[(size_t)i + 1] - aptr[(size_t)i]; };
+    std::stable_sort(byDeg.begin(), byDeg.end(), [&](int32_t a, int32_t b) { return deg(a) < deg(b); });
+    std::vector<char> seen((size_t)N, 0);
+    std::vector<int32_t> nb;
+    for (int32_t start : byDeg) {
+        if (seen[(size_t)start]) continue;
+        seen[(size_t)start] = 1;
+        size_t head = order.size();
+        order.push_back(start);
+        while (head < order.size()) {
+            const int32_t u = order[head++];
+            nb.clear();
+            for (int64_t p = aptr[(size_t)u]; p < aptr[(size_t)u + 1]; ++p) {
+                const int32_t v = adj[(size_t)p];
+                if (!seen[(size_t)v]) { seen[(size_t)v] = 1; nb.push_back(v); }
+            }
+            std::stable_sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg(a) < deg(b); });
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    pnew->assign((size_t)N, 0);
+    for (int32_t k = 0; k < N; ++k) (*pnew)[(size_t)order[(size_t)(N - 1 - k)]] = k;
+}
+
+// Whether (and how) to relabel a CSR instance's spins (sbqa_reorder).
+static void plan_reorder(const sbqa_coupling *J, int32_t N, int mode, std::vector<int32_t> *pnew) {
+    pnew->clear();
+    if (mode == SBQA_REORDER_OFF || (J->nnz == 0 && J->n3 == 0)) return;
+    if (mode == SBQA_REORDER_AUTO && N < 16384) return;
+    std::vector<int64_t> aptr;
+    std::vector<int32_t> adj;
+    spin_adjacency(J, N, &aptr, &adj);
+    const double before = mean_span(aptr, adj, N, {});
+    if (mode == SBQA_REORDER_AUTO && before <= (double)N / 64.0) return;
+    std::vector<int32_t> p;
+    rcm_order(aptr, adj, N, &p);
+    if (mode == SBQA_REORDER_AUTO && mean_span(aptr, adj, N, p) * 4.0 > before) return;
+    *pnew = std::move(p);
+}
+
+// The coupling with spins relabelled by pnew: row pnew[i] holds spin i's
+// couplings in the given order (columns relabelled), triples keep their
+// order with relabelled members; h permuted alike. The vectors own the data.
+struct Relabelled {
+    std::vector<int32_t> rp, col, tri;
+    std::vector<double> val, h;
+    sbqa_coupling J{};
+};
+static void relabel(const sbqa_coupling *J, const double *h, int32_t N, const std::vector<int32_t> &pnew,
+                    Relabelled *r) {
+    std::vector<int32_t> orig((size_t)N);
+    for (int32_t i = 0; i < N; ++i) orig[(size_t)pnew[(size_t)i]] = i;
+    r->rp.assign((size_t)N + 1, 0);
+    for (int32_t k = 0; k < N; ++k) {
+        const int32_t i = orig[(size_t)k];
+        r->rp[(size_t)k + 1] = r->rp[(size_t)k] + (J->row_ptr[i + 1] - J->row_ptr[i]);
+    }
+    r->col.resize((size_t)J->nnz);
+    r->val.resize((size_t)J->nnz);
+    for (int32_t k = 0; k < N; ++k) {
+        const int32_t i = orig[(size_t)k];
+        int64_t q = r->rp[(size_t)k];
+        for (int32_t p = J->row_ptr[i]; p < J->row_ptr[i + 1]; ++p, ++q) {
+            r->col[(size_t)q] = pnew[(size_t)J->col[p]];
+            r->val[(size_t)q] = J->val[p];
+        }
+    }
+    r->tri.resize((size_t)3 * J->n3);
+    for (int64_t q = 0; q < 3 * J->n3; ++q) r->tri[(size_t)q] = pnew[(size_t)J->tri[q]];
+    if (h) {
+        r->h.resize((size_t)N);
+        for (int32_t i = 0; i < N; ++i) r->h[(size_t)pnew[(size_t)i]] = h[i];
+    }
+    r->J = *J;
+    r->J.row_ptr = r->rp.data();
+    r->J.col = r->col.data();
+    r->J.val = r->val.data();
+    r->J.tri = J->n3 ? r->tri.data() : nullptr;
+}
+
 sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                        const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out,
                        bool allow_resident) {
@@ -827,6 +955,15 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
         if (e != hipSuccess) { delete c; return fail(SBQA_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
         c->stream = c->own_stream;
     }
+    Relabelled rl;
+    if (facts.path == PATH_CSR) {
+        plan_reorder(J, N, s->reorder, &c->pnew);
+        if (!c->pnew.empty()) {
+            relabel(J, h, N, c->pnew, &rl);
+            J = &rl.J;
+            h = h ? rl.h.data() : nullptr;
+        }
+    }
     {
         std::string why;
         const bool plan = facts.path == PATH_CSR ? resident_plan(c, J, &why) : small_plan(c, &why);
@@ -840,9 +977,18 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
     if (facts.path != PATH_CSR)
         set_tile(&c->L, s->dense_tile ? s->dense_tile / 64 : tune_dense_mbw(facts.path, c->L.C, c->L.Np, c->stream));
     st = ctx_upload(c, J, h);
+    if (st == SBQA_OK && !c->pnew.empty()) {
+        std::vector<int32_t> orig((size_t)N);
+        for (int32_t i = 0; i < N; ++i) orig[(size_t)c->pnew[(size_t)i]] = i;
+        hipError_t e = dalloc(c, &c->porig, (size_t)N);
+        if (e == hipSuccess) e = hipMemcpyAsync(c->porig, orig.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);   // the staging vector dies here
+        if (e != hipSuccess) st = fail(SBQA_EDEVICE, "relabelling: %s", hipGetErrorString(e));
+    }
     if (st == SBQA_OK) {
         const bool sm = facts.path == PATH_CSR;
-        hipError_t e = launch_init_state(N, c->L.C, sm ? c->L.Cs : c->L.Np, sm, s->seed, s->init_amp, c->x[0], c->y, c->stream);
+        hipError_t e = launch_init_state(N, c->L.C, sm ? c->L.Cs : c->L.Np, sm, s->seed, s->init_amp, c->porig, c->x[0],
+                                         c->y, c->stream);
         if (e != hipSuccess) st = fail(SBQA_EDEVICE, "init: %s", hipGetErrorString(e));
     }
     if (st == SBQA_OK) st = rebuild_operand(c);
@@ -961,8 +1107,20 @@ sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins) {
         if (st != SBQA_OK) return st;
     }
     if (energies) HIP_TRY(hipMemcpyAsync(energies, c->bestE, sizeof(double) * c->runs, hipMemcpyDeviceToHost, c->stream));
-    if (spins) HIP_TRY(hipMemcpyAsync(spins, c->bestSpins, (size_t)c->runs * c->N, hipMemcpyDeviceToHost, c->stream));
+    std::vector<int8_t> rows;
+    if (spins) {
+        int8_t *dst = spins;
+        if (!c->pnew.empty()) {
+            rows.resize((size_t)c->runs * c->N);
+            dst = rows.data();
+        }
+        HIP_TRY(hipMemcpyAsync(dst, c->bestSpins, (size_t)c->runs * c->N, hipMemcpyDeviceToHost, c->stream));
+    }
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (spins && !c->pnew.empty())   // back to the caller's spin order
+        for (int r = 0; r < c->runs; ++r)
+            for (int i = 0; i < c->N; ++i)
+                spins[(size_t)r * c->N + i] = rows[(size_t)r * c->N + c->pnew[(size_t)i]];
     return ctx_check_async(c);
 }
 
@@ -998,6 +1156,7 @@ sbqa_schedule sbqa_schedule_default(void) {
     s.loop_kernel = SBQA_LOOP_AUTO;
     s.dense_tile = 0;
     s.j_packing = SBQA_JPACK_AUTO;
+    s.reorder = SBQA_REORDER_AUTO;
     return s;
 }
 
@@ -1049,7 +1208,14 @@ sbqa_status sbqa_energy(sbqa_ctx *c, const int8_t *spins, int32_t count, double 
     hipError_t e = hipMalloc(&E, sizeof(double) * count);
     if (e != hipSuccess) { (void)hipFree(ds); return fail(SBQA_ENOMEM, "hipMalloc: %s", hipGetErrorString(e)); }
     struct Guard { void *a, *b, *c2, *d; ~Guard() { (void)hipFree(a); (void)hipFree(b); (void)hipFree(c2); (void)hipFree(d); } } gd{ds, E, nullptr, nullptr};
-    HIP_TRY(hipMemcpyAsync(ds, spins, (size_t)count * N, hipMemcpyHostToDevice, c->stream));
+    std::vector<int8_t> rows;
+    if (!c->pnew.empty()) {   // the caller's spin order to the internal rows
+        rows.resize((size_t)count * N);
+        for (int32_t m = 0; m < count; ++m)
+            for (int i = 0; i < N; ++i) rows[(size_t)m * N + c->pnew[(size_t)i]] = spins[(size_t)m * N + i];
+    }
+    HIP_TRY(hipMemcpyAsync(ds, rows.empty() ? spins : rows.data(), (size_t)count * N, hipMemcpyHostToDevice, c->stream));
+    if (!rows.empty()) HIP_TRY(hipStreamSynchronize(c->stream));   // the staging vector dies at return
     if (c->facts.path == PATH_CSR) {
         HIP_TRY(launch_csr_energy_spins(N, count, c->rp, c->col, c->val64, c->tri3(), h64, ds, E, c->stream));
     } else {
@@ -1085,7 +1251,9 @@ sbqa_status sbqa_fields(sbqa_ctx *c, float *phi) {
         buf.resize((size_t)N * Cs);
         HIP_TRY(hipMemcpyAsync(buf.data(), c->phi, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
-        for (int i = 0; i < N; ++i) std::memcpy(phi + (size_t)i * C, buf.data() + (size_t)i * Cs, sizeof(float) * C);
+        for (int i = 0; i < N; ++i)
+            std::memcpy(phi + (size_t)i * C, buf.data() + (size_t)(c->pnew.empty() ? i : c->pnew[(size_t)i]) * Cs,
+                        sizeof(float) * C);
         return SBQA_OK;
     }
     const int Np = c->L.Np;
@@ -1118,12 +1286,14 @@ sbqa_status sbqa_get_state(sbqa_ctx *c, float *x, float *y) {
         sbqa_status e = ctx_check_async(c);
         if (e != SBQA_OK) return e;
     }
-    for (int i = 0; i < N; ++i)
+    for (int i = 0; i < N; ++i) {
+        const size_t row = c->pnew.empty() ? (size_t)i : (size_t)c->pnew[(size_t)i];   // internal row of spin i
         for (int cc = 0; cc < C; ++cc) {
-            const size_t o = sm ? (size_t)i * ld + cc : (size_t)cc * ld + i;
+            const size_t o = sm ? row * ld + cc : (size_t)cc * ld + i;
             if (x) x[(size_t)i * C + cc] = bx[o];
             if (y) y[(size_t)i * C + cc] = by[o];
         }
+    }
     return SBQA_OK;
 }
 
@@ -1138,12 +1308,14 @@ sbqa_status sbqa_set_state(sbqa_ctx *c, const float *x, const float *y) {
         if (!std::isfinite(x[q]) || !std::isfinite(y[q]) || std::fabs(x[q]) > 1.0f)
             return fail(SBQA_EINVAL, "state must be finite with |x| <= 1 (index %zu)", q);
     std::vector<float> bx(tot, 0.0f), by(tot, 0.0f);
-    for (int i = 0; i < N; ++i)
+    for (int i = 0; i < N; ++i) {
+        const size_t row = c->pnew.empty() ? (size_t)i : (size_t)c->pnew[(size_t)i];   // internal row of spin i
         for (int cc = 0; cc < C; ++cc) {
-            const size_t o = sm ? (size_t)i * ld + cc : (size_t)cc * ld + i;
+            const size_t o = sm ? row * ld + cc : (size_t)cc * ld + i;
             bx[o] = x[(size_t)i * C + cc];
             by[o] = y[(size_t)i * C + cc];
         }
+    }
     HIP_TRY(hipMemcpyAsync(c->x[c->cur], bx.data(), sizeof(float) * tot, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->y, by.data(), sizeof(float) * tot, hipMemcpyHostToDevice, c->stream));
     sbqa_status st = rebuild_operand(c);
@@ -1192,6 +1364,7 @@ sbqa_status sbqa_info(sbqa_ctx *c, sbqa_info_t *info) {
     info->device_bytes = c->bytes;
     info->resident = c->resident ? 1 : 0;
     info->tile_cols = c->facts.path == PATH_CSR ? 0 : 64 * c->L.mbw;
+    info->reordered = c->pnew.empty() ? 0 : 1;
     return SBQA_OK;
 }
 

@@ -113,6 +113,8 @@ struct sbqa_ctx {
     float *Jsm = nullptr;               // small dense loop: J float32 [N][N]
     int res_D = 0, res_rows = 0, res_nwg = 0;
     int32_t *colpad = nullptr;          // [rows][D]
+    std::vector<int32_t> pnew;          // CSR spins relabelled: row of the caller's spin i (empty: identity)
+    int32_t *porig = nullptr;           // [N] the caller's spin index of each row (relabelled only)
     float *valpad = nullptr;            // [D][rows]
     float *coefA = nullptr;             // [S]
     float *delta_tab = nullptr;         // [S+1]

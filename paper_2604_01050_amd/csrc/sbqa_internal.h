@@ -232,8 +232,10 @@ hipError_t launch_csr_fields(int fmode, int N, int Cs, int C, const int32_t *row
                              const int8_t *g, float *phi, hipStream_t st);
 
 // Counter-based initial state: x, y ~ U[-amp, amp] from Philox4x32-10 keyed by
-// seed, counter (i, c). spin_major selects [N][ld] (CSR) or [C][ld] (dense).
-hipError_t launch_init_state(int N, int C, int ld, bool spin_major, uint64_t seed, double amp,
+// seed, counter (i, c), i the caller's spin index: orig[row] when rows hold
+// relabelled spins, else the row. spin_major selects [N][ld] (CSR) or [C][ld]
+// (dense).
+hipError_t launch_init_state(int N, int C, int ld, bool spin_major, uint64_t seed, double amp, const int32_t *orig,
                              float *x, float *y, hipStream_t st);
 
 // Readout spins sign(x) (sign(0) = +1) as float64 +-1 into S[Cp][Np]

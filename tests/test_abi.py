@@ -50,6 +50,7 @@ def test_schedule_default_matches_paper_ranges(abi):
     assert (s.alpha_lo, s.alpha_hi) == (0.5, 1.0)
     assert s.jp_kind == abi.JP_PAPER and s.fmode == abi.F_TERNARY
     assert s.loop_kernel == abi.LOOP_AUTO and s.dense_tile == 0   # resident loops and tiles chosen by the library
+    assert s.reorder == abi.REORDER_AUTO and s.j_packing == abi.JPACK_AUTO
 
 
 def _expect(abi, status, **kw):
@@ -86,6 +87,7 @@ def test_validation_errors(abi):
     assert "dense_tile" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, dense_tile=96)
     assert "loop_kernel" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, loop_kernel=7)
     assert "j_packing" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, j_packing=2)
+    assert "reorder" in _expect(abi, abi.EINVAL, J=J, R=2, runs=2, reorder=3)
     # CSR: asymmetric, out of range, unsorted, bf16 precision
     E = inst.regular_graph(20, 3, 2)
     rp, col, val = inst.edges_to_csr(20, E, inst.gaussian_edges(len(E), 3))

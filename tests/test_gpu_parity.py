@@ -418,6 +418,7 @@ def test_hubo_large_heavy_hex(sb, orc):
     _log("large heavy-hex hubo N=%d triples=%d" % (N, len(K)))
     _full_size_step(sb, orc, csr=csr, N=N, R=R, runs=runs, nrows=48, S=1000, tri=T, K=K)
     ctx = _ctx(sb, csr=csr, tri=T, K=K, R=R, runs=runs, steps=100, seed=3)
+    assert sb.sbqa_info(ctx)["reordered"]          # vertex and bond sites far apart: relabelled (AUTO)
     sb.sbqa_step(ctx, 100)
     Eb, sp = sb.sbqa_best(ctx)
     np.testing.assert_allclose(orc.energy(sp, csr=csr, tri=T, K=K), Eb, rtol=1e-12, atol=1e-9)
@@ -627,6 +628,7 @@ def test_large_cubic_lattice(sb, orc):
     h = inst.gaussian_fields(N, 0.1, 2202)
     _full_size_step(sb, orc, csr=csr, h=h, N=N, R=R, runs=runs, nrows=48, S=1000)
     ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=200, seed=9)
+    assert not sb.sbqa_info(ctx)["reordered"]      # lattice order is already local (REORDER_AUTO)
     sb.sbqa_step(ctx, 200)
     Eb, sp = sb.sbqa_best(ctx)
     np.testing.assert_allclose(orc.energy(sp, csr=csr, h=h), Eb, rtol=1e-12, atol=1e-9)
@@ -926,3 +928,71 @@ def test_resident_rejects_unfit_instances(sb):
         assert ei.value.status == sb.EINVAL and why in ei.value.message, ei.value.message
         ctx = _ctx(sb, J=J, **kw)
         assert not sb.sbqa_info(ctx)["resident"]
+
+
+# ------------------------------------------------------------ internal spin relabelling
+@pytest.mark.gpu
+@pytest.mark.parametrize("case", ["hubo_int", "ising_resident", "ising_stream"])
+def test_internal_relabelling_is_invisible(sb, orc, case):
+    """CSR spins relabelled internally (reverse Cuthill-McKee, REORDER_ON)
+    against the given order (REORDER_OFF): the seeded initial state, the state
+    after any number of steps, the fields and (integer weights) the best
+    energies and spins are the same bit for bit, in the caller's spin order;
+    real weights: best energies to 1e-12 (their FP64 sums run in another row
+    order). sbqa_energy of given spins agrees with the oracle either way."""
+    if case == "hubo_int":
+        N, P2, w2, T, K = inst.hubo_heavy_hex(12, 12, 71, dist="int")
+        csr = inst.edges_to_csr(N, P2, w2)
+        h = np.round(inst.gaussian_fields(N, 2.0, 72))
+        extra = dict(tri=T, K=K)
+        R, runs = 8, 3
+    else:
+        N = 600
+        E = inst.regular_graph(N, 3, 73)
+        csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 74))
+        h = inst.gaussian_fields(N, 0.1, 75)
+        extra = dict(loop_kernel=sb.LOOP_RESIDENT if case == "ising_resident" else sb.LOOP_STREAM)
+        T = K = None
+        R, runs = 8, 4
+    S = 90
+    _log("relabelling %s N=%d" % (case, N))
+    out = {}
+    for mode in (sb.REORDER_OFF, sb.REORDER_ON):
+        ctx = _ctx(sb, csr=csr, h=h, R=R, runs=runs, steps=S, seed=7, energy_every=15, reorder=mode, **extra)
+        assert sb.sbqa_info(ctx)["reordered"] == (mode == sb.REORDER_ON)
+        r = [sb.sbqa_get_state(ctx)]
+        sb.sbqa_step(ctx, 31)
+        r += [sb.sbqa_get_state(ctx), sb.sbqa_fields(ctx)]
+        sb.sbqa_step(ctx, S - 31)
+        r += [sb.sbqa_get_state(ctx)]
+        E, sp = sb.sbqa_best(ctx)
+        spins = np.where(r[-1][0].T >= 0, 1, -1).astype(np.int8)[:5]
+        out[mode] = (r, E, sp, sb.sbqa_energy(ctx, spins), spins)
+        sb.sbqa_destroy(ctx)
+    (ra, Ea, sa, ea, spins), (rb, Eb, sbest, eb, _) = out[sb.REORDER_OFF], out[sb.REORDER_ON]
+    for u, v in zip(ra, rb):
+        for a, b in zip(u if isinstance(u, tuple) else (u,), v if isinstance(v, tuple) else (v,)):
+            assert np.array_equal(a, b)
+    eo = orc.energy(spins, csr=csr, h=h, tri=T, K=K)
+    if case == "hubo_int":
+        assert np.array_equal(Ea, Eb) and np.array_equal(sa, sbest)
+        assert np.array_equal(ea, eo) and np.array_equal(eb, eo)
+    else:
+        np.testing.assert_allclose(Eb, Ea, rtol=1e-12, atol=1e-12)
+        assert np.array_equal(sa, sbest)
+        np.testing.assert_allclose(ea, eo, rtol=1e-12)
+        np.testing.assert_allclose(eb, eo, rtol=1e-12)
+    # the served result of a relabelled instance equals the standalone one
+    if case == "hubo_int":
+        srv = sb.sbqa_server_create(1 << 28, 2)
+        t = sb.sbqa_submit(srv, csr=csr, h=h, R=R, runs=runs, steps=S, seed=7, jp_kind=sb.JP_LINEAR, jp_start=0.5,
+                           jp_end=0.0, energy_every=15, reorder=sb.REORDER_ON, tri=T, K=K)
+        import time
+        t0 = time.time()
+        res = None
+        while res is None and time.time() - t0 < 60:
+            res = sb.sbqa_poll(srv, t)
+            time.sleep(0.005)
+        assert res is not None
+        assert np.array_equal(res[0], Eb) and np.array_equal(res[1], sbest)
+        sb.sbqa_server_destroy(srv)
