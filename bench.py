@@ -165,6 +165,15 @@ def resident_ops_per_step(w):
     return 1.0 * nnz * C + 13.0 * N * C
 
 
+def dense_kernel_name(info):
+    """The dense step kernel the library launches: bit-packed +-1 J at the
+    128-column tile runs as the split-K kernel when both K halves fill the
+    prefetch pipeline (spins padded to a multiple of 512, of 1024 for that)."""
+    Np = -(-info["N"] // 512) * 512
+    split = info["path"] in ("dense_fp8_packed", "dense_fp4_packed") and info["tile_cols"] == 128 and Np % 1024 == 0
+    return "k_dense_step_sk" if split else "k_dense_step"
+
+
 def algorithmic_flops(w):
     N, C = w["N"], w["R"] * w["runs"]
     return 2.0 * N * N * C
@@ -541,7 +550,7 @@ def main():
             unit = "TOP/s" if info["path"] == "dense_int8" else "TFLOP/s"
             out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": unit,
                                "frac": fl / avg_s / 1e12 / peak,
-                               "traffic": measured_traffic(a.workload, info["path"]), "kernel": "k_dense_step",
+                               "traffic": measured_traffic(a.workload, info["path"]), "kernel": dense_kernel_name(info),
                                "avg_step_us": avg_s * 1e6, "algorithmic_flops_per_step": fl}
     sb.sbqa_destroy(ctx)
     if a.workload == "sparse6" and not a.no_serve:

@@ -364,19 +364,21 @@ __device__ __forceinline__ void update_store(const DenseStepArgs &a, int c, int 
 // through LDS (lds: at least 4 waves x 16 x (DENSE_TN + 4) floats) so that a
 // lane holds 4 consecutive spins of one replica column (f32 MFMA results:
 // register r of a lane is row 4*(lane/16) + r, column lane%16); then load
-// every input of the lane's items before the first store.
+// every input of the lane's items before the first store. wq: the wave's
+// index among the 4 waves of the tile's columns (default: its workgroup
+// index); the transpose buffer is indexed by the workgroup wave index.
 template <int PATH, int MBW, int EPI>
 __device__ __forceinline__ void dense_epilogue(const DenseStepArgs &a, f4 (&acc)[MBW][DENSE_TN / 16], int nt, int mchunk,
-                                               uint8_t *lds) {
+                                               uint8_t *lds, int wq = -1) {
     constexpr int RBT = DENSE_TN / 16;
     constexpr int TS = DENSE_TN + 4;
     constexpr bool JPK = path_packed(Path(PATH));
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wt = threadIdx.x >> 6, w = wq < 0 ? wt : wq;
     const int n0 = nt * DENSE_TN;
     const int mb0 = (mchunk * 4 + w) * MBW;
     const int nkc = a.nkc;
     __syncthreads();
-    float *T = reinterpret_cast<float *>(lds) + w * 16 * TS;
+    float *T = reinterpret_cast<float *>(lds) + wt * 16 * TS;
     const int g = lane >> 4, r16 = lane & 15;
     constexpr int QPR = DENSE_TN / 4;         // spin quads per row
     constexpr int ITEMS = 16 * QPR / 64;      // (row, quad) items per lane and m-block
@@ -596,6 +598,133 @@ __global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArg
     dense_step_body<PATH, MBW, EPI>(a, blockIdx.x, blockIdx.y);
 }
 
+// Split-K step for exact contractions: a 128-spin tile (8 row blocks) x
+// 64*MBW columns, 8 waves; waves 0-3 sum the first half of K and waves 4-7
+// the second, each wave owning MBW m-blocks and all 8 row blocks, so every
+// operand fragment feeds 8 row blocks. The halves are added through LDS
+// (integer-valued sums: the order does not change the result), then wave
+// (h, w) runs the update epilogue of the 64-spin half h.
+template <int PATH, int MBW, int EPI>
+__global__ __launch_bounds__(2 * DENSE_THREADS) void k_dense_step_sk(const DenseStepArgs a) {
+    static_assert(path_packed(Path(PATH)), "split-K kernel: bit-packed exact paths only");
+    constexpr int PD = Pipe<PATH>::depth;
+    constexpr int NT = Terms<PATH>::n;
+    constexpr int RBG = DENSE_TN / 16;            // row blocks per 64-spin J group
+    constexpr int RB = 2 * RBG;                   // row blocks per tile
+    constexpr int SLOT = RB * FRAG_BYTES;         // expanded J of one K chunk
+    constexpr int TS = DENSE_TN + 4;
+    constexpr int TBYTES = 8 * 16 * TS * 4;
+    constexpr int RBYTES = 2 * 4 * MBW * RBG * 64 * 16;
+    constexpr int JB = 4 * SLOT;
+    constexpr int LDS_BYTES = JB > TBYTES ? (JB > RBYTES ? JB : RBYTES) : (TBYTES > RBYTES ? TBYTES : RBYTES);
+    __shared__ __align__(16) uint8_t lds[LDS_BYTES];
+
+    const int nt2 = blockIdx.x, mchunk = blockIdx.y;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, h = wv >> 2, w = wv & 3;
+    const int nkc = a.nkc, nkh = nkc / 2;
+    const int l16 = lane * 16;
+    constexpr int JFRAG = pk_frag_bytes(Path(PATH));
+    using JWord = std::conditional_t<is_fp4<PATH>, uint2, uint32_t>;
+    constexpr int JCH = RBG * JFRAG;
+    constexpr int XCH = MBW * FRAG_BYTES;
+    // this wave stages row blocks 2w and 2w+1 of the tile (J group 2*nt2 + w/2)
+    const int64_t jgrp = (int64_t)(2 * nt2 + (w >> 1)) * nkc * JCH + ((2 * w) & 3) * JFRAG + lane * (int)sizeof(JWord);
+    const int64_t xgrp = (int64_t)(mchunk * 4 + w) * nkc * XCH + l16;
+    const uint8_t *jsrc = a.J + jgrp;
+    const uint8_t *xsrc = a.g + xgrp;
+
+    JWord jw[PD][2];
+    uint4 xr[PD][MBW][2];
+    f4 acc[MBW][RB];
+#pragma unroll
+    for (int i = 0; i < MBW; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) acc[i][j] = f4{0, 0, 0, 0};
+
+    const int rev = a.reverse;
+    auto chunk_at = [&](int j) -> int64_t { const int kc = h * nkh + j; return rev ? nkc - 1 - kc : kc; };
+    auto load_j = [&](int s, int j) {
+        const int64_t o = chunk_at(j) * JCH;
+        jw[s][0] = *reinterpret_cast<const JWord *>(jsrc + o);
+        jw[s][1] = *reinterpret_cast<const JWord *>(jsrc + o + JFRAG);
+    };
+    auto load_x = [&](uint4 (&d)[MBW][2], int j) {
+        const int64_t o = chunk_at(j) * XCH;
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb) {
+            d[mb][0] = ld16(xsrc + o + mb * FRAG_BYTES);
+            d[mb][1] = ld16(xsrc + o + mb * FRAG_BYTES + 1024);
+        }
+    };
+#pragma unroll
+    for (int s = 0; s < PD; ++s) {
+        load_j(s, s);
+        __builtin_amdgcn_sched_barrier(0);
+        load_x(xr[s], s);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll 1
+    for (int j0 = 0; j0 < nkh; j0 += PD) {
+#pragma unroll
+        for (int s = 0; s < PD; ++s) {
+            const int j = j0 + s;
+            const int jn = (j + PD < nkh) ? j + PD : j;
+            uint8_t *slot = lds + (h * 2 + (j & 1)) * SLOT;
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                Frag32 f;
+                if constexpr (is_fp4<PATH>) f = unpack_pm1_fp4(jw[s][e]);
+                else f = unpack_pm1(jw[s][e]);
+                uint8_t *dst = slot + (2 * w + e) * FRAG_BYTES + l16;
+                *reinterpret_cast<uint4 *>(dst) = f.lo;
+                *reinterpret_cast<uint4 *>(dst + 1024) = f.hi;
+            }
+            load_j(s, jn);
+            __syncthreads();
+            Frag32 bjb[2];
+            auto read_j = [&](Frag32 &d, int p) {
+                d.lo = *reinterpret_cast<const uint4 *>(slot + p * FRAG_BYTES + l16);
+                d.hi = *reinterpret_cast<const uint4 *>(slot + p * FRAG_BYTES + 1024 + l16);
+            };
+            read_j(bjb[0], 0);
+#pragma unroll
+            for (int p = 0; p < RB; ++p) {
+                if (p + 1 < RB) read_j(bjb[(p + 1) & 1], p + 1);
+                const Frag32 &bj = bjb[p & 1];
+                static_for<0, NT>([&](auto tc) {
+                    constexpr int T = decltype(tc)::value;
+#pragma unroll
+                    for (int mb = 0; mb < MBW; ++mb) {
+                        const Frag32 ax{xr[s][mb][0], xr[s][mb][1]};
+                        mma_term<PATH, T>(acc[mb][p], ax, bj, ax, bj);
+                    }
+                });
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            load_x(xr[s], jn);
+        }
+    }
+    // add the two K halves: wave (h, w) keeps row blocks [4h, 4h + 4)
+    __syncthreads();
+    f4 *red = reinterpret_cast<f4 *>(lds);
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+        for (int p = 0; p < RBG; ++p)
+            red[(((h * 4 + w) * MBW + mb) * RBG + p) * 64 + lane] = h == 0 ? acc[mb][RBG + p] : acc[mb][p];
+    __syncthreads();
+    f4 mine[MBW][RBG];
+#pragma unroll
+    for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+        for (int p = 0; p < RBG; ++p) {
+            const f4 o = red[((((1 - h) * 4 + w) * MBW + mb) * RBG + p) * 64 + lane];
+            const f4 m = h == 0 ? acc[mb][p] : acc[mb][RBG + p];
+            mine[mb][p] = f4{m[0] + o[0], m[1] + o[1], m[2] + o[2], m[3] + o[3]};
+        }
+    dense_epilogue<PATH, MBW, EPI>(a, mine, 2 * nt2 + h, mchunk, lds, w);
+}
+
 // Grouped step of every dense instance of one serving group (same path and
 // m-blocks per wave): a grid-stride loop over the tiles of all tasks (task q
 // owns virtual blocks [first, first + nblocks), nchunk spin tiles per column
@@ -759,6 +888,14 @@ __global__ __launch_bounds__(256) void k_readout_operand(int N, int Np, int nkc,
 
 template <int PATH, int EPI>
 hipError_t launch_step_mbw(int mbw, dim3 grid, const DenseStepArgs &a, hipStream_t st) {
+    // 128-column tile of a bit-packed path: the split-K form when both K
+    // halves fill the prefetch pipeline (same fields, integer-valued sums)
+    if constexpr (path_packed(Path(PATH))) {
+        if (mbw == 2 && a.nkc % (2 * dense_depth(Path(PATH))) == 0 && grid.x % 2 == 0) {
+            hipLaunchKernelGGL((k_dense_step_sk<PATH, 2, EPI>), dim3(grid.x / 2, grid.y), dim3(2 * DENSE_THREADS), 0, st, a);
+            return hipGetLastError();
+        }
+    }
     switch (mbw) {
         case 1: hipLaunchKernelGGL((k_dense_step<PATH, 1, EPI>), grid, dim3(DENSE_THREADS), 0, st, a); break;
         case 2: hipLaunchKernelGGL((k_dense_step<PATH, 2, EPI>), grid, dim3(DENSE_THREADS), 0, st, a); break;

@@ -77,6 +77,18 @@ def test_committed_traffic_used_only_for_its_source(tmp_path, monkeypatch):
     assert bench.measured_traffic("sparse6_resident", "csr_resident") is None
 
 
+def test_dense_kernel_name():
+    """Bit-packed J at the 128-column tile runs split-K when the padded spin
+    count is a multiple of 1024 (the library's launch rule)."""
+    import bench
+    base = {"N": 16384, "path": "dense_fp4_packed", "tile_cols": 128}
+    assert bench.dense_kernel_name(base) == "k_dense_step_sk"
+    assert bench.dense_kernel_name(dict(base, path="dense_fp8_packed", N=2000)) == "k_dense_step_sk"
+    assert bench.dense_kernel_name(dict(base, N=1500)) == "k_dense_step"       # padded to 1536
+    assert bench.dense_kernel_name(dict(base, tile_cols=256)) == "k_dense_step"
+    assert bench.dense_kernel_name(dict(base, path="dense_int8")) == "k_dense_step"
+
+
 def test_unknown_workload_is_rejected():
     import bench
     with pytest.raises(SystemExit):

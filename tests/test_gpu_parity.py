@@ -285,6 +285,33 @@ def test_dense_tiles_identical(sb, prec, fmode, coup):
             assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("prec,fmode", [("PREC_FP8", 0), ("PREC_FP8", 1), ("PREC_FP4", 0)])
+def test_dense_split_k_identical(sb, orc, prec, fmode):
+    """Bit-packed +-1 J with N = 2000 (K in 16 fp8 / 8 fp4 chunks): the
+    128-column tile runs as the split-K kernel (two K halves added through
+    LDS), the 64- and 256-column tiles in one pass; the integer-valued fields,
+    trajectories, readout energies and best spins agree bit-for-bit, and the
+    energies equal the oracle's."""
+    N, R, runs, S = 2000, 8, 32, 25
+    J = inst.sk_pm1(N, 51)
+    h = inst.gaussian_fields(N, 1.0, 52).round()
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.2, 53)
+    _log("dense split-K %s fmode %d N=%d C=%d" % (prec, fmode, N, R * runs))
+    out = []
+    for tile in (128, 64, 256):
+        ctx = _ctx(sb, J=J, h=h, R=R, runs=runs, steps=S, fmode=fmode, precision=getattr(sb, prec), dense_tile=tile,
+                   loop_kernel=sb.LOOP_STREAM)
+        assert sb.sbqa_info(ctx)["tile_cols"] == tile
+        sb.sbqa_set_state(ctx, X0, Y0)
+        sb.sbqa_step(ctx, S)
+        Eb, sp = sb.sbqa_best(ctx)
+        out.append(sb.sbqa_get_state(ctx) + (sb.sbqa_fields(ctx), Eb, sp))
+    for other in out[1:]:
+        for a, b in zip(out[0], other):
+            assert np.array_equal(a, b)
+    np.testing.assert_array_equal(orc.energy(out[0][-1], J=J, h=h), out[0][-2])
+
+
 def test_fp8_and_fp32_trajectories_identical(sb):
     """J in {-1,+1} with ternary f: fields are exact integers in fp8 and fp4
     (J bit-packed, or as e4m3 bytes / e2m1 nibbles) and fp32, so whole
