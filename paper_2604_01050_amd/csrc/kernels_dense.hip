@@ -603,7 +603,8 @@ __global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArg
 // the second, each wave owning MBW m-blocks and all 8 row blocks, so every
 // operand fragment feeds 8 row blocks. The halves are added through LDS
 // (integer-valued sums: the order does not change the result), then wave
-// (h, w) runs the update epilogue of the 64-spin half h.
+// (h, w) runs the update epilogue of the 64-spin half h. J is staged through
+// LDS two K chunks at a time (four slots per half), one barrier per pair.
 template <int PATH, int MBW, int EPI>
 __global__ __launch_bounds__(2 * DENSE_THREADS) void k_dense_step_sk(const DenseStepArgs a) {
     static_assert(path_packed(Path(PATH)), "split-K kernel: bit-packed exact paths only");
@@ -615,7 +616,8 @@ __global__ __launch_bounds__(2 * DENSE_THREADS) void k_dense_step_sk(const Dense
     constexpr int TS = DENSE_TN + 4;
     constexpr int TBYTES = 8 * 16 * TS * 4;
     constexpr int RBYTES = 2 * 4 * MBW * RBG * 64 * 16;
-    constexpr int JB = 4 * SLOT;
+    constexpr int JB = 8 * SLOT;                  // 4 slots per K half: one barrier per 2 chunks
+    static_assert(PD % 2 == 0, "chunks are staged in pairs");
     constexpr int LDS_BYTES = JB > TBYTES ? (JB > RBYTES ? JB : RBYTES) : (TBYTES > RBYTES ? TBYTES : RBYTES);
     __shared__ __align__(16) uint8_t lds[LDS_BYTES];
 
@@ -669,18 +671,27 @@ __global__ __launch_bounds__(2 * DENSE_THREADS) void k_dense_step_sk(const Dense
         for (int s = 0; s < PD; ++s) {
             const int j = j0 + s;
             const int jn = (j + PD < nkh) ? j + PD : j;
-            uint8_t *slot = lds + (h * 2 + (j & 1)) * SLOT;
+            uint8_t *slot = lds + (h * 4 + (j & 3)) * SLOT;
+            // chunks j and j + 1 are staged together (slots j % 4 and
+            // (j + 1) % 4 were last read for chunks j - 4 and j - 3, which
+            // every wave finished before the barrier of chunk pair j - 2)
+            if (s % 2 == 0) {
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                Frag32 f;
-                if constexpr (is_fp4<PATH>) f = unpack_pm1_fp4(jw[s][e]);
-                else f = unpack_pm1(jw[s][e]);
-                uint8_t *dst = slot + (2 * w + e) * FRAG_BYTES + l16;
-                *reinterpret_cast<uint4 *>(dst) = f.lo;
-                *reinterpret_cast<uint4 *>(dst + 1024) = f.hi;
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int e = 0; e < 2; ++e) {
+                        Frag32 f;
+                        if constexpr (is_fp4<PATH>) f = unpack_pm1_fp4(jw[s + q][e]);
+                        else f = unpack_pm1(jw[s + q][e]);
+                        uint8_t *dst = lds + (h * 4 + ((j + q) & 3)) * SLOT + (2 * w + e) * FRAG_BYTES + l16;
+                        *reinterpret_cast<uint4 *>(dst) = f.lo;
+                        *reinterpret_cast<uint4 *>(dst + 1024) = f.hi;
+                    }
+                const int jn1 = (j + 1 + PD < nkh) ? j + 1 + PD : j + 1;
+                load_j(s, jn);
+                load_j(s + 1, jn1);
+                __syncthreads();
             }
-            load_j(s, jn);
-            __syncthreads();
             Frag32 bjb[2];
             auto read_j = [&](Frag32 &d, int p) {
                 d.lo = *reinterpret_cast<const uint4 *>(slot + p * FRAG_BYTES + l16);
