@@ -149,7 +149,7 @@ def algorithmic_bytes(w, info):
 # VALU peak of MI355X in fp32 lane operations: 256 CUs x 4 SIMDs x 16 lanes x
 # 2.4 GHz = 39.3 Tops/s, one operation per lane per cycle (the 157.3 TFLOP/s
 # fp32 vector figure counts an FMA as two flops and needs packed fp32, which
-# this build does not emit).
+# the library is compiled without).
 PEAK_VALU_OPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
