@@ -167,10 +167,12 @@ def resident_ops_per_step(w):
 
 def dense_kernel_name(info):
     """The dense step kernel the library launches: bit-packed +-1 J at the
-    128-column tile runs as the split-K kernel when both K halves fill the
-    prefetch pipeline (spins padded to a multiple of 512, of 1024 for that)."""
+    128-column tile runs as the split-K kernel when the K chunks (128 spins
+    each in fp8, 256 in fp4; spins padded to a multiple of 512) split into
+    two halves of an even count."""
     Np = -(-info["N"] // 512) * 512
-    split = info["path"] in ("dense_fp8_packed", "dense_fp4_packed") and info["tile_cols"] == 128 and Np % 1024 == 0
+    nkc = {"dense_fp8_packed": Np // 128, "dense_fp4_packed": Np // 256}.get(info["path"], 1)
+    split = info["path"] in ("dense_fp8_packed", "dense_fp4_packed") and info["tile_cols"] == 128 and nkc % 4 == 0
     return "k_dense_step_sk" if split else "k_dense_step"
 
 

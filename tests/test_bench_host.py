@@ -78,13 +78,14 @@ def test_committed_traffic_used_only_for_its_source(tmp_path, monkeypatch):
 
 
 def test_dense_kernel_name():
-    """Bit-packed J at the 128-column tile runs split-K when the padded spin
-    count is a multiple of 1024 (the library's launch rule)."""
+    """Bit-packed J at the 128-column tile runs split-K when the K chunks
+    split into two even halves (the library's launch rule)."""
     import bench
     base = {"N": 16384, "path": "dense_fp4_packed", "tile_cols": 128}
     assert bench.dense_kernel_name(base) == "k_dense_step_sk"
     assert bench.dense_kernel_name(dict(base, path="dense_fp8_packed", N=2000)) == "k_dense_step_sk"
-    assert bench.dense_kernel_name(dict(base, N=1500)) == "k_dense_step"       # padded to 1536
+    assert bench.dense_kernel_name(dict(base, N=1500)) == "k_dense_step"       # fp4: 6 chunks of 256
+    assert bench.dense_kernel_name(dict(base, path="dense_fp8_packed", N=300)) == "k_dense_step_sk"   # 4 of 128
     assert bench.dense_kernel_name(dict(base, tile_cols=256)) == "k_dense_step"
     assert bench.dense_kernel_name(dict(base, path="dense_int8")) == "k_dense_step"
 
