@@ -234,9 +234,10 @@ def copy_calibration():
     print("copy calibration: 3 x copy of %d bytes" % (a.numel() * 4), flush=True)
 
 
-def cpu_baseline(w, target_s=15.0):
+def cpu_baseline(w, target_s=15.0, single_s=4.0):
     """The FP64 oracle on the host cores over the first steps of the same
-    workload: inputs from the shared generators, c0 and J_perp from the oracle."""
+    workload: inputs from the shared generators, c0 and J_perp from the oracle;
+    then a shorter window on one thread."""
     import oracle
     import sbqa_instances as inst
     oracle.build()
@@ -252,8 +253,20 @@ def cpu_baseline(w, target_s=15.0):
         X, Y = P.step(X, Y, oracle.pump(n, S), oracle.delta32(0.7, n, S), np.full(runs, jt[n]))
         n += 1
     dt = time.perf_counter() - t0
-    return {"value": N * R * runs * n / dt, "unit": "replica-spin updates/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "sample": "first %d of %d steps of the same workload (FP64 C oracle, OpenMP)" % (n, S)}
+    cores = oracle.num_threads()
+    # one thread, continuing from the state reached
+    oracle.set_threads(1)
+    t1, n1 = time.perf_counter(), 0
+    while n + n1 < S and (time.perf_counter() - t1) < single_s:
+        X, Y = P.step(X, Y, oracle.pump(n + n1, S), oracle.delta32(0.7, n + n1, S), np.full(runs, jt[n + n1]))
+        n1 += 1
+    d1 = time.perf_counter() - t1
+    oracle.set_threads(cores)
+    out = {"value": N * R * runs * n / dt, "unit": "replica-spin updates/s", "cores": cores,
+           "kind": "oracle", "sample": "first %d of %d steps of the same workload (FP64 C oracle, OpenMP)" % (n, S)}
+    if n1:
+        out["single_thread"] = {"value": N * R * runs * n1 / d1, "sample": "the next %d steps on one thread" % n1}
+    return out
 
 
 # ------------------------------------------------------------------ serving
