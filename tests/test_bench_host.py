@@ -90,6 +90,19 @@ def test_dense_kernel_name():
     assert bench.dense_kernel_name(dict(base, path="dense_int8")) == "k_dense_step"
 
 
+def test_dense_traffic_summaries_name_the_launched_kernel():
+    """The committed counter summaries of the SK N = 16384 packed-J workloads
+    (taken at the 128-column tile) name the kernel the launch rule selects."""
+    import bench
+    for workload, path in (("sk_fp8", "dense_fp8_packed"), ("sk_fp4", "dense_fp4_packed")):
+        kv = {}
+        for line in open(os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)):
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+        assert kv["kernel"] == bench.dense_kernel_name({"N": 16384, "path": path, "tile_cols": 128})
+
+
 def test_unknown_workload_is_rejected():
     import bench
     with pytest.raises(SystemExit):
