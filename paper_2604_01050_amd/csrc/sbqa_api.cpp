@@ -197,9 +197,12 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
         const int32_t *rp = J->row_ptr, *cl = J->col;
         const double *vl = J->val;
         if (J->nnz < 0 || rp[0] != 0 || (int64_t)rp[N] != J->nnz) return fail(SBQA_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] == nnz");
+        // pass 0: every row's range lies inside [0, nnz] before col or val is read
+        for (int32_t i = 0; i < N; ++i)
+            if (rp[i + 1] < rp[i] || (int64_t)rp[i + 1] > J->nnz)
+                return fail(SBQA_EINVAL, "row_ptr must be non-decreasing within [0, nnz] (row %d)", i);
         // pass 1: structure of every row (so pass 2 may search any row)
         for (int32_t i = 0; i < N; ++i) {
-            if (rp[i + 1] < rp[i]) return fail(SBQA_EINVAL, "row_ptr decreases at row %d", i);
             for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
                 if (cl[p] < 0 || cl[p] >= N) return fail(SBQA_EINVAL, "col[%d] = %d out of range", p, cl[p]);
                 if (p > rp[i] && cl[p] <= cl[p - 1]) return fail(SBQA_EINVAL, "columns of row %d not strictly ascending", i);

@@ -101,6 +101,13 @@ def test_validation_errors(abi):
     c3[0], c3[1] = c3[1], c3[0]
     _expect(abi, abi.EINVAL, csr=(rp, c3, val), R=2, runs=2)
     _expect(abi, abi.EINVAL, csr=(rp, col, val), R=2, runs=2, precision=abi.PREC_BF16X3)
+    # an interior row_ptr entry past nnz (later entries decrease again): rejected before
+    # any col or val entry outside the caller's nnz-long arrays is read
+    bad_rp = np.array([0, 100, 5], dtype=np.int32)
+    assert "row_ptr" in _expect(abi, abi.EINVAL, csr=(bad_rp, np.array([1, 1, 1, 0, 0], dtype=np.int32),
+                                                      np.ones(5)), R=2, runs=2)
+    assert "row_ptr" in _expect(abi, abi.EINVAL, csr=(np.array([0, -2, 2], dtype=np.int32),
+                                                      np.array([1, 0], dtype=np.int32), np.ones(2)), R=2, runs=2)
     # three-body terms: CSR only, indices in range and distinct, finite weights
     T = np.array([[0, 1, 2], [3, 4, 5]])
     Kw = np.array([1.0, -2.0])

@@ -547,3 +547,77 @@ def test_heavy_hex_generator():
     for a, b, c in T:
         links = sum((min(u, v), max(u, v)) in es for u, v in ((a, b), (b, c), (a, c)))
         assert links == 2                                # a path l - m - n
+
+
+# ------------------------------------------- checkers used by the GPU tests
+@pytest.mark.parametrize("kind", ["dense", "csr", "csr3"])
+@pytest.mark.parametrize("fmode", [0, 1, 2])
+def test_step_rows_equals_full_step(orc, kind, fmode):
+    """The row-sampled step (the checker of every full-size GPU test) is the
+    full step of Eqs. 6-7 restricted to the given rows, bit for bit: fields,
+    positions and momenta. With three-body terms (Eq. 11) this pins its
+    per-row three-body sum against the whole-list sum, which the single-flip
+    identity above pins against the energy."""
+    N, R, runs = 37, 4, 3
+    rng = np.random.default_rng(101 + fmode)
+    tri = K = None
+    if kind == "dense":
+        J, csr = inst.dense_gaussian(N, 102), None
+    else:
+        P2, w2, T, Kt, _ = inst.random_hubo(N, 60, 45, 103)
+        csr = _hubo_csr(N, P2, w2)
+        J = None
+        if kind == "csr3":
+            tri, K = T, Kt + 0.5 * inst.gaussian_fields(len(Kt), 1.0, 104)
+    h = inst.gaussian_fields(N, 0.3, 105)
+    P = orc.Problem(N, R, runs, J=J, csr=csr, h=h, dt=0.5, c0=0.21, fmode=fmode, tri=tri, K=K)
+    X, Y = inst.uniform_state(N, R * runs, 0.6, 106)
+    jr = np.array([0.11, 0.37, 0.02])
+    an, dn = 0.43, np.float32(0.29)
+    Xf, Yf, Pf = P.step(X, Y, an, dn, jr, want_phi=True)
+    for rows in (np.arange(N), rng.permutation(N)[:9], np.array([N - 1, 0, 5, 5])):
+        Xo, Yo, Po = P.step_rows(X, Y, an, dn, jr, rows)
+        assert np.array_equal(Po, Pf[rows]), (kind, fmode)
+        assert np.array_equal(Xo, Xf[rows]) and np.array_equal(Yo, Yf[rows]), (kind, fmode)
+
+
+def test_jperp_paper_table_closed_form_values(orc):
+    """Eq. 5 / Eq. S12 tabulated per step: entry n is J_perp at s = n/S with
+    Gamma_x(t) = Gamma_x(0)[(1 - s)^alpha + 1e-5]. Values of
+    (1/(2 beta)) ln coth(beta Gamma_x / R) worked out independently to ten
+    digits, at s = 0 and 0.5 (table entries 0 and S/2) and s = 1 (the end of
+    the anneal, one step past the table)."""
+    S = 1000
+    cases = [  # beta, alpha, Gamma_x(0), R, values at s = 0, 0.5, 1
+        (1.0, 1.0, 1.0, 1, (0.1361679773, 0.3859599074, 5.7564627325)),
+        (0.5, 0.5, 1.0, 16, (3.4660513560, 3.8124580975, 14.9786613678)),
+        (1.5, 1.0, 1.0, 32, (1.0203309520, 1.2511936883, 4.8577320866)),
+    ]
+    for beta, alpha, g0, R, want in cases:
+        tab = orc.jperp_paper_table(beta, alpha, g0 / R, S)
+        assert tab[0] == pytest.approx(want[0], rel=2e-10, abs=0)
+        assert tab[S // 2] == pytest.approx(want[1], rel=2e-10, abs=0)
+        end = orc.jperp(beta, orc.gamma_x(g0 / R, alpha, 1.0))
+        assert end == pytest.approx(want[2], rel=2e-10, abs=0)
+        assert tab[-1] < end
+
+
+def test_fields_dense_exact_and_equal_to_csr(orc):
+    """The dense coupling sum Phi = J G of Eq. 7 for integer J and an operand
+    in {-1, 0, +1}: every sum is an exact integer, so it must equal the exact
+    int64 product bit for bit (J deliberately asymmetric, so a transposed
+    operand fails), and the CSR form of the same J."""
+    N, C = 45, 13
+    rng = np.random.default_rng(111)
+    J = rng.integers(-5, 6, size=(N, N)).astype(float)
+    np.fill_diagonal(J, 0.0)
+    G = rng.integers(-1, 2, size=(N, C)).astype(float)
+    want = (J.astype(np.int64) @ G.astype(np.int64)).astype(float)
+    Phi = orc.fields(G, J=J)
+    assert np.array_equal(Phi, want)
+    nz = np.nonzero(J)
+    rp = np.concatenate([[0], np.cumsum(np.bincount(nz[0], minlength=N))]).astype(np.int32)
+    assert np.array_equal(orc.fields(G, csr=(rp, nz[1].astype(np.int32), J[nz])), want)
+    # one hand-sized case: row 0 of [[0, 2], [-3, 0]] . [[1, -1], [0, 1]]
+    assert np.array_equal(orc.fields(np.array([[1.0, -1.0], [0.0, 1.0]]), J=np.array([[0.0, 2.0], [-3.0, 0.0]])),
+                          [[0.0, 2.0], [-3.0, 3.0]])
