@@ -8,6 +8,8 @@
 //     earlier evaluations kept on equal energy.
 #include "sbqa_internal.h"
 
+#include <algorithm>
+
 namespace sbqa {
 namespace {
 
@@ -37,7 +39,7 @@ __device__ __forceinline__ float uniform_sym(uint32_t bits, double amp) {
     return (float)(amp * (2.0 * u - 1.0));
 }
 
-__global__ void k_init_state(int N, int C, int ld, int spin_major, uint32_t key_lo, uint32_t key_hi,
+__global__ void k_init_state(int N, int C, int order, int ld, uint32_t key_lo, uint32_t key_hi,
                              double amp, const int32_t *__restrict__ orig, float *__restrict__ x,
                              float *__restrict__ y) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -47,9 +49,17 @@ __global__ void k_init_state(int N, int C, int ld, int spin_major, uint32_t key_
     // the spins are relabelled internally)
     const uint32_t si = orig ? (uint32_t)orig[i] : (uint32_t)i;
     const uint4 r = philox4x32_10(make_uint4(si, (uint32_t)c, 0u, 0u), make_uint2(key_lo, key_hi));
-    const int64_t o = spin_major ? (int64_t)i * ld + c : (int64_t)c * ld + i;
+    const int64_t o = state_off(order, ld, i, c);
     x[o] = uniform_sym(r.x, amp);
     y[o] = uniform_sym(r.y, amp);
+}
+
+__global__ void k_state_reorder(int N, int C, int order_in, int ld_in, const float *__restrict__ src,
+                                int order_out, int ld_out, float *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * C) return;
+    const int i = (int)(e / C), c = (int)(e % C);
+    dst[state_off(order_out, ld_out, i, c)] = src[state_off(order_in, ld_in, i, c)];
 }
 
 __global__ void k_readout_f64(int N, int Np, int C, int ld, int spin_major, const float *__restrict__ x,
@@ -138,9 +148,10 @@ __device__ __forceinline__ double tri_psi(const Tri3 &t3, int i, SpinOf spin) {
     return psi;
 }
 
-// CSR energies of the readout of a spin-major state. Stage 1: block (row
-// block rb, 256 columns) accumulates per column over its rows in row order.
-__global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int Cs, int C, int rows_per_blk,
+// CSR energies of the readout of a state (element (i, c) at
+// state_off(order, ld, i, c)). Stage 1: block (row block rb, 256 columns)
+// accumulates per column over its rows in row order.
+__global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int order, int ld, int C, int rows_per_blk,
                                                             const int32_t *__restrict__ row_ptr,
                                                             const int32_t *__restrict__ col,
                                                             const double *__restrict__ val, const Tri3 t3,
@@ -151,15 +162,15 @@ __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int Cs, int C
     const int rb = blockIdx.y;
     if (c >= C) return;
     double q = 0.0, l = 0.0, q3 = 0.0;
-    auto spin = [&](int j) { return x[(int64_t)j * Cs + c] >= 0.0f ? 1.0 : -1.0; };
+    auto spin = [&](int j) { return x[state_off(order, ld, j, c)] >= 0.0f ? 1.0 : -1.0; };
     const int i0 = rb * rows_per_blk, i1 = min(N, i0 + rows_per_blk);
     for (int i = i0; i < i1; ++i) {
         double phi = 0.0;
         for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
-            const float xv = x[(int64_t)col[p] * Cs + c];
+            const float xv = x[state_off(order, ld, col[p], c)];
             phi += val[p] * (xv >= 0.0f ? 1.0 : -1.0);
         }
-        const double s = x[(int64_t)i * Cs + c] >= 0.0f ? 1.0 : -1.0;
+        const double s = x[state_off(order, ld, i, c)] >= 0.0f ? 1.0 : -1.0;
         q += s * phi;
         if (h) l += h[i] * s;
         if (t3.ptr) q3 += s * tri_psi(t3, i, spin);
@@ -196,6 +207,133 @@ __global__ __launch_bounds__(256) void k_csr_energy_final(int C, int nrb, const 
     if (t == 0) E[c] = -0.5 * sq[0] - sl[0] - s3[0] / 3.0;
 }
 
+// CSR energies of the readout of a column-block state (ORDER_COLBLOCK8, no
+// three-body terms), one workgroup per block of 8 columns. The sums are those
+// of k_csr_energy_partial + k_csr_energy_final, in the same order: per column,
+// row blocks of rpb rows summed in row order (neighbours in CSR order), row
+// block rb added by thread rb % 256 in increasing rb, then the same LDS tree;
+// so the energies equal those of a spin-major context bit for bit. The block's
+// signs go to LDS once as sign-bit masks (0 or 0x80000000 per row and column,
+// sign(0) = +1): a term s_j J_ij, or s_i phi_i, is its float64 operand with
+// the high word xor-ed by the mask, exactly the product by +-1. Thread rb reads
+// its row block's couplings as one contiguous, 16-byte aligned run
+// ([nrb][RS][D] column indices and float64 weights, RS = rpb rounded up to 8,
+// padding index 0 with weight 0: a zero term leaves the sum unchanged;
+// [nrb][RS] fields h, 0 past N), eight rows of loads in flight at once (rows
+// past the block's end are discarded by a select).
+__device__ __forceinline__ double flip_sign(double v, uint32_t mask) {
+    return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int nrb, int rpb, int RS,
+                                                             const int32_t *__restrict__ rcol,
+                                                             const double *__restrict__ rval,
+                                                             const double *__restrict__ rh,
+                                                             const float *__restrict__ x, double *__restrict__ E) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint4 *sm = reinterpret_cast<uint4 *>(smem);   // [N][2]: sign masks of columns 0-3, 4-7
+    const int w = blockIdx.x, t = threadIdx.x;
+    const float *xb = x + (int64_t)w * ld * 8;
+    auto msk = [](float v) { return v < 0.0f ? 0x80000000u : 0u; };
+    // 16 rows per thread in flight (one round trip for N <= 4096)
+    for (int base = 0; base < N; base += 256 * 16) {
+        float4 a[16], b[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = min(base + u * 256 + t, N - 1);
+            a[u] = *reinterpret_cast<const float4 *>(xb + (int64_t)i * 8);
+            b[u] = *reinterpret_cast<const float4 *>(xb + (int64_t)i * 8 + 4);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = base + u * 256 + t;
+            if (i < N) {
+                sm[2 * i] = make_uint4(msk(a[u].x), msk(a[u].y), msk(a[u].z), msk(a[u].w));
+                sm[2 * i + 1] = make_uint4(msk(b[u].x), msk(b[u].y), msk(b[u].z), msk(b[u].w));
+            }
+        }
+    }
+    __syncthreads();
+    constexpr int RB = 8;   // rows whose loads are issued together
+    double q[8], l[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q[k] = l[k] = 0.0;
+    for (int rb = t; rb < nrb; rb += 256) {
+        double pq[8], pl[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) pq[k] = pl[k] = 0.0;
+        const int i0 = rb * rpb, nrow = min(N - i0, rpb);
+        const int4 *cb = reinterpret_cast<const int4 *>(rcol + (int64_t)rb * RS * D);
+        const double2 *vb = reinterpret_cast<const double2 *>(rval + (int64_t)rb * RS * D);
+        const double2 *hb = reinterpret_cast<const double2 *>(rh + (int64_t)rb * RS);
+        for (int jb = 0; jb < nrow; jb += RB) {
+            int4 c4[RB * D / 4];
+            double2 v2[RB * D / 2], h2[RB / 2];
+#pragma unroll
+            for (int e = 0; e < RB * D / 4; ++e) c4[e] = cb[jb * D / 4 + e];
+#pragma unroll
+            for (int e = 0; e < RB * D / 2; ++e) v2[e] = vb[jb * D / 2 + e];
+#pragma unroll
+            for (int e = 0; e < RB / 2; ++e) h2[e] = hb[jb / 2 + e];
+            const int *cj = reinterpret_cast<const int *>(c4);
+            const double *vj = reinterpret_cast<const double *>(v2);
+            const double *hv = reinterpret_cast<const double *>(h2);
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const bool valid = jb + r < nrow;
+                double phi[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) phi[k] = 0.0;
+#pragma unroll
+                for (int p = 0; p < D; ++p) {
+                    const int j = cj[r * D + p];
+                    const uint4 m0 = sm[2 * j], m1 = sm[2 * j + 1];
+                    const uint32_t m[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+                    const double v = vj[r * D + p];
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) phi[k] += flip_sign(v, m[k]);
+                }
+                const int i = i0 + min(jb + r, nrow - 1);
+                const uint4 m0 = sm[2 * i], m1 = sm[2 * i + 1];
+                const uint32_t m[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const double nq = pq[k] + flip_sign(phi[k], m[k]), nl = pl[k] + flip_sign(hv[r], m[k]);
+                    pq[k] = valid ? nq : pq[k];
+                    pl[k] = valid ? nl : pl[k];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            q[k] += pq[k];
+            l[k] += pl[k];
+        }
+    }
+    __syncthreads();   // the sign masks are dead: their LDS holds the reduction
+    double *sq = reinterpret_cast<double *>(smem), *sl = sq + 8 * 256;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        sq[k * 256 + t] = q[k];
+        sl[k * 256 + t] = l[k];
+    }
+    __syncthreads();
+    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+        if (t < s2)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                sq[k * 256 + t] += sq[k * 256 + t + s2];
+                sl[k * 256 + t] += sl[k * 256 + t + s2];
+            }
+        __syncthreads();
+    }
+    if (t < 8) {
+        const double s3 = 0.0;   // no three-body terms on this path
+        E[w * 8 + t] = -0.5 * sq[t * 256] - sl[t * 256] - s3 / 3.0;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *__restrict__ row_ptr,
                                                           const int32_t *__restrict__ col,
                                                           const double *__restrict__ val, const Tri3 t3,
@@ -228,63 +366,67 @@ __global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *
     if (t == 0) E[m] = -0.5 * sq[0] - sl[0] - s3[0] / 3.0;
 }
 
-// One wavefront per run: argmin over the run's replicas (tie -> lowest k)
-// reduced across lanes, then the stored best is replaced only when strictly
-// lower and the winner's readout spins are copied. The comparison is kept in
+// One workgroup per run. Its first wavefront takes the argmin over the run's
+// replicas (tie -> lowest k), reduced across lanes; the stored best (or +inf
+// when reset) is replaced only when strictly lower. Then the whole workgroup
+// copies the winner's readout spins (sign(0) = +1). The comparison is kept in
 // vector registers on purpose: a wave-uniform float64 compare feeding a scalar
 // select was observed to be lowered with a stale condition code on gfx950.
-__global__ __launch_bounds__(64) void k_best_select(int R, const double *__restrict__ E, double *__restrict__ best_E,
-                                                    int64_t *__restrict__ best_step, int *__restrict__ sel,
-                                                    int64_t step) {
-    const int r = blockIdx.x, lane = threadIdx.x;
-    double eb = INFINITY;
-    int kb = 0x7FFFFFFF;
-    for (int k = lane; k < R; k += 64) {
-        const double e = E[(int64_t)r * R + k];
-        if (e < eb) { eb = e; kb = k; }
-    }
+__global__ __launch_bounds__(1024) void k_best_update(int N, int R, int order, int ld, const float *__restrict__ x,
+                                                     const double *__restrict__ E, double *__restrict__ best_E,
+                                                     int64_t *__restrict__ best_step,
+                                                     int8_t *__restrict__ best_spins, int64_t step, int reset) {
+    __shared__ int sel;
+    const int r = blockIdx.x, t = threadIdx.x;
+    if (t < 64) {
+        double eb = INFINITY;
+        int kb = 0x7FFFFFFF;
+        for (int k = t; k < R; k += 64) {
+            const double e = E[(int64_t)r * R + k];
+            if (e < eb) { eb = e; kb = k; }
+        }
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const double eo = __shfl_xor(eb, off);
-        const int ko = __shfl_xor(kb, off);
-        const bool take = (eo < eb) || (eo == eb && ko < kb);
-        eb = take ? eo : eb;
-        kb = take ? ko : kb;
-    }
-    const double cur = best_E[r];
-    const int better = (eb < cur) ? 1 : 0;
-    if (lane == 0) {
-        sel[r] = better ? kb : -1;
-        if (better) {
-            best_E[r] = eb;
-            best_step[r] = step;
+        for (int off = 32; off > 0; off >>= 1) {
+            const double eo = __shfl_xor(eb, off);
+            const int ko = __shfl_xor(kb, off);
+            const bool take = (eo < eb) || (eo == eb && ko < kb);
+            eb = take ? eo : eb;
+            kb = take ? ko : kb;
+        }
+        const double cur = reset ? INFINITY : best_E[r];
+        const int better = (eb < cur) ? 1 : 0;
+        if (t == 0) {
+            sel = better ? kb : -1;
+            if (better) {
+                best_E[r] = eb;
+                best_step[r] = step;
+            }
         }
     }
-}
-
-// Copy of the winning replica's readout spins (sign(0) = +1) for the runs
-// whose best improved: block (chunk, run), one spin per thread.
-__global__ __launch_bounds__(256) void k_best_copy(int N, int R, int ld, int spin_major,
-                                                   const float *__restrict__ x, const int *__restrict__ sel,
-                                                   int8_t *__restrict__ best_spins) {
-    const int r = blockIdx.y;
-    const int k = sel[r];
+    __syncthreads();
+    const int k = sel;
     if (k < 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
     const int c = r * R + k;
-    const float v = spin_major ? x[(int64_t)i * ld + c] : x[(int64_t)c * ld + i];
-    best_spins[(int64_t)r * N + i] = v >= 0.0f ? 1 : -1;
+    for (int i = t; i < N; i += 1024) best_spins[(int64_t)r * N + i] = x[state_off(order, ld, i, c)] >= 0.0f ? 1 : -1;
 }
 
 }  // namespace
 
-hipError_t launch_init_state(int N, int C, int ld, bool spin_major, uint64_t seed, double amp, const int32_t *orig,
+hipError_t launch_init_state(int N, int C, int order, int ld, uint64_t seed, double amp, const int32_t *orig,
                              float *x, float *y, hipStream_t st) {
     const int64_t n = (int64_t)N * C;
     dim3 grid((unsigned)((n + 255) / 256)), block(256);
-    hipLaunchKernelGGL(k_init_state, grid, block, 0, st, N, C, ld, spin_major ? 1 : 0, (uint32_t)seed,
-                       (uint32_t)(seed >> 32), amp, orig, x, y);
+    hipLaunchKernelGGL(k_init_state, grid, block, 0, st, N, C, order, ld, (uint32_t)seed, (uint32_t)(seed >> 32), amp,
+                       orig, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_reorder(int N, int C, int order_in, int ld_in, const float *src, int order_out, int ld_out,
+                                float *dst, hipStream_t st) {
+    const int64_t n = (int64_t)N * C;
+    if (n == 0) return hipSuccess;
+    dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_state_reorder, grid, block, 0, st, N, C, order_in, ld_in, src, order_out, ld_out, dst);
     return hipGetLastError();
 }
 
@@ -310,14 +452,41 @@ hipError_t launch_energy_reduce(int N, int Np, int count, int Cp, int splits, co
     return hipGetLastError();
 }
 
-hipError_t launch_csr_energy_state(int N, int Cs, int C, const int32_t *row_ptr, const int32_t *col,
+hipError_t launch_csr_energy_state(int N, int order, int ld, int C, const int32_t *row_ptr, const int32_t *col,
                                    const double *val, const Tri3 &t3, const double *h, const float *x,
                                    double *partial, int nblk_rows, double *E, hipStream_t st) {
     const int rows_per_blk = (N + nblk_rows - 1) / nblk_rows;
     dim3 grid((C + 255) / 256, nblk_rows), block(256);
-    hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, Cs, C, rows_per_blk, row_ptr, col, val, t3, h, x,
-                       partial);
+    hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, order, ld, C, rows_per_blk, row_ptr, col, val, t3,
+                       h, x, partial);
     hipLaunchKernelGGL(k_csr_energy_final, dim3(C), dim3(256), 0, st, C, nblk_rows, partial, E);
+    return hipGetLastError();
+}
+
+int energy_colblock_rows(int rpb) { return (rpb + 7) / 8 * 8; }
+
+hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
+                                      const double *rval, const double *rh, const float *x, double *E,
+                                      hipStream_t st) {
+    const size_t lds = std::max<size_t>((size_t)N * 32, 2 * 8 * 256 * sizeof(double));
+    // even D: a batch of 8 rows is whole 16-byte vectors, and so is every row block's run
+    if (C % 8 || ld < N || (int64_t)nrb * rpb < N || lds > 160 * 1024 || D % 2) return hipErrorInvalidValue;
+    const int RS = energy_colblock_rows(rpb);
+    const dim3 grid(C / 8), block(256);
+    switch (D) {
+#define SBQA_ECB(D_)                                                                                                 \
+    case D_: {                                                                                                       \
+        const void *fn = reinterpret_cast<const void *>(&k_csr_energy_colblock<D_>);                                 \
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+        if (e != hipSuccess) return e;                                                                               \
+        hipLaunchKernelGGL(k_csr_energy_colblock<D_>, grid, block, lds, st, N, ld, nrb, rpb, RS, rcol, rval, rh, x,  \
+                           E);                                                                                       \
+        break;                                                                                                       \
+    }
+        SBQA_ECB(4) SBQA_ECB(6) SBQA_ECB(8) SBQA_ECB(12) SBQA_ECB(16)
+#undef SBQA_ECB
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -333,12 +502,11 @@ hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const floa
     return hipGetLastError();
 }
 
-hipError_t launch_best_update(int N, int R, int runs, int ld, bool spin_major, const float *x, const double *E,
-                              double *best_E, int64_t *best_step, int8_t *best_spins, int *sel, int64_t step,
+hipError_t launch_best_update(int N, int R, int runs, int order, int ld, const float *x, const double *E,
+                              double *best_E, int64_t *best_step, int8_t *best_spins, int64_t step, bool reset,
                               hipStream_t st) {
-    hipLaunchKernelGGL(k_best_select, dim3(runs), dim3(64), 0, st, R, E, best_E, best_step, sel, step);
-    hipLaunchKernelGGL(k_best_copy, dim3((N + 255) / 256, runs), dim3(256), 0, st, N, R, ld, spin_major ? 1 : 0, x,
-                       sel, best_spins);
+    hipLaunchKernelGGL(k_best_update, dim3(runs), dim3(1024), 0, st, N, R, order, ld, x, E, best_E, best_step,
+                       best_spins, step, reset ? 1 : 0);
     return hipGetLastError();
 }
 

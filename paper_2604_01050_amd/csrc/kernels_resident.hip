@@ -1,5 +1,5 @@
 // Register-resident CSR SBQA loop for gfx950: many steps of Eqs. 6-7 per
-// cooperative launch (see the description below).
+// launch (see the description below).
 #include "csr_common.h"
 
 namespace sbqa {
@@ -22,8 +22,12 @@ using namespace csr;
 // reads the neighbouring columns of the two workgroups next to it in the ring
 // (coherent agent-scope accesses and per-workgroup step counters,
 // double-buffered by step parity). Every wait is bounded: on timeout the error word is set and
-// every later wait ends at once, so the grid always drains. The launch is
-// cooperative, so all workgroups are co-resident.
+// every later wait ends at once, so the grid always drains. The host launches
+// the loop only when every workgroup fits on the device at once (occupancy
+// times CUs); there is no grid-wide barrier, so an ordinary launch suffices.
+// The state and operand are stored column-block-major (ORDER_COLBLOCK8): the
+// 8 columns of a workgroup for all rows are one contiguous run, so its
+// starting loads and final stores are whole-line sequential accesses.
 // ---------------------------------------------------------------------------
 constexpr int RES_COLS = 8;
 constexpr int RES_THREADS = 512;
@@ -129,7 +133,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
     for (int q = 0; q < RPT; ++q) {
         int r = t + q * RES_THREADS;
         asm volatile("" : "+v"(r));
-        op[r] = operand_to_half(*reinterpret_cast<const uint2 *>(a.g + (int64_t)r * a.Cs + c0));
+        op[r] = operand_to_half(*reinterpret_cast<const uint2 *>(a.g + ((int64_t)w * NR + r) * RES_COLS));
 #pragma unroll
         for (int p = 0; p < D; ++p) wv[(q * D + p) * RES_THREADS + t] = a.valpad[(int64_t)p * NR + r];
     }
@@ -145,8 +149,8 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         for (int q = 0; q < RPT; ++q) {
             int r = t + q * RES_THREADS;
             asm volatile("" : "+v"(r));
-            const float *xrow = a.x + (int64_t)r * a.Cs + c0;
-            const float *yrow = a.y + (int64_t)r * a.Cs + c0;
+            const float *xrow = a.x + ((int64_t)w * NR + r) * RES_COLS;
+            const float *yrow = a.y + ((int64_t)w * NR + r) * RES_COLS;
             const float4 x0 = *reinterpret_cast<const float4 *>(xrow);
             const float4 x1 = *reinterpret_cast<const float4 *>(xrow + 4);
             const float4 y0 = *reinterpret_cast<const float4 *>(yrow);
@@ -277,13 +281,13 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
     for (int q = 0; q < RPT; ++q) {
         int r = t + q * RES_THREADS;
         asm volatile("" : "+v"(r));
-        float *xrow = a.x + (int64_t)r * a.Cs + c0;
-        float *yrow = a.y + (int64_t)r * a.Cs + c0;
+        float *xrow = a.x + ((int64_t)w * NR + r) * RES_COLS;
+        float *yrow = a.y + ((int64_t)w * NR + r) * RES_COLS;
         *reinterpret_cast<float4 *>(xrow) = make_float4(xs[q][0], xs[q][1], xs[q][2], xs[q][3]);
         *reinterpret_cast<float4 *>(xrow + 4) = make_float4(xs[q][4], xs[q][5], xs[q][6], xs[q][7]);
         *reinterpret_cast<float4 *>(yrow) = make_float4(ys[q][0], ys[q][1], ys[q][2], ys[q][3]);
         *reinterpret_cast<float4 *>(yrow + 4) = make_float4(ys[q][4], ys[q][5], ys[q][6], ys[q][7]);
-        *reinterpret_cast<uint2 *>(a.g + (int64_t)r * a.Cs + c0) = operand_to_int8(op[r]);
+        *reinterpret_cast<uint2 *>(a.g + ((int64_t)w * NR + r) * RES_COLS) = operand_to_int8(op[r]);
     }
 }
 
@@ -326,7 +330,7 @@ static hipError_t launch_res(const ResidentArgs &a, int nwg, hipStream_t st) {
     if (e != hipSuccess) return e;
     ResidentArgs arg = a;
     void *args[] = {&arg};
-    return hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(RES_THREADS), args, (unsigned)lds, st);
+    return hipLaunchKernel(fn, dim3(nwg), dim3(RES_THREADS), args, (unsigned)lds, st);
 }
 
 template <int RPT>
@@ -343,7 +347,7 @@ static hipError_t launch_res_d(const ResidentArgs &a, int D, int nwg, hipStream_
 
 hipError_t launch_csr_resident(const ResidentArgs &a, int D, hipStream_t st) {
     const int rpt = resident_rpt(a.N);
-    if (a.R % RES_COLS || a.Cs % RES_COLS || rpt < 0 || a.N > 65535) return hipErrorInvalidValue;
+    if (a.R % RES_COLS || rpt < 0 || a.N > 65535) return hipErrorInvalidValue;
     const int nwg = a.nwg;
     switch (rpt) {
         case 1: return launch_res_d<1>(a, D, nwg, st);

@@ -473,7 +473,7 @@ using namespace sbqa;
 
 sbqa_ctx::~sbqa_ctx() {
     for (void *p : allocs) (void)hipFree(p);
-    if (err_host) (void)hipHostFree(err_host);
+    if (rhost) (void)hipHostFree(rhost);
     if (own_stream) (void)hipStreamDestroy(own_stream);
 }
 
@@ -502,12 +502,22 @@ static sbqa_status check_device(int *dev) {
 
 namespace sbqa {
 
+// Elements of one state buffer (x or y) including padding.
+static size_t state_elems(const sbqa_ctx *c) {
+    if (c->order == ORDER_REPLICA_MAJOR) return (size_t)c->L.C * c->ld;
+    if (c->order == ORDER_COLBLOCK8) return (size_t)c->L.C * c->ld;
+    return (size_t)c->N * c->ld;
+}
+
 // Build operand f(X) of the current step from the current state.
 sbqa_status rebuild_operand(sbqa_ctx *c) {
     const float d = delta_at(&c->s, c->step);
     if (c->facts.path == PATH_CSR) {
+        // elementwise over the whole buffer: column-block order has C == Cs
+        // and zero padded rows, whose operand is 0
+        const int rows = c->order == ORDER_COLBLOCK8 ? c->res_rows : c->N;
         if (c->s.fmode != SBQA_F_BALLISTIC)
-            HIP_TRY(launch_csr_operand(c->s.fmode, c->N, c->L.Cs, c->L.C, c->x[c->cur], (int8_t *)c->g[c->cur], d, c->stream));
+            HIP_TRY(launch_csr_operand(c->s.fmode, rows, c->L.Cs, c->L.C, c->x[c->cur], (int8_t *)c->g[c->cur], d, c->stream));
     } else {
         HIP_TRY(launch_dense_operand(c->facts.path, c->s.fmode, c->N, c->L.Np, c->L.C, c->L.nkc, c->L.mbw, c->x[c->cur],
                                      c->g[c->cur], c->g_lo[c->cur], d, c->stream));
@@ -535,10 +545,14 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
     }
     HIP_TRY(dalloc(c, &c->E, (size_t)std::max(C, Cp)));
-    HIP_TRY(dalloc(c, &c->bestE, (size_t)runs));
     HIP_TRY(dalloc(c, &c->bestStep, (size_t)runs));
-    HIP_TRY(dalloc(c, &c->bestSpins, (size_t)runs * N));
-    HIP_TRY(dalloc(c, &c->bestSel, (size_t)runs));
+    c->rbytes = (size_t)8 * runs + 8 + (size_t)runs * N;
+    HIP_TRY(dalloc(c, &c->rdev, c->rbytes));
+    HIP_TRY(hipHostMalloc((void **)&c->rhost, c->rbytes, hipHostMallocDefault));
+    std::memset(c->rhost, 0, c->rbytes);
+    c->bestE = reinterpret_cast<double *>(c->rdev);
+    c->err = reinterpret_cast<int *>(c->rdev + (size_t)8 * runs);
+    c->bestSpins = reinterpret_cast<int8_t *>(c->rdev + (size_t)8 * runs + 8);
 
     const int hrows = std::max(Np, c->resident ? c->res_rows : 0);
     std::vector<float> h32((size_t)hrows, 0.0f);
@@ -608,8 +622,9 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         HIP_TRY(hipMemcpyAsync(c->col, J->col, sizeof(int32_t) * nnz, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(c->val, v32.data(), sizeof(float) * nnz, hipMemcpyHostToDevice, c->stream));
         HIP_TRY(hipMemcpyAsync(c->val64, J->val, sizeof(double) * nnz, hipMemcpyHostToDevice, c->stream));
-        std::vector<int32_t> cp;
+        std::vector<int32_t> cp, rc;
         std::vector<float> vp;
+        std::vector<double> rv, rhv;
         if (c->resident) {
             // padded neighbour lists (CSR order, then index 0 with weight 0),
             // ring exchange buffers
@@ -621,14 +636,30 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
                     cp[(size_t)i * D + q] = J->col[J->row_ptr[i] + q];
                     vp[(size_t)q * NR + i] = (float)J->val[J->row_ptr[i] + q];
                 }
+            // the readout energies' copy: one run per energy row block
+            const int nrb = c->L.csr_nrb, rpb = (N + nrb - 1) / nrb, RS = energy_colblock_rows(rpb);
+            rc.assign((size_t)nrb * RS * D, 0);
+            rv.assign((size_t)nrb * RS * D, 0.0);
+            rhv.assign((size_t)nrb * RS, 0.0);
+            for (int i = 0; i < N; ++i) {
+                const size_t row = (size_t)(i / rpb) * RS + (size_t)(i % rpb);
+                for (int q = 0; q < J->row_ptr[i + 1] - J->row_ptr[i]; ++q) {
+                    rc[row * D + q] = J->col[J->row_ptr[i] + q];
+                    rv[row * D + q] = J->val[J->row_ptr[i] + q];
+                }
+                if (h) rhv[row] = h[i];
+            }
             HIP_TRY(dalloc(c, &c->colpad, cp.size()));
             HIP_TRY(dalloc(c, &c->valpad, vp.size()));
+            HIP_TRY(dalloc(c, &c->rcol, rc.size()));
+            HIP_TRY(dalloc(c, &c->rval, rv.size()));
+            HIP_TRY(dalloc(c, &c->rh, rhv.size()));
+            HIP_TRY(hipMemcpyAsync(c->rcol, rc.data(), sizeof(int32_t) * rc.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->rval, rv.data(), sizeof(double) * rv.size(), hipMemcpyHostToDevice, c->stream));
+            HIP_TRY(hipMemcpyAsync(c->rh, rhv.data(), sizeof(double) * rhv.size(), hipMemcpyHostToDevice, c->stream));
             HIP_TRY(dalloc(c, &c->xpub, (size_t)2 * c->res_nwg * 2 * NR));
             HIP_TRY(dalloc(c, &c->flags, (size_t)c->res_nwg));
             HIP_TRY(dalloc(c, &c->epoch_cnt, (size_t)c->res_nwg));
-            HIP_TRY(dalloc(c, &c->err, 1));
-            HIP_TRY(hipHostMalloc((void **)&c->err_host, sizeof(int), hipHostMallocDefault));
-            *c->err_host = 0;
             HIP_TRY(hipMemcpyAsync(c->colpad, cp.data(), sizeof(int32_t) * cp.size(), hipMemcpyHostToDevice, c->stream));
             HIP_TRY(hipMemcpyAsync(c->valpad, vp.data(), sizeof(float) * vp.size(), hipMemcpyHostToDevice, c->stream));
         }
@@ -730,9 +761,13 @@ sbqa_status ctx_step_once(sbqa_ctx *c) {
 sbqa_status ctx_state_energies(sbqa_ctx *c) {
     const bool sm = c->facts.path == PATH_CSR;
     const double *h64 = c->has_h ? c->h64 : nullptr;
-    if (sm) {
-        HIP_TRY(launch_csr_energy_state(c->N, c->L.Cs, c->L.C, c->rp, c->col, c->val64, c->tri3(), h64, c->x[c->cur], c->csr_partial,
-                                        c->L.csr_nrb, c->E, c->stream));
+    if (sm && c->order == ORDER_COLBLOCK8 && !c->facts.n3) {
+        const int nrb = c->L.csr_nrb, rpb = (c->N + nrb - 1) / nrb;
+        HIP_TRY(launch_csr_energy_colblock(c->N, c->ld, c->L.C, c->res_D, nrb, rpb, c->rcol, c->rval, c->rh,
+                                           c->x[c->cur], c->E, c->stream));
+    } else if (sm) {
+        HIP_TRY(launch_csr_energy_state(c->N, c->order, c->ld, c->L.C, c->rp, c->col, c->val64, c->tri3(), h64, c->x[c->cur],
+                                        c->csr_partial, c->L.csr_nrb, c->E, c->stream));
     } else if (c->facts.path == PATH_FP8 || c->facts.path == PATH_FP8PK || c->facts.path == PATH_I8 ||
                path_fp4(c->facts.path)) {
         // integer J: J s on MFMA is exact, so the energies equal the float64
@@ -755,13 +790,11 @@ sbqa_status ctx_state_energies(sbqa_ctx *c) {
     return SBQA_OK;
 }
 
-sbqa_status ctx_evaluate(sbqa_ctx *c) {
+sbqa_status ctx_evaluate(sbqa_ctx *c, bool reset) {
     sbqa_status st = ctx_state_energies(c);
     if (st != SBQA_OK) return st;
-    const bool sm = c->facts.path == PATH_CSR;
-    const int ld = sm ? c->L.Cs : c->L.Np;
-    HIP_TRY(launch_best_update(c->N, c->R, c->runs, ld, sm, c->x[c->cur], c->E, c->bestE, c->bestStep, c->bestSpins, c->bestSel,
-                               (int64_t)c->step, c->stream));
+    HIP_TRY(launch_best_update(c->N, c->R, c->runs, c->order, c->ld, c->x[c->cur], c->E, c->bestE, c->bestStep,
+                               c->bestSpins, (int64_t)c->step, reset, c->stream));
     c->last_eval_step = c->step;
     return SBQA_OK;
 }
@@ -979,6 +1012,16 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
     }
     if (facts.path != PATH_CSR)
         set_tile(&c->L, s->dense_tile ? s->dense_tile / 64 : tune_dense_mbw(facts.path, c->L.C, c->L.Np, c->stream));
+    if (facts.path != PATH_CSR) {
+        c->order = ORDER_REPLICA_MAJOR;
+        c->ld = c->L.Np;
+    } else if (c->resident) {
+        c->order = ORDER_COLBLOCK8;   // C is a multiple of 8 (R is), so Cs == C
+        c->ld = c->res_rows;
+    } else {
+        c->order = ORDER_SPIN_MAJOR;
+        c->ld = c->L.Cs;
+    }
     st = ctx_upload(c, J, h);
     if (st == SBQA_OK && !c->pnew.empty()) {
         std::vector<int32_t> orig((size_t)N);
@@ -989,9 +1032,8 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
         if (e != hipSuccess) st = fail(SBQA_EDEVICE, "relabelling: %s", hipGetErrorString(e));
     }
     if (st == SBQA_OK) {
-        const bool sm = facts.path == PATH_CSR;
-        hipError_t e = launch_init_state(N, c->L.C, sm ? c->L.Cs : c->L.Np, sm, s->seed, s->init_amp, c->porig, c->x[0],
-                                         c->y, c->stream);
+        hipError_t e = launch_init_state(N, c->L.C, c->order, c->ld, s->seed, s->init_amp, c->porig, c->x[0], c->y,
+                                         c->stream);
         if (e != hipSuccess) st = fail(SBQA_EDEVICE, "init: %s", hipGetErrorString(e));
     }
     if (st == SBQA_OK) st = rebuild_operand(c);
@@ -1028,12 +1070,13 @@ static sbqa_status ctx_step_small(sbqa_ctx *c, uint32_t K) {
     return rebuild_operand(c);
 }
 
-// K steps of the register-resident loop in one cooperative launch.
+// K steps of the register-resident loop in one launch. A wait that timed out
+// sets the error word of the readout block, which every synchronising call
+// copies back and reports.
 static sbqa_status ctx_step_resident(sbqa_ctx *c, uint32_t K) {
     if (c->facts.path != PATH_CSR) return ctx_step_small(c, K);
     ResidentArgs a;
     a.N = c->N;
-    a.Cs = c->L.Cs;
     a.R = c->R;
     a.S = (int)c->s.steps;
     a.n0 = (int)c->step;
@@ -1059,15 +1102,20 @@ static sbqa_status ctx_step_resident(sbqa_ctx *c, uint32_t K) {
     a.epoch = ++c->epoch;
     a.err = c->err;
     HIP_TRY(launch_csr_resident(a, c->res_D, c->stream));
-    HIP_TRY(hipMemcpyAsync(c->err_host, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     c->step += K;
     return SBQA_OK;
 }
 
 sbqa_status ctx_check_async(sbqa_ctx *c) {
-    if (c->err_host && *c->err_host)
+    if (c->rhost && *reinterpret_cast<const int *>(c->rhost + (size_t)8 * c->runs))
         return fail(SBQA_EDEVICE, "resident sparse loop: a ring-neighbour wait timed out; the state is invalid");
     return SBQA_OK;
+}
+
+sbqa_status ctx_sync(sbqa_ctx *c) {
+    HIP_TRY(hipMemcpyAsync(c->rhost + (size_t)8 * c->runs, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return ctx_check_async(c);
 }
 
 sbqa_status ctx_step(sbqa_ctx *c, uint32_t n) {
@@ -1099,31 +1147,28 @@ sbqa_status ctx_step(sbqa_ctx *c, uint32_t n) {
     return SBQA_OK;
 }
 
+// Readout: without energy tracking the best of the current state alone
+// (the previous best discarded on the device, no host round trip); then the
+// readout block (best energies, error word, best spins) in one copy to pinned
+// memory and one synchronisation.
 sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins) {
-    sbqa_status st;
-    if (c->s.energy_every == 0) {
-        st = ctx_reset_best(c);
+    const bool reset = c->s.energy_every == 0;
+    if (reset || c->last_eval_step != (int64_t)c->step) {
+        sbqa_status st = ctx_evaluate(c, reset);
         if (st != SBQA_OK) return st;
     }
-    if (c->last_eval_step != (int64_t)c->step) {
-        st = ctx_evaluate(c);
-        if (st != SBQA_OK) return st;
-    }
-    if (energies) HIP_TRY(hipMemcpyAsync(energies, c->bestE, sizeof(double) * c->runs, hipMemcpyDeviceToHost, c->stream));
-    std::vector<int8_t> rows;
-    if (spins) {
-        int8_t *dst = spins;
-        if (!c->pnew.empty()) {
-            rows.resize((size_t)c->runs * c->N);
-            dst = rows.data();
-        }
-        HIP_TRY(hipMemcpyAsync(dst, c->bestSpins, (size_t)c->runs * c->N, hipMemcpyDeviceToHost, c->stream));
-    }
+    HIP_TRY(hipMemcpyAsync(c->rhost, c->rdev, c->rbytes, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    if (spins && !c->pnew.empty())   // back to the caller's spin order
-        for (int r = 0; r < c->runs; ++r)
-            for (int i = 0; i < c->N; ++i)
-                spins[(size_t)r * c->N + i] = rows[(size_t)r * c->N + c->pnew[(size_t)i]];
+    const double *bE = reinterpret_cast<const double *>(c->rhost);
+    const int8_t *bS = reinterpret_cast<const int8_t *>(c->rhost + (size_t)8 * c->runs + 8);
+    if (energies) std::memcpy(energies, bE, sizeof(double) * c->runs);
+    if (spins) {
+        if (c->pnew.empty()) std::memcpy(spins, bS, (size_t)c->runs * c->N);
+        else   // back to the caller's spin order
+            for (int r = 0; r < c->runs; ++r)
+                for (int i = 0; i < c->N; ++i)
+                    spins[(size_t)r * c->N + i] = bS[(size_t)r * c->N + c->pnew[(size_t)i]];
+    }
     return ctx_check_async(c);
 }
 
@@ -1249,8 +1294,20 @@ sbqa_status sbqa_fields(sbqa_ctx *c, float *phi) {
     std::vector<float> buf;
     if (c->facts.path == PATH_CSR) {
         const int Cs = c->L.Cs;
-        HIP_TRY(launch_csr_fields(c->s.fmode, N, Cs, C, c->rp, c->col, c->val, c->tri3(), c->x[c->cur], (const int8_t *)c->g[c->cur],
-                                  c->phi, c->stream));
+        const float *xs = c->x[c->cur];
+        const int8_t *gs = (const int8_t *)c->g[c->cur];
+        if (c->order == ORDER_COLBLOCK8) {
+            // the fields kernel gathers spin-major rows: a spin-major copy of
+            // the state and its operand in the unused ping-pong halves
+            float *xsm = c->x[1 - c->cur];
+            int8_t *gsm = (int8_t *)c->g[1 - c->cur];
+            HIP_TRY(launch_state_reorder(N, C, c->order, c->ld, xs, ORDER_SPIN_MAJOR, Cs, xsm, c->stream));
+            if (c->s.fmode != SBQA_F_BALLISTIC)
+                HIP_TRY(launch_csr_operand(c->s.fmode, N, Cs, C, xsm, gsm, delta_at(&c->s, c->step), c->stream));
+            xs = xsm;
+            gs = gsm;
+        }
+        HIP_TRY(launch_csr_fields(c->s.fmode, N, Cs, C, c->rp, c->col, c->val, c->tri3(), xs, gs, c->phi, c->stream));
         buf.resize((size_t)N * Cs);
         HIP_TRY(hipMemcpyAsync(buf.data(), c->phi, sizeof(float) * buf.size(), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
@@ -1278,23 +1335,20 @@ sbqa_status sbqa_get_state(sbqa_ctx *c, float *x, float *y) {
     clear_error();
     if (!c) return fail(SBQA_EINVAL, "NULL context");
     const int N = c->N, C = c->L.C;
-    const bool sm = c->facts.path == PATH_CSR;
-    const int ld = sm ? c->L.Cs : c->L.Np;
-    const size_t tot = sm ? (size_t)N * ld : (size_t)C * ld;
+    const size_t tot = state_elems(c);
     std::vector<float> bx(tot), by(tot);
     HIP_TRY(hipMemcpyAsync(bx.data(), c->x[c->cur], sizeof(float) * tot, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipMemcpyAsync(by.data(), c->y, sizeof(float) * tot, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
     {
-        sbqa_status e = ctx_check_async(c);
+        sbqa_status e = ctx_sync(c);
         if (e != SBQA_OK) return e;
     }
     for (int i = 0; i < N; ++i) {
-        const size_t row = c->pnew.empty() ? (size_t)i : (size_t)c->pnew[(size_t)i];   // internal row of spin i
+        const int row = c->pnew.empty() ? i : c->pnew[(size_t)i];   // internal row of spin i
         for (int cc = 0; cc < C; ++cc) {
-            const size_t o = sm ? row * ld + cc : (size_t)cc * ld + i;
-            if (x) x[(size_t)i * C + cc] = bx[o];
-            if (y) y[(size_t)i * C + cc] = by[o];
+            const int64_t o = state_off(c->order, c->ld, row, cc);
+            if (x) x[(size_t)i * C + cc] = bx[(size_t)o];
+            if (y) y[(size_t)i * C + cc] = by[(size_t)o];
         }
     }
     return SBQA_OK;
@@ -1304,19 +1358,17 @@ sbqa_status sbqa_set_state(sbqa_ctx *c, const float *x, const float *y) {
     clear_error();
     if (!c || !x || !y) return fail(SBQA_EINVAL, "NULL argument");
     const int N = c->N, C = c->L.C;
-    const bool sm = c->facts.path == PATH_CSR;
-    const int ld = sm ? c->L.Cs : c->L.Np;
-    const size_t tot = sm ? (size_t)N * ld : (size_t)C * ld;
+    const size_t tot = state_elems(c);
     for (size_t q = 0; q < (size_t)N * C; ++q)
         if (!std::isfinite(x[q]) || !std::isfinite(y[q]) || std::fabs(x[q]) > 1.0f)
             return fail(SBQA_EINVAL, "state must be finite with |x| <= 1 (index %zu)", q);
-    std::vector<float> bx(tot, 0.0f), by(tot, 0.0f);
+    std::vector<float> bx(tot, 0.0f), by(tot, 0.0f);   // padding rows and columns stay zero
     for (int i = 0; i < N; ++i) {
-        const size_t row = c->pnew.empty() ? (size_t)i : (size_t)c->pnew[(size_t)i];   // internal row of spin i
+        const int row = c->pnew.empty() ? i : c->pnew[(size_t)i];   // internal row of spin i
         for (int cc = 0; cc < C; ++cc) {
-            const size_t o = sm ? row * ld + cc : (size_t)cc * ld + i;
-            bx[o] = x[(size_t)i * C + cc];
-            by[o] = y[(size_t)i * C + cc];
+            const int64_t o = state_off(c->order, c->ld, row, cc);
+            bx[(size_t)o] = x[(size_t)i * C + cc];
+            by[(size_t)o] = y[(size_t)i * C + cc];
         }
     }
     HIP_TRY(hipMemcpyAsync(c->x[c->cur], bx.data(), sizeof(float) * tot, hipMemcpyHostToDevice, c->stream));
@@ -1374,8 +1426,7 @@ sbqa_status sbqa_info(sbqa_ctx *c, sbqa_info_t *info) {
 sbqa_status sbqa_sync(sbqa_ctx *c) {
     clear_error();
     if (!c) return fail(SBQA_EINVAL, "NULL context");
-    HIP_TRY(hipStreamSynchronize(c->stream));
-    return ctx_check_async(c);
+    return ctx_sync(c);
 }
 
 void sbqa_destroy(sbqa_ctx *c) {

@@ -55,8 +55,10 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
 sbqa_status ctx_step(sbqa_ctx *c, uint32_t n);
 sbqa_status ctx_step_once(sbqa_ctx *c);
 sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins);
-sbqa_status ctx_check_async(sbqa_ctx *c);  // after a stream synchronisation
-sbqa_status ctx_evaluate(sbqa_ctx *c);     // energies of the current state -> best tracking
+sbqa_status ctx_check_async(sbqa_ctx *c);  // after a readout copy and a stream synchronisation
+sbqa_status ctx_sync(sbqa_ctx *c);         // fetch the error word, synchronise, check it
+// energies of the current state -> best tracking (reset: the previous best is discarded)
+sbqa_status ctx_evaluate(sbqa_ctx *c, bool reset = false);
 
 }  // namespace sbqa
 
@@ -76,7 +78,10 @@ struct sbqa_ctx {
     std::vector<void *> allocs;
     bool has_h = false;
 
-    // state (dense: [C][Np] replica-major; CSR: [N][Cs] spin-major)
+    // state (dense: [C][Np] replica-major; CSR: [N][Cs] spin-major, or
+    // column-block-major [C/8][rows][8] for the register-resident loop);
+    // element (i, c) at state_off(order, ld, i, c)
+    int order = 0, ld = 0;
     float *x[2] = {nullptr, nullptr};
     float *y = nullptr;
     int cur = 0;
@@ -102,10 +107,15 @@ struct sbqa_ctx {
     double *S64 = nullptr, *phis64 = nullptr;
     double *csr_partial = nullptr;
     double *E = nullptr;
-    double *bestE = nullptr;
     int64_t *bestStep = nullptr;
+    // readout block, one device allocation copied to the host in one piece:
+    // best energies [runs] float64, the error word of the resident loop (8
+    // bytes), best spins [runs][N] int8; rhost is its pinned host copy
+    uint8_t *rdev = nullptr, *rhost = nullptr;
+    size_t rbytes = 0;
+    double *bestE = nullptr;
+    int *err = nullptr;                 // ring-neighbour wait timeouts (resident loop)
     int8_t *bestSpins = nullptr;
-    int *bestSel = nullptr;             // [runs] scratch of the best update
 
     // resident loops: register-resident CSR loop (kernels_csr.hip) or the
     // small dense loop (kernels_small.hip)
@@ -116,12 +126,14 @@ struct sbqa_ctx {
     std::vector<int32_t> pnew;          // CSR spins relabelled: row of the caller's spin i (empty: identity)
     int32_t *porig = nullptr;           // [N] the caller's spin index of each row (relabelled only)
     float *valpad = nullptr;            // [D][rows]
+    // readout energies of the resident loop: couplings as one run per energy
+    // row block (launch_csr_energy_colblock)
+    int32_t *rcol = nullptr;            // [nrb][RS][D]
+    double *rval = nullptr, *rh = nullptr;   // [nrb][RS][D], [nrb][RS]
     float *coefA = nullptr;             // [S]
     float *delta_tab = nullptr;         // [S+1]
     float *xpub = nullptr;              // [2][nwg][2][rows] published edge columns
     int *flags = nullptr, *epoch_cnt = nullptr;
-    int *err = nullptr;                 // ring-neighbour wait timeouts
-    int *err_host = nullptr;            // pinned copy of err
     int epoch = 0;
 
     ~sbqa_ctx();

@@ -26,6 +26,20 @@ constexpr int GEMM_BN = 128;
 constexpr int GEMM_KB = 128;
 constexpr int GEMM_THREADS = 256;
 
+// Order of a state buffer (x, y, and the CSR operand) in device memory:
+//   ORDER_SPIN_MAJOR    [rows][ld]: CSR contexts stepped one launch per step;
+//   ORDER_REPLICA_MAJOR [C][ld]:    dense contexts;
+//   ORDER_COLBLOCK8     [C/8][ld][8] (ld = padded rows): CSR contexts of the
+//                       register-resident loop, whose workgroups own 8
+//                       consecutive replica columns for every spin, so that a
+//                       workgroup's state is one contiguous run.
+enum StateOrder : int32_t { ORDER_SPIN_MAJOR = 0, ORDER_REPLICA_MAJOR = 1, ORDER_COLBLOCK8 = 2 };
+__host__ __device__ inline int64_t state_off(int order, int ld, int i, int c) {
+    return order == ORDER_SPIN_MAJOR      ? (int64_t)i * ld + c
+           : order == ORDER_REPLICA_MAJOR ? (int64_t)c * ld + i
+                                          : ((int64_t)(c >> 3) * ld + i) * 8 + (c & 7);
+}
+
 // Per-step scalars of the fused update (Eqs. 6-7), precomputed on the host in
 // float64 and rounded once to float32.
 struct StepCoef {
@@ -175,16 +189,16 @@ hipError_t launch_csr_step(int fmode, int N, int Cs, int R, int runs, const int3
                            int8_t *g_out, const float *jp, int64_t jp_stride, StepCoef k,
                            hipStream_t st);
 
-// Register-resident CSR loop (K steps per cooperative launch); see
-// kernels_csr.hip. Arrays are device pointers; NR = resident_rows(N) rows,
-// rows N..NR-1 are zero padding.
+// Register-resident CSR loop (K steps per launch, every workgroup
+// co-resident); see kernels_resident.hip. Arrays are device pointers;
+// NR = resident_rows(N) rows, rows N..NR-1 are zero padding.
 struct ResidentArgs {
-    int N, Cs, R, S, n0, K, fmode, nwg;
+    int N, R, S, n0, K, fmode, nwg;
     const int32_t *colpad;  // [NR][D] neighbour indices (padding: index 0, weight 0)
     const float *valpad;    // [D][NR] weights, padded with 0
     const float *h;         // [NR]
-    float *x, *y;           // [NR][Cs] state, updated in place
-    int8_t *g;              // [NR][Cs] operand, updated in place
+    float *x, *y;           // ORDER_COLBLOCK8 [nwg][NR][8] state, updated in place
+    int8_t *g;              // ORDER_COLBLOCK8 [nwg][NR][8] operand, updated in place
     const float *jp;        // [runs][S]
     const float *coefA;     // [S]   (a0 - a_n)/R
     const float *delta;     // [S+1] Delta_n
@@ -233,10 +247,14 @@ hipError_t launch_csr_fields(int fmode, int N, int Cs, int C, const int32_t *row
 
 // Counter-based initial state: x, y ~ U[-amp, amp] from Philox4x32-10 keyed by
 // seed, counter (i, c), i the caller's spin index: orig[row] when rows hold
-// relabelled spins, else the row. spin_major selects [N][ld] (CSR) or [C][ld]
-// (dense).
-hipError_t launch_init_state(int N, int C, int ld, bool spin_major, uint64_t seed, double amp, const int32_t *orig,
+// relabelled spins, else the row; element (i, c) at state_off(order, ld, i, c).
+hipError_t launch_init_state(int N, int C, int order, int ld, uint64_t seed, double amp, const int32_t *orig,
                              float *x, float *y, hipStream_t st);
+
+// Copy of an N x C float state from one order to another (rows of dst outside
+// [0, N) are left as they are).
+hipError_t launch_state_reorder(int N, int C, int order_in, int ld_in, const float *src, int order_out, int ld_out,
+                                float *dst, hipStream_t st);
 
 // Readout spins sign(x) (sign(0) = +1) as float64 +-1 into S[Cp][Np]
 // (zero padding) from the state, for the energy GEMM.
@@ -252,11 +270,23 @@ hipError_t launch_energy_reduce(int N, int Np, int count, int Cp, int splits,
                                 const double *phis, const double *S, const double *h,
                                 double *E, hipStream_t st);
 
-// CSR energies of the readout of x ([N][Cs]) or of given spins.
-hipError_t launch_csr_energy_state(int N, int Cs, int C, const int32_t *row_ptr,
+// CSR energies of the readout of x (element (i, c) at state_off(order, ld, i, c))
+// or of given spins.
+hipError_t launch_csr_energy_state(int N, int order, int ld, int C, const int32_t *row_ptr,
                                    const int32_t *col, const double *val, const Tri3 &t3, const double *h,
                                    const float *x, double *partial, int nblk_rows, double *E,
                                    hipStream_t st);
+// The same energies of a column-block state (ORDER_COLBLOCK8 with leading
+// dimension ld >= N, C % 8 == 0, N * 32 bytes of LDS, even D, no three-body
+// terms), equal bit for bit. The couplings of row block rb (rows rb*rpb ..
+// rb*rpb + rpb - 1, the row blocks of the spin-major energies: nrb * rpb >= N)
+// are one run per row block: rcol / rval [nrb][RS][D] (neighbours in CSR
+// order, then index 0 with weight 0), rh [nrb][RS] (h, 0 past N), with
+// RS = energy_colblock_rows(rpb).
+int energy_colblock_rows(int rpb);
+hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
+                                      const double *rval, const double *rh, const float *x, double *E,
+                                      hipStream_t st);
 hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col,
                                    const double *val, const Tri3 &t3, const double *h, const int8_t *spins,
                                    double *E, hipStream_t st);
@@ -271,10 +301,10 @@ hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const floa
                                 hipStream_t st);
 
 // Per-run best over replicas with tie -> lowest k; updates best_E/best_step
-// when strictly lower and copies the winning readout spins. sel: [runs]
-// scratch (the winning replica, or -1).
-hipError_t launch_best_update(int N, int R, int runs, int ld, bool spin_major, const float *x,
-                              const double *E, double *best_E, int64_t *best_step,
-                              int8_t *best_spins, int *sel, int64_t step, hipStream_t st);
+// when strictly lower (than +inf when reset: the previous best is discarded)
+// and copies the winning readout spins; one launch, one workgroup per run.
+hipError_t launch_best_update(int N, int R, int runs, int order, int ld, const float *x, const double *E,
+                              double *best_E, int64_t *best_step, int8_t *best_spins, int64_t step, bool reset,
+                              hipStream_t st);
 
 }  // namespace sbqa

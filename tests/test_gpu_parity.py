@@ -870,6 +870,7 @@ def test_resident_loop_matches_streaming(sb, orc, name, N, d, R, runs, fmode, ee
         assert sb.sbqa_info(ctx)["resident"] == (kern == sb.LOOP_RESIDENT)
         sb.sbqa_step(ctx, 37)
         mid = sb.sbqa_get_state(ctx)
+        phi_mid = sb.sbqa_fields(ctx)
         sb.sbqa_step(ctx, 1)
         one = sb.sbqa_get_state(ctx)
         x, y = one
@@ -878,12 +879,13 @@ def test_resident_loop_matches_streaming(sb, orc, name, N, d, R, runs, fmode, ee
         sb.sbqa_step(ctx, S - 88)
         fin = sb.sbqa_get_state(ctx)
         best = sb.sbqa_best(ctx)
-        out[kern] = (mid, one, fin, best, sb.sbqa_best_step(ctx), sb.sbqa_info(ctx)["c0"])
+        out[kern] = (mid, one, fin, best, sb.sbqa_best_step(ctx), sb.sbqa_info(ctx)["c0"], phi_mid)
     a, b = out[sb.LOOP_STREAM], out[sb.LOOP_RESIDENT]
     for u, v in zip(a[:3], b[:3]):
         assert np.array_equal(u[0], v[0]) and np.array_equal(u[1], v[1])
     assert np.array_equal(a[3][0], b[3][0]) and np.array_equal(a[3][1], b[3][1])
     assert np.array_equal(a[4], b[4])
+    assert np.array_equal(a[6], b[6])      # fields hook from the column-block state
     # one resident step (37 -> 38) against the oracle
     (X, Y), (xg, yg) = b[0], b[1]
     P = orc.Problem(N, R, runs, csr=csr, h=h, dt=0.5, a0=1.0, c0=b[5], fmode=fmode)
