@@ -15,13 +15,17 @@ launch of that kernel, or all K steps are one resident launch); its roofline use
 algorithmic bytes (HBM-bound kernels) or operations (MFMA and VALU-bound
 kernels) per launch computed below.
 
-The default line also carries "serving": a short mixed stream (128 instances,
-Poisson arrivals at 0.8 of the measured service rate) with its p50/p99 solve
-latency, the second half of the metric; --workload serve runs the full
-512-instance stream.
+The default line also carries "configs", the other configurations measured
+on the same GPU in the same run, each with its own step count, step time,
+roofline and readout: SK N = 64 (small resident loop), SK N = 16384 on the fp8
+and fp4 paths (bit-packed J) against the plain fp32 path, Gaussian N = 8192 on
+the split-bf16 path against fp32 with the single-step field error of both
+against the float64 product on sampled rows, and the mixed serving stream of
+512 instances (Poisson arrivals at 0.8 of the measured service rate) with its
+p50/p99 solve latency, the second half of the metric.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
-                       [--no-cpu-baseline] [--no-serve]
+                       [--no-cpu-baseline] [--no-configs] [--no-serve]
 """
 from __future__ import annotations
 
@@ -40,6 +44,16 @@ HBM_PEAK_GBS = 8000.0
 PEAK = {"fp4": 10060.0, "fp8": 5030.0, "int8": 5030.0, "bf16": 2520.0, "fp32": 157.3, "fp64": 78.6}  # T(FL)OP/s dense MFMA
 
 
+_CACHE = {}
+
+
+def _cached(key, fn):
+    """Large generated matrices shared by several workloads of one run."""
+    if key not in _CACHE:
+        _CACHE[key] = fn()
+    return _CACHE[key]
+
+
 def make_workload(name: str):
     import sbqa_instances as inst
     if name == "sparse6":
@@ -53,14 +67,14 @@ def make_workload(name: str):
     if name in ("sk_fp4", "sk_fp4_bytes"):
         N, R, runs, S = 16384, 16, 16, 10000
         packed = name == "sk_fp4"
-        return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP4", fmode=0,
+        return dict(J=_cached("sk16384", lambda: inst.sk_pm1(N, 3001)), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP4", fmode=0,
                     j_packing=None if packed else "JPACK_BYTES",
                     desc="SK N=16384 J=+-1 (%s), R=16 x 16 runs, 10000 steps, ternary f"
                          % ("1 bit per coupling, e2m1 fp4 MFMA" if packed else "e2m1 nibbles"), dtype="fp4")
     if name in ("sk_fp8", "sk_fp8_bytes"):
         N, R, runs, S = 16384, 16, 16, 10000
         packed = name == "sk_fp8"
-        return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP8", fmode=0,
+        return dict(J=_cached("sk16384", lambda: inst.sk_pm1(N, 3001)), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP8", fmode=0,
                     j_packing=None if packed else "JPACK_BYTES",
                     desc="SK N=16384 J=+-1 (%s), R=16 x 16 runs, 10000 steps, ternary f"
                          % ("1 bit per coupling, e4m3 MFMA" if packed else "e4m3 bytes"), dtype="fp8")
@@ -74,16 +88,16 @@ def make_workload(name: str):
                          "10000 steps, ternary f" % ("int8" if i8 else "fp32 path"), dtype="int8" if i8 else "f32")
     if name == "sk_fp32":
         N, R, runs, S = 16384, 16, 16, 10000
-        return dict(J=inst.sk_pm1(N, 3001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32", fmode=0,
+        return dict(J=_cached("sk16384", lambda: inst.sk_pm1(N, 3001)), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32", fmode=0,
                     desc="SK N=16384 J=+-1 (fp32 path), R=16 x 16 runs, 10000 steps, ternary f", dtype="f32")
     if name == "gauss_bf16x3":
         N, R, runs, S = 8192, 16, 32, 5000
-        return dict(J=inst.dense_gaussian(N, 4001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_BF16X3",
+        return dict(J=_cached("gauss8192", lambda: inst.dense_gaussian(N, 4001)), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_BF16X3",
                     fmode=2, desc="dense N=8192 J~N(0,1), ballistic, bf16 hi+lo, R=16 x 32 runs, 5000 steps",
                     dtype="bf16x3")
     if name == "gauss_fp32":
         N, R, runs, S = 8192, 16, 32, 5000
-        return dict(J=inst.dense_gaussian(N, 4001), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32",
+        return dict(J=_cached("gauss8192", lambda: inst.dense_gaussian(N, 4001)), h=None, N=N, R=R, runs=runs, S=S, prec="PREC_FP32",
                     fmode=2, desc="dense N=8192 J~N(0,1), ballistic, fp32, R=16 x 32 runs, 5000 steps",
                     dtype="f32")
     if name in ("cubic88", "square800"):
@@ -433,6 +447,138 @@ def tte_main(a):
     print(json.dumps(out), flush=True)
 
 
+def measure(sb, w, K, warmup, stream, loop_kernel="auto", events=True, workload=None):
+    """One timed solve of workload w: a warmup solve of `warmup` steps, then K
+    steps of a fresh context and the readout, timed on the host clock; the
+    dominant kernel's average launch comes from one HIP event pair around the
+    K steps on the context's stream. Returns the result fields and the
+    context's readout (best energies)."""
+    import torch
+    wctx = create(sb, w, seed=1, loop_kernel=loop_kernel)
+    sb.sbqa_set_stream(wctx, stream)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter()
+    ctx = create(sb, w, seed=2, loop_kernel=loop_kernel)
+    sb.sbqa_set_stream(ctx, stream)
+    info = sb.sbqa_info(ctx)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t_create
+    # warmup: a separate solve, right before the timed one
+    sb.sbqa_step(wctx, min(max(warmup, 1), w["S"]))
+    sb.sbqa_best(wctx)
+    sb.sbqa_destroy(wctx)
+    torch.cuda.synchronize()
+    resident = info["resident"]
+    ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) if events else None
+    t0 = time.perf_counter()
+    if ev:
+        ev[0].record(stream)
+    if resident:
+        sb.sbqa_step(ctx, K)
+    else:
+        for q in range(K):
+            sb.sbqa_step(ctx, 1)
+    if ev:
+        ev[1].record(stream)
+    E, spins = sb.sbqa_best(ctx)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    N, R, runs = w["N"], w["R"], w["runs"]
+    out = {
+        "value": N * R * runs * K / t, "steps": K, "ms_per_step": 1e3 * t / K,
+        "path": info["path"] + ("_resident" if resident else ""),
+        "best_energy": {"mean": float(np.mean(E)), "min": float(np.min(E))},
+        "end_to_end": {"seconds": create_s + t, "create_s": create_s,
+                       "updates_per_s": N * R * runs * K / (create_s + t)},
+    }
+    if ev:
+        launches = 1 if resident else K
+        avg_s = ev[0].elapsed_time(ev[1]) * 1e-3 / launches
+        out["readout_ms"] = 1e3 * t - ev[0].elapsed_time(ev[1])
+        if resident:
+            ops = K * resident_ops_per_step(w)
+            sparse = "csr" in w
+            tr = measured_traffic((workload or "") + "_resident", "csr_resident") if sparse and workload else None
+            out["roofline"] = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": PEAK_VALU_OPS,
+                               "unit": "Tops/s (fp32 VALU lane ops)", "frac": ops / avg_s / 1e12 / PEAK_VALU_OPS,
+                               "traffic": None if tr is None else tr * K,
+                               "kernel": "k_csr_resident" if sparse else "k_dense_small",
+                               "avg_launch_us": avg_s * 1e6, "steps_per_launch": K,
+                               "algorithmic_ops_per_launch": ops}
+        elif info["path"] == "csr_fp32":
+            ab = algorithmic_bytes(w, info)
+            out["roofline"] = {"bound": "hbm", "achieved": ab / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ab / avg_s / 1e9 / HBM_PEAK_GBS,
+                               "traffic": measured_traffic(workload, info["path"]) if workload else None,
+                               "kernel": "k_csr_step", "avg_launch_us": avg_s * 1e6,
+                               "algorithmic_bytes_per_launch": ab}
+        else:
+            fl = algorithmic_flops(w)
+            peak = PEAK[{"dense_fp8": "fp8", "dense_fp8_packed": "fp8", "dense_int8": "int8", "dense_fp4": "fp4",
+                         "dense_fp4_packed": "fp4", "dense_fp32": "fp32",
+                         "dense_bf16x3": "bf16"}[info["path"]]]
+            unit = "TOP/s" if info["path"] == "dense_int8" else "TFLOP/s"
+            out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": unit,
+                               "frac": fl / avg_s / 1e12 / peak,
+                               "traffic": measured_traffic(workload, info["path"]) if workload else None,
+                               "kernel": dense_kernel_name(info), "avg_step_us": avg_s * 1e6,
+                               "algorithmic_flops_per_step": fl}
+    return out, ctx
+
+
+def field_error(sb, ctx, w, rows):
+    """Single-step field error of a dense context against the float64 product
+    J . f(X) on sampled rows (ballistic f: the operand is the float32 state):
+    normwise ||phi - phi64|| / ||phi64|| and the largest element error over
+    the sum of magnitudes of the terms that form it."""
+    x, _ = sb.sbqa_get_state(ctx)
+    phi = sb.sbqa_fields(ctx)[rows].astype(np.float64)
+    J = w["J"][rows]
+    G = x.astype(np.float64)
+    ref = J @ G
+    mag = np.abs(J) @ np.abs(G)
+    err = np.abs(phi - ref)
+    return {"rows": len(rows), "normwise": float(np.linalg.norm(err) / np.linalg.norm(ref)),
+            "max_over_term_magnitude": float(np.max(err / np.maximum(mag, 1e-300)))}
+
+
+def dense_configs(sb, stream, K):
+    """Dense configurations on the same GPU: SK N = 16384 (fp8 and fp4 with
+    bit-packed J against the plain fp32 path) and Gaussian N = 8192 (split
+    bf16 hi+lo against fp32, with the single-step field error of both)."""
+    import torch
+    res = {}
+    sk = {}
+    for name, key in (("sk_fp8", "fp8"), ("sk_fp4", "fp4"), ("sk_fp32", "fp32")):
+        w = make_workload(name)
+        r, ctx = measure(sb, w, K, K, stream, workload=name)
+        sb.sbqa_destroy(ctx)
+        r["workload"] = w["desc"]
+        sk[key] = r
+        print("dense %s: %.3f ms/step" % (name, r["roofline"]["avg_step_us"] / 1e3), file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    for key in ("fp8", "fp4"):
+        sk[key + "_over_fp32"] = sk[key]["value"] / sk["fp32"]["value"]
+    # +-1 couplings with a ternary operand: every field is an exact integer on all three paths,
+    # so their trajectories and best energies agree exactly
+    sk["best_energies_equal"] = sk["fp8"]["best_energy"] == sk["fp32"]["best_energy"] == sk["fp4"]["best_energy"]
+    res["sk_N16384_C256"] = sk
+    g = {}
+    rows = np.random.default_rng(77).choice(8192, 24, replace=False)
+    for name, key in (("gauss_bf16x3", "bf16x3"), ("gauss_fp32", "fp32")):
+        w = make_workload(name)
+        r, ctx = measure(sb, w, K, K, stream, workload=name)
+        r["field_error"] = field_error(sb, ctx, w, rows)
+        sb.sbqa_destroy(ctx)
+        r["workload"] = w["desc"]
+        g[key] = r
+        print("dense %s: %.3f ms/step" % (name, r["roofline"]["avg_step_us"] / 1e3), file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    g["bf16x3_over_fp32"] = g["bf16x3"]["value"] / g["fp32"]["value"]
+    res["gauss_N8192_C512"] = g
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,9 +587,11 @@ def main():
     ap.add_argument("--workload", default="sparse6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true",
-                    help="default workload: skip the short mixed serving stream (p50/p99 solve latency)")
-    ap.add_argument("--serve-quick", type=int, default=128,
-                    help="default workload: instances of the short serving stream reported beside the main line")
+                    help="default workload: skip the mixed serving stream (p50/p99 solve latency)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="default workload: skip the other configurations (dense paths, serving stream)")
+    ap.add_argument("--dense-steps", type=int, default=200,
+                    help="default workload: timed steps of each dense configuration")
     ap.add_argument("--no-events", action="store_true", help="no events in the timed region")
     ap.add_argument("--calibrate", action="store_true", help="also run a copy kernel of known size (counter scaling)")
     ap.add_argument("--dense-tile", type=int, default=0,
@@ -484,100 +632,50 @@ def main():
     if K < 1 or K > w["S"]:
         raise SystemExit("--steps must be in [1, %d] (one solve of the schedule)" % w["S"])
     stream = torch.cuda.Stream()
-
-    # warmup context first (it also takes the process's one-time start-up:
-    # code objects, device queries); then the timed context, whose creation
-    # from host arrays (validation, upload, initial state) the end-to-end wall
-    # time counts; `value` counts the steps and the readout
-    wctx = create(sb, w, seed=1, loop_kernel=a.loop_kernel)
-    sb.sbqa_set_stream(wctx, stream)
-    torch.cuda.synchronize()
-    t_create = time.perf_counter()
-    ctx = create(sb, w, seed=2, loop_kernel=a.loop_kernel)
-    sb.sbqa_set_stream(ctx, stream)
-    info = sb.sbqa_info(ctx)
-    torch.cuda.synchronize()
-    create_s = time.perf_counter() - t_create
-
-    # warmup: a separate solve, right before the timed one
-    sb.sbqa_step(wctx, min(a.warmup, w["S"]))
-    sb.sbqa_best(wctx)
-    sb.sbqa_destroy(wctx)
-    torch.cuda.synchronize()
-    resident = info["resident"]
-    # One event pair on the context stream brackets the K steps (one resident
-    # launch, or K back-to-back launches of one kernel each): the average
-    # launch duration is their elapsed time over the launches, gaps included.
-    ev = None if a.no_events else (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-    t0 = time.perf_counter()
-    if ev:
-        ev[0].record(stream)
-    if resident:
-        sb.sbqa_step(ctx, K)
-    else:
-        for q in range(K):
-            sb.sbqa_step(ctx, 1)
-    if ev:
-        ev[1].record(stream)
-    E, spins = sb.sbqa_best(ctx)
-    torch.cuda.synchronize()
-    t_end = time.perf_counter()
-    t = t_end - t0
+    r, ctx = measure(sb, w, K, a.warmup, stream, loop_kernel=a.loop_kernel, events=not a.no_events,
+                     workload=a.workload)
+    sb.sbqa_destroy(ctx)
     N, R, runs = w["N"], w["R"], w["runs"]
-    value = N * R * runs * K / t
-    launch_ms = [ev[0].elapsed_time(ev[1]) / (1 if resident else K)] if ev else []
     out = {
         "metric": "replica-spin updates/s (N*R*runs*steps/s)",
-        "value": value, "unit": "replica-spin updates/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
-        "ms_per_step": 1e3 * t / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "value": r["value"], "unit": "replica-spin updates/s", "n_gpus": 1, "steps": K, "warmup": a.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": w["dtype"], "data": "synthetic",
-        "config": {"workload": w["desc"], "N": N, "R": R, "runs": runs, "schedule_steps": w["S"],
-                   "path": info["path"] + ("_resident" if resident else "")},
-        "best_energy": {"mean": float(np.mean(E)), "min": float(np.min(E))},
-        "end_to_end": {"seconds": create_s + t, "create_s": create_s,
-                       "updates_per_s": N * R * runs * K / (create_s + t),
-                       "includes": "sbqa_create from host arrays (validation, upload, initial state), "
-                                   "the K steps and the readout"},
+        "config": {"workload": w["desc"], "N": N, "R": R, "runs": runs, "schedule_steps": w["S"], "path": r["path"]},
+        "best_energy": r["best_energy"],
+        "end_to_end": dict(r["end_to_end"], includes="sbqa_create from host arrays (validation, upload, initial "
+                                                     "state), the K steps and the readout"),
     }
-    if launch_ms:
-        avg_s = float(np.mean(launch_ms)) * 1e-3
-        if resident:
-            ops = K * resident_ops_per_step(w)
-            sparse = "csr" in w
-            tr = measured_traffic(a.workload + "_resident", "csr_resident") if sparse else None
-            out["roofline"] = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": PEAK_VALU_OPS,
-                               "unit": "Tops/s (fp32 VALU lane ops)", "frac": ops / avg_s / 1e12 / PEAK_VALU_OPS,
-                               "traffic": None if tr is None else tr * K,
-                               "kernel": "k_csr_resident" if sparse else "k_dense_small",
-                               "avg_launch_us": avg_s * 1e6, "steps_per_launch": K,
-                               "algorithmic_ops_per_launch": ops}
-        elif info["path"] == "csr_fp32":
-            ab = algorithmic_bytes(w, info)
-            out["roofline"] = {"bound": "hbm", "achieved": ab / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                               "frac": ab / avg_s / 1e9 / HBM_PEAK_GBS,
-                               "traffic": measured_traffic(a.workload, info["path"]),
-                               "kernel": "k_csr_step", "avg_launch_us": avg_s * 1e6,
-                               "algorithmic_bytes_per_launch": ab}
-        else:
-            fl = algorithmic_flops(w)
-            peak = PEAK[{"dense_fp8": "fp8", "dense_fp8_packed": "fp8", "dense_int8": "int8", "dense_fp4": "fp4",
-                         "dense_fp4_packed": "fp4", "dense_fp32": "fp32",
-                         "dense_bf16x3": "bf16"}[info["path"]]]
-            unit = "TOP/s" if info["path"] == "dense_int8" else "TFLOP/s"
-            out["roofline"] = {"bound": "mfma", "achieved": fl / avg_s / 1e12, "peak": peak, "unit": unit,
-                               "frac": fl / avg_s / 1e12 / peak,
-                               "traffic": measured_traffic(a.workload, info["path"]), "kernel": dense_kernel_name(info),
-                               "avg_step_us": avg_s * 1e6, "algorithmic_flops_per_step": fl}
-    sb.sbqa_destroy(ctx)
-    if a.workload == "sparse6" and not a.no_serve:
-        # second half of the headline metric: p99 solve latency of the mixed stream
+    if "roofline" in r:
+        out["roofline"] = r["roofline"]
+        out["readout_ms"] = r["readout_ms"]
+    if a.workload == "sparse6" and not a.no_configs:
+        # the other configurations, measured on the same GPU in the same run: the small
+        # dense instance, the dense fp8 / fp4 / split-bf16 paths against fp32, and the
+        # mixed serving stream (the p50/p99 half of the metric)
+        cfg = {}
         try:
-            sv = serve_measure(a, a.serve_quick)
-            out["serving"] = {"instances": a.serve_quick, "updates_per_s": sv["value"], "latency_s": sv["latency_s"],
-                              "workload": sv["config"]["workload"], "service_rate_per_s": sv["service_rate_per_s"],
-                              "gpu_busy_fraction": sv["gpu_busy_fraction"]}
+            w1 = make_workload("sk64")
+            r1, c1 = measure(sb, w1, 1000, 200, stream, workload="sk64")
+            sb.sbqa_destroy(c1)
+            r1["workload"] = w1["desc"]
+            cfg["sk_N64_C32"] = r1
         except Exception as e:   # reported, never hides the main line
-            out["serving"] = {"error": repr(e)}
+            cfg["sk_N64_C32"] = {"error": repr(e)}
+        try:
+            cfg.update(dense_configs(sb, stream, a.dense_steps))
+        except Exception as e:
+            cfg["dense"] = {"error": repr(e)}
+        if not a.no_serve:
+            try:
+                sv = serve_measure(a, a.serve_instances)
+                cfg["serving"] = {"instances": a.serve_instances, "updates_per_s": sv["value"],
+                                  "latency_s": sv["latency_s"], "workload": sv["config"]["workload"],
+                                  "service_rate_per_s": sv["service_rate_per_s"],
+                                  "gpu_busy_fraction": sv["gpu_busy_fraction"], "makespan_s": sv["makespan_s"]}
+            except Exception as e:
+                cfg["serving"] = {"error": repr(e)}
+        out["configs"] = cfg
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
