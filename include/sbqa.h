@@ -260,6 +260,27 @@ sbqa_status sbqa_best_step(sbqa_ctx *ctx, int64_t *step_of_best);
 sbqa_status sbqa_energy(sbqa_ctx *ctx, const int8_t *spins, int32_t count, double *out);
 
 /*
+ * sbqa_energy for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. It
+ * calls no allocating routine and does not synchronise.
+ *   spins  DEVICE pointer, count*N int8 (+-1, not validated: other values are
+ *          used as given), the caller's spin order.
+ *   out    DEVICE pointer, count float64, written by the context's stream.
+ * The result equals sbqa_energy's bit for bit (same kernels, same order).
+ * Scratch: a library-owned device array of SBQA_NOALLOC_SCRATCH_BYTES per GPU,
+ * created when the library's code is loaded on that GPU and held until the
+ * process ends. Dense couplings need 8*cp*Np*(1 + es) bytes of it (cp = count
+ * rounded up to 128, Np the padded N, es in {1,2,4,8} the K splits of the
+ * float64 GEMM), relabelled CSR couplings count*N bytes, other CSR couplings
+ * none; a call that needs more returns SBQA_EINVAL before any device work.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (other streams or threads) race. spins and out must be device memory
+ * (SBQA_EINVAL otherwise).
+ */
+#define SBQA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+sbqa_status sbqa_energy_noalloc(sbqa_ctx *ctx, const int8_t *spins, int32_t count, double *out);
+
+/*
  * Coupling sum of Eq. 7 for the current state: phi[N*C] float32 (row-major
  * like the state) = J . f(X) with the threshold of the current step, in the
  * context's contraction precision. Test hook; synchronises.

@@ -70,6 +70,7 @@ def _load() -> ct.CDLL:
         "sbqa_best": ([vp, vp, vp], i32),
         "sbqa_best_step": ([vp, vp], i32),
         "sbqa_energy": ([vp, vp, i32, vp], i32),
+        "sbqa_energy_noalloc": ([vp, vp, i32, vp], i32),
         "sbqa_fields": ([vp, vp], i32),
         "sbqa_get_state": ([vp, vp, vp], i32),
         "sbqa_set_state": ([vp, vp, vp], i32),
@@ -208,6 +209,12 @@ def sbqa_energy(ctx: Context, spins) -> np.ndarray:
     E = np.empty(s.shape[0], dtype=np.float64)
     _check(lib.sbqa_energy(ctx.ptr, _p(s), s.shape[0], _p(E)))
     return E
+
+
+def sbqa_energy_noalloc(ctx: Context, spins_ptr: int, count: int, out_ptr: int) -> None:
+    """spins_ptr / out_ptr: device addresses (count*N int8, count float64);
+    asynchronous on the context's stream."""
+    _check(lib.sbqa_energy_noalloc(ctx.ptr, spins_ptr, count, out_ptr))
 
 
 def sbqa_fields(ctx: Context) -> np.ndarray:

@@ -410,7 +410,25 @@ __global__ __launch_bounds__(1024) void k_best_update(int N, int R, int order, i
     for (int i = t; i < N; i += 1024) best_spins[(int64_t)r * N + i] = x[state_off(order, ld, i, c)] >= 0.0f ? 1 : -1;
 }
 
+// Spin rows from the caller's spin order to the internal rows: row i holds the
+// caller's spin orig[i].
+__global__ void k_spins_to_rows(int N, int count, const int32_t *__restrict__ orig, const int8_t *__restrict__ in,
+                                int8_t *__restrict__ out) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * count) return;
+    const int64_t m = e / N;
+    const int i = (int)(e - m * N);
+    out[e] = in[m * N + orig[i]];
+}
+
 }  // namespace
+
+hipError_t launch_spins_to_rows(int N, int count, const int32_t *orig, const int8_t *in, int8_t *out, hipStream_t st) {
+    const int64_t n = (int64_t)N * count;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_spins_to_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, N, count, orig, in, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_init_state(int N, int C, int order, int ld, uint64_t seed, double amp, const int32_t *orig,
                              float *x, float *y, hipStream_t st) {

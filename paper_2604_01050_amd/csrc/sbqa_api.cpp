@@ -790,6 +790,31 @@ sbqa_status ctx_state_energies(sbqa_ctx *c) {
     return SBQA_OK;
 }
 
+EnergyGemm energy_gemm(const sbqa_ctx *c, int count) {
+    EnergyGemm g;
+    const int Np = c->L.Np;
+    g.cp = (int)round_up(count, GEMM_BM);
+    const int64_t tiles = (int64_t)(Np / GEMM_BN) * (g.cp / GEMM_BM);
+    const int64_t nke = (int64_t)Np * 8 / GEMM_KB;
+    g.es = 1;
+    while (tiles * g.es < 512 && g.es < 8 && nke % (2 * g.es) == 0 && nke / (2 * g.es) >= 4) g.es *= 2;
+    return g;
+}
+
+sbqa_status ctx_energies_dev(sbqa_ctx *c, const int8_t *ds, int32_t count, double *E, double *S, double *P) {
+    const int N = c->N;
+    const double *h64 = c->has_h ? c->h64 : nullptr;
+    if (c->facts.path == PATH_CSR) {
+        HIP_TRY(launch_csr_energy_spins(N, count, c->rp, c->col, c->val64, c->tri3(), h64, ds, E, c->stream));
+    } else {
+        const EnergyGemm g = energy_gemm(c, count);
+        HIP_TRY(launch_spins_to_f64(N, c->L.Np, count, ds, S, c->stream));
+        HIP_TRY(launch_gemm_f64(S, c->J64, P, c->L.Np, g.cp, g.es, c->stream));
+        HIP_TRY(launch_energy_reduce(N, c->L.Np, count, g.cp, g.es, P, S, h64, E, c->stream));
+    }
+    return SBQA_OK;
+}
+
 sbqa_status ctx_evaluate(sbqa_ctx *c, bool reset) {
     sbqa_status st = ctx_state_energies(c);
     if (st != SBQA_OK) return st;
@@ -1249,7 +1274,6 @@ sbqa_status sbqa_energy(sbqa_ctx *c, const int8_t *spins, int32_t count, double 
     const int N = c->N;
     for (int64_t q = 0; q < (int64_t)count * N; ++q)
         if (spins[q] != 1 && spins[q] != -1) return fail(SBQA_EINVAL, "spins must be +-1 (index %lld)", (long long)q);
-    const double *h64 = c->has_h ? c->h64 : nullptr;
     int8_t *ds = nullptr;
     double *E = nullptr;
     HIP_TRY(hipMalloc(&ds, (size_t)count * N));
@@ -1264,24 +1288,16 @@ sbqa_status sbqa_energy(sbqa_ctx *c, const int8_t *spins, int32_t count, double 
     }
     HIP_TRY(hipMemcpyAsync(ds, rows.empty() ? spins : rows.data(), (size_t)count * N, hipMemcpyHostToDevice, c->stream));
     if (!rows.empty()) HIP_TRY(hipStreamSynchronize(c->stream));   // the staging vector dies at return
-    if (c->facts.path == PATH_CSR) {
-        HIP_TRY(launch_csr_energy_spins(N, count, c->rp, c->col, c->val64, c->tri3(), h64, ds, E, c->stream));
-    } else {
-        const int Np = c->L.Np;
-        const int cp = (int)round_up(count, GEMM_BM);
-        const int64_t tiles = (int64_t)(Np / GEMM_BN) * (cp / GEMM_BM);
-        const int64_t nke = (int64_t)Np * 8 / GEMM_KB;
-        int es = 1;
-        while (tiles * es < 512 && es < 8 && nke % (2 * es) == 0 && nke / (2 * es) >= 4) es *= 2;
-        double *S = nullptr, *P = nullptr;
-        HIP_TRY(hipMalloc(&S, sizeof(double) * cp * Np));
+    double *S = nullptr, *P = nullptr;
+    if (c->facts.path != PATH_CSR) {
+        const EnergyGemm g = energy_gemm(c, count);
+        HIP_TRY(hipMalloc(&S, sizeof(double) * g.cp * c->L.Np));
         gd.c2 = S;
-        HIP_TRY(hipMalloc(&P, sizeof(double) * es * cp * Np));
+        HIP_TRY(hipMalloc(&P, sizeof(double) * g.es * g.cp * c->L.Np));
         gd.d = P;
-        HIP_TRY(launch_spins_to_f64(N, Np, count, ds, S, c->stream));
-        HIP_TRY(launch_gemm_f64(S, c->J64, P, Np, cp, es, c->stream));
-        HIP_TRY(launch_energy_reduce(N, Np, count, cp, es, P, S, h64, E, c->stream));
     }
+    sbqa_status st = ctx_energies_dev(c, ds, count, E, S, P);
+    if (st != SBQA_OK) return st;
     HIP_TRY(hipMemcpyAsync(out, E, sizeof(double) * count, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     return SBQA_OK;

@@ -59,6 +59,17 @@ sbqa_status ctx_check_async(sbqa_ctx *c);  // after a readout copy and a stream 
 sbqa_status ctx_sync(sbqa_ctx *c);         // fetch the error word, synchronise, check it
 // energies of the current state -> best tracking (reset: the previous best is discarded)
 sbqa_status ctx_evaluate(sbqa_ctx *c, bool reset = false);
+// Energies of count spin rows already on the device in the internal spin
+// order (ds [count][N] int8 +-1) into E [count], on the context's stream.
+// Dense couplings need float64 scratch S [cp][Np] and P [es][cp][Np] with the
+// sizes energy_gemm gives (the GEMM's K splits follow the shape, so every
+// caller sums in the same order); CSR couplings need none (S, P unused).
+struct EnergyGemm {
+    int cp = 0;   // count padded to GEMM_BM
+    int es = 1;   // K splits
+};
+EnergyGemm energy_gemm(const sbqa_ctx *c, int count);
+sbqa_status ctx_energies_dev(sbqa_ctx *c, const int8_t *ds, int32_t count, double *E, double *S, double *P);
 
 }  // namespace sbqa
 

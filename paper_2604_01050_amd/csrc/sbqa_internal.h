@@ -261,6 +261,10 @@ hipError_t launch_state_reorder(int N, int C, int order_in, int ld_in, const flo
 hipError_t launch_readout_f64(int N, int Np, int C, int ld, bool spin_major, const float *x,
                               double *S, hipStream_t st);
 
+// Spin rows [count][N] in the caller's order -> internal rows (row i holds the
+// caller's spin orig[i]).
+hipError_t launch_spins_to_rows(int N, int count, const int32_t *orig, const int8_t *in, int8_t *out, hipStream_t st);
+
 // int8 spins [count][N] -> float64 S[Cp][Np].
 hipError_t launch_spins_to_f64(int N, int Np, int count, const int8_t *spins, double *S,
                                hipStream_t st);

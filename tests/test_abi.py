@@ -119,6 +119,14 @@ def test_validation_errors(abi):
     _expect(abi, abi.EINVAL, J=J, R=2, runs=2, jp_kind=abi.JP_TABLE)
 
 
+def test_noalloc_energy_argument_errors(abi):
+    """The allocation-free energy entry point checks its arguments before any
+    device work."""
+    assert abi.lib.sbqa_energy_noalloc(None, None, 1, None) == abi.EINVAL
+    assert abi.lib.sbqa_energy_noalloc(None, None, 0, None) == abi.EINVAL
+    assert "NULL" in abi.sbqa_last_error()
+
+
 def test_server_argument_errors(abi):
     with pytest.raises(abi.SbqaError):
         abi.sbqa_server_create(0, 4)
