@@ -719,6 +719,36 @@ def test_best_energy_statistics_256_seeds(sb, orc):
     assert stats.ks_2samp(g, o).pvalue > 0.01
 
 
+def test_bf16x3_matches_fp32_statistics_256_seeds(sb):
+    """Real-valued couplings (the Gaussian dense configuration at a smaller
+    N): J ~ N(0,1) symmetric, h = 0, ballistic f, R = 16, 2 runs per seed,
+    256 seeds, 1000 steps, J_perp linear 0.5 -> 0, from identical initial
+    states. The split-bf16 contraction (hi+lo products, float32 sums) and the
+    plain float32 one follow different rounding, so the chaotic trajectories
+    part; their per-seed best energies must still agree in distribution: mean
+    difference within 3 sigma and two-sample KS p > 0.01."""
+    stats = pytest.importorskip("scipy.stats")
+    N, R, runs_per_seed, seeds, S = 256, 16, 2, 256, 1000
+    runs = runs_per_seed * seeds
+    J = inst.dense_gaussian(N, 1101)
+    X0, Y0 = inst.uniform_state(N, R * runs, 0.1, 1102)
+    best = {}
+    for name, prec in (("bf16x3", sb.PREC_BF16X3), ("fp32", sb.PREC_FP32)):
+        _log("statistics bf16x3 vs fp32: %s, %d seeds x %d runs, N=%d, S=%d" % (name, seeds, runs_per_seed, N, S))
+        ctx = _ctx(sb, J=J, R=R, runs=runs, steps=S, precision=prec, fmode=sb.F_BALLISTIC)
+        sb.sbqa_set_state(ctx, X0, Y0)
+        sb.sbqa_step(ctx, S)
+        E, _ = sb.sbqa_best(ctx)
+        best[name] = E.reshape(seeds, runs_per_seed).min(axis=1)
+        sb.sbqa_destroy(ctx)
+    g, f = best["bf16x3"], best["fp32"]
+    se = math.sqrt(g.var() / seeds + f.var() / seeds)
+    _log("  bf16x3 mean %.4f min %.4f | fp32 mean %.4f min %.4f | se %.4f | identical seeds %d"
+         % (g.mean(), g.min(), f.mean(), f.min(), se, int(np.sum(g == f))))
+    assert abs(g.mean() - f.mean()) <= 3 * se + 1e-12
+    assert stats.ks_2samp(g, f).pvalue > 0.01
+
+
 # -------------------------------------------------------------------- serving
 def test_serving_graph_blocks_alone_equals_mix(sb):
     """Longer schedules (several full step blocks, replayed from a captured
