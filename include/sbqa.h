@@ -133,7 +133,8 @@ typedef enum { SBQA_REORDER_AUTO = 0, SBQA_REORDER_OFF = 1, SBQA_REORDER_ON = 2 
  * J must be symmetric with a zero diagonal and finite entries.
  *   dense    N*N float64, row-major.
  *   row_ptr  N+1 int32, col nnz int32 (0 <= col < N), val nnz float64;
- *            both (i,j) and (j,i) stored; duplicate entries are rejected.
+ *            both (i,j) and (j,i) stored; duplicate entries are rejected;
+ *            col and val may be NULL when nnz is 0.
  * Optional native three-body terms (the cubic part of the HUBO Hamiltonian,
  * Eq. 11; CSR couplings only, nnz may be 0):
  *   n3       number of triples (0: none)

@@ -60,6 +60,50 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     return OUT
 
 
+# Host sanitizers for the test driver tests/sanitize/host_checks.cpp: only
+# the host part of each source is instrumented (each -fsanitize= behind
+# -Xarch_host); device code is built as above.
+SANITIZERS = {
+    "asan": ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"],
+    "tsan": ["-Xarch_host", "-fsanitize=thread"],
+}
+
+
+def build_sanitized(kind: str, verbose: bool = False) -> str:
+    """Build the host-check driver (which includes the runtime's API source)
+    with the other sources, host parts instrumented by `kind` ("asan": address
+    + undefined behaviour, "tsan": threads). Returns the executable's path."""
+    san = SANITIZERS[kind]
+    bdir = os.path.join(BUILD, "sanitize_" + kind)
+    os.makedirs(bdir, exist_ok=True)
+    driver = os.path.join(ROOT, "tests", "sanitize", "host_checks.cpp")
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    srcs = [x for x in srcs if os.path.basename(x) != "sbqa_api.cpp"] + [driver]
+
+    def comp(src):
+        obj = os.path.join(bdir, os.path.basename(src) + ".o")
+        cmd = [HIPCC, *COMMON, *san, "-Xarch_host", "-g"]
+        if src.endswith(".cpp"):
+            cmd += ["-x", "hip"]
+        cmd += ["-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))
+        return obj
+
+    with cf.ThreadPoolExecutor(min(8, len(srcs))) as ex:
+        objs = list(ex.map(comp, srcs))
+    exe = os.path.join(bdir, "host_checks")
+    cmd = [HIPCC, "--offload-arch=" + ARCH, *san, "-o", exe, *objs, "-lpthread"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed: %s\n%s" % (r.stdout, r.stderr))
+    if verbose:
+        print("built", exe)
+    return exe
+
+
 if __name__ == "__main__":
     build(verbose=True)
     sys.exit(0)

@@ -193,7 +193,8 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
         ss = d.ss;
         facts->nnz = 0;
     } else {
-        if (!J->row_ptr || !J->col || !J->val) return fail(SBQA_EINVAL, "CSR needs row_ptr, col and val");
+        if (!J->row_ptr || (J->nnz != 0 && (!J->col || !J->val)))
+            return fail(SBQA_EINVAL, "CSR needs row_ptr, and col and val unless nnz is 0");
         const int32_t *rp = J->row_ptr, *cl = J->col;
         const double *vl = J->val;
         if (J->nnz < 0 || rp[0] != 0 || (int64_t)rp[N] != J->nnz) return fail(SBQA_EINVAL, "row_ptr[0] must be 0 and row_ptr[N] == nnz");
