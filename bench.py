@@ -248,10 +248,21 @@ def copy_calibration():
     print("copy calibration: 3 x copy of %d bytes" % (a.numel() * 4), flush=True)
 
 
-def cpu_baseline(w, target_s=15.0, single_s=4.0):
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(w, window_s=5.0, windows=3, single_s=4.0):
     """The FP64 oracle on the host cores over the first steps of the same
-    workload: inputs from the shared generators, c0 and J_perp from the oracle;
-    then a shorter window on one thread."""
+    workload (inputs from the shared generators, c0 and J_perp from the
+    oracle): the median rate of three consecutive windows on all threads, then
+    a shorter window on one thread."""
     import oracle
     import sbqa_instances as inst
     oracle.build()
@@ -261,12 +272,16 @@ def cpu_baseline(w, target_s=15.0, single_s=4.0):
     jt = oracle.jperp_linear_table(0.5, 0.0, S)
     X0, Y0 = inst.uniform_state(N, R * runs, 0.1, 99)
     X, Y = X0.astype(np.float64), Y0.astype(np.float64)
-    t0 = time.perf_counter()
-    n = 0
-    while n < S and (time.perf_counter() - t0) < target_s:
-        X, Y = P.step(X, Y, oracle.pump(n, S), oracle.delta32(0.7, n, S), np.full(runs, jt[n]))
-        n += 1
-    dt = time.perf_counter() - t0
+    n, rates, counts = 0, [], []
+    for _ in range(windows):
+        t0, k = time.perf_counter(), 0
+        while n < S and (time.perf_counter() - t0) < window_s:
+            X, Y = P.step(X, Y, oracle.pump(n, S), oracle.delta32(0.7, n, S), np.full(runs, jt[n]))
+            n += 1
+            k += 1
+        if k:
+            rates.append(N * R * runs * k / (time.perf_counter() - t0))
+            counts.append(k)
     cores = oracle.num_threads()
     # one thread, continuing from the state reached
     oracle.set_threads(1)
@@ -276,8 +291,12 @@ def cpu_baseline(w, target_s=15.0, single_s=4.0):
         n1 += 1
     d1 = time.perf_counter() - t1
     oracle.set_threads(cores)
-    out = {"value": N * R * runs * n / dt, "unit": "replica-spin updates/s", "cores": cores,
-           "kind": "oracle", "sample": "first %d of %d steps of the same workload (FP64 C oracle, OpenMP)" % (n, S)}
+    out = {"value": float(np.median(rates)), "unit": "replica-spin updates/s", "cores": cores,
+           "kind": "oracle",
+           "sample": "the first %d of %d steps of the same workload in %d consecutive windows of about %.0f s "
+                     "(%s steps), median rate (FP64 C oracle, OpenMP)"
+                     % (n, S, len(rates), window_s, "/".join(str(c) for c in counts), ),
+           "windows": rates, "cpu_model": _cpu_model(), "compile_flags": " ".join(oracle.CFLAGS)}
     if n1:
         out["single_thread"] = {"value": N * R * runs * n1 / d1, "sample": "the next %d steps on one thread" % n1}
     return out
