@@ -795,10 +795,10 @@ __global__ __launch_bounds__(256) void k_convert_j(const double *__restrict__ J6
 // like the byte copy (groups of DENSE_TN/16 row blocks): one thread per
 // (fragment, lane, dword), consecutive threads write consecutive dwords. A bit
 // is set where J_ij < 0; the diagonal and the padding read 0 and so hold +1
-// (the step's epilogue removes both).
-template <bool FP4>
-__global__ __launch_bounds__(256) void k_convert_j_pk(const double *__restrict__ J64, int Np, int nkc,
-                                                     uint32_t *__restrict__ Jd) {
+// (the step's epilogue removes both). `neg(i, j)` tells whether J_ij < 0 for
+// i, j < Np: from the zero-padded float64 copy, or from row-major sign bits.
+template <bool FP4, class Neg>
+__device__ __forceinline__ void convert_j_pk(int Np, int nkc, uint32_t *__restrict__ Jd, Neg neg) {
     constexpr int RBT = DENSE_TN / 16, DW = FP4 ? 2 : 1;
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (int64_t)(Np / 16) * nkc * 64 * DW) return;
@@ -808,28 +808,44 @@ __global__ __launch_bounds__(256) void k_convert_j_pk(const double *__restrict__
     const int64_t t = frag / RBT;
     const int kc = (int)(t % nkc), rb = (int)(t / nkc) * RBT + w;
     const int g = lane >> 4;
-    const double *row = J64 + (int64_t)(16 * rb + (lane & 15)) * Np;
+    const int i = 16 * rb + (lane & 15);
     uint32_t bits = 0;
     if constexpr (FP4) {
         // half d: K = 256 kc + 64 g + 32 d + 8 k + i for nibble i of dword k
-        const double *src = row + 256 * kc + 64 * g + 32 * d;
+        const int j0 = 256 * kc + 64 * g + 32 * d;
 #pragma unroll
         for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
-                if (src[8 * k + i] < 0.0) bits |= 1u << (4 * i + k);
+            for (int e = 0; e < 8; ++e)
+                if (neg(i, j0 + 8 * k + e)) bits |= 1u << (4 * e + k);
     } else {
-        // byte b = 4 k + i of the lane's 32: K = 128 kc + 32 g + 16 (b / 16) + b % 16
-        const double *src = row + 128 * kc + 32 * g;
+        // byte b = 4 k + e of the lane's 32: K = 128 kc + 32 g + 16 (b / 16) + b % 16
+        const int j0 = 128 * kc + 32 * g;
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int bb = 4 * k + i;
-                if (src[16 * (bb >> 4) + (bb & 15)] < 0.0) bits |= 1u << (8 * i + k);
+            for (int e = 0; e < 4; ++e) {
+                const int bb = 4 * k + e;
+                if (neg(i, j0 + 16 * (bb >> 4) + (bb & 15))) bits |= 1u << (8 * e + k);
             }
     }
     Jd[q] = bits;
+}
+
+template <bool FP4>
+__global__ __launch_bounds__(256) void k_convert_j_pk(const double *__restrict__ J64, int Np, int nkc,
+                                                     uint32_t *__restrict__ Jd) {
+    convert_j_pk<FP4>(Np, nkc, Jd, [&](int i, int j) { return J64[(int64_t)i * Np + j] < 0.0; });
+}
+
+// From row-major sign bits of an N x N matrix (bit j % 32 of word
+// i * words + j / 32 set where J_ij < 0); rows and columns past N read +1.
+template <bool FP4>
+__global__ __launch_bounds__(256) void k_convert_j_pk_bits(const uint32_t *__restrict__ sb, int N, int words, int Np,
+                                                          int nkc, uint32_t *__restrict__ Jd) {
+    convert_j_pk<FP4>(Np, nkc, Jd, [&](int i, int j) {
+        return i < N && j < N && ((sb[(int64_t)i * words + (j >> 5)] >> (j & 31)) & 1u) != 0u;
+    });
 }
 
 template <int PATH, int MBW>
@@ -957,6 +973,23 @@ hipError_t launch_dense_step(Path path, DenseEpilogue epi, int mbw, int Cg, cons
         case PATH_FP4PK: return launch_step_path<PATH_FP4PK>(epi, mbw, grid, a, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_convert_j_bits(Path path, const uint32_t *sign_bits, int N, int Np, int nkc, void *Jd,
+                                 hipStream_t st) {
+    if (!path_packed(path) || Np % 128 || Np % path_kpc(path) || nkc != dense_nkc(path, Np) || N > Np)
+        return hipErrorInvalidValue;
+    const bool fp4 = path_fp4(path);
+    const int words = (N + 31) / 32;
+    const int64_t nq = (int64_t)(Np / 16) * nkc * 64 * (fp4 ? 2 : 1);
+    const dim3 grid((unsigned)((nq + 255) / 256));
+    if (fp4)
+        hipLaunchKernelGGL(k_convert_j_pk_bits<true>, grid, dim3(256), 0, st, sign_bits, N, words, Np, nkc,
+                           static_cast<uint32_t *>(Jd));
+    else
+        hipLaunchKernelGGL(k_convert_j_pk_bits<false>, grid, dim3(256), 0, st, sign_bits, N, words, Np, nkc,
+                           static_cast<uint32_t *>(Jd));
+    return hipGetLastError();
 }
 
 hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void *Jd, void *Jd_lo, hipStream_t st) {

@@ -410,6 +410,14 @@ __global__ __launch_bounds__(1024) void k_best_update(int N, int R, int order, i
     for (int i = t; i < N; i += 1024) best_spins[(int64_t)r * N + i] = x[state_off(order, ld, i, c)] >= 0.0f ? 1 : -1;
 }
 
+// Row-major N x N float64 rows into the first N columns of rows of length Np.
+__global__ void k_pad_rows(const double *__restrict__ src, int N, int Np, double *__restrict__ dst) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)N * N) return;
+    const int64_t i = e / N, j = e - i * N;
+    dst[i * Np + j] = src[e];
+}
+
 // Spin rows from the caller's spin order to the internal rows: row i holds the
 // caller's spin orig[i].
 __global__ void k_spins_to_rows(int N, int count, const int32_t *__restrict__ orig, const int8_t *__restrict__ in,
@@ -422,6 +430,14 @@ __global__ void k_spins_to_rows(int N, int count, const int32_t *__restrict__ or
 }
 
 }  // namespace
+
+hipError_t launch_pad_rows(const double *src, int N, int Np, double *dst, hipStream_t st) {
+    const int64_t n = (int64_t)N * N;
+    if (Np < N) return hipErrorInvalidValue;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, N, Np, dst);
+    return hipGetLastError();
+}
 
 hipError_t launch_spins_to_rows(int N, int count, const int32_t *orig, const int8_t *in, int8_t *out, hipStream_t st) {
     const int64_t n = (int64_t)N * count;

@@ -283,6 +283,26 @@ sbqa_status validate_instance(const sbqa_coupling *J, const double *h, int32_t N
     return SBQA_OK;
 }
 
+void pack_sign_bits(const double *J, int32_t N, std::vector<uint32_t> *bits) {
+    const int64_t words = (N + 31) / 32;
+    bits->assign((size_t)(N * words), 0u);
+    auto rows = [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t j = 0; j < N; ++j)
+                if (J[i * N + j] < 0.0) (*bits)[(size_t)(i * words + j / 32)] |= 1u << (j % 32);
+    };
+    const int nt = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (nt <= 1 || N < 512) {
+        rows(0, N);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const int64_t per = (N + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t)
+        pool.emplace_back(rows, std::min<int64_t>(N, t * per), std::min<int64_t>(N, (t + 1) * per));
+    for (std::thread &t : pool) t.join();
+}
+
 // Geometry and byte count of a context (also used by the server's admission).
 void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Layout *L) {
     const int64_t C = (int64_t)R * runs;
@@ -317,9 +337,10 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         b += 3 * C * (int64_t)L->Np * 4;                                  // x ping-pong, y
         b += 2 * dense_plane_bytes(f.path, L->Cg, L->Np) * planes;        // operand ping-pong
         b += dense_j_bytes(f.path, L->Np) * planes;                       // J
-        b += (int64_t)L->Np * L->Np * 8;                                  // J fp64 (energies)
+        if (f.jbits) b += (int64_t)N * ((N + 31) / 32) * 4;               // sign bits the J copy is built from
+        else b += (int64_t)L->Np * L->Np * 8;                             // J fp64 (energies, source of J)
         b += (int64_t)L->Np * 12;                                         // h
-        b += (int64_t)L->Cp * L->Np * 8 * (1 + es);                      // readout + energy partials
+        if (!path_energy_mfma(f.path)) b += (int64_t)L->Cp * L->Np * 8 * (1 + es);   // fp64 readout + energy partials
         L->csr_nrb = 0;
     }
     b += (int64_t)runs * (int64_t)0;  // schedule tables counted by the caller (steps known there)
@@ -526,7 +547,7 @@ sbqa_status rebuild_operand(sbqa_ctx *c) {
     return SBQA_OK;
 }
 
-sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
+sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, const uint32_t *jbits) {
     const int N = c->N, Np = c->L.Np, Cs = c->L.Cs, C = c->L.C, Cp = c->L.Cp;
     const Path path = c->facts.path;
     const int runs = c->runs;
@@ -680,8 +701,10 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         c->g[q] = gb;
         c->g_lo[q] = glo;
     }
-    HIP_TRY(dalloc(c, &c->S64, (size_t)Cp * Np));
-    HIP_TRY(dalloc(c, &c->phis64, (size_t)c->L.esplits * Cp * Np));
+    if (!path_energy_mfma(path)) {   // float64 readout spins and energy GEMM partials
+        HIP_TRY(dalloc(c, &c->S64, (size_t)Cp * Np));
+        HIP_TRY(dalloc(c, &c->phis64, (size_t)c->L.esplits * Cp * Np));
+    }
     if (c->resident) {
         // small dense loop: J float32 [N][N]
         std::vector<float> jsm((size_t)N * N);
@@ -691,6 +714,21 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
         HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
     }
 
+    if (c->facts.jbits) {
+        // +-1 J as sign bits: the bit-packed contraction copy is built from
+        // them; no float64 copy (the readout energies run on MFMA)
+        if (!jbits || !path_packed(path)) return fail(SBQA_EINVAL, "sign bits need a bit-packed +-1 path");
+        uint8_t *jd;
+        uint32_t *sb;
+        const size_t words = (size_t)(N + 31) / 32;
+        HIP_TRY(dalloc(c, &jd, (size_t)dense_j_bytes(path, Np)));
+        HIP_TRY(dalloc(c, &sb, (size_t)N * words));
+        c->Jd = jd;
+        HIP_TRY(hipMemcpyAsync(sb, jbits, sizeof(uint32_t) * N * words, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(launch_convert_j_bits(path, sb, N, Np, nkc, jd, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));   // the caller may free the bits on return
+        return SBQA_OK;
+    }
     // J in the contraction precision (fragment-tiled) and in float64
     // (row-major, energies), zero padded.
     const double *A = J->dense;
@@ -702,10 +740,21 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h) {
     c->Jd = jd;
     c->Jd_lo = jlo;
     c->J64 = j64;
-    // float64 rows straight into the zero-padded row-major copy (energies),
-    // then the contraction copy is derived from it on the device
-    HIP_TRY(hipMemcpy2DAsync(j64, sizeof(double) * Np, A, sizeof(double) * N, sizeof(double) * N, N,
-                             hipMemcpyHostToDevice, c->stream));
+    // float64 J into the zero-padded row-major copy (energies), then the
+    // contraction copy is derived from it on the device. The host array goes
+    // up in one contiguous copy (a pitched copy from pageable memory is split
+    // into one transfer per row); when rows need padding it lands in a
+    // temporary buffer first and is spread into the padded rows on the GPU.
+    if (N == Np) {
+        HIP_TRY(hipMemcpyAsync(j64, A, sizeof(double) * N * N, hipMemcpyHostToDevice, c->stream));
+    } else {
+        double *tmp = nullptr;
+        HIP_TRY(hipMalloc(&tmp, sizeof(double) * (size_t)N * N));
+        struct Tmp { double *p; ~Tmp() { (void)hipFree(p); } } guard{tmp};
+        HIP_TRY(hipMemcpyAsync(tmp, A, sizeof(double) * N * N, hipMemcpyHostToDevice, c->stream));
+        HIP_TRY(launch_pad_rows(tmp, N, Np, j64, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));   // tmp is freed at return
+    }
     HIP_TRY(launch_convert_j(path, j64, Np, nkc, jd, jlo, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));   // the caller may free J on return
     return SBQA_OK;
@@ -804,6 +853,8 @@ EnergyGemm energy_gemm(const sbqa_ctx *c, int count) {
 
 sbqa_status ctx_energies_dev(sbqa_ctx *c, const int8_t *ds, int32_t count, double *E, double *S, double *P) {
     const int N = c->N;
+    if (c->facts.path != PATH_CSR && !c->J64)
+        return fail(SBQA_EINVAL, "this context keeps no float64 copy of J (built from sign bits)");
     const double *h64 = c->has_h ? c->h64 : nullptr;
     if (c->facts.path == PATH_CSR) {
         HIP_TRY(launch_csr_energy_spins(N, count, c->rp, c->col, c->val64, c->tri3(), h64, ds, E, c->stream));
@@ -996,7 +1047,7 @@ static void relabel(const sbqa_coupling *J, const double *h, int32_t N, const st
 
 sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                        const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out,
-                       bool allow_resident) {
+                       bool allow_resident, const uint32_t *jbits) {
     sbqa_ctx *c = new (std::nothrow) sbqa_ctx();
     if (!c) return fail(SBQA_ENOMEM, "out of host memory");
     c->N = N;
@@ -1026,6 +1077,7 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
             h = h ? rl.h.data() : nullptr;
         }
     }
+    if (facts.jbits) allow_resident = false;   // the small dense loop needs J in float32
     {
         std::string why;
         const bool plan = facts.path == PATH_CSR ? resident_plan(c, J, &why) : small_plan(c, &why);
@@ -1048,7 +1100,7 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
         c->order = ORDER_SPIN_MAJOR;
         c->ld = c->L.Cs;
     }
-    st = ctx_upload(c, J, h);
+    st = ctx_upload(c, J, h, jbits);
     if (st == SBQA_OK && !c->pnew.empty()) {
         std::vector<int32_t> orig((size_t)N);
         for (int32_t i = 0; i < N; ++i) orig[(size_t)c->pnew[(size_t)i]] = i;

@@ -21,7 +21,20 @@ struct InstanceFacts {
     double rms = 0.0;        // rms of the N(N-1) off-diagonal couplings
     int64_t nnz = 0;
     Path path = PATH_F32;
+    // dense +-1 J handed over as row-major sign bits (the serving loop packs
+    // them on the host): the bit-packed contraction copy is built from them
+    // and no float64 copy of J is kept (integer J: the readout energies run
+    // on MFMA), so sbqa_energy is not available on such a context
+    bool jbits = false;
 };
+// The readout energies of these paths are exact MFMA contractions (no
+// float64 copy of J or energy GEMM buffers needed for them).
+constexpr bool path_energy_mfma(Path p) {
+    return p == PATH_FP8 || p == PATH_FP8PK || p == PATH_I8 || p == PATH_FP4 || p == PATH_FP4PK;
+}
+// Row-major sign bits of a dense +-1 J (InstanceFacts::jbits), ceil(N/32)
+// words per row; parallel over row blocks for large N.
+void pack_sign_bits(const double *J, int32_t N, std::vector<uint32_t> *bits);
 
 // Device geometry of a context.
 struct Layout {
@@ -49,9 +62,10 @@ StepCoef step_coef(const sbqa_schedule *s, double c0, int R, uint32_t n);
 
 // allow_resident: false for contexts that share the GPU with other work (the
 // resident loop needs all its workgroups co-resident).
+// jbits: the sign bits of a dense J when facts.jbits (J->dense is then unused).
 sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                        const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out,
-                       bool allow_resident);
+                       bool allow_resident, const uint32_t *jbits = nullptr);
 sbqa_status ctx_step(sbqa_ctx *c, uint32_t n);
 sbqa_status ctx_step_once(sbqa_ctx *c);
 sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins);

@@ -175,6 +175,12 @@ hipError_t launch_group_dense(Path path, int mbw, const GroupHeader *hdr, const 
 // blocks) from the zero-padded row-major float64 J64 [Np][Np].
 hipError_t launch_convert_j(Path path, const double *J64, int Np, int nkc, void *Jd, void *Jd_lo, hipStream_t st);
 
+// Bit-packed +-1 J (PATH_FP8PK / PATH_FP4PK) from row-major sign bits of the
+// N x N matrix: words = ceil(N / 32) uint32 per row, bit j % 32 of word
+// i * words + j / 32 set where J_ij < 0 (the diagonal clear).
+hipError_t launch_convert_j_bits(Path path, const uint32_t *sign_bits, int N, int Np, int nkc, void *Jd,
+                                 hipStream_t st);
+
 // Operand f(X) (fragment-tiled, groups of mbw row blocks) from state [C][Np]
 // with threshold delta.
 hipError_t launch_dense_operand(Path path, int fmode, int N, int Np, int C, int nkc, int mbw, const float *x,
@@ -260,6 +266,10 @@ hipError_t launch_state_reorder(int N, int C, int order_in, int ld_in, const flo
 // (zero padding) from the state, for the energy GEMM.
 hipError_t launch_readout_f64(int N, int Np, int C, int ld, bool spin_major, const float *x,
                               double *S, hipStream_t st);
+
+// Row-major N x N float64 src into the first N columns of the rows of dst
+// (row length Np >= N; the rest of dst is left as it is).
+hipError_t launch_pad_rows(const double *src, int N, int Np, double *dst, hipStream_t st);
 
 // Spin rows [count][N] in the caller's order -> internal rows (row i holds the
 // caller's spin orig[i]).

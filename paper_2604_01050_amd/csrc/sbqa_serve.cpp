@@ -111,6 +111,7 @@ struct Request {
     int32_t N = 0, R = 0, runs = 0;
     sbqa_schedule s{};
     std::vector<double> dense, val, h, beta, alpha;
+    std::vector<uint32_t> jbits;   // dense +-1 J on a bit-packed path: its sign bits instead of `dense`
     std::vector<int32_t> row_ptr, col, tri;
     std::vector<double> K;
     std::vector<float> jp_table;
@@ -326,7 +327,7 @@ static void creator(sbqa_server *srv) {
         s.alpha = r.alpha.empty() ? nullptr : r.alpha.data();
         s.jp_table = r.jp_table.empty() ? nullptr : r.jp_table.data();
         sbqa_status st = ctx_create(&J, r.h.empty() ? nullptr : r.h.data(), r.N, r.R, r.runs, &s, r.facts,
-                                    srv->create_stream, &sl->ctx, false);
+                                    srv->create_stream, &sl->ctx, false, r.jbits.empty() ? nullptr : r.jbits.data());
         if (st == SBQA_OK && hipStreamSynchronize(srv->create_stream) != hipSuccess)
             st = fail(SBQA_EDEVICE, "context set-up did not complete");
         if (st == SBQA_OK) {
@@ -339,6 +340,8 @@ static void creator(sbqa_server *srv) {
         }
         r.dense.clear();
         r.dense.shrink_to_fit();
+        r.jbits.clear();
+        r.jbits.shrink_to_fit();
         {
             std::lock_guard<std::mutex> lk(srv->mu);
             srv->ready.push_back(std::move(sl));
@@ -493,6 +496,9 @@ sbqa_status sbqa_submit(sbqa_server *srv, const sbqa_coupling *J, const double *
     if (!r) return fail(SBQA_ENOMEM, "out of host memory");
     sbqa_status st = validate_instance(J, h, N, R, runs, s, &r->facts);
     if (st != SBQA_OK) return st;
+    // dense +-1 couplings on a bit-packed path travel as sign bits (N^2/8
+    // bytes instead of N^2 float64) and keep no float64 copy on the device
+    if (J->dense && r->facts.pm1 && path_packed(r->facts.path)) r->facts.jbits = true;
     r->bytes = instance_bytes(N, R, runs, r->facts, s->steps);
     if (r->bytes > srv->budget)
         return fail(SBQA_EBUDGET, "instance needs %zu device bytes, budget is %zu", r->bytes, srv->budget);
@@ -500,7 +506,8 @@ sbqa_status sbqa_submit(sbqa_server *srv, const sbqa_coupling *J, const double *
     r->R = R;
     r->runs = runs;
     r->s = *s;
-    if (J->dense) r->dense.assign(J->dense, J->dense + (size_t)N * N);
+    if (J->dense && r->facts.jbits) pack_sign_bits(J->dense, N, &r->jbits);
+    else if (J->dense) r->dense.assign(J->dense, J->dense + (size_t)N * N);
     else {
         r->row_ptr.assign(J->row_ptr, J->row_ptr + N + 1);
         r->col.assign(J->col, J->col + J->nnz);

@@ -826,8 +826,8 @@ def test_serving_alone_equals_mix(sb):
         sb.sbqa_destroy(ctx)
     srv = sb.sbqa_server_create(96 << 20, 3)
     tickets = [sb.sbqa_submit(srv, J=J, csr=csr, **kw) for J, csr, kw in items]
-    with pytest.raises(sb.SbqaError) as ei:
-        sb.sbqa_submit(srv, J=inst.sk_pm1(4096, 1), R=8, runs=4, steps=10)
+    with pytest.raises(sb.SbqaError) as ei:   # real-valued J: float32 + float64 copies, 192 MiB
+        sb.sbqa_submit(srv, J=inst.dense_gaussian(4096, 1), R=8, runs=4, steps=10, fmode=sb.F_BALLISTIC)
     assert ei.value.status == sb.EBUDGET
     import time
     got = {}
