@@ -802,6 +802,48 @@ def test_serving_graph_blocks_alone_equals_mix(sb):
     sb.sbqa_server_destroy(srv)
 
 
+def test_serving_alone_equals_mix_stream_sizes(sb):
+    """The serving configuration's shapes: R = 16 x 8 runs (C = 128), a dense
+    SK +-1 instance of N = 8192 (bit-packed fp8, built from sign bits on the
+    server), a sparse d-regular Gaussian instance of N = 8000, and smaller ones
+    of both kinds; served results equal the standalone runs bit for bit."""
+    rng = np.random.default_rng(71)
+    specs = [("dense", 8192), ("sparse", 8000), ("dense", 1536), ("sparse", 700), ("dense", 300)]
+    items = []
+    for q, (kind, N) in enumerate(specs):
+        kw = dict(R=16, runs=8, steps=100, seed=740 + q, jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0)
+        if kind == "dense":
+            items.append((inst.sk_pm1(N, 750 + q), None, dict(kw, precision=sb.PREC_FP8)))
+        else:
+            d = int(rng.integers(3, 13))
+            E = inst.regular_graph(N, d, 760 + q)
+            items.append((None, inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 770 + q)), kw))
+    _log("serving at stream sizes: %s" % specs)
+    alone = []
+    for J, csr, kw in items:
+        ctx = sb.sbqa_create(J=J, csr=csr, **kw)
+        sb.sbqa_step(ctx, kw["steps"])
+        alone.append(sb.sbqa_best(ctx))
+        sb.sbqa_destroy(ctx)
+    srv = sb.sbqa_server_create(8 << 30, 3)
+    tickets = [sb.sbqa_submit(srv, J=J, csr=csr, **kw) for J, csr, kw in items]
+    import time
+    got = {}
+    t0 = time.time()
+    while len(got) < len(tickets) and time.time() - t0 < 120:
+        for t in tickets:
+            if t not in got:
+                r = sb.sbqa_poll(srv, t)
+                if r is not None:
+                    got[t] = r
+        time.sleep(0.005)
+    assert len(got) == len(tickets)
+    for t, (Ea, sa), (kind, N) in zip(tickets, alone, specs):
+        Em, sm, _ = got[t]
+        assert np.array_equal(Ea, Em) and np.array_equal(sa, sm), (kind, N)
+    sb.sbqa_server_destroy(srv)
+
+
 def test_serving_alone_equals_mix(sb):
     """Continuous batching: instances of mixed size and density submitted to a
     server (small budget, 3 slots, so some wait) give exactly the results they
