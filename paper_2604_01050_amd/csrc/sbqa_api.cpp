@@ -1227,16 +1227,21 @@ sbqa_status ctx_step(sbqa_ctx *c, uint32_t n) {
 
 // Readout: without energy tracking the best of the current state alone
 // (the previous best discarded on the device, no host round trip); then the
-// readout block (best energies, error word, best spins) in one copy to pinned
-// memory and one synchronisation.
-sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins) {
+// readout block (best energies, error word, best spins) in one copy to the
+// pinned host block. Nothing waits: the results are there once the context's
+// stream has passed this point.
+sbqa_status ctx_readout_async(sbqa_ctx *c) {
     const bool reset = c->s.energy_every == 0;
     if (reset || c->last_eval_step != (int64_t)c->step) {
         sbqa_status st = ctx_evaluate(c, reset);
         if (st != SBQA_OK) return st;
     }
     HIP_TRY(hipMemcpyAsync(c->rhost, c->rdev, c->rbytes, hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(hipStreamSynchronize(c->stream));
+    return SBQA_OK;
+}
+
+// The results of the last ctx_readout_async, once its work has completed.
+sbqa_status ctx_readout_collect(sbqa_ctx *c, double *energies, int8_t *spins) {
     const double *bE = reinterpret_cast<const double *>(c->rhost);
     const int8_t *bS = reinterpret_cast<const int8_t *>(c->rhost + (size_t)8 * c->runs + 8);
     if (energies) std::memcpy(energies, bE, sizeof(double) * c->runs);
@@ -1248,6 +1253,13 @@ sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins) {
                     spins[(size_t)r * c->N + i] = bS[(size_t)r * c->N + c->pnew[(size_t)i]];
     }
     return ctx_check_async(c);
+}
+
+sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins) {
+    sbqa_status st = ctx_readout_async(c);
+    if (st != SBQA_OK) return st;
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return ctx_readout_collect(c, energies, spins);
 }
 
 }  // namespace sbqa

@@ -69,6 +69,10 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
 sbqa_status ctx_step(sbqa_ctx *c, uint32_t n);
 sbqa_status ctx_step_once(sbqa_ctx *c);
 sbqa_status ctx_best(sbqa_ctx *c, double *energies, int8_t *spins);
+// ctx_best in two halves: enqueue the readout (no wait), then, once the
+// context's stream has passed it, copy the results out.
+sbqa_status ctx_readout_async(sbqa_ctx *c);
+sbqa_status ctx_readout_collect(sbqa_ctx *c, double *energies, int8_t *spins);
 sbqa_status ctx_check_async(sbqa_ctx *c);  // after a readout copy and a stream synchronisation
 sbqa_status ctx_sync(sbqa_ctx *c);         // fetch the error word, synchronise, check it
 // energies of the current state -> best tracking (reset: the previous best is discarded)

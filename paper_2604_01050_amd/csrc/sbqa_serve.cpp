@@ -12,7 +12,10 @@
 // workgroups its standalone kernel would run, so its result does not depend
 // on the mix. At block boundaries finished instances are read out (best over
 // replicas, Sec. II.B) and retired, tracked energies are evaluated, and queued
-// requests take their place.
+// requests take their place. A finished instance's readout is enqueued behind
+// the block that finished it and collected once an event says it is done (the
+// next blocks are queued meanwhile), and its context is released without
+// waiting on the server stream, so retirements do not drain the GPU.
 #include "sbqa_ctx.h"
 
 #include <algorithm>
@@ -134,6 +137,8 @@ struct Slot {
     std::unique_ptr<Request> req;
     sbqa_ctx *ctx = nullptr;
     size_t bytes = 0;
+    bool retiring = false;      // readout enqueued, waiting for `done`
+    hipEvent_t done = nullptr;  // recorded on the server stream behind the readout
 };
 
 }  // namespace
@@ -175,6 +180,44 @@ struct sbqa_server {
     double busy_s = 0.0;
 };
 
+static void record_result(sbqa_server *srv, Slot &sl, Result res) {
+    res.latency_s = std::chrono::duration<double>(Clock::now() - sl.req->t_submit).count();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (res.status == SBQA_OK) {
+        srv->completed += 1;
+        srv->updates += (double)sl.req->N * sl.req->R * sl.req->runs * sl.req->s.steps;
+    }
+    srv->results[sl.req->ticket] = std::move(res);
+}
+
+// Enqueue the readout of a finished instance behind its last step block.
+static sbqa_status begin_retire(sbqa_server *srv, Slot &sl) {
+    if (!sl.done) HIP_CHECK_SERVE(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    const sbqa_status st = ctx_readout_async(sl.ctx);
+    if (st != SBQA_OK) return st;
+    HIP_CHECK_SERVE(hipEventRecord(sl.done, srv->stream));
+    sl.retiring = true;
+    return SBQA_OK;
+}
+
+// Its results once the readout has completed; the context's work is all
+// done, so it is released without a stream synchronisation.
+static void end_retire(sbqa_server *srv, Slot &sl) {
+    Result res;
+    res.status = SBQA_OK;
+    res.energies.resize(sl.req->runs);
+    res.spins.resize((size_t)sl.req->runs * sl.req->N);
+    const sbqa_status b = ctx_readout_collect(sl.ctx, res.energies.data(), res.spins.data());
+    if (b != SBQA_OK) {
+        res.status = b;
+        res.error = last_error();
+    }
+    delete sl.ctx;
+    sl.ctx = nullptr;
+    sl.retiring = false;
+    record_result(srv, sl, std::move(res));
+}
+
 static void finish(sbqa_server *srv, Slot &sl, sbqa_status st, const char *msg) {
     Result res;
     res.status = st;
@@ -189,15 +232,10 @@ static void finish(sbqa_server *srv, Slot &sl, sbqa_status st, const char *msg) 
     } else {
         res.error = msg ? msg : "";
     }
-    res.latency_s = std::chrono::duration<double>(Clock::now() - sl.req->t_submit).count();
     if (sl.ctx) sbqa_destroy(sl.ctx);
     sl.ctx = nullptr;
-    std::lock_guard<std::mutex> lk(srv->mu);
-    if (res.status == SBQA_OK) {
-        srv->completed += 1;
-        srv->updates += (double)sl.req->N * sl.req->R * sl.req->runs * sl.req->s.steps;
-    }
-    srv->results[sl.req->ticket] = std::move(res);
+    sl.retiring = false;
+    record_result(srv, sl, std::move(res));
 }
 
 // One step block for every resident instance: rewrite the task table, then
@@ -393,7 +431,9 @@ static void scheduler(sbqa_server *srv) {
             }
             int q = 0;
             while (slots[q].req) ++q;
+            const hipEvent_t ev = slots[q].done;   // the slot's event outlives its occupants
             slots[q] = std::move(*sp);
+            slots[q].done = ev;
             ++active;
         }
         // ---- one step block for every resident instance (grouped launches)
@@ -410,10 +450,40 @@ static void scheduler(sbqa_server *srv) {
                 --active;
             }
         }
-        // ---- retire finished instances
+        // ---- retire finished instances: readouts go behind the block just
+        // queued; the ones whose readout has completed hand over their results
+        bool running = false, waiting = false;
         for (Slot &sl : slots) {
-            if (!sl.ctx || sl.ctx->step < sl.ctx->s.steps) continue;
-            finish(srv, sl, SBQA_OK, nullptr);
+            if (!sl.ctx) continue;
+            if (sl.ctx->step < sl.ctx->s.steps) {
+                running = true;
+                continue;
+            }
+            if (!sl.retiring) {
+                const sbqa_status rs = begin_retire(srv, sl);
+                if (rs != SBQA_OK) {
+                    const std::string msg = last_error();
+                    finish(srv, sl, rs, msg.c_str());
+                    used -= sl.bytes;
+                    sl.req.reset();
+                    --admitted;
+                    --active;
+                    continue;
+                }
+            }
+            waiting = true;
+        }
+        if (waiting && !running) {
+            // nothing else to queue: wait for the oldest readout instead of spinning
+            for (Slot &sl : slots)
+                if (sl.ctx && sl.retiring) {
+                    (void)hipEventSynchronize(sl.done);
+                    break;
+                }
+        }
+        for (Slot &sl : slots) {
+            if (!sl.ctx || !sl.retiring || hipEventQuery(sl.done) != hipSuccess) continue;
+            end_retire(srv, sl);
             used -= sl.bytes;
             sl.req.reset();
             --admitted;
@@ -424,8 +494,10 @@ static void scheduler(sbqa_server *srv) {
             srv->busy_s += std::chrono::duration<double>(Clock::now() - t0).count();
         }
     }
-    for (Slot &sl : slots)
+    for (Slot &sl : slots) {
         if (sl.ctx) sbqa_destroy(sl.ctx);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+    }
 }
 
 static void release(sbqa_server *srv) {
