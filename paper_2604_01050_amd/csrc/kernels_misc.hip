@@ -9,6 +9,9 @@
 #include "sbqa_internal.h"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 namespace sbqa {
 namespace {
@@ -497,6 +500,20 @@ hipError_t launch_csr_energy_state(int N, int order, int ld, int C, const int32_
     return hipGetLastError();
 }
 
+hipError_t ensure_dyn_lds(const void *fn, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> limit;   // (kernel, device) -> limit set
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t &cur = limit[{fn, dev}];
+    if (lds <= cur) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) cur = lds;
+    return e;
+}
+
 int energy_colblock_rows(int rpb) { return (rpb + 7) / 8 * 8; }
 
 hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
@@ -511,7 +528,7 @@ hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int 
 #define SBQA_ECB(D_)                                                                                                 \
     case D_: {                                                                                                       \
         const void *fn = reinterpret_cast<const void *>(&k_csr_energy_colblock<D_>);                                 \
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                \
+        hipError_t e = ensure_dyn_lds(fn, lds);                                                                      \
         if (e != hipSuccess) return e;                                                                               \
         hipLaunchKernelGGL(k_csr_energy_colblock<D_>, grid, block, lds, st, N, ld, nrb, rpb, RS, rcol, rval, rh, x,  \
                            E);                                                                                       \

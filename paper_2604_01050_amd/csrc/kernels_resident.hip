@@ -326,7 +326,7 @@ template <int RPT, int D>
 static hipError_t launch_res(const ResidentArgs &a, int nwg, hipStream_t st) {
     const void *fn = reinterpret_cast<const void *>(&k_csr_resident<RPT, D>);
     const size_t lds = resident_lds_bytes(a.N, D);
-    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_dyn_lds(fn, lds);
     if (e != hipSuccess) return e;
     ResidentArgs arg = a;
     void *args[] = {&arg};
@@ -365,7 +365,7 @@ hipError_t resident_max_blocks(int D, int N, int *blocks_per_cu) {
 #define SBQA_OCC(R_, D_)                                                                                   \
     do {                                                                                                    \
         const void *f_ = reinterpret_cast<const void *>(&k_csr_resident<R_, D_>);                          \
-        e = hipFuncSetAttribute(f_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                  \
+        e = ensure_dyn_lds(f_, lds);                                                                        \
         if (e == hipSuccess)                                                                                \
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f_, RES_THREADS, lds);          \
     } while (0)

@@ -101,8 +101,7 @@ hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
         a.n0 + a.K > a.S)
         return hipErrorInvalidValue;
     const size_t lds = small_lds_bytes(a.N, a.R);
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_dense_small),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = ensure_dyn_lds(reinterpret_cast<const void *>(&k_dense_small), lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_dense_small, dim3(runs), dim3(SM_THREADS), lds, st, a);
     return hipGetLastError();

@@ -222,6 +222,10 @@ int resident_rpt(int N);             // rows per thread, or -1 when N is too lar
 int resident_rows(int N);            // padded row count NR, or -1
 int resident_threads();
 hipError_t resident_max_blocks(int D, int N, int *blocks_per_cu);
+// Raises a kernel's dynamic LDS limit on the current device to at least lds
+// bytes. The runtime call is made only when the limit grows (one lookup under
+// a mutex otherwise), so that launches do not pay for it every time.
+hipError_t ensure_dyn_lds(const void *fn, size_t lds);
 hipError_t launch_csr_resident(const ResidentArgs &a, int D, hipStream_t st);
 
 // Resident loop for small dense instances (kernels_small.hip): one
