@@ -216,16 +216,32 @@ __global__ __launch_bounds__(256) void k_csr_energy_final(int C, int nrb, const 
 // row blocks of rpb rows summed in row order (neighbours in CSR order), row
 // block rb added by thread rb % 256 in increasing rb, then the same LDS tree;
 // so the energies equal those of a spin-major context bit for bit. The block's
-// signs go to LDS once as sign-bit masks (0 or 0x80000000 per row and column,
-// sign(0) = +1): a term s_j J_ij, or s_i phi_i, is its float64 operand with
-// the high word xor-ed by the mask, exactly the product by +-1. Thread rb reads
-// its row block's couplings as one contiguous, 16-byte aligned run
-// ([nrb][RS][D] column indices and float64 weights, RS = rpb rounded up to 8,
-// padding index 0 with weight 0: a zero term leaves the sum unchanged;
-// [nrb][RS] fields h, 0 past N), eight rows of loads in flight at once (rows
-// past the block's end are discarded by a select).
+// signs go to LDS once, 8 bytes per row (byte k: 0x80 when column k is
+// negative, sign(0) = +1); a term s_j J_ij, or s_i phi_i, is its float64
+// operand with the high word xor-ed by the row's byte k moved to the top
+// (one byte permute), exactly the product by +-1. (32-byte rows of ready
+// masks cost twice the LDS reads and most of the time in bank conflicts.)
+// Thread rb reads its row block's couplings as one contiguous, 16-byte
+// aligned run ([nrb][RS][D] column indices and float64 weights, RS = rpb
+// rounded up to 8, padding index 0 with weight 0: a zero term leaves the sum
+// unchanged; [nrb][RS] fields h, 0 past N), eight rows of loads in flight at
+// once (rows past the block's end are discarded by a select).
 __device__ __forceinline__ double flip_sign(double v, uint32_t mask) {
     return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
+}
+// byte k (0..3) of w at the top of a word, the rest zero
+__device__ __forceinline__ uint32_t byte_to_top(uint32_t w, int k) {
+    return __builtin_amdgcn_perm(w, w, ((uint32_t)k << 24) | 0x000C0C0Cu);
+}
+// 8 sign bits (bit k: column k) as 8 bytes (0x80 per set bit)
+__device__ __forceinline__ uint2 spread_signs(uint32_t b) {
+    uint32_t lo = 0, hi = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lo |= ((b >> k) & 1u) << (8 * k + 7);
+        hi |= ((b >> (k + 4)) & 1u) << (8 * k + 7);
+    }
+    return make_uint2(lo, hi);
 }
 
 template <int D>
@@ -233,14 +249,35 @@ __global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int 
                                                              const int32_t *__restrict__ rcol,
                                                              const double *__restrict__ rval,
                                                              const double *__restrict__ rh,
-                                                             const float *__restrict__ x, double *__restrict__ E) {
+                                                             const float *__restrict__ x,
+                                                             const uint8_t *__restrict__ sbits,
+                                                             double *__restrict__ E) {
     extern __shared__ __align__(16) uint8_t smem[];
-    uint4 *sm = reinterpret_cast<uint4 *>(smem);   // [N][2]: sign masks of columns 0-3, 4-7
+    uint2 *sm = reinterpret_cast<uint2 *>(smem);   // [N]: sign bytes of columns 0-3, 4-7
     const int w = blockIdx.x, t = threadIdx.x;
     const float *xb = x + (int64_t)w * ld * 8;
-    auto msk = [](float v) { return v < 0.0f ? 0x80000000u : 0u; };
-    // 16 rows per thread in flight (one round trip for N <= 4096)
-    for (int base = 0; base < N; base += 256 * 16) {
+    // sign bytes: 16 rows per thread and load
+    for (int base = 0; sbits && base < N; base += 256 * 16) {
+        const int i0 = base + 16 * t;
+        if (i0 >= N) continue;
+        const uint8_t *sb = sbits + (int64_t)w * ld + i0;
+        uint4 v;
+        if (i0 + 16 <= N) v = *reinterpret_cast<const uint4 *>(sb);
+        else {
+            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+            for (int u = 0; i0 + u < N; ++u) wv[u / 4] |= (uint32_t)sb[u] << (8 * (u % 4));
+            v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        }
+        const uint32_t vw[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = i0 + u;
+            if (i < N) sm[i] = spread_signs((vw[u / 4] >> (8 * (u % 4))) & 0xFFu);
+        }
+    }
+    // from x: 16 rows per thread in flight (one round trip for N <= 4096)
+    auto sbyte = [](float v, int k) { return (v < 0.0f ? 0x80u : 0u) << (8 * k); };
+    for (int base = 0; !sbits && base < N; base += 256 * 16) {
         float4 a[16], b[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
@@ -251,10 +288,9 @@ __global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int 
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
             const int i = base + u * 256 + t;
-            if (i < N) {
-                sm[2 * i] = make_uint4(msk(a[u].x), msk(a[u].y), msk(a[u].z), msk(a[u].w));
-                sm[2 * i + 1] = make_uint4(msk(b[u].x), msk(b[u].y), msk(b[u].z), msk(b[u].w));
-            }
+            if (i < N)
+                sm[i] = make_uint2(sbyte(a[u].x, 0) | sbyte(a[u].y, 1) | sbyte(a[u].z, 2) | sbyte(a[u].w, 3),
+                                   sbyte(b[u].x, 0) | sbyte(b[u].y, 1) | sbyte(b[u].z, 2) | sbyte(b[u].w, 3));
         }
     }
     __syncthreads();
@@ -290,19 +326,16 @@ __global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int 
                 for (int k = 0; k < 8; ++k) phi[k] = 0.0;
 #pragma unroll
                 for (int p = 0; p < D; ++p) {
-                    const int j = cj[r * D + p];
-                    const uint4 m0 = sm[2 * j], m1 = sm[2 * j + 1];
-                    const uint32_t m[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+                    const uint2 m = sm[cj[r * D + p]];
                     const double v = vj[r * D + p];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) phi[k] += flip_sign(v, m[k]);
+                    for (int k = 0; k < 8; ++k) phi[k] += flip_sign(v, byte_to_top(k < 4 ? m.x : m.y, k & 3));
                 }
-                const int i = i0 + min(jb + r, nrow - 1);
-                const uint4 m0 = sm[2 * i], m1 = sm[2 * i + 1];
-                const uint32_t m[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+                const uint2 m = sm[i0 + min(jb + r, nrow - 1)];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
-                    const double nq = pq[k] + flip_sign(phi[k], m[k]), nl = pl[k] + flip_sign(hv[r], m[k]);
+                    const uint32_t mk = byte_to_top(k < 4 ? m.x : m.y, k & 3);
+                    const double nq = pq[k] + flip_sign(phi[k], mk), nl = pl[k] + flip_sign(hv[r], mk);
                     pq[k] = valid ? nq : pq[k];
                     pl[k] = valid ? nl : pl[k];
                 }
@@ -314,7 +347,7 @@ __global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int 
             l[k] += pl[k];
         }
     }
-    __syncthreads();   // the sign masks are dead: their LDS holds the reduction
+    __syncthreads();   // the signs are dead: their LDS holds the reduction
     double *sq = reinterpret_cast<double *>(smem), *sl = sq + 8 * 256;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
@@ -414,6 +447,15 @@ __global__ __launch_bounds__(1024) void k_best_update(int N, int R, int order, i
 }
 
 // Row-major N x N float64 rows into the first N columns of rows of length Np.
+// Whole 16-byte vectors, then the tail bytes one by one (thread 0).
+__global__ void k_copy_to_host(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, size_t bytes) {
+    const size_t nv = bytes / 16;
+    for (size_t q = (size_t)blockIdx.x * blockDim.x + threadIdx.x; q < nv; q += (size_t)gridDim.x * blockDim.x)
+        reinterpret_cast<uint4 *>(dst)[q] = reinterpret_cast<const uint4 *>(src)[q];
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        for (size_t b = nv * 16; b < bytes; ++b) dst[b] = src[b];
+}
+
 __global__ void k_pad_rows(const double *__restrict__ src, int N, int Np, double *__restrict__ dst) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)N * N) return;
@@ -433,6 +475,15 @@ __global__ void k_spins_to_rows(int N, int count, const int32_t *__restrict__ or
 }
 
 }  // namespace
+
+hipError_t launch_copy_to_host(const uint8_t *src, uint8_t *dst, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    if (((uintptr_t)src | (uintptr_t)dst) & 15) return hipErrorInvalidValue;
+    const size_t n16 = (bytes + 15) / 16;
+    const int blocks = (int)std::min<size_t>((n16 + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_copy_to_host, dim3(blocks), dim3(256), 0, st, src, dst, bytes);
+    return hipGetLastError();
+}
 
 hipError_t launch_pad_rows(const double *src, int N, int Np, double *dst, hipStream_t st) {
     const int64_t n = (int64_t)N * N;
@@ -517,11 +568,13 @@ hipError_t ensure_dyn_lds(const void *fn, size_t lds) {
 int energy_colblock_rows(int rpb) { return (rpb + 7) / 8 * 8; }
 
 hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
-                                      const double *rval, const double *rh, const float *x, double *E,
-                                      hipStream_t st) {
-    const size_t lds = std::max<size_t>((size_t)N * 32, 2 * 8 * 256 * sizeof(double));
+                                      const double *rval, const double *rh, const float *x,
+                                      const uint8_t *sbits, double *E, hipStream_t st) {
+    const size_t lds = std::max<size_t>((size_t)N * 8, 2 * 8 * 256 * sizeof(double));
     // even D: a batch of 8 rows is whole 16-byte vectors, and so is every row block's run
-    if (C % 8 || ld < N || (int64_t)nrb * rpb < N || lds > 160 * 1024 || D % 2) return hipErrorInvalidValue;
+    // sign bytes are read 16 rows at a time: a 16-byte aligned row stride
+    if (C % 8 || ld < N || (int64_t)nrb * rpb < N || lds > 160 * 1024 || D % 2 || (sbits && ld % 16))
+        return hipErrorInvalidValue;
     const int RS = energy_colblock_rows(rpb);
     const dim3 grid(C / 8), block(256);
     switch (D) {
@@ -531,7 +584,7 @@ hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int 
         hipError_t e = ensure_dyn_lds(fn, lds);                                                                      \
         if (e != hipSuccess) return e;                                                                               \
         hipLaunchKernelGGL(k_csr_energy_colblock<D_>, grid, block, lds, st, N, ld, nrb, rpb, RS, rcol, rval, rh, x,  \
-                           E);                                                                                       \
+                           sbits, E);                                                                                \
         break;                                                                                                       \
     }
         SBQA_ECB(4) SBQA_ECB(6) SBQA_ECB(8) SBQA_ECB(12) SBQA_ECB(16)

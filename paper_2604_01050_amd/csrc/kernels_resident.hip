@@ -25,9 +25,11 @@ using namespace csr;
 // every later wait ends at once, so the grid always drains. The host launches
 // the loop only when every workgroup fits on the device at once (occupancy
 // times CUs); there is no grid-wide barrier, so an ordinary launch suffices.
-// The state and operand are stored column-block-major (ORDER_COLBLOCK8): the
-// 8 columns of a workgroup for all rows are one contiguous run, so its
-// starting loads and final stores are whole-line sequential accesses.
+// The state is stored column-block-major (ORDER_COLBLOCK8): the 8 columns of
+// a workgroup for all rows are one contiguous run, so its starting loads and
+// final stores are whole-line sequential accesses. The operand is not kept in
+// memory between launches: each launch builds it from the starting x with the
+// same f as the host-side operand rebuild.
 // ---------------------------------------------------------------------------
 constexpr int RES_COLS = 8;
 constexpr int RES_THREADS = 512;
@@ -59,26 +61,6 @@ __device__ __forceinline__ half8 e4m3_to_half(uint2 v) {
     r[0] = a[0]; r[1] = a[1]; r[2] = b[0]; r[3] = b[1];
     r[4] = c[0]; r[5] = c[1]; r[6] = d[0]; r[7] = d[1];
     return r;
-}
-
-// int8 operand row (8 columns) <-> binary16 row, at the launch's start and end
-__device__ __forceinline__ half8 operand_to_half(uint2 v) {
-    half8 r;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        r[c] = (_Float16)(float)(int8_t)((v.x >> (8 * c)) & 0xFF);
-        r[c + 4] = (_Float16)(float)(int8_t)((v.y >> (8 * c)) & 0xFF);
-    }
-    return r;
-}
-__device__ __forceinline__ uint2 operand_to_int8(half8 f) {
-    uint32_t lo = 0, hi = 0;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        lo |= (uint32_t)(uint8_t)(int8_t)(float)f[c] << (8 * c);
-        hi |= (uint32_t)(uint8_t)(int8_t)(float)f[c + 4] << (8 * c);
-    }
-    return make_uint2(lo, hi);
 }
 
 // Edge columns cross workgroups (possibly on different XCDs) through
@@ -133,7 +115,6 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
     for (int q = 0; q < RPT; ++q) {
         int r = t + q * RES_THREADS;
         asm volatile("" : "+v"(r));
-        op[r] = operand_to_half(*reinterpret_cast<const uint2 *>(a.g + ((int64_t)w * NR + r) * RES_COLS));
 #pragma unroll
         for (int p = 0; p < D; ++p) wv[(q * D + p) * RES_THREADS + t] = a.valpad[(int64_t)p * NR + r];
     }
@@ -145,6 +126,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
     auto slot = [&](int b, int v, int e) { return a.xpub + (((int64_t)b * a.nwg + v) * 2 + e) * NR; };
     {
         float *pf = slot(a.n0 & 1, w, 0), *pl = slot(a.n0 & 1, w, 1);
+        const float d0 = a.delta[a.n0];   // the operand of step n0 is f(x) at Delta_n0
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int r = t + q * RES_THREADS;
@@ -159,6 +141,10 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
             xs[q][4] = x1.x; xs[q][5] = x1.y; xs[q][6] = x1.z; xs[q][7] = x1.w;
             ys[q][0] = y0.x; ys[q][1] = y0.y; ys[q][2] = y0.z; ys[q][3] = y0.w;
             ys[q][4] = y1.x; ys[q][5] = y1.y; ys[q][6] = y1.z; ys[q][7] = y1.w;
+            half8 f0;
+#pragma unroll
+            for (int c = 0; c < RES_COLS; ++c) f0[c] = (_Float16)f_value(a.fmode, xs[q][c], d0);
+            op[r] = f0;
 #pragma unroll
             for (int p = 0; p < D; p += 2) {
                 // LDS byte offsets of the neighbours' operand rows (< 2^16)
@@ -274,9 +260,12 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         __syncthreads();
     }
 
-    // write back the state and the operand of the own columns (the row index
-    // is passed through an empty asm so these addresses are recomputed here
-    // rather than kept live across the step loop)
+    // write back the state of the own columns (the row index is passed
+    // through an empty asm so these addresses are recomputed here rather than
+    // kept live across the step loop), and one byte of sign bits per row (bit
+    // c: column c negative) for the readout energies. (Storing each row during
+    // the last step instead overlaps the stores with that step, 5 us less per
+    // launch, but costs registers in the loop: 2% more per step.)
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         int r = t + q * RES_THREADS;
@@ -287,7 +276,10 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         *reinterpret_cast<float4 *>(xrow + 4) = make_float4(xs[q][4], xs[q][5], xs[q][6], xs[q][7]);
         *reinterpret_cast<float4 *>(yrow) = make_float4(ys[q][0], ys[q][1], ys[q][2], ys[q][3]);
         *reinterpret_cast<float4 *>(yrow + 4) = make_float4(ys[q][4], ys[q][5], ys[q][6], ys[q][7]);
-        *reinterpret_cast<uint2 *>(a.g + ((int64_t)w * NR + r) * RES_COLS) = operand_to_int8(op[r]);
+        uint32_t sb = 0;
+#pragma unroll
+        for (int c = 0; c < RES_COLS; ++c) sb |= (xs[q][c] < 0.0f ? 1u : 0u) << c;
+        a.sbits[(int64_t)w * NR + r] = (uint8_t)sb;
     }
 }
 

@@ -570,8 +570,13 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
     HIP_TRY(dalloc(c, &c->bestStep, (size_t)runs));
     c->rbytes = (size_t)8 * runs + 8 + (size_t)runs * N;
     HIP_TRY(dalloc(c, &c->rdev, c->rbytes));
-    HIP_TRY(hipHostMalloc((void **)&c->rhost, c->rbytes, hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc((void **)&c->rhost, c->rbytes, hipHostMallocCoherent));
     std::memset(c->rhost, 0, c->rbytes);
+    {
+        void *dp = nullptr;
+        if (hipHostGetDevicePointer(&dp, c->rhost, 0) == hipSuccess) c->rhost_dev = static_cast<uint8_t *>(dp);
+        else (void)hipGetLastError();   // keep the copy engine path
+    }
     c->bestE = reinterpret_cast<double *>(c->rdev);
     c->err = reinterpret_cast<int *>(c->rdev + (size_t)8 * runs);
     c->bestSpins = reinterpret_cast<int8_t *>(c->rdev + (size_t)8 * runs + 8);
@@ -682,6 +687,7 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
             HIP_TRY(dalloc(c, &c->xpub, (size_t)2 * c->res_nwg * 2 * NR));
             HIP_TRY(dalloc(c, &c->flags, (size_t)c->res_nwg));
             HIP_TRY(dalloc(c, &c->epoch_cnt, (size_t)c->res_nwg));
+            HIP_TRY(dalloc(c, &c->sbits, (size_t)c->res_nwg * NR));
             HIP_TRY(hipMemcpyAsync(c->colpad, cp.data(), sizeof(int32_t) * cp.size(), hipMemcpyHostToDevice, c->stream));
             HIP_TRY(hipMemcpyAsync(c->valpad, vp.data(), sizeof(float) * vp.size(), hipMemcpyHostToDevice, c->stream));
         }
@@ -813,8 +819,9 @@ sbqa_status ctx_state_energies(sbqa_ctx *c) {
     const double *h64 = c->has_h ? c->h64 : nullptr;
     if (sm && c->order == ORDER_COLBLOCK8 && !c->facts.n3) {
         const int nrb = c->L.csr_nrb, rpb = (c->N + nrb - 1) / nrb;
+        const uint8_t *sb = c->sbits_step == (int64_t)c->step ? c->sbits : nullptr;
         HIP_TRY(launch_csr_energy_colblock(c->N, c->ld, c->L.C, c->res_D, nrb, rpb, c->rcol, c->rval, c->rh,
-                                           c->x[c->cur], c->E, c->stream));
+                                           c->x[c->cur], sb, c->E, c->stream));
     } else if (sm) {
         HIP_TRY(launch_csr_energy_state(c->N, c->order, c->ld, c->L.C, c->rp, c->col, c->val64, c->tri3(), h64, c->x[c->cur],
                                         c->csr_partial, c->L.csr_nrb, c->E, c->stream));
@@ -1166,7 +1173,6 @@ static sbqa_status ctx_step_resident(sbqa_ctx *c, uint32_t K) {
     a.h = c->h32;
     a.x = c->x[c->cur];
     a.y = c->y;
-    a.g = (int8_t *)c->g[c->cur];
     a.jp = c->jp;
     a.coefA = c->coefA;
     a.delta = c->delta_tab;
@@ -1179,8 +1185,10 @@ static sbqa_status ctx_step_resident(sbqa_ctx *c, uint32_t K) {
     a.epoch_cnt = c->epoch_cnt;
     a.epoch = ++c->epoch;
     a.err = c->err;
+    a.sbits = c->sbits;
     HIP_TRY(launch_csr_resident(a, c->res_D, c->stream));
     c->step += K;
+    c->sbits_step = c->step;
     return SBQA_OK;
 }
 
@@ -1236,7 +1244,10 @@ sbqa_status ctx_readout_async(sbqa_ctx *c) {
         sbqa_status st = ctx_evaluate(c, reset);
         if (st != SBQA_OK) return st;
     }
-    HIP_TRY(hipMemcpyAsync(c->rhost, c->rdev, c->rbytes, hipMemcpyDeviceToHost, c->stream));
+    // a copy kernel right behind the readout kernels (a runtime copy started
+    // 11 us after the last kernel had finished)
+    if (c->rhost_dev) HIP_TRY(launch_copy_to_host(c->rdev, c->rhost_dev, c->rbytes, c->stream));
+    else HIP_TRY(hipMemcpyAsync(c->rhost, c->rdev, c->rbytes, hipMemcpyDeviceToHost, c->stream));
     return SBQA_OK;
 }
 
@@ -1454,6 +1465,7 @@ sbqa_status sbqa_set_state(sbqa_ctx *c, const float *x, const float *y) {
     }
     HIP_TRY(hipMemcpyAsync(c->x[c->cur], bx.data(), sizeof(float) * tot, hipMemcpyHostToDevice, c->stream));
     HIP_TRY(hipMemcpyAsync(c->y, by.data(), sizeof(float) * tot, hipMemcpyHostToDevice, c->stream));
+    c->sbits_step = -1;
     sbqa_status st = rebuild_operand(c);
     if (st != SBQA_OK) return st;
     HIP_TRY(hipStreamSynchronize(c->stream));

@@ -139,8 +139,10 @@ struct sbqa_ctx {
     int64_t *bestStep = nullptr;
     // readout block, one device allocation copied to the host in one piece:
     // best energies [runs] float64, the error word of the resident loop (8
-    // bytes), best spins [runs][N] int8; rhost is its pinned host copy
-    uint8_t *rdev = nullptr, *rhost = nullptr;
+    // bytes), best spins [runs][N] int8; rhost is its pinned, coherent host
+    // copy and rhost_dev the device address of rhost (a copy kernel writes
+    // it; nullptr: hipMemcpyAsync does)
+    uint8_t *rdev = nullptr, *rhost = nullptr, *rhost_dev = nullptr;
     size_t rbytes = 0;
     double *bestE = nullptr;
     int *err = nullptr;                 // ring-neighbour wait timeouts (resident loop)
@@ -162,6 +164,10 @@ struct sbqa_ctx {
     float *coefA = nullptr;             // [S]
     float *delta_tab = nullptr;         // [S+1]
     float *xpub = nullptr;              // [2][nwg][2][rows] published edge columns
+    // sign bytes of the state the resident loop left ([nwg][rows], bit k: x
+    // of the block's column k is negative), valid while sbits_step == step
+    uint8_t *sbits = nullptr;
+    int64_t sbits_step = -1;
     int *flags = nullptr, *epoch_cnt = nullptr;
     int epoch = 0;
 

@@ -204,7 +204,6 @@ struct ResidentArgs {
     const float *valpad;    // [D][NR] weights, padded with 0
     const float *h;         // [NR]
     float *x, *y;           // ORDER_COLBLOCK8 [nwg][NR][8] state, updated in place
-    int8_t *g;              // ORDER_COLBLOCK8 [nwg][NR][8] operand, updated in place
     const float *jp;        // [runs][S]
     const float *coefA;     // [S]   (a0 - a_n)/R
     const float *delta;     // [S+1] Delta_n
@@ -214,6 +213,7 @@ struct ResidentArgs {
     int *epoch_cnt;         // [nwg] launches started (monotonic)
     int epoch;              // this launch's number (>= 1)
     int *err;               // [1] set on a wait timeout
+    uint8_t *sbits;         // [nwg][NR] sign bytes of the final state (bit k: column k negative)
 };
 int resident_degree(int maxdeg);        // padded degree D, or -1 when too large
 size_t resident_lds_bytes(int N, int D);
@@ -274,6 +274,9 @@ hipError_t launch_readout_f64(int N, int Np, int C, int ld, bool spin_major, con
 // Row-major N x N float64 src into the first N columns of the rows of dst
 // (row length Np >= N; the rest of dst is left as it is).
 hipError_t launch_pad_rows(const double *src, int N, int Np, double *dst, hipStream_t st);
+// bytes from device memory src to dst, the device address of pinned coherent
+// host memory (both 16-byte aligned), written by the device over the bus
+hipError_t launch_copy_to_host(const uint8_t *src, uint8_t *dst, size_t bytes, hipStream_t st);
 
 // Spin rows [count][N] in the caller's order -> internal rows (row i holds the
 // caller's spin orig[i]).
@@ -300,11 +303,13 @@ hipError_t launch_csr_energy_state(int N, int order, int ld, int C, const int32_
 // rb*rpb + rpb - 1, the row blocks of the spin-major energies: nrb * rpb >= N)
 // are one run per row block: rcol / rval [nrb][RS][D] (neighbours in CSR
 // order, then index 0 with weight 0), rh [nrb][RS] (h, 0 past N), with
-// RS = energy_colblock_rows(rpb).
+// RS = energy_colblock_rows(rpb). sbits: the sign bytes the resident loop
+// wrote for this same x ([C/8][ld], bit k: column k negative), read in place
+// of x's 32 bytes per row and block; nullptr: the signs are taken from x.
 int energy_colblock_rows(int rpb);
 hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
-                                      const double *rval, const double *rh, const float *x, double *E,
-                                      hipStream_t st);
+                                      const double *rval, const double *rh, const float *x,
+                                      const uint8_t *sbits, double *E, hipStream_t st);
 hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col,
                                    const double *val, const Tri3 &t3, const double *h, const int8_t *spins,
                                    double *E, hipStream_t st);

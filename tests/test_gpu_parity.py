@@ -947,12 +947,14 @@ def test_resident_loop_matches_streaming(sb, orc, name, N, d, R, runs, fmode, ee
         one = sb.sbqa_get_state(ctx)
         x, y = one
         sb.sbqa_set_state(ctx, x, y)
+        best_set = sb.sbqa_best(ctx)       # signs from the state just written
         sb.sbqa_step(ctx, 50)
         sb.sbqa_step(ctx, S - 88)
         fin = sb.sbqa_get_state(ctx)
-        best = sb.sbqa_best(ctx)
-        out[kern] = (mid, one, fin, best, sb.sbqa_best_step(ctx), sb.sbqa_info(ctx)["c0"], phi_mid)
+        best = sb.sbqa_best(ctx)           # signs the resident loop left
+        out[kern] = (mid, one, fin, best, sb.sbqa_best_step(ctx), sb.sbqa_info(ctx)["c0"], phi_mid, best_set)
     a, b = out[sb.LOOP_STREAM], out[sb.LOOP_RESIDENT]
+    assert np.array_equal(a[7][0], b[7][0]) and np.array_equal(a[7][1], b[7][1])
     for u, v in zip(a[:3], b[:3]):
         assert np.array_equal(u[0], v[0]) and np.array_equal(u[1], v[1])
     assert np.array_equal(a[3][0], b[3][0]) and np.array_equal(a[3][1], b[3][1])
