@@ -2,6 +2,8 @@
 // launch (see the description below).
 #include "csr_common.h"
 
+#include <type_traits>
+
 namespace sbqa {
 namespace {
 
@@ -166,7 +168,13 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
     __syncthreads();
 
     float kA = a.coefA[a.n0], dn = a.delta[a.n0 + 1], jpr = a.jp[(int64_t)run * a.S + a.n0];
-    for (int s = 0; s < a.K; ++s) {
+    // one step; the launch's last one (LAST) is a separate copy that stores
+    // each row's final state as soon as the row is updated, so that the
+    // stores drain while the other rows compute, and skips the hand-over to
+    // a next step (with the stores in the loop itself the loop needed 27 more
+    // registers and ran 2% slower)
+    auto step = [&](int s, auto last_c) __attribute__((always_inline)) {
+        constexpr bool LAST = decltype(last_c)::value;
         // compiler-only barriers: the loop-invariant LDS weights are re-read
         // every step instead of being pinned in registers, and the packed
         // neighbour offsets are unpacked every step instead of being kept
@@ -179,7 +187,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         const int n = a.n0 + s;
         const float d = (a.fmode == 1) ? 0.0f : dn;
         const float kA_n = kA, jp_n = jpr;
-        if (s + 1 < a.K) {  // the next step's scalars load while this step runs
+        if (!LAST) {  // the next step's scalars load while this step runs
             kA = a.coefA[n + 1];
             dn = a.delta[n + 2];
             jpr = a.jp[(int64_t)run * a.S + n + 1];
@@ -237,13 +245,29 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
             // next step and their condition masks pile up in scalar registers
 #pragma unroll
             for (int c = 0; c < RES_COLS; ++c) asm volatile("" : "+v"(ys[q][c]));
-            fnew[q] = pack_e4m3(fv);
-            publish(pf + r, xs[q][0]);
-            publish(pl + r, xs[q][RES_COLS - 1]);
+            if constexpr (LAST) {
+                // the final state of the row, and one byte of sign bits (bit
+                // c: column c negative) for the readout energies
+                float *xrow = a.x + ((int64_t)w * NR + r) * RES_COLS;
+                float *yrow = a.y + ((int64_t)w * NR + r) * RES_COLS;
+                *reinterpret_cast<float4 *>(xrow) = make_float4(xs[q][0], xs[q][1], xs[q][2], xs[q][3]);
+                *reinterpret_cast<float4 *>(xrow + 4) = make_float4(xs[q][4], xs[q][5], xs[q][6], xs[q][7]);
+                *reinterpret_cast<float4 *>(yrow) = make_float4(ys[q][0], ys[q][1], ys[q][2], ys[q][3]);
+                *reinterpret_cast<float4 *>(yrow + 4) = make_float4(ys[q][4], ys[q][5], ys[q][6], ys[q][7]);
+                uint32_t sb = 0;
+#pragma unroll
+                for (int c = 0; c < RES_COLS; ++c) sb |= (xs[q][c] < 0.0f ? 1u : 0u) << c;
+                a.sbits[(int64_t)w * NR + r] = (uint8_t)sb;
+            } else {
+                fnew[q] = pack_e4m3(fv);
+                publish(pf + r, xs[q][0]);
+                publish(pl + r, xs[q][RES_COLS - 1]);
+            }
             // keep rows apart in the schedule: hoisting every row's gathers
             // ahead raises the register demand past two waves per SIMD
             __builtin_amdgcn_sched_barrier(0);
         }
+        if constexpr (LAST) return;
         __syncthreads();  // every wave is done reading the step-n operand
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
@@ -258,29 +282,9 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
             wait_neighbours(a.flags, wl, wr, n + 1, a.err);
         }
         __syncthreads();
-    }
-
-    // write back the state of the own columns (the row index is passed
-    // through an empty asm so these addresses are recomputed here rather than
-    // kept live across the step loop), and one byte of sign bits per row (bit
-    // c: column c negative) for the readout energies. (Storing each row during
-    // the last step instead overlaps the stores with that step, 5 us less per
-    // launch, but costs registers in the loop: 2% more per step.)
-#pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-        int r = t + q * RES_THREADS;
-        asm volatile("" : "+v"(r));
-        float *xrow = a.x + ((int64_t)w * NR + r) * RES_COLS;
-        float *yrow = a.y + ((int64_t)w * NR + r) * RES_COLS;
-        *reinterpret_cast<float4 *>(xrow) = make_float4(xs[q][0], xs[q][1], xs[q][2], xs[q][3]);
-        *reinterpret_cast<float4 *>(xrow + 4) = make_float4(xs[q][4], xs[q][5], xs[q][6], xs[q][7]);
-        *reinterpret_cast<float4 *>(yrow) = make_float4(ys[q][0], ys[q][1], ys[q][2], ys[q][3]);
-        *reinterpret_cast<float4 *>(yrow + 4) = make_float4(ys[q][4], ys[q][5], ys[q][6], ys[q][7]);
-        uint32_t sb = 0;
-#pragma unroll
-        for (int c = 0; c < RES_COLS; ++c) sb |= (xs[q][c] < 0.0f ? 1u : 0u) << c;
-        a.sbits[(int64_t)w * NR + r] = (uint8_t)sb;
-    }
+    };
+    for (int s = 0; s + 1 < a.K; ++s) step(s, std::false_type{});
+    step(a.K - 1, std::true_type{});
 }
 
 }  // namespace
