@@ -183,14 +183,14 @@ __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int order, in
     partial[((int64_t)rb * C + c) * 3 + 2] = q3;
 }
 
-// Stage 2: block per column, strided per-thread sums over the row blocks,
-// then a fixed LDS tree.
-__global__ __launch_bounds__(256) void k_csr_energy_final(int C, int nrb, const double *__restrict__ partial,
-                                                          double *__restrict__ E) {
-    __shared__ double sq[256], sl[256], s3[256];
+// Stage 2: block per column, thread t sums the row blocks of slot t in
+// increasing order, then the pairwise tree over the slots.
+__global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_final(int C, int nrb, const double *__restrict__ partial,
+                                                                   double *__restrict__ E) {
+    __shared__ double sq[ENERGY_SLOTS], sl[ENERGY_SLOTS], s3[ENERGY_SLOTS];
     const int c = blockIdx.x, t = threadIdx.x;
     double q = 0.0, l = 0.0, q3 = 0.0;
-    for (int rb = t; rb < nrb; rb += 256) {
+    for (int rb = t; rb < nrb; rb += ENERGY_SLOTS) {
         q += partial[((int64_t)rb * C + c) * 3];
         l += partial[((int64_t)rb * C + c) * 3 + 1];
         q3 += partial[((int64_t)rb * C + c) * 3 + 2];
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256) void k_csr_energy_final(int C, int nrb, const 
     sl[t] = l;
     s3[t] = q3;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = ENERGY_SLOTS / 2; w > 0; w >>= 1) {
         if (t < w) {
             sq[t] += sq[t + w];
             sl[t] += sl[t + w];
@@ -211,21 +211,21 @@ __global__ __launch_bounds__(256) void k_csr_energy_final(int C, int nrb, const 
 }
 
 // CSR energies of the readout of a column-block state (ORDER_COLBLOCK8, no
-// three-body terms), one workgroup per block of 8 columns. The sums are those
-// of k_csr_energy_partial + k_csr_energy_final, in the same order: per column,
-// row blocks of rpb rows summed in row order (neighbours in CSR order), row
-// block rb added by thread rb % 256 in increasing rb, then the same LDS tree;
-// so the energies equal those of a spin-major context bit for bit. The block's
-// signs go to LDS once, 8 bytes per row (byte k: 0x80 when column k is
-// negative, sign(0) = +1); a term s_j J_ij, or s_i phi_i, is its float64
-// operand with the high word xor-ed by the row's byte k moved to the top
-// (one byte permute), exactly the product by +-1. (32-byte rows of ready
-// masks cost twice the LDS reads and most of the time in bank conflicts.)
-// Thread rb reads its row block's couplings as one contiguous, 16-byte
-// aligned run ([nrb][RS][D] column indices and float64 weights, RS = rpb
-// rounded up to 8, padding index 0 with weight 0: a zero term leaves the sum
-// unchanged; [nrb][RS] fields h, 0 past N), eight rows of loads in flight at
-// once (rows past the block's end are discarded by a select).
+// three-body terms), one workgroup of ENERGY_SLOTS threads per block of 8
+// columns. The sums are those of k_csr_energy_partial + k_csr_energy_final,
+// in the same order: per column, row blocks of rpb rows summed in row order
+// (neighbours in CSR order), row block rb added by thread rb % ENERGY_SLOTS
+// in increasing rb, then the same pairwise tree; so the energies equal those
+// of a spin-major context bit for bit. The block's signs go to LDS once, 8
+// bytes per row (byte k: 0x80 when column k is negative, sign(0) = +1); a
+// term s_j J_ij, or s_i phi_i, is its float64 operand with the high word
+// xor-ed by the row's byte k moved to the top (one byte permute), exactly the
+// product by +-1. The couplings are stored with the row block innermost
+// ([RS][D][nrb] column indices and float64 weights, padding index 0 with
+// weight 0: a zero term leaves the sum unchanged; [RS][nrb] fields h, 0 past
+// N), so that the threads of a wave, which take consecutive row blocks, read
+// consecutive words (a run per row block put every lane on its own cache
+// lines).
 __device__ __forceinline__ double flip_sign(double v, uint32_t mask) {
     return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
 }
@@ -245,19 +245,25 @@ __device__ __forceinline__ uint2 spread_signs(uint32_t b) {
 }
 
 template <int D>
-__global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int nrb, int rpb, int RS,
-                                                             const int32_t *__restrict__ rcol,
-                                                             const double *__restrict__ rval,
-                                                             const double *__restrict__ rh,
-                                                             const float *__restrict__ x,
-                                                             const uint8_t *__restrict__ sbits,
-                                                             double *__restrict__ E) {
+__global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_colblock(int N, int ld, int nrb, int rpb, int RS,
+                                                                      const int32_t *__restrict__ rcol,
+                                                                      const double *__restrict__ rval,
+                                                                      const double *__restrict__ rh,
+                                                                      const float *__restrict__ x,
+                                                                      const uint8_t *__restrict__ sbits,
+                                                                      double *__restrict__ E) {
+    constexpr int T = ENERGY_SLOTS;
+    // rows whose loads are issued together, neighbours per group of loads
+    // (within 128 registers per lane)
+    constexpr int RB = D <= 4 ? 2 : 1;
+    constexpr int G = D <= 8 ? D : 4;
+    static_assert(D % G == 0, "whole neighbour groups");
     extern __shared__ __align__(16) uint8_t smem[];
     uint2 *sm = reinterpret_cast<uint2 *>(smem);   // [N]: sign bytes of columns 0-3, 4-7
     const int w = blockIdx.x, t = threadIdx.x;
     const float *xb = x + (int64_t)w * ld * 8;
     // sign bytes: 16 rows per thread and load
-    for (int base = 0; sbits && base < N; base += 256 * 16) {
+    for (int base = 0; sbits && base < N; base += T * 16) {
         const int i0 = base + 16 * t;
         if (i0 >= N) continue;
         const uint8_t *sb = sbits + (int64_t)w * ld + i0;
@@ -275,61 +281,64 @@ __global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int 
             if (i < N) sm[i] = spread_signs((vw[u / 4] >> (8 * (u % 4))) & 0xFFu);
         }
     }
-    // from x: 16 rows per thread in flight (one round trip for N <= 4096)
+    // from x: 4 rows per thread in flight (one round trip for N <= 4096)
     auto sbyte = [](float v, int k) { return (v < 0.0f ? 0x80u : 0u) << (8 * k); };
-    for (int base = 0; !sbits && base < N; base += 256 * 16) {
-        float4 a[16], b[16];
+    for (int base = 0; !sbits && base < N; base += T * 4) {
+        float4 a[4], b[4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = min(base + u * 256 + t, N - 1);
+        for (int u = 0; u < 4; ++u) {
+            const int i = min(base + u * T + t, N - 1);
             a[u] = *reinterpret_cast<const float4 *>(xb + (int64_t)i * 8);
             b[u] = *reinterpret_cast<const float4 *>(xb + (int64_t)i * 8 + 4);
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = base + u * 256 + t;
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * T + t;
             if (i < N)
                 sm[i] = make_uint2(sbyte(a[u].x, 0) | sbyte(a[u].y, 1) | sbyte(a[u].z, 2) | sbyte(a[u].w, 3),
                                    sbyte(b[u].x, 0) | sbyte(b[u].y, 1) | sbyte(b[u].z, 2) | sbyte(b[u].w, 3));
         }
     }
     __syncthreads();
-    constexpr int RB = 8;   // rows whose loads are issued together
     double q[8], l[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) q[k] = l[k] = 0.0;
-    for (int rb = t; rb < nrb; rb += 256) {
+    for (int rb = t; rb < nrb; rb += T) {
         double pq[8], pl[8];
 #pragma unroll
         for (int k = 0; k < 8; ++k) pq[k] = pl[k] = 0.0;
         const int i0 = rb * rpb, nrow = min(N - i0, rpb);
-        const int4 *cb = reinterpret_cast<const int4 *>(rcol + (int64_t)rb * RS * D);
-        const double2 *vb = reinterpret_cast<const double2 *>(rval + (int64_t)rb * RS * D);
-        const double2 *hb = reinterpret_cast<const double2 *>(rh + (int64_t)rb * RS);
         for (int jb = 0; jb < nrow; jb += RB) {
-            int4 c4[RB * D / 4];
-            double2 v2[RB * D / 2], h2[RB / 2];
+            double hv[RB];
+            // rows past the block's end: their run's padding (RS >= rpb
+            // rounded up to RB), discarded below
 #pragma unroll
-            for (int e = 0; e < RB * D / 4; ++e) c4[e] = cb[jb * D / 4 + e];
-#pragma unroll
-            for (int e = 0; e < RB * D / 2; ++e) v2[e] = vb[jb * D / 2 + e];
-#pragma unroll
-            for (int e = 0; e < RB / 2; ++e) h2[e] = hb[jb / 2 + e];
-            const int *cj = reinterpret_cast<const int *>(c4);
-            const double *vj = reinterpret_cast<const double *>(v2);
-            const double *hv = reinterpret_cast<const double *>(h2);
+            for (int r = 0; r < RB; ++r) hv[r] = rh[(uint32_t)((jb + r) * nrb + rb)];
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const bool valid = jb + r < nrow;
                 double phi[8];
 #pragma unroll
                 for (int k = 0; k < 8; ++k) phi[k] = 0.0;
+                // neighbours in groups of G (all of them for D <= 8): a
+                // group's loads in flight together
 #pragma unroll
-                for (int p = 0; p < D; ++p) {
-                    const uint2 m = sm[cj[r * D + p]];
-                    const double v = vj[r * D + p];
+                for (int p0 = 0; p0 < D; p0 += G) {
+                    int cj[G];
+                    double vj[G];
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) phi[k] += flip_sign(v, byte_to_top(k < 4 ? m.x : m.y, k & 3));
+                    for (int e = 0; e < G; ++e) {
+                        const uint32_t o = (uint32_t)(((jb + r) * D + p0 + e) * nrb + rb);   // < 2^31
+                        cj[e] = rcol[o];
+                        vj[e] = rval[o];
+                    }
+#pragma unroll
+                    for (int p = 0; p < G; ++p) {
+                        const uint2 m = sm[cj[p]];
+                        const double v = vj[p];
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) phi[k] += flip_sign(v, byte_to_top(k < 4 ? m.x : m.y, k & 3));
+                    }
                 }
                 const uint2 m = sm[i0 + min(jb + r, nrow - 1)];
 #pragma unroll
@@ -348,25 +357,25 @@ __global__ __launch_bounds__(256) void k_csr_energy_colblock(int N, int ld, int 
         }
     }
     __syncthreads();   // the signs are dead: their LDS holds the reduction
-    double *sq = reinterpret_cast<double *>(smem), *sl = sq + 8 * 256;
+    double *sq = reinterpret_cast<double *>(smem), *sl = sq + 8 * T;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        sq[k * 256 + t] = q[k];
-        sl[k * 256 + t] = l[k];
+        sq[k * T + t] = q[k];
+        sl[k * T + t] = l[k];
     }
     __syncthreads();
-    for (int s2 = 128; s2 > 0; s2 >>= 1) {
+    for (int s2 = T / 2; s2 > 0; s2 >>= 1) {
         if (t < s2)
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                sq[k * 256 + t] += sq[k * 256 + t + s2];
-                sl[k * 256 + t] += sl[k * 256 + t + s2];
+                sq[k * T + t] += sq[k * T + t + s2];
+                sl[k * T + t] += sl[k * T + t + s2];
             }
         __syncthreads();
     }
     if (t < 8) {
         const double s3 = 0.0;   // no three-body terms on this path
-        E[w * 8 + t] = -0.5 * sq[t * 256] - sl[t * 256] - s3 / 3.0;
+        E[w * 8 + t] = -0.5 * sq[t * T] - sl[t * T] - s3 / 3.0;
     }
 }
 
@@ -547,7 +556,7 @@ hipError_t launch_csr_energy_state(int N, int order, int ld, int C, const int32_
     dim3 grid((C + 255) / 256, nblk_rows), block(256);
     hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, order, ld, C, rows_per_blk, row_ptr, col, val, t3,
                        h, x, partial);
-    hipLaunchKernelGGL(k_csr_energy_final, dim3(C), dim3(256), 0, st, C, nblk_rows, partial, E);
+    hipLaunchKernelGGL(k_csr_energy_final, dim3(C), dim3(ENERGY_SLOTS), 0, st, C, nblk_rows, partial, E);
     return hipGetLastError();
 }
 
@@ -565,18 +574,22 @@ hipError_t ensure_dyn_lds(const void *fn, size_t lds) {
     return e;
 }
 
-int energy_colblock_rows(int rpb) { return (rpb + 7) / 8 * 8; }
+// rows of a row block in the coupling copy: rpb rounded up to the kernel's
+// batch of rows (2)
+int energy_colblock_rows(int rpb) { return (rpb + 1) / 2 * 2; }
 
 hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
                                       const double *rval, const double *rh, const float *x,
                                       const uint8_t *sbits, double *E, hipStream_t st) {
-    const size_t lds = std::max<size_t>((size_t)N * 8, 2 * 8 * 256 * sizeof(double));
+    const size_t lds = std::max<size_t>((size_t)N * 8, 2 * 8 * (size_t)ENERGY_SLOTS * sizeof(double));
     // even D: a batch of 8 rows is whole 16-byte vectors, and so is every row block's run
     // sign bytes are read 16 rows at a time: a 16-byte aligned row stride
-    if (C % 8 || ld < N || (int64_t)nrb * rpb < N || lds > 160 * 1024 || D % 2 || (sbits && ld % 16))
-        return hipErrorInvalidValue;
     const int RS = energy_colblock_rows(rpb);
-    const dim3 grid(C / 8), block(256);
+    // the kernel indexes the coupling copy with 32-bit offsets
+    if (C % 8 || ld < N || (int64_t)nrb * rpb < N || lds > 160 * 1024 || D % 2 || (sbits && ld % 16) ||
+        (int64_t)RS * D * nrb >= ((int64_t)1 << 31))
+        return hipErrorInvalidValue;
+    const dim3 grid(C / 8), block(ENERGY_SLOTS);
     switch (D) {
 #define SBQA_ECB(D_)                                                                                                 \
     case D_: {                                                                                                       \

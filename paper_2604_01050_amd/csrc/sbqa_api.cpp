@@ -320,9 +320,11 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         b += 2 * (int64_t)N * L->Cs;                                      // int8 operand ping-pong
         b += (int64_t)(N + 1) * 4 + f.nnz * (4 + 4 + 8);                 // CSR
         b += (int64_t)N * 12;                                             // h32, h64
-        // energy row blocks: about 2048 blocks over the column chunks, >= 16 rows each
+        // energy row blocks: at least one per reduction slot (ENERGY_SLOTS),
+        // about 2048 blocks over the column chunks, >= 4 rows each
         const int64_t ncb = (C + 255) / 256;
-        L->csr_nrb = (int)std::max<int64_t>(1, std::min<int64_t>((N + 15) / 16, (2048 + ncb - 1) / ncb));
+        L->csr_nrb = (int)std::max<int64_t>(
+            1, std::min<int64_t>((N + 3) / 4, std::max<int64_t>(ENERGY_SLOTS, (2048 + ncb - 1) / ncb)));
         b += (int64_t)L->csr_nrb * C * 24;
         if (f.n3) b += (int64_t)(N + 1) * 4 + 3 * f.n3 * (8 + 4 + 8);    // three-body lists
         b += (int64_t)N * L->Cs * 4;                                      // phi (fields hook)
@@ -611,7 +613,10 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
         HIP_TRY(dalloc(c, &c->col, (size_t)nnz + 8));
         HIP_TRY(dalloc(c, &c->val, (size_t)nnz + 8));
         HIP_TRY(dalloc(c, &c->val64, (size_t)nnz));
-        HIP_TRY(dalloc(c, &c->csr_partial, (size_t)c->L.csr_nrb * C * 3));
+        // row-block partials of the spin-major energies (the column-block
+        // readout of a resident context reduces on chip)
+        if (c->order != ORDER_COLBLOCK8 || J->n3 > 0)
+            HIP_TRY(dalloc(c, &c->csr_partial, (size_t)c->L.csr_nrb * C * 3));
         if (J->n3 > 0) {
             // three-body terms listed per member spin, triples in the given
             // order; +4 entries: the step reads them in batches of up to 4
@@ -663,18 +668,19 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
                     cp[(size_t)i * D + q] = J->col[J->row_ptr[i] + q];
                     vp[(size_t)q * NR + i] = (float)J->val[J->row_ptr[i] + q];
                 }
-            // the readout energies' copy: one run per energy row block
+            // the readout energies' copy, grouped by the energy row blocks:
+            // [row in block][neighbour][row block]
             const int nrb = c->L.csr_nrb, rpb = (N + nrb - 1) / nrb, RS = energy_colblock_rows(rpb);
             rc.assign((size_t)nrb * RS * D, 0);
             rv.assign((size_t)nrb * RS * D, 0.0);
             rhv.assign((size_t)nrb * RS, 0.0);
             for (int i = 0; i < N; ++i) {
-                const size_t row = (size_t)(i / rpb) * RS + (size_t)(i % rpb);
+                const size_t rb = (size_t)(i / rpb), r = (size_t)(i % rpb);
                 for (int q = 0; q < J->row_ptr[i + 1] - J->row_ptr[i]; ++q) {
-                    rc[row * D + q] = J->col[J->row_ptr[i] + q];
-                    rv[row * D + q] = J->val[J->row_ptr[i] + q];
+                    rc[(r * D + q) * nrb + rb] = J->col[J->row_ptr[i] + q];
+                    rv[(r * D + q) * nrb + rb] = J->val[J->row_ptr[i] + q];
                 }
-                if (h) rhv[row] = h[i];
+                if (h) rhv[r * nrb + rb] = h[i];
             }
             HIP_TRY(dalloc(c, &c->colpad, cp.size()));
             HIP_TRY(dalloc(c, &c->valpad, vp.size()));

@@ -292,17 +292,23 @@ hipError_t launch_energy_reduce(int N, int Np, int count, int Cp, int splits,
                                 double *E, hipStream_t st);
 
 // CSR energies of the readout of x (element (i, c) at state_off(order, ld, i, c))
-// or of given spins.
+// or of given spins. The state energies are summed in one fixed order: per
+// column, row blocks of rpb = ceil(N / nblk_rows) rows, each summed in row
+// order (neighbours in CSR order); row block rb added into slot
+// rb % ENERGY_SLOTS in increasing rb; then a pairwise tree over the slots
+// (slot t += slot t + w for w = ENERGY_SLOTS/2, ..., 1). nblk_rows >=
+// ENERGY_SLOTS unless N is smaller, so that every slot can be one thread's.
+constexpr int ENERGY_SLOTS = 1024;
 hipError_t launch_csr_energy_state(int N, int order, int ld, int C, const int32_t *row_ptr,
                                    const int32_t *col, const double *val, const Tri3 &t3, const double *h,
                                    const float *x, double *partial, int nblk_rows, double *E,
                                    hipStream_t st);
 // The same energies of a column-block state (ORDER_COLBLOCK8 with leading
-// dimension ld >= N, C % 8 == 0, N * 32 bytes of LDS, even D, no three-body
+// dimension ld >= N, C % 8 == 0, N * 8 bytes of LDS, even D, no three-body
 // terms), equal bit for bit. The couplings of row block rb (rows rb*rpb ..
 // rb*rpb + rpb - 1, the row blocks of the spin-major energies: nrb * rpb >= N)
-// are one run per row block: rcol / rval [nrb][RS][D] (neighbours in CSR
-// order, then index 0 with weight 0), rh [nrb][RS] (h, 0 past N), with
+// are stored row block innermost: rcol / rval [RS][D][nrb] (neighbours in CSR
+// order, then index 0 with weight 0), rh [RS][nrb] (h, 0 past N), with
 // RS = energy_colblock_rows(rpb). sbits: the sign bytes the resident loop
 // wrote for this same x ([C/8][ld], bit k: column k negative), read in place
 // of x's 32 bytes per row and block; nullptr: the signs are taken from x.
