@@ -293,10 +293,17 @@ sbqa_status sbqa_fields(sbqa_ctx *ctx, float *phi);
 sbqa_status sbqa_get_state(sbqa_ctx *ctx, float *x, float *y);
 sbqa_status sbqa_set_state(sbqa_ctx *ctx, const float *x, const float *y);
 
-/* Per-run (beta_r, alpha_r) in use ([runs] float64 each; NULL skips). */
+/* Per-run parameters of the inter-replica coupling schedule in use (Sec. II.B:
+ * each run draws its own beta_r and alpha_r from the stated ranges; Eq. 5
+ * takes them): [runs] float64 each, caller-allocated; NULL skips that
+ * output. Host-only (no device work). EINVAL for a NULL context. */
 sbqa_status sbqa_run_params(sbqa_ctx *ctx, double *beta, double *alpha);
 
-/* Inter-replica coupling table in use: jp[runs*steps] float32, run-major. */
+/* The inter-replica coupling J_perp(t_n) of Eq. 5 (or the linear or caller
+ * table the schedule names) as the kernels read it: jp[runs*steps] float32,
+ * run-major (jp[r*steps + n] for run r at step n), caller-allocated. Read
+ * from the host copy the device table was uploaded from (no device work).
+ * EINVAL for NULL arguments. */
 sbqa_status sbqa_jperp_table(sbqa_ctx *ctx, float *jp);
 
 /* Issue the context's device work on `hip_stream` (a hipStream_t, e.g.
