@@ -449,19 +449,24 @@ __device__ __forceinline__ void dense_epilogue(const DenseStepArgs &a, f4 (&acc)
 // walks K backwards: alternating the direction every step starts each step on
 // the J chunks the previous one touched last.
 // ---------------------------------------------------------------------------
-template <int PATH, int MBW, int EPI>
-__device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, int mchunk) {
+// CG column groups of 4 waves share the tile's J staging (CG = 2: a
+// 64-spin x 128*MBW-column workgroup of 8 waves reads every J fragment once
+// for twice the columns; with two J planes, group cg stages plane cg).
+template <int PATH, int MBW, int EPI, int CG = 1>
+__device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, int mchunk_wg) {
     constexpr int PL = Pipe<PATH>::planes;
     constexpr int PD = Pipe<PATH>::depth;
     constexpr int NT = Terms<PATH>::n;
     constexpr int RBT = DENSE_TN / 16;          // J row blocks per tile
     constexpr int SLOT = PL * RBT * FRAG_BYTES;  // J fragments of one K chunk
     constexpr int TS = DENSE_TN + 4;             // epilogue transpose row stride (floats)
-    constexpr int TBYTES = 4 * 16 * TS * 4;
+    constexpr int TBYTES = 4 * CG * 16 * TS * 4;
     constexpr int LDS_BYTES = (2 * SLOT > TBYTES) ? 2 * SLOT : TBYTES;
+    static_assert(CG == 1 || (CG == 2 && PL == 2), "two column groups split the two J planes");
     __shared__ __align__(16) uint8_t lds[LDS_BYTES];
 
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, w = wv & 3, cg = wv >> 2;
+    const int mchunk = mchunk_wg * CG + cg;       // this wave's 64*MBW-column chunk
     const int n0 = nt * DENSE_TN;
     const int mb0 = (mchunk * 4 + w) * MBW;       // first m-block of this wave
     const int nkc = a.nkc;
@@ -496,6 +501,10 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
         const int64_t o = chunk_at(kc) * JCH;
         if constexpr (JPK) {
             jw[s] = *reinterpret_cast<const JWord *>(jsrc + o);
+        } else if constexpr (CG == 2) {
+            const uint8_t *src = cg ? jsrc_lo : jsrc;
+            jr[s][0][0] = ld16(src + o);
+            jr[s][0][1] = ld16(src + o + 1024);
         } else {
             jr[s][0][0] = ld16(jsrc + o);
             jr[s][0][1] = ld16(jsrc + o + 1024);
@@ -549,6 +558,10 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
                 uint8_t *dst = slot + w * FRAG_BYTES + l16;
                 *reinterpret_cast<uint4 *>(dst) = f.lo;
                 *reinterpret_cast<uint4 *>(dst + 1024) = f.hi;
+            } else if constexpr (CG == 2) {
+                uint8_t *dst = slot + (cg * RBT + w) * FRAG_BYTES + l16;
+                *reinterpret_cast<uint4 *>(dst) = jr[s][0][0];
+                *reinterpret_cast<uint4 *>(dst + 1024) = jr[s][0][1];
             } else {
 #pragma unroll
                 for (int pl = 0; pl < PL; ++pl) {
@@ -590,12 +603,19 @@ __device__ __forceinline__ void dense_step_body(const DenseStepArgs &a, int nt, 
         }
     }
 
-    dense_epilogue<PATH, MBW, EPI>(a, acc, nt, mchunk, lds);
+    dense_epilogue<PATH, MBW, EPI>(a, acc, nt, mchunk, lds, w);
 }
 
 template <int PATH, int MBW, int EPI>
 __global__ __launch_bounds__(DENSE_THREADS) void k_dense_step(const DenseStepArgs a) {
     dense_step_body<PATH, MBW, EPI>(a, blockIdx.x, blockIdx.y);
+}
+
+// The same step with two column groups per workgroup (two J planes, each
+// staged by one group): grid (Np / DENSE_TN, Cg / (128 * MBW)).
+template <int PATH, int MBW, int EPI>
+__global__ __launch_bounds__(2 * DENSE_THREADS) void k_dense_step_cg2(const DenseStepArgs a) {
+    dense_step_body<PATH, MBW, EPI, 2>(a, blockIdx.x, blockIdx.y);
 }
 
 // K chunks in flight per wave in the split-K kernel (fp8 and fp4 alike;
@@ -924,6 +944,15 @@ hipError_t launch_step_mbw(int mbw, dim3 grid, const DenseStepArgs &a, hipStream
     if constexpr (path_packed(Path(PATH))) {
         if (mbw == 2 && a.nkc % (2 * SK_DEPTH) == 0 && grid.x % 2 == 0) {
             hipLaunchKernelGGL((k_dense_step_sk<PATH, 2, EPI>), dim3(grid.x / 2, grid.y), dim3(2 * DENSE_THREADS), 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    // two J planes: two column groups per workgroup read each J fragment once
+    // for 256 columns (half the J traffic of two 128-column workgroups)
+    if constexpr (Pipe<PATH>::planes == 2) {
+        if (mbw == 2 && grid.y % 2 == 0) {
+            hipLaunchKernelGGL((k_dense_step_cg2<PATH, 2, EPI>), dim3(grid.x, grid.y / 2), dim3(2 * DENSE_THREADS), 0, st,
+                               a);
             return hipGetLastError();
         }
     }
