@@ -114,7 +114,9 @@ struct sbqa_ctx {
     float *x[2] = {nullptr, nullptr};
     float *y = nullptr;
     int cur = 0;
-    void *g[2] = {nullptr, nullptr};    // operand f(X), ping-pong with x: dense fragment-tiled, CSR int8 [N][Cs]
+    // operand f(X), ping-pong with x: dense fragment-tiled, CSR int8 [N][Cs]
+    // (the resident CSR loop builds its own from x at each launch)
+    void *g[2] = {nullptr, nullptr};
     void *g_lo[2] = {nullptr, nullptr}; // bf16 low part (BF16X3)
     float *phi = nullptr;               // CSR fields hook [N][Cs]
     void *Jd = nullptr, *Jd_lo = nullptr;  // dense J in contraction precision, fragment-tiled
@@ -157,10 +159,10 @@ struct sbqa_ctx {
     std::vector<int32_t> pnew;          // CSR spins relabelled: row of the caller's spin i (empty: identity)
     int32_t *porig = nullptr;           // [N] the caller's spin index of each row (relabelled only)
     float *valpad = nullptr;            // [D][rows]
-    // readout energies of the resident loop: couplings as one run per energy
-    // row block (launch_csr_energy_colblock)
-    int32_t *rcol = nullptr;            // [nrb][RS][D]
-    double *rval = nullptr, *rh = nullptr;   // [nrb][RS][D], [nrb][RS]
+    // readout energies of the resident loop: the couplings grouped by the
+    // energy row blocks, row block innermost (launch_csr_energy_colblock)
+    int32_t *rcol = nullptr;            // [RS][D][nrb]
+    double *rval = nullptr, *rh = nullptr;   // [RS][D][nrb], [RS][nrb]
     float *coefA = nullptr;             // [S]
     float *delta_tab = nullptr;         // [S+1]
     float *xpub = nullptr;              // [2][nwg][2][rows] published edge columns
