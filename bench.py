@@ -187,7 +187,14 @@ def dense_kernel_name(info):
     Np = -(-info["N"] // 512) * 512
     nkc = {"dense_fp8_packed": Np // 128, "dense_fp4_packed": Np // 256}.get(info["path"], 1)
     split = info["path"] in ("dense_fp8_packed", "dense_fp4_packed") and info["tile_cols"] == 128 and nkc % 4 == 0
-    return "k_dense_step_sk" if split else "k_dense_step"
+    if split:
+        return "k_dense_step_sk"
+    # two J planes at the 128-column tile: two column groups per workgroup
+    # when the padded columns make whole pairs of 128-column chunks
+    cg = -(-(info["R"] * info["runs"]) // 128) * 128
+    if info["path"] == "dense_bf16x3" and info["tile_cols"] == 128 and cg % 256 == 0:
+        return "k_dense_step_cg2"
+    return "k_dense_step"
 
 
 def algorithmic_flops(w):
