@@ -191,9 +191,10 @@ def dense_kernel_name(info):
         return "k_dense_step_sk"
     # two J planes at the 128-column tile: two column groups per workgroup
     # when the padded columns make whole pairs of 128-column chunks
-    cg = -(-(info["R"] * info["runs"]) // 128) * 128
-    if info["path"] == "dense_bf16x3" and info["tile_cols"] == 128 and cg % 256 == 0:
-        return "k_dense_step_cg2"
+    if info["path"] == "dense_bf16x3" and info["tile_cols"] == 128:
+        cg = -(-(info["R"] * info["runs"]) // 128) * 128
+        if cg % 256 == 0:
+            return "k_dense_step_cg2"
     return "k_dense_step"
 
 

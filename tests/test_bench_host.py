@@ -88,19 +88,29 @@ def test_dense_kernel_name():
     assert bench.dense_kernel_name(dict(base, path="dense_fp8_packed", N=300)) == "k_dense_step_sk"   # 4 of 128
     assert bench.dense_kernel_name(dict(base, tile_cols=256)) == "k_dense_step"
     assert bench.dense_kernel_name(dict(base, path="dense_int8")) == "k_dense_step"
+    # two J planes (bf16 hi+lo) at the 128-column tile: two column groups per
+    # workgroup when the padded columns make whole 256-column pairs
+    bf = {"N": 8192, "path": "dense_bf16x3", "tile_cols": 128, "R": 16, "runs": 32}
+    assert bench.dense_kernel_name(bf) == "k_dense_step_cg2"
+    assert bench.dense_kernel_name(dict(bf, runs=8)) == "k_dense_step"          # C = 128: one chunk
+    assert bench.dense_kernel_name(dict(bf, runs=12)) == "k_dense_step_cg2"     # C = 192 -> 256
+    assert bench.dense_kernel_name(dict(bf, tile_cols=64)) == "k_dense_step"
 
 
 def test_dense_traffic_summaries_name_the_launched_kernel():
     """The committed counter summaries of the SK N = 16384 packed-J workloads
-    (taken at the 128-column tile) name the kernel the launch rule selects."""
+    and of the Gaussian N = 8192 bf16 hi+lo workload (taken at the 128-column
+    tile) name the kernel the launch rule selects."""
     import bench
-    for workload, path in (("sk_fp8", "dense_fp8_packed"), ("sk_fp4", "dense_fp4_packed")):
+    for workload, info in (("sk_fp8", {"N": 16384, "path": "dense_fp8_packed", "R": 16, "runs": 16}),
+                           ("sk_fp4", {"N": 16384, "path": "dense_fp4_packed", "R": 16, "runs": 16}),
+                           ("gauss_bf16x3", {"N": 8192, "path": "dense_bf16x3", "R": 16, "runs": 32})):
         kv = {}
         for line in open(os.path.join(ROOT, "profiles", "traffic_%s.txt" % workload)):
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
                 kv[k.strip()] = v.strip()
-        assert kv["kernel"] == bench.dense_kernel_name({"N": 16384, "path": path, "tile_cols": 128})
+        assert kv["kernel"] == bench.dense_kernel_name(dict(info, tile_cols=128))
 
 
 def test_unknown_workload_is_rejected():
