@@ -695,6 +695,12 @@ def main():
             r1, c1 = measure(sb, w1, 1000, 200, stream, workload="sk64")
             sb.sbqa_destroy(c1)
             r1["workload"] = w1["desc"]
+            # the same solve with one launch per step (the MFMA step kernel)
+            r2, c2 = measure(sb, w1, 1000, 200, stream, loop_kernel="stream", workload="sk64")
+            sb.sbqa_destroy(c2)
+            r1["one_launch_per_step"] = {"value": r2["value"], "ms_per_step": r2["ms_per_step"],
+                                         "avg_step_us": r2.get("roofline", {}).get("avg_step_us"),
+                                         "path": r2["path"]}
             cfg["sk_N64_C32"] = r1
         except Exception as e:   # reported, never hides the main line
             cfg["sk_N64_C32"] = {"error": repr(e)}
