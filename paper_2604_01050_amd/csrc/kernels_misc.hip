@@ -244,14 +244,56 @@ __device__ __forceinline__ uint2 spread_signs(uint32_t b) {
     return make_uint2(lo, hi);
 }
 
-template <int D>
+// Best of run r (Sec. II.B), by the first wavefront of a workgroup (t < 64):
+// the argmin over the run's R energies (tie -> lowest k), reduced across
+// lanes; the stored best (+inf when reset) is replaced only when strictly
+// lower. Thread 0 sets *sel to the winning replica, or -1 when the stored best
+// stays, and *kept to the stored best energy after the update. The comparison
+// is kept in vector registers on purpose: a wave-uniform float64 compare
+// feeding a scalar select was observed to be lowered with a stale condition
+// code on gfx950. AGENT: the energies were written by other workgroups of the
+// same launch (coherent loads).
+template <bool AGENT>
+__device__ __forceinline__ void select_best(const double *E, int r, int R, int t, double *best_E, int64_t *best_step,
+                                            int64_t step, int reset, int *sel, double *kept) {
+    if (t >= 64) return;
+    double eb = INFINITY;
+    int kb = 0x7FFFFFFF;
+    for (int k = t; k < R; k += 64) {
+        const double *ep = E + (int64_t)r * R + k;
+        const double e = AGENT ? __hip_atomic_load(const_cast<double *>(ep), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                               : *ep;
+        if (e < eb) { eb = e; kb = k; }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const double eo = __shfl_xor(eb, off);
+        const int ko = __shfl_xor(kb, off);
+        const bool take = (eo < eb) || (eo == eb && ko < kb);
+        eb = take ? eo : eb;
+        kb = take ? ko : kb;
+    }
+    const double stored = best_E[r];
+    const double cur = reset ? INFINITY : stored;
+    const int better = (eb < cur) ? 1 : 0;
+    if (t == 0) {
+        *sel = better ? kb : -1;
+        *kept = better ? eb : stored;
+        if (better) {
+            best_E[r] = eb;
+            best_step[r] = step;
+        }
+    }
+}
+
+template <int D, bool FUSE>
 __global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_colblock(int N, int ld, int nrb, int rpb, int RS,
                                                                       const int32_t *__restrict__ rcol,
                                                                       const double *__restrict__ rval,
                                                                       const double *__restrict__ rh,
                                                                       const float *__restrict__ x,
                                                                       const uint8_t *__restrict__ sbits,
-                                                                      double *__restrict__ E) {
+                                                                      double *__restrict__ E, const ReadoutFuse f) {
     constexpr int T = ENERGY_SLOTS;
     // rows whose loads are issued together, neighbours per group of loads
     // (within 128 registers per lane)
@@ -373,9 +415,70 @@ __global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_colblock(int N, int
             }
         __syncthreads();
     }
-    if (t < 8) {
-        const double s3 = 0.0;   // no three-body terms on this path
-        E[w * 8 + t] = -0.5 * sq[t * T] - sl[t * T] - s3 / 3.0;
+    const double s3 = 0.0;   // no three-body terms on this path
+    if constexpr (!FUSE) {
+        if (t < 8) E[w * 8 + t] = -0.5 * sq[t * T] - sl[t * T] - s3 / 3.0;
+    } else {
+        // the best update of the run and the readout block, by the last of
+        // the run's R / 8 workgroups to finish its energies: they are stored
+        // coherently for the device and completed before the run's arrival
+        // counter is raised; the last one reads them after it (and sets the
+        // counter back to zero for the next launch)
+        __shared__ int last, sel;
+        __shared__ double kept;
+        if (t < 8)
+            __hip_atomic_store(E + w * 8 + t, -0.5 * sq[t * T] - sl[t * T] - s3 / 3.0, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        if (w == 0 && t == 0) *reinterpret_cast<int *>(f.host + (size_t)8 * f.runs) = *f.err;
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        const int P = f.R / 8, run = w / P;
+        if (t == 0) {
+            const int old = __hip_atomic_fetch_add(f.cnt + run, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = old == P - 1;
+            if (last) __hip_atomic_store(f.cnt + run, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (!last) return;
+        select_best<true>(E, run, f.R, t, f.best_E, f.best_step, f.step, f.reset, &sel, &kept);
+        __syncthreads();
+        if (t == 0) reinterpret_cast<double *>(f.host)[run] = kept;
+        // spins of the winner (sign(0) = +1) to the device best and the host
+        // block, or the stored best spins to the host block; 8 rows a thread
+        const int k = sel;
+        int8_t *dev = f.best_spins + (int64_t)run * N;
+        int8_t *hst = reinterpret_cast<int8_t *>(f.host + (size_t)8 * f.runs + 8) + (int64_t)run * N;
+        const int c = run * f.R + k, wb = c >> 3, kk = c & 7;
+        for (int i0 = 8 * t; i0 < N; i0 += 8 * T) {
+            int8_t v[8];
+            if (k < 0) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = i0 + u < N ? dev[i0 + u] : 0;
+            } else if (sbits) {
+                // rows up to ld are in the buffer (ld >= N, a multiple of 16)
+                const uint2 b = *reinterpret_cast<const uint2 *>(sbits + (int64_t)wb * ld + i0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = (((u < 4 ? b.x : b.y) >> (8 * (u & 3) + kk)) & 1u) ? -1 : 1;
+            } else {
+                // rows up to ld are in the state (zero past N)
+                const float *xw = x + ((int64_t)wb * ld + i0) * 8 + kk;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = xw[u * 8] >= 0.0f ? 1 : -1;
+            }
+            // dev and hst have the same offset from 256-byte aligned bases
+            if (i0 + 8 <= N && ((uintptr_t)(dev + i0) & 7u) == 0) {
+                uint2 pk = make_uint2(0u, 0u);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) (u < 4 ? pk.x : pk.y) |= (uint32_t)(uint8_t)v[u] << (8 * (u & 3));
+                if (k >= 0) *reinterpret_cast<uint2 *>(dev + i0) = pk;
+                *reinterpret_cast<uint2 *>(hst + i0) = pk;
+            } else {
+                for (int u = 0; u < 8 && i0 + u < N; ++u) {
+                    if (k >= 0) dev[i0 + u] = v[u];
+                    hst[i0 + u] = v[u];
+                }
+            }
+        }
     }
 }
 
@@ -411,43 +514,16 @@ __global__ __launch_bounds__(256) void k_csr_energy_spins(int N, const int32_t *
     if (t == 0) E[m] = -0.5 * sq[0] - sl[0] - s3[0] / 3.0;
 }
 
-// One workgroup per run. Its first wavefront takes the argmin over the run's
-// replicas (tie -> lowest k), reduced across lanes; the stored best (or +inf
-// when reset) is replaced only when strictly lower. Then the whole workgroup
-// copies the winner's readout spins (sign(0) = +1). The comparison is kept in
-// vector registers on purpose: a wave-uniform float64 compare feeding a scalar
-// select was observed to be lowered with a stale condition code on gfx950.
+// One workgroup per run: the best update of select_best, then the whole
+// workgroup copies the winner's readout spins (sign(0) = +1).
 __global__ __launch_bounds__(1024) void k_best_update(int N, int R, int order, int ld, const float *__restrict__ x,
                                                      const double *__restrict__ E, double *__restrict__ best_E,
                                                      int64_t *__restrict__ best_step,
                                                      int8_t *__restrict__ best_spins, int64_t step, int reset) {
     __shared__ int sel;
+    __shared__ double kept;
     const int r = blockIdx.x, t = threadIdx.x;
-    if (t < 64) {
-        double eb = INFINITY;
-        int kb = 0x7FFFFFFF;
-        for (int k = t; k < R; k += 64) {
-            const double e = E[(int64_t)r * R + k];
-            if (e < eb) { eb = e; kb = k; }
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) {
-            const double eo = __shfl_xor(eb, off);
-            const int ko = __shfl_xor(kb, off);
-            const bool take = (eo < eb) || (eo == eb && ko < kb);
-            eb = take ? eo : eb;
-            kb = take ? ko : kb;
-        }
-        const double cur = reset ? INFINITY : best_E[r];
-        const int better = (eb < cur) ? 1 : 0;
-        if (t == 0) {
-            sel = better ? kb : -1;
-            if (better) {
-                best_E[r] = eb;
-                best_step[r] = step;
-            }
-        }
-    }
+    select_best<false>(E, r, R, t, best_E, best_step, step, reset, &sel, &kept);
     __syncthreads();
     const int k = sel;
     if (k < 0) return;
@@ -578,9 +654,10 @@ hipError_t ensure_dyn_lds(const void *fn, size_t lds) {
 // batch of rows (2)
 int energy_colblock_rows(int rpb) { return (rpb + 1) / 2 * 2; }
 
-hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
-                                      const double *rval, const double *rh, const float *x,
-                                      const uint8_t *sbits, double *E, hipStream_t st) {
+template <bool FUSE>
+static hipError_t colblock_launch(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
+                                  const double *rval, const double *rh, const float *x, const uint8_t *sbits,
+                                  double *E, const ReadoutFuse &f, hipStream_t st) {
     const size_t lds = std::max<size_t>((size_t)N * 8, 2 * 8 * (size_t)ENERGY_SLOTS * sizeof(double));
     // even D: a batch of 8 rows is whole 16-byte vectors, and so is every row block's run
     // sign bytes are read 16 rows at a time: a 16-byte aligned row stride
@@ -589,15 +666,20 @@ hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int 
     if (C % 8 || ld < N || (int64_t)nrb * rpb < N || lds > 160 * 1024 || D % 2 || (sbits && ld % 16) ||
         (int64_t)RS * D * nrb >= ((int64_t)1 << 31))
         return hipErrorInvalidValue;
+    // fused readout: whole 8-column blocks per run, rows up to a multiple of 8
+    // readable in the state (ld % 8 == 0), every buffer present
+    if (FUSE && (f.R <= 0 || f.R % 8 || f.runs <= 0 || (int64_t)f.R * f.runs != C || ld % 8 || !f.best_E ||
+                 !f.best_step || !f.best_spins || !f.err || !f.cnt || !f.host || ((uintptr_t)f.host & 7u)))
+        return hipErrorInvalidValue;
     const dim3 grid(C / 8), block(ENERGY_SLOTS);
     switch (D) {
 #define SBQA_ECB(D_)                                                                                                 \
     case D_: {                                                                                                       \
-        const void *fn = reinterpret_cast<const void *>(&k_csr_energy_colblock<D_>);                                 \
+        const void *fn = reinterpret_cast<const void *>(&k_csr_energy_colblock<D_, FUSE>);                           \
         hipError_t e = ensure_dyn_lds(fn, lds);                                                                      \
         if (e != hipSuccess) return e;                                                                               \
-        hipLaunchKernelGGL(k_csr_energy_colblock<D_>, grid, block, lds, st, N, ld, nrb, rpb, RS, rcol, rval, rh, x,  \
-                           sbits, E);                                                                                \
+        hipLaunchKernelGGL((k_csr_energy_colblock<D_, FUSE>), grid, block, lds, st, N, ld, nrb, rpb, RS, rcol, rval, \
+                           rh, x, sbits, E, f);                                                                      \
         break;                                                                                                       \
     }
         SBQA_ECB(4) SBQA_ECB(6) SBQA_ECB(8) SBQA_ECB(12) SBQA_ECB(16)
@@ -605,6 +687,18 @@ hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int 
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
+                                      const double *rval, const double *rh, const float *x,
+                                      const uint8_t *sbits, double *E, hipStream_t st) {
+    return colblock_launch<false>(N, ld, C, D, nrb, rpb, rcol, rval, rh, x, sbits, E, ReadoutFuse{}, st);
+}
+
+hipError_t launch_csr_readout_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
+                                       const double *rval, const double *rh, const float *x,
+                                       const uint8_t *sbits, double *E, const ReadoutFuse &f, hipStream_t st) {
+    return colblock_launch<true>(N, ld, C, D, nrb, rpb, rcol, rval, rh, x, sbits, E, f, st);
 }
 
 hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col, const double *val,

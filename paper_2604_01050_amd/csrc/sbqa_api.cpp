@@ -694,6 +694,7 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
             HIP_TRY(dalloc(c, &c->flags, (size_t)c->res_nwg));
             HIP_TRY(dalloc(c, &c->epoch_cnt, (size_t)c->res_nwg));
             HIP_TRY(dalloc(c, &c->sbits, (size_t)c->res_nwg * NR));
+            HIP_TRY(dalloc(c, &c->rd_cnt, (size_t)runs));
             HIP_TRY(hipMemcpyAsync(c->colpad, cp.data(), sizeof(int32_t) * cp.size(), hipMemcpyHostToDevice, c->stream));
             HIP_TRY(hipMemcpyAsync(c->valpad, vp.data(), sizeof(float) * vp.size(), hipMemcpyHostToDevice, c->stream));
         }
@@ -819,15 +820,20 @@ sbqa_status ctx_step_once(sbqa_ctx *c) {
     return SBQA_OK;
 }
 
+// The sign bytes the resident loop wrote for the current state, or nullptr
+// when the state has been replaced since.
+static const uint8_t *colblock_signs(const sbqa_ctx *c) {
+    return c->sbits_step == (int64_t)c->step ? c->sbits : nullptr;
+}
+
 // Energies of the readout of the current state into c->E[0..C).
 sbqa_status ctx_state_energies(sbqa_ctx *c) {
     const bool sm = c->facts.path == PATH_CSR;
     const double *h64 = c->has_h ? c->h64 : nullptr;
     if (sm && c->order == ORDER_COLBLOCK8 && !c->facts.n3) {
         const int nrb = c->L.csr_nrb, rpb = (c->N + nrb - 1) / nrb;
-        const uint8_t *sb = c->sbits_step == (int64_t)c->step ? c->sbits : nullptr;
         HIP_TRY(launch_csr_energy_colblock(c->N, c->ld, c->L.C, c->res_D, nrb, rpb, c->rcol, c->rval, c->rh,
-                                           c->x[c->cur], sb, c->E, c->stream));
+                                           c->x[c->cur], colblock_signs(c), c->E, c->stream));
     } else if (sm) {
         HIP_TRY(launch_csr_energy_state(c->N, c->order, c->ld, c->L.C, c->rp, c->col, c->val64, c->tri3(), h64, c->x[c->cur],
                                         c->csr_partial, c->L.csr_nrb, c->E, c->stream));
@@ -1246,7 +1252,28 @@ sbqa_status ctx_step(sbqa_ctx *c, uint32_t n) {
 // stream has passed this point.
 sbqa_status ctx_readout_async(sbqa_ctx *c) {
     const bool reset = c->s.energy_every == 0;
-    if (reset || c->last_eval_step != (int64_t)c->step) {
+    const bool eval = reset || c->last_eval_step != (int64_t)c->step;
+    if (eval && c->rd_cnt && c->rhost_dev && c->order == ORDER_COLBLOCK8 && !c->facts.n3) {
+        // resident context: energies, best update and the host block in one
+        // launch (the same values as the three-launch form below)
+        const int nrb = c->L.csr_nrb, rpb = (c->N + nrb - 1) / nrb;
+        ReadoutFuse f;
+        f.R = c->R;
+        f.runs = c->runs;
+        f.best_E = c->bestE;
+        f.best_step = c->bestStep;
+        f.best_spins = c->bestSpins;
+        f.err = c->err;
+        f.cnt = c->rd_cnt;
+        f.host = c->rhost_dev;
+        f.step = (int64_t)c->step;
+        f.reset = reset ? 1 : 0;
+        HIP_TRY(launch_csr_readout_colblock(c->N, c->ld, c->L.C, c->res_D, nrb, rpb, c->rcol, c->rval, c->rh,
+                                            c->x[c->cur], colblock_signs(c), c->E, f, c->stream));
+        c->last_eval_step = c->step;
+        return SBQA_OK;
+    }
+    if (eval) {
         sbqa_status st = ctx_evaluate(c, reset);
         if (st != SBQA_OK) return st;
     }

@@ -170,6 +170,9 @@ struct sbqa_ctx {
     // of the block's column k is negative), valid while sbits_step == step
     uint8_t *sbits = nullptr;
     int64_t sbits_step = -1;
+    // per-run arrival counters of the one-launch readout of a resident
+    // context (launch_csr_readout_colblock), zero between launches
+    int *rd_cnt = nullptr;
     int *flags = nullptr, *epoch_cnt = nullptr;
     int epoch = 0;
 

@@ -316,6 +316,29 @@ int energy_colblock_rows(int rpb);
 hipError_t launch_csr_energy_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
                                       const double *rval, const double *rh, const float *x,
                                       const uint8_t *sbits, double *E, hipStream_t st);
+// The same energies followed by the readout of a run, in one launch: the best
+// update of launch_best_update (without the copy of x's spins, which are taken
+// from sbits or x as above) by the last workgroup of each run to finish, which
+// then writes the run's best energy and best spins straight into the pinned
+// host readout block (host: its device address; layout best energies
+// [runs] float64, the error word at byte 8*runs, best spins [runs][N] at
+// byte 8*runs + 8), and workgroup 0 copies the error word err there. cnt:
+// [runs] arrival counters, zero before the launch and left zero after it.
+// R % 8 == 0, C == R * runs, ld % 8 == 0.
+struct ReadoutFuse {
+    int R = 0, runs = 0;
+    double *best_E = nullptr;
+    int64_t *best_step = nullptr;
+    int8_t *best_spins = nullptr;
+    const int *err = nullptr;
+    int *cnt = nullptr;
+    uint8_t *host = nullptr;
+    int64_t step = 0;
+    int reset = 0;
+};
+hipError_t launch_csr_readout_colblock(int N, int ld, int C, int D, int nrb, int rpb, const int32_t *rcol,
+                                       const double *rval, const double *rh, const float *x,
+                                       const uint8_t *sbits, double *E, const ReadoutFuse &f, hipStream_t st);
 hipError_t launch_csr_energy_spins(int N, int count, const int32_t *row_ptr, const int32_t *col,
                                    const double *val, const Tri3 &t3, const double *h, const int8_t *spins,
                                    double *E, hipStream_t st);
