@@ -19,7 +19,7 @@
  *     Symplectic Euler: y += dt*F(x_n); x += dt*(a0/R)*y; |x| > 1 ->
  *     x = sign(x), y = 0.
  *   - Energy E(s) = -1/2 s^T J s - h^T s; spins are int8 +-1 with the
- *     readout s_i = sign(x_i), sign(0) = +1 (Sec. II.A, "s_i = sign(q_i)").
+ *     readout s_i = sign(x_i), sign(0) = +1 (Sec. II.A, where the position is q_i).
  *   - Every pointer argument is a HOST pointer unless stated otherwise.
  *     Inputs are copied before the call returns (the caller keeps ownership
  *     and may free them). Outputs are caller-allocated.
@@ -241,7 +241,7 @@ sbqa_status sbqa_create(const sbqa_coupling *J, const double *h, int32_t N, int3
 sbqa_status sbqa_step(sbqa_ctx *ctx, uint32_t n);
 
 /*
- * Best solution per run (Sec. II.B: "return the best solution"): the minimum
+ * Best solution per run (Sec. II.B: the output of a solve): the minimum
  * energy over the run's R replicas of the current state (and over the tracked
  * evaluations when energy_every > 0). Ties: lowest replica, earliest step.
  *   energies  [runs] float64 out (may be NULL)

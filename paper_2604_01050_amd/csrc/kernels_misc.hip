@@ -1,5 +1,5 @@
 // Initial state, readout, energies and best-solution selection for gfx950.
-//   * Initial state: x, y ~ U[-amp, amp] ("random state", Sec. II.A) from the
+//   * Initial state: x, y ~ U[-amp, amp] (random start, Sec. II.A) from the
 //     counter-based Philox4x32-10 generator (Salmon et al., SC'11), keyed by
 //     the seed and counted by (i, c), so the draw is layout-independent.
 //   * Energies E(s) = -1/2 s^T J s - h^T s of readouts s = sign(x) (sign(0) =
