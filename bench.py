@@ -301,9 +301,10 @@ def cpu_baseline(w, window_s=5.0, windows=3, single_s=4.0):
     oracle.set_threads(cores)
     out = {"value": float(np.median(rates)), "unit": "replica-spin updates/s", "cores": cores,
            "kind": "oracle",
-           "sample": "the first %d of %d steps of the same workload in %d consecutive windows of about %.0f s "
+           "sample": "the first %d of %d steps of the same workload in %d consecutive window%s of about %.0f s "
                      "(%s steps), median rate (FP64 C oracle, OpenMP)"
-                     % (n, S, len(rates), window_s, "/".join(str(c) for c in counts), ),
+                     % (n, S, len(rates), "s" if len(rates) != 1 else "", window_s,
+                        "/".join(str(c) for c in counts)),
            "windows": rates, "cpu_model": _cpu_model(), "compile_flags": " ".join(oracle.CFLAGS)}
     if n1:
         out["single_thread"] = {"value": N * R * runs * n1 / d1, "sample": "the next %d steps on one thread" % n1}
@@ -578,10 +579,12 @@ def field_error(sb, ctx, w, rows):
             "max_over_term_magnitude": float(np.max(err / np.maximum(mag, 1e-300)))}
 
 
-def dense_configs(sb, stream, K):
+def dense_configs(sb, stream, K, cpu=True):
     """Dense configurations on the same GPU: SK N = 16384 (fp8 and fp4 with
     bit-packed J against the plain fp32 path) and Gaussian N = 8192 (split
-    bf16 hi+lo against fp32, with the single-step field error of both)."""
+    bf16 hi+lo against fp32, with the single-step field error of both); with
+    cpu, each also beside the FP64 oracle on the host cores over its first
+    steps (one window of about 5 s, at least one step)."""
     import torch
     res = {}
     sk = {}
@@ -598,6 +601,8 @@ def dense_configs(sb, stream, K):
     # +-1 couplings with a ternary operand: every field is an exact integer on all three paths,
     # so their trajectories and best energies agree exactly
     sk["best_energies_equal"] = sk["fp8"]["best_energy"] == sk["fp32"]["best_energy"] == sk["fp4"]["best_energy"]
+    if cpu:
+        sk["cpu_baseline"] = cpu_baseline(w, window_s=5.0, windows=1, single_s=0.0)
     res["sk_N16384_C256"] = sk
     g = {}
     rows = np.random.default_rng(77).choice(8192, 24, replace=False)
@@ -611,6 +616,8 @@ def dense_configs(sb, stream, K):
         print("dense %s: %.3f ms/step" % (name, r["roofline"]["avg_step_us"] / 1e3), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     g["bf16x3_over_fp32"] = g["bf16x3"]["value"] / g["fp32"]["value"]
+    if cpu:
+        g["cpu_baseline"] = cpu_baseline(w, window_s=5.0, windows=1, single_s=0.0)
     res["gauss_N8192_C512"] = g
     return res
 
@@ -705,7 +712,7 @@ def main():
         except Exception as e:   # reported, never hides the main line
             cfg["sk_N64_C32"] = {"error": repr(e)}
         try:
-            cfg.update(dense_configs(sb, stream, a.dense_steps))
+            cfg.update(dense_configs(sb, stream, a.dense_steps, cpu=not a.no_cpu_baseline))
         except Exception as e:
             cfg["dense"] = {"error": repr(e)}
         if not a.no_serve:

@@ -918,6 +918,8 @@ RESIDENT_CASES = [
     ("two_blocks_sign", 700, 5, 16, 5, 1, 0),
     ("three_blocks_deg12_tracking", 2000, 12, 24, 3, 0, 7),
     ("small_ring_tracking", 333, 3, 8, 2, 0, 5),
+    ("deg8_readout_row_pairs", 1500, 8, 8, 3, 0, 0),
+    ("deg16_sign_tracking", 902, 16, 16, 2, 1, 9),
 ]
 
 
