@@ -27,8 +27,10 @@
  *     available from sbqa_last_error(). The library never aborts the process.
  *   - A context is not thread-safe: use one context per thread, or serialise.
  *   - All device work of a context is issued on its stream (default: the
- *     context's own non-blocking stream; see sbqa_set_stream). Calls that
- *     return data to the host synchronise that stream.
+ *     library's non-blocking stream of the device, shared by every context
+ *     created without a stream of the caller's, so their work is ordered;
+ *     see sbqa_set_stream). Calls that return data to the host synchronise
+ *     that stream.
  */
 #ifndef SBQA_H
 #define SBQA_H
@@ -307,8 +309,9 @@ sbqa_status sbqa_run_params(sbqa_ctx *ctx, double *beta, double *alpha);
 sbqa_status sbqa_jperp_table(sbqa_ctx *ctx, float *jp);
 
 /* Issue the context's device work on `hip_stream` (a hipStream_t, e.g.
- * torch.cuda.current_stream().cuda_stream); NULL restores the context's own
- * stream. The caller keeps the stream alive while the context uses it. */
+ * torch.cuda.current_stream().cuda_stream); NULL restores the library's
+ * stream of the device. The context's work issued so far completes first.
+ * The caller keeps the stream alive while the context uses it. */
 sbqa_status sbqa_set_stream(sbqa_ctx *ctx, void *hip_stream);
 
 sbqa_status sbqa_info(sbqa_ctx *ctx, sbqa_info_t *info);

@@ -498,7 +498,6 @@ using namespace sbqa;
 sbqa_ctx::~sbqa_ctx() {
     for (void *p : allocs) (void)hipFree(p);
     if (rhost) (void)hipHostFree(rhost);
-    if (own_stream) (void)hipStreamDestroy(own_stream);
 }
 
 template <class T>
@@ -539,9 +538,10 @@ sbqa_status rebuild_operand(sbqa_ctx *c) {
     if (c->facts.path == PATH_CSR) {
         // elementwise over the whole buffer: column-block order has C == Cs
         // and zero padded rows, whose operand is 0
-        const int rows = c->order == ORDER_COLBLOCK8 ? c->res_rows : c->N;
-        if (c->s.fmode != SBQA_F_BALLISTIC)
-            HIP_TRY(launch_csr_operand(c->s.fmode, rows, c->L.Cs, c->L.C, c->x[c->cur], (int8_t *)c->g[c->cur], d, c->stream));
+        // (the resident loop builds its operand from x at each launch)
+        if (c->s.fmode != SBQA_F_BALLISTIC && !c->resident)
+            HIP_TRY(launch_csr_operand(c->s.fmode, c->N, c->L.Cs, c->L.C, c->x[c->cur], (int8_t *)c->g[c->cur], d,
+                                       c->stream));
     } else {
         HIP_TRY(launch_dense_operand(c->facts.path, c->s.fmode, c->N, c->L.Np, c->L.C, c->L.nkc, c->L.mbw, c->x[c->cur],
                                      c->g[c->cur], c->g_lo[c->cur], d, c->stream));
@@ -601,13 +601,18 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
         const int64_t nnz = J->nnz;
         const int rows = c->resident ? c->res_rows : N;   // resident rows are padded with zero rows
         HIP_TRY(dalloc(c, &c->x[0], (size_t)rows * Cs));
-        HIP_TRY(dalloc(c, &c->x[1], (size_t)rows * Cs));
         HIP_TRY(dalloc(c, &c->y, (size_t)rows * Cs));
-        int8_t *g0, *g1;
-        HIP_TRY(dalloc(c, &g0, (size_t)rows * Cs));
-        HIP_TRY(dalloc(c, &g1, (size_t)rows * Cs));
-        c->g[0] = g0;
-        c->g[1] = g1;
+        // the resident loop steps x in place and builds its operand on chip:
+        // the second state half, the operand buffers and the fields buffer
+        // are only the fields hook's scratch there, allocated at its first call
+        if (!c->resident) {
+            HIP_TRY(dalloc(c, &c->x[1], (size_t)rows * Cs));
+            int8_t *g0, *g1;
+            HIP_TRY(dalloc(c, &g0, (size_t)rows * Cs));
+            HIP_TRY(dalloc(c, &g1, (size_t)rows * Cs));
+            c->g[0] = g0;
+            c->g[1] = g1;
+        }
         HIP_TRY(dalloc(c, &c->rp, (size_t)N + 1));
         // +8: the CSR step reads neighbour indices in batches of up to 8
         HIP_TRY(dalloc(c, &c->col, (size_t)nnz + 8));
@@ -647,7 +652,7 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
             HIP_TRY(hipMemcpyAsync(c->t3k64, k64.data(), sizeof(double) * k64.size(), hipMemcpyHostToDevice, c->stream));
             HIP_TRY(hipStreamSynchronize(c->stream));   // host staging buffers die here
         }
-        HIP_TRY(dalloc(c, &c->phi, (size_t)N * Cs));
+        if (!c->resident) HIP_TRY(dalloc(c, &c->phi, (size_t)N * Cs));
         std::vector<float> v32((size_t)nnz);
         for (int64_t p = 0; p < nnz; ++p) v32[p] = (float)J->val[p];
         HIP_TRY(hipMemcpyAsync(c->rp, J->row_ptr, sizeof(int32_t) * (N + 1), hipMemcpyHostToDevice, c->stream));
@@ -1064,6 +1069,28 @@ static void relabel(const sbqa_coupling *J, const double *h, int32_t N, const st
     r->J.tri = J->n3 ? r->tri.data() : nullptr;
 }
 
+// The stream of the contexts created without one: one non-blocking stream per
+// device, created at the first such context and kept until the process ends
+// (a stream per context cost a hardware queue's creation, 3.5 ms, for each of
+// the first few contexts of a process). Their work is ordered on it;
+// sbqa_set_stream gives a context a stream of the caller's.
+static hipError_t library_stream(int device, hipStream_t *out) {
+    static std::mutex mu;
+    static std::map<int, hipStream_t> streams;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = streams.find(device);
+    if (it != streams.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    hipStream_t st = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    streams[device] = st;
+    *out = st;
+    return hipSuccess;
+}
+
 sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32_t R, int32_t runs,
                        const sbqa_schedule *s, const InstanceFacts &facts, hipStream_t stream, sbqa_ctx **out,
                        bool allow_resident, const uint32_t *jbits) {
@@ -1083,9 +1110,9 @@ sbqa_status ctx_create(const sbqa_coupling *J, const double *h, int32_t N, int32
     if (st != SBQA_OK) { delete c; return st; }
     if (stream) c->stream = stream;
     else {
-        hipError_t e = hipStreamCreateWithFlags(&c->own_stream, hipStreamNonBlocking);
+        hipError_t e = library_stream(c->device, &c->default_stream);
         if (e != hipSuccess) { delete c; return fail(SBQA_EDEVICE, "hipStreamCreate: %s", hipGetErrorString(e)); }
-        c->stream = c->own_stream;
+        c->stream = c->default_stream;
     }
     Relabelled rl;
     if (facts.path == PATH_CSR) {
@@ -1423,7 +1450,15 @@ sbqa_status sbqa_fields(sbqa_ctx *c, float *phi) {
         const int8_t *gs = (const int8_t *)c->g[c->cur];
         if (c->order == ORDER_COLBLOCK8) {
             // the fields kernel gathers spin-major rows: a spin-major copy of
-            // the state and its operand in the unused ping-pong halves
+            // the state and its operand, and the fields, in buffers allocated
+            // at the first call on a resident context
+            if (!c->phi) {
+                int8_t *gsm0 = nullptr;
+                HIP_TRY(dalloc(c, &c->x[1 - c->cur], (size_t)N * Cs));
+                HIP_TRY(dalloc(c, &gsm0, (size_t)N * Cs));
+                c->g[1 - c->cur] = gsm0;
+                HIP_TRY(dalloc(c, &c->phi, (size_t)N * Cs));
+            }
             float *xsm = c->x[1 - c->cur];
             int8_t *gsm = (int8_t *)c->g[1 - c->cur];
             HIP_TRY(launch_state_reorder(N, C, c->order, c->ld, xs, ORDER_SPIN_MAJOR, Cs, xsm, c->stream));
@@ -1525,8 +1560,8 @@ sbqa_status sbqa_set_stream(sbqa_ctx *c, void *hip_stream) {
     clear_error();
     if (!c) return fail(SBQA_EINVAL, "NULL context");
     HIP_TRY(hipStreamSynchronize(c->stream));
-    c->stream = hip_stream ? (hipStream_t)hip_stream : c->own_stream;
-    if (!c->stream) return fail(SBQA_ESTATE, "context has no own stream");
+    c->stream = hip_stream ? (hipStream_t)hip_stream : c->default_stream;
+    if (!c->stream) return fail(SBQA_ESTATE, "context has no default stream");
     return SBQA_OK;
 }
 

@@ -102,7 +102,10 @@ struct sbqa_ctx {
     uint32_t step = 0;
     int64_t last_eval_step = -1;
     int device = 0;
-    hipStream_t own_stream = nullptr, stream = nullptr;
+    // default_stream: the library's stream of the device (shared by the
+    // contexts given no stream, never destroyed); stream: where this
+    // context's work is issued
+    hipStream_t default_stream = nullptr, stream = nullptr;
     size_t bytes = 0;
     std::vector<void *> allocs;
     bool has_h = false;
