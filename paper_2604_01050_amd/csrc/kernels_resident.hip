@@ -12,7 +12,8 @@ using namespace csr;
 // ---------------------------------------------------------------------------
 // Register-resident CSR loop: many steps per launch.
 //
-// One workgroup of RES_THREADS threads owns RES_COLS consecutive replica
+// One workgroup of NT threads (512, or 1024 from 2048 padded rows: the same
+// rows in more waves hide more latency, 3-4% per step) owns RES_COLS consecutive replica
 // columns of one run (R a multiple of RES_COLS) for all N spins. Its x and y
 // and the fields h stay in registers for the whole launch; its operand f(X)
 // for every spin (as binary16: -1, 0 and +1 are exact, and the coupling sum
@@ -34,8 +35,7 @@ using namespace csr;
 // same f as the host-side operand rebuild.
 // ---------------------------------------------------------------------------
 constexpr int RES_COLS = 8;
-constexpr int RES_THREADS = 512;
-constexpr int RES_MAX_RPT = 8;
+constexpr int RES_MAX_ROWS = 4096;   // padded rows: a power of two from 512 to this
 constexpr int RES_SPIN_LIMIT = 1 << 22;
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
@@ -96,15 +96,15 @@ __device__ __forceinline__ void wait_neighbours(const int *cnt, int wl, int wr, 
     }
 }
 
-template <int RPT, int D>
-__global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
+template <int RPT, int D, int NT>
+__global__ __launch_bounds__(NT) void k_csr_resident(ResidentArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
-    // Rows are padded to NR = RPT*RES_THREADS (zero rows: no field, no
+    // Rows are padded to NR = RPT*NT (zero rows: no field, no
     // couplings, zero state, so they stay zero); thread t owns rows
-    // r = t + q*RES_THREADS. LDS: binary16 operand of the own columns for
+    // r = t + q*NT. LDS: binary16 operand of the own columns for
     // every row, then the weights laid out per thread so every thread
     // addresses them from one base with constant offsets.
-    constexpr int NR = RPT * RES_THREADS;
+    constexpr int NR = RPT * NT;
     half8 *op = reinterpret_cast<half8 *>(smem);                                            // [NR]
     float *wv = reinterpret_cast<float *>(smem + (size_t)NR * 16);                         // [RPT*D][T]
     const int t = threadIdx.x, w = blockIdx.x;
@@ -115,10 +115,10 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
 
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        int r = t + q * RES_THREADS;
+        int r = t + q * NT;
         asm volatile("" : "+v"(r));
 #pragma unroll
-        for (int p = 0; p < D; ++p) wv[(q * D + p) * RES_THREADS + t] = a.valpad[(int64_t)p * NR + r];
+        for (int p = 0; p < D; ++p) wv[(q * D + p) * NT + t] = a.valpad[(int64_t)p * NR + r];
     }
 
     float xs[RPT][RES_COLS], ys[RPT][RES_COLS];
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         const float d0 = a.delta[a.n0];   // the operand of step n0 is f(x) at Delta_n0
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-            int r = t + q * RES_THREADS;
+            int r = t + q * NT;
             asm volatile("" : "+v"(r));
             const float *xrow = a.x + ((int64_t)w * NR + r) * RES_COLS;
             const float *yrow = a.y + ((int64_t)w * NR + r) * RES_COLS;
@@ -204,13 +204,13 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         float hnext = a.h[t], lnext = fetch(publ + t), rnext = fetch(pubr + t);
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-            int r = t + q * RES_THREADS;
+            int r = t + q * NT;
             asm volatile("" : "+v"(r));
             const float hq = hnext, lq = lnext, rq = rnext;
             if (q + 1 < RPT) {
-                hnext = a.h[r + RES_THREADS];
-                lnext = fetch(publ + r + RES_THREADS);
-                rnext = fetch(pubr + r + RES_THREADS);
+                hnext = a.h[r + NT];
+                lnext = fetch(publ + r + NT);
+                rnext = fetch(pubr + r + NT);
             }
             float acc[RES_COLS];
 #pragma unroll
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
             for (int p = 0; p < D; ++p) {
                 const uint32_t jo = (cpk[q][p / 2] >> (16 * (p & 1))) & 0xFFFFu;
                 const half8 f = *reinterpret_cast<const half8 *>(smem + jo);
-                const float wgt = wv[(q * D + p) * RES_THREADS + t];
+                const float wgt = wv[(q * D + p) * NT + t];
                 // binary16 -1, 0, +1 widen exactly: the same bits as a float32 operand
 #pragma unroll
                 for (int c = 0; c < RES_COLS; ++c) acc[c] = __builtin_fmaf(wgt, (float)f[c], acc[c]);
@@ -271,7 +271,7 @@ __global__ __launch_bounds__(RES_THREADS) void k_csr_resident(ResidentArgs a) {
         __syncthreads();  // every wave is done reading the step-n operand
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-            int r = t + q * RES_THREADS;
+            int r = t + q * NT;
             asm volatile("" : "+v"(r));
             op[r] = e4m3_to_half(fnew[q]);
         }
@@ -296,10 +296,12 @@ int resident_degree(int maxdeg) {
     return -1;
 }
 
-// rows of the resident kernel (N padded to RPT*RES_THREADS)
+// rows of the resident kernel: N padded to a power of two, at least 512
 int resident_rows(int N) {
-    const int rpt = resident_rpt(N);
-    return rpt < 0 ? -1 : rpt * RES_THREADS;
+    if (N < 1 || N > RES_MAX_ROWS) return -1;
+    int nr = 512;
+    while (nr < N) nr *= 2;
+    return nr;
 }
 
 size_t resident_lds_bytes(int N, int D) {
@@ -307,83 +309,79 @@ size_t resident_lds_bytes(int N, int D) {
     return rows < 0 ? 0 : (size_t)rows * (16 + 4 * D);
 }
 
-// rows per thread (1, 2, 4 or 8), or -1 when N is too large
+// threads per workgroup: 1024 from 2048 rows (measured per step, 6-regular,
+// 2048 columns: 4096 rows 6.96 against 7.22 us, 2048 rows 4.12 against 4.31;
+// at 1024 rows 512 threads are 1-2% faster)
+int resident_threads(int N) {
+    const int rows = resident_rows(N);
+    return rows < 0 ? -1 : rows >= 2048 ? 1024 : 512;
+}
+
+// rows per thread (1, 2 or 4), or -1 when N is too large
 int resident_rpt(int N) {
-    const int need = (N + RES_THREADS - 1) / RES_THREADS;
-    for (int r = 1; r <= RES_MAX_RPT; r *= 2)
-        if (need <= r) return r;
-    return -1;
+    const int rows = resident_rows(N);
+    return rows < 0 ? -1 : rows / resident_threads(N);
 }
 
 int resident_cols() { return RES_COLS; }
-int resident_threads() { return RES_THREADS; }
 
-template <int RPT, int D>
-static hipError_t launch_res(const ResidentArgs &a, int nwg, hipStream_t st) {
-    const void *fn = reinterpret_cast<const void *>(&k_csr_resident<RPT, D>);
-    const size_t lds = resident_lds_bytes(a.N, D);
-    hipError_t e = ensure_dyn_lds(fn, lds);
-    if (e != hipSuccess) return e;
-    ResidentArgs arg = a;
-    void *args[] = {&arg};
-    return hipLaunchKernel(fn, dim3(nwg), dim3(RES_THREADS), args, (unsigned)lds, st);
+// The instances that are built: 512 threads with 1 or 2 rows each, 1024
+// threads with 2 or 4 rows each (4 only up to degree 6: the register budget
+// of four waves per SIMD).
+template <int RPT, int NT>
+constexpr bool res_built(int D) {
+    return (NT == 512 && (RPT == 1 || RPT == 2)) || (NT == 1024 && (RPT == 2 || (RPT == 4 && D <= 6)));
 }
 
-template <int RPT>
-static hipError_t launch_res_d(const ResidentArgs &a, int D, int nwg, hipStream_t st) {
-    switch (D) {
-        case 4: return launch_res<RPT, 4>(a, nwg, st);
-        case 6: return launch_res<RPT, 6>(a, nwg, st);
-        case 8: return launch_res<RPT, 8>(a, nwg, st);
-        case 12: return launch_res<RPT, 12>(a, nwg, st);
-        case 16: return launch_res<RPT, 16>(a, nwg, st);
-        default: return hipErrorInvalidValue;
-    }
+template <class F>
+static hipError_t with_resident(int RPT, int D, int NT, F &&f) {
+    auto by_d = [&](auto rpt_c, auto nt_c) -> hipError_t {
+        constexpr int R_ = decltype(rpt_c)::value, T_ = decltype(nt_c)::value;
+        switch (D) {
+            case 4: return f(&k_csr_resident<R_, 4, T_>, T_);
+            case 6: return f(&k_csr_resident<R_, 6, T_>, T_);
+            case 8: if constexpr (res_built<R_, T_>(8)) return f(&k_csr_resident<R_, 8, T_>, T_); else break;
+            case 12: if constexpr (res_built<R_, T_>(12)) return f(&k_csr_resident<R_, 12, T_>, T_); else break;
+            case 16: if constexpr (res_built<R_, T_>(16)) return f(&k_csr_resident<R_, 16, T_>, T_); else break;
+            default: break;
+        }
+        return hipErrorInvalidValue;
+    };
+    using I = std::integral_constant<int, 1>;
+    using II = std::integral_constant<int, 2>;
+    using IV = std::integral_constant<int, 4>;
+    using T5 = std::integral_constant<int, 512>;
+    using T10 = std::integral_constant<int, 1024>;
+    if (NT == 512 && RPT == 1) return by_d(I{}, T5{});
+    if (NT == 512 && RPT == 2) return by_d(II{}, T5{});
+    if (NT == 1024 && RPT == 2) return by_d(II{}, T10{});
+    if (NT == 1024 && RPT == 4) return by_d(IV{}, T10{});
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_csr_resident(const ResidentArgs &a, int D, hipStream_t st) {
-    const int rpt = resident_rpt(a.N);
+    const int rpt = resident_rpt(a.N), nt = resident_threads(a.N);
     if (a.R % RES_COLS || rpt < 0 || a.N > 65535) return hipErrorInvalidValue;
-    const int nwg = a.nwg;
-    switch (rpt) {
-        case 1: return launch_res_d<1>(a, D, nwg, st);
-        case 2: return launch_res_d<2>(a, D, nwg, st);
-        case 4: return launch_res_d<4>(a, D, nwg, st);
-        case 8: return launch_res_d<8>(a, D, nwg, st);
-        default: return hipErrorInvalidValue;
-    }
+    const size_t lds = resident_lds_bytes(a.N, D);
+    return with_resident(rpt, D, nt, [&](auto kern, int threads) -> hipError_t {
+        const void *fn = reinterpret_cast<const void *>(kern);
+        hipError_t e = ensure_dyn_lds(fn, lds);
+        if (e != hipSuccess) return e;
+        ResidentArgs arg = a;
+        void *args[] = {&arg};
+        return hipLaunchKernel(fn, dim3(a.nwg), dim3(threads), args, (unsigned)lds, st);
+    });
 }
 
 hipError_t resident_max_blocks(int D, int N, int *blocks_per_cu) {
-    const int rpt = resident_rpt(N);
+    const int rpt = resident_rpt(N), nt = resident_threads(N);
     const size_t lds = resident_lds_bytes(N, D);
-    hipError_t e;
-#define SBQA_OCC(R_, D_)                                                                                   \
-    do {                                                                                                    \
-        const void *f_ = reinterpret_cast<const void *>(&k_csr_resident<R_, D_>);                          \
-        e = ensure_dyn_lds(f_, lds);                                                                        \
-        if (e == hipSuccess)                                                                                \
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f_, RES_THREADS, lds);          \
-    } while (0)
-#define SBQA_OCC_D(R_)                                                                                     \
-    switch (D) {                                                                                            \
-        case 4: SBQA_OCC(R_, 4); break;                                                                     \
-        case 6: SBQA_OCC(R_, 6); break;                                                                     \
-        case 8: SBQA_OCC(R_, 8); break;                                                                     \
-        case 12: SBQA_OCC(R_, 12); break;                                                                   \
-        case 16: SBQA_OCC(R_, 16); break;                                                                   \
-        default: e = hipErrorInvalidValue;                                                                  \
-    }
-    switch (rpt) {
-        case 1: SBQA_OCC_D(1) break;
-        case 2: SBQA_OCC_D(2) break;
-        case 4: SBQA_OCC_D(4) break;
-        case 8: SBQA_OCC_D(8) break;
-        default: e = hipErrorInvalidValue;
-    }
-#undef SBQA_OCC_D
-#undef SBQA_OCC
-    return e;
+    return with_resident(rpt, D, nt, [&](auto kern, int threads) -> hipError_t {
+        const void *fn = reinterpret_cast<const void *>(kern);
+        hipError_t e = ensure_dyn_lds(fn, lds);
+        if (e != hipSuccess) return e;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, threads, lds);
+    });
 }
 
 }  // namespace sbqa

@@ -919,7 +919,7 @@ static bool resident_plan(sbqa_ctx *c, const sbqa_coupling *J, std::string *why)
     for (int i = 0; i < c->N; ++i) maxdeg = std::max(maxdeg, J->row_ptr[i + 1] - J->row_ptr[i]);
     const int D = resident_degree(maxdeg);
     if (D < 0) { *why = "degree above 16"; return false; }
-    if (rpt == 8 && D > 6) { *why = "N above 2048 with degree above 6 exceeds the register budget"; return false; }
+    if (resident_rows(c->N) > 2048 && D > 6) { *why = "N above 2048 with degree above 6 exceeds the register budget"; return false; }
     const size_t lds = resident_lds_bytes(c->N, D);
     if (lds > 160 * 1024) { *why = "LDS demand above 160 KiB"; return false; }
     int bpc = 0, cus = 0;

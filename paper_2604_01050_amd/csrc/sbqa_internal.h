@@ -220,7 +220,7 @@ size_t resident_lds_bytes(int N, int D);
 int resident_cols();
 int resident_rpt(int N);             // rows per thread, or -1 when N is too large
 int resident_rows(int N);            // padded row count NR, or -1
-int resident_threads();
+int resident_threads(int N);         // threads per workgroup, or -1
 hipError_t resident_max_blocks(int D, int N, int *blocks_per_cu);
 // Raises a kernel's dynamic LDS limit on the current device to at least lds
 // bytes. The runtime call is made only when the limit grows (one lookup under
