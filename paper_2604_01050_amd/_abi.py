@@ -61,6 +61,14 @@ def _load() -> ct.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsbqa.so is not built (run paper_2604_01050_amd.build.build()); "
                           "there is no fallback path")
+    # PyTorch ships its own HIP runtime: loaded first, it is the one the
+    # library binds to, so the process holds one runtime (loading the library
+    # first left two, and the library's could not use PyTorch's streams and
+    # reported too few co-resident workgroups for the resident loop)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ct.CDLL(LIB_PATH)
     vp, i32, u32, u64, d = ct.c_void_p, ct.c_int32, ct.c_uint32, ct.c_uint64, ct.c_double
     sig = {

@@ -1035,6 +1035,33 @@ def test_resident_rejects_unfit_instances(sb):
         assert not sb.sbqa_info(ctx)["resident"]
 
 
+def test_package_imported_before_torch_keeps_one_runtime(sb):
+    """Imported before PyTorch, the binding still leaves one HIP runtime in
+    the process (PyTorch's): in a fresh process that imports the package
+    first, the benchmark's sparse shape runs the resident loop on a PyTorch
+    stream and reads out."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = "\n".join([
+        "import paper_2604_01050_amd as sb",
+        "import torch",
+        "import sbqa_instances as inst",
+        "N = 4096",
+        "E = inst.regular_graph(N, 6, 9001)",
+        "csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 9002))",
+        "c = sb.sbqa_create(csr=csr, R=32, runs=64, steps=50, loop_kernel=sb.LOOP_RESIDENT)",
+        "st = torch.cuda.Stream()",
+        "sb.sbqa_set_stream(c, st)",
+        "sb.sbqa_step(c, 5)",
+        "E0, _ = sb.sbqa_best(c)",
+        "print('resident', sb.sbqa_info(c)['resident'], bool(abs(E0[0]) < 1e12))",
+        "sb.sbqa_destroy(c)"])
+    _log("package imported before torch: fresh process, resident sparse N=4096")
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=110)
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "resident True True" in r.stdout, r.stdout
+
+
 # ------------------------------------------------------------ internal spin relabelling
 @pytest.mark.gpu
 @pytest.mark.parametrize("case", ["hubo_int", "ising_resident", "ising_stream"])
