@@ -1,17 +1,26 @@
-// Resident loop for small dense instances (gfx950): one workgroup per run
-// keeps J (float32) and the positions and operand of its R replicas in LDS and
-// the velocities in registers, and advances K steps of Eqs. 6-7 per launch,
-// so a small all-to-all instance costs one launch per K steps instead of one
-// per step. Fields are summed in a fixed order over j (four interleaved
-// partial sums), so integer couplings with a ternary or sign operand give
-// exactly the fields of the MFMA path.
+// Resident loop for small dense instances (gfx950): one workgroup per run;
+// each thread keeps one row of J (float32) in registers for the whole launch
+// and owns that spin in some of the run's replicas, whose positions and
+// operand sit in LDS (every lane of a wave reads the same operand row, a
+// broadcast) and whose velocities stay in registers; the loop advances K
+// steps of Eqs. 6-7 per launch, so a small all-to-all instance costs one
+// launch per K steps instead of one per step. Fields are summed in a fixed
+// order over j (four interleaved partial sums), so integer couplings with a
+// ternary or sign operand give exactly the fields of the MFMA path.
 #include "sbqa_internal.h"
+
+#include <type_traits>
 
 namespace sbqa {
 namespace {
 
-constexpr int SM_THREADS = 512;   // two waves per SIMD: 1.50 against 1.99 us per step at N = 64, R = 8
-constexpr int SM_EPT = SMALL_MAX_ELEMS / SM_THREADS;  // replica-spin elements per thread
+constexpr int SM_THREADS = 512;   // two waves per SIMD
+// replica-spin elements per thread: thread t keeps row i = t % N of J in
+// registers and owns replicas t / N + m * (SM_THREADS / N); the largest m
+// count over N <= SMALL_MAX_N and R * N <= SMALL_MAX_ELEMS is 10 (N = 104)
+constexpr int SM_EPT = 10;
+
+__host__ __device__ constexpr int small_row_stride(int N) { return (N + 3) / 4 * 4; }
 
 __device__ __forceinline__ float f_small(int fmode, float x, float delta) {
     if (fmode == 2) return x;                       // bSB
@@ -21,101 +30,145 @@ __device__ __forceinline__ float f_small(int fmode, float x, float delta) {
 }
 
 #pragma clang fp contract(off)
+// NMAX: N rounded up to 32, 64 or 128 (J row registers); M: replicas per
+// thread, ceil(R / (SM_THREADS / N)) rounded up to 1, 2, 4 or SM_EPT; FULL:
+// N == NMAX (the coupling sum needs no bounds)
+template <int NMAX, int M, bool FULL>
 __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
-    extern __shared__ float sm[];
-    const int N = a.N, R = a.R, NS = N + 1;      // odd J row stride: conflict-free column walks
-    float *Js = sm;                               // [N][N+1]
-    float *xs = Js + N * NS;                      // [R][N] positions of this run
-    float *fs = xs + R * N;                       // [R][N] operand f(x)
-    const int run = blockIdx.x, tid = threadIdx.x, E = R * N;
-    for (int e = tid; e < N * N; e += SM_THREADS) Js[(e / N) * NS + e % N] = a.J[e];
-
-    // this thread's elements e = tid + q*SM_THREADS: replica k = e / N, spin i = e % N
-    float yv[SM_EPT], hv[SM_EPT];
-    int ek[SM_EPT], ei[SM_EPT];
+    extern __shared__ __align__(16) float sm[];
+    const int N = a.N, R = a.R, NS = small_row_stride(N);
+    float *xs = sm;                               // [R][NS] positions of this run
+    float *fs = xs + R * NS;                      // [R][NS] operand f(x), zero past N
+    const int run = blockIdx.x, tid = threadIdx.x;
+    const int G = SM_THREADS / N, i = tid % N, g = tid / N;
+    const bool active = g < G;
+    const int N4 = N & ~3;
+    // row i of J, zero past N: the padding terms add +0 to sums that start
+    // at +0 and so never hold -0
+    float jr[NMAX];
 #pragma unroll
-    for (int q = 0; q < SM_EPT; ++q) {
-        const int e = tid + q * SM_THREADS;
-        ek[q] = e / N;
-        ei[q] = e - ek[q] * N;
-        if (e < E) {
-            const int64_t o = (int64_t)(run * R + ek[q]) * a.Np + ei[q];
+    for (int j = 0; j < NMAX; ++j) jr[j] = (active && j < N) ? a.J[(int64_t)i * N + j] : 0.0f;
+    for (int e = tid; e < R * NS; e += SM_THREADS) fs[e] = 0.0f;
+    __syncthreads();
+    // this thread's replicas k = g + m * G
+    float yv[M], hv[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = g + m * G;
+        if (active && k < R) {
+            const int64_t o = (int64_t)(run * R + k) * a.Np + i;
             const float x = a.x[o];
-            xs[e] = x;
-            fs[e] = f_small(a.fmode, x, a.delta[a.n0]);
-            yv[q] = a.y[o];
-            hv[q] = a.h[ei[q]];
+            xs[k * NS + i] = x;
+            fs[k * NS + i] = f_small(a.fmode, x, a.delta[a.n0]);
+            yv[m] = a.y[o];
+            hv[m] = a.h[i];
         }
     }
     __syncthreads();
 
+    // the step's scalars are loaded one step ahead (their loads drain while
+    // the previous step runs instead of stalling the update)
+    float kA_next = a.coefA[a.n0], dnext_next = a.delta[a.n0 + 1], jpr_next = a.jp[(int64_t)run * a.S + a.n0];
     for (int n = a.n0; n < a.n0 + a.K; ++n) {
-        const float kA = a.coefA[n], dnext = a.delta[n + 1], jpr = a.jp[(int64_t)run * a.S + n];
-        float xn[SM_EPT];
+        const float kA = kA_next, dnext = dnext_next, jpr = jpr_next;
+        if (n + 1 < a.n0 + a.K) {
+            kA_next = a.coefA[n + 1];
+            dnext_next = a.delta[n + 2];
+            jpr_next = a.jp[(int64_t)run * a.S + n + 1];
+        }
+        float xn[M];
 #pragma unroll
-        for (int q = 0; q < SM_EPT; ++q) {
-            const int e = tid + q * SM_THREADS;
-            if (e >= E) continue;
-            const int k = ek[q], i = ei[q];
-            const float *jrow = Js + i * NS, *frow = fs + k * N;
-            // four interleaved partial sums over j = 4m + u, then (s0 + s1) +
-            // (s2 + s3): a fixed order with four independent FMA chains
+        for (int m = 0; m < M; ++m) {
+            const int k = g + m * G;
+            if (!active || k >= R) continue;
+            const float4 *frow = reinterpret_cast<const float4 *>(fs + k * NS);
+            // four interleaved partial sums over j = 4m + u below N4, the
+            // tail j = N4..N-1 into s0, then (s0 + s1) + (s2 + s3): a fixed
+            // order with four independent FMA chains
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
-            int j = 0;
-            for (; j + 3 < N; j += 4) {
-                s0 = fmaf(jrow[j], frow[j], s0);
-                s1 = fmaf(jrow[j + 1], frow[j + 1], s1);
-                s2 = fmaf(jrow[j + 2], frow[j + 2], s2);
-                s3 = fmaf(jrow[j + 3], frow[j + 3], s3);
+#pragma unroll
+            for (int j = 0; j < NMAX; j += 4) {
+                if (FULL || j < N4) {
+                    const float4 f = frow[j / 4];
+                    s0 = fmaf(jr[j], f.x, s0);
+                    s1 = fmaf(jr[j + 1], f.y, s1);
+                    s2 = fmaf(jr[j + 2], f.z, s2);
+                    s3 = fmaf(jr[j + 3], f.w, s3);
+                } else if (j < N) {
+                    const float4 f = frow[j / 4];
+                    s0 = fmaf(jr[j], f.x, s0);
+                    if (j + 1 < N) s0 = fmaf(jr[j + 1], f.y, s0);
+                    if (j + 2 < N) s0 = fmaf(jr[j + 2], f.z, s0);
+                }
             }
-            for (; j < N; ++j) s0 = fmaf(jrow[j], frow[j], s0);
             const float phi = (s0 + s1) + (s2 + s3);
             const int kl = (k == 0) ? R - 1 : k - 1, kr = (k == R - 1) ? 0 : k + 1;
-            const float x = xs[e], xl = xs[kl * N + i], xr = xs[kr * N + i];
-            const float force = (-kA * x + a.kB * (phi + hv[q])) + jpr * (xl + xr);
-            float yn = yv[q] + a.dt * force;
+            const float x = xs[k * NS + i], xl = xs[kl * NS + i], xr = xs[kr * NS + i];
+            const float force = (-kA * x + a.kB * (phi + hv[m])) + jpr * (xl + xr);
+            float yn = yv[m] + a.dt * force;
             float xv = x + a.kD * yn;
             if (fabsf(xv) > 1.0f) {
                 xv = xv > 0.0f ? 1.0f : -1.0f;
                 yn = 0.0f;
             }
-            yv[q] = yn;
-            xn[q] = xv;
+            yv[m] = yn;
+            xn[m] = xv;
         }
         __syncthreads();   // every read of step n's positions and operand is done
 #pragma unroll
-        for (int q = 0; q < SM_EPT; ++q) {
-            const int e = tid + q * SM_THREADS;
-            if (e >= E) continue;
-            xs[e] = xn[q];
-            fs[e] = f_small(a.fmode, xn[q], dnext);
+        for (int m = 0; m < M; ++m) {
+            const int k = g + m * G;
+            if (!active || k >= R) continue;
+            xs[k * NS + i] = xn[m];
+            fs[k * NS + i] = f_small(a.fmode, xn[m], dnext);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int q = 0; q < SM_EPT; ++q) {
-        const int e = tid + q * SM_THREADS;
-        if (e >= E) continue;
-        const int64_t o = (int64_t)(run * R + ek[q]) * a.Np + ei[q];
-        a.x[o] = xs[e];
-        a.y[o] = yv[q];
+    for (int m = 0; m < M; ++m) {
+        const int k = g + m * G;
+        if (!active || k >= R) continue;
+        const int64_t o = (int64_t)(run * R + k) * a.Np + i;
+        a.x[o] = xs[k * NS + i];
+        a.y[o] = yv[m];
     }
 }
 #pragma clang fp contract(on)
 
 }  // namespace
 
-size_t small_lds_bytes(int N, int R) { return sizeof(float) * ((size_t)N * (N + 1) + 2 * (size_t)R * N); }
+size_t small_lds_bytes(int N, int R) { return sizeof(float) * 2 * (size_t)R * small_row_stride(N); }
 
 hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
     if (a.N < 1 || a.N > SMALL_MAX_N || a.R < 1 || a.R * a.N > SMALL_MAX_ELEMS || a.K < 1 || a.n0 < 0 ||
         a.n0 + a.K > a.S)
         return hipErrorInvalidValue;
+    // every replica of the run has a thread group: R <= SM_EPT * (SM_THREADS / N)
+    if (a.R > SM_EPT * (SM_THREADS / a.N)) return hipErrorInvalidValue;
     const size_t lds = small_lds_bytes(a.N, a.R);
-    hipError_t e = ensure_dyn_lds(reinterpret_cast<const void *>(&k_dense_small), lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_dense_small, dim3(runs), dim3(SM_THREADS), lds, st, a);
-    return hipGetLastError();
+    auto go = [&](auto kern) -> hipError_t {
+        hipError_t e = ensure_dyn_lds(reinterpret_cast<const void *>(kern), lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3(runs), dim3(SM_THREADS), lds, st, a);
+        return hipGetLastError();
+    };
+    const int G = SM_THREADS / a.N, m = (a.R + G - 1) / G;
+    auto by_m = [&](auto nmax) -> hipError_t {
+        constexpr int NM = decltype(nmax)::value;
+        if (a.N == NM) {
+            if (m <= 1) return go(&k_dense_small<NM, 1, true>);
+            if (m <= 2) return go(&k_dense_small<NM, 2, true>);
+            if (m <= 4) return go(&k_dense_small<NM, 4, true>);
+            return go(&k_dense_small<NM, SM_EPT, true>);
+        }
+        if (m <= 1) return go(&k_dense_small<NM, 1, false>);
+        if (m <= 2) return go(&k_dense_small<NM, 2, false>);
+        if (m <= 4) return go(&k_dense_small<NM, 4, false>);
+        return go(&k_dense_small<NM, SM_EPT, false>);
+    };
+    if (a.N <= 32) return by_m(std::integral_constant<int, 32>{});
+    if (a.N <= 64) return by_m(std::integral_constant<int, 64>{});
+    return by_m(std::integral_constant<int, 128>{});
 }
 
 }  // namespace sbqa
