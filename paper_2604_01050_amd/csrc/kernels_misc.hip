@@ -406,18 +406,36 @@ __global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_colblock(int N, int
         sl[k * T + t] = l[k];
     }
     __syncthreads();
-    for (int s2 = T / 2; s2 > 0; s2 >>= 1) {
-        if (t < s2)
+    // the same pairwise tree over the T slots of each of the 16 sums (q and
+    // l of 8 columns), one sum per wave, in registers: lane ln holds slots
+    // ln + 64 j (j < 16); the levels of width 512, 256, 128 and 64 add
+    // register j + width / 64 into j, the levels 32 .. 1 add lane ln + width
+    // into lane ln, so slot t + width is added into slot t at every level,
+    // as in the spin-major kernels
+    static_assert(T == 1024, "16 waves of 64 lanes, 16 slots per lane");
+    __shared__ double red[16];
+    {
+        const int u = t >> 6, ln = t & 63;
+        const double *src = u < 8 ? sq + u * T : sl + (u - 8) * T;
+        double v[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                sq[k * T + t] += sq[k * T + t + s2];
-                sl[k * T + t] += sl[k * T + t + s2];
-            }
-        __syncthreads();
+        for (int j = 0; j < 8; ++j) v[j] = src[ln + 64 * j] + src[ln + 64 * (j + 8)];
+#pragma unroll
+        for (int wd = 4; wd >= 1; wd >>= 1)
+#pragma unroll
+            for (int j = 0; j < wd; ++j) v[j] = v[j] + v[j + wd];
+        double x = v[0];
+#pragma unroll
+        for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+            const double o = __shfl_down(x, s2);
+            if (ln < s2) x = x + o;
+        }
+        if (ln == 0) red[u] = x;
     }
+    __syncthreads();
     const double s3 = 0.0;   // no three-body terms on this path
     if constexpr (!FUSE) {
-        if (t < 8) E[w * 8 + t] = -0.5 * sq[t * T] - sl[t * T] - s3 / 3.0;
+        if (t < 8) E[w * 8 + t] = -0.5 * red[t] - red[8 + t] - s3 / 3.0;
     } else {
         // the best update of the run and the readout block, by the last of
         // the run's R / 8 workgroups to finish its energies: they are stored
@@ -427,7 +445,7 @@ __global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_colblock(int N, int
         __shared__ int last, sel;
         __shared__ double kept;
         if (t < 8)
-            __hip_atomic_store(E + w * 8 + t, -0.5 * sq[t * T] - sl[t * T] - s3 / 3.0, __ATOMIC_RELAXED,
+            __hip_atomic_store(E + w * 8 + t, -0.5 * red[t] - red[8 + t] - s3 / 3.0, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_AGENT);
         if (w == 0 && t == 0) *reinterpret_cast<int *>(f.host + (size_t)8 * f.runs) = *f.err;
         __builtin_amdgcn_s_waitcnt(0);
