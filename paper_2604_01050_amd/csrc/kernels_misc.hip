@@ -152,8 +152,8 @@ __device__ __forceinline__ double tri_psi(const Tri3 &t3, int i, SpinOf spin) {
 }
 
 // CSR energies of the readout of a state (element (i, c) at
-// state_off(order, ld, i, c)). Stage 1: block (row block rb, 256 columns)
-// accumulates per column over its rows in row order.
+// state_off(order, ld, i, c)). Stage 1: block (row block rb, up to 256
+// columns) accumulates per column over its rows in row order.
 __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int order, int ld, int C, int rows_per_blk,
                                                             const int32_t *__restrict__ row_ptr,
                                                             const int32_t *__restrict__ col,
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int order, in
                                                             const double *__restrict__ h,
                                                             const float *__restrict__ x,
                                                             double *__restrict__ partial) {
-    const int c = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
     const int rb = blockIdx.y;
     if (c >= C) return;
     double q = 0.0, l = 0.0, q3 = 0.0;
@@ -183,6 +183,30 @@ __global__ __launch_bounds__(256) void k_csr_energy_partial(int N, int order, in
     partial[((int64_t)rb * C + c) * 3 + 2] = q3;
 }
 
+// The pairwise tree over ENERGY_SLOTS = 1024 slots (slot t += slot t + w for
+// w = 512, 256, ..., 1) reduced by one wave in registers: lane ln holds slots
+// ln + 64 j (j < 16); the levels of width 512 .. 64 add register
+// j + width / 64 into j, the levels 32 .. 1 add lane ln + width into lane
+// ln, so every level adds the same pairs, left + right, as the slot-by-slot
+// tree. Lane 0 returns the sum of src[0 .. 1023].
+__device__ __forceinline__ double wave_tree1024(const double *src, int ln) {
+    static_assert(ENERGY_SLOTS == 1024, "16 slots per lane of a 64-lane wave");
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = src[ln + 64 * j] + src[ln + 64 * (j + 8)];
+#pragma unroll
+    for (int wd = 4; wd >= 1; wd >>= 1)
+#pragma unroll
+        for (int j = 0; j < wd; ++j) v[j] = v[j] + v[j + wd];
+    double x = v[0];
+#pragma unroll
+    for (int s2 = 32; s2 >= 1; s2 >>= 1) {
+        const double o = __shfl_down(x, s2);
+        if (ln < s2) x = x + o;
+    }
+    return x;
+}
+
 // Stage 2: block per column, thread t sums the row blocks of slot t in
 // increasing order, then the pairwise tree over the slots.
 __global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_final(int C, int nrb, const double *__restrict__ partial,
@@ -199,15 +223,15 @@ __global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_final(int C, int nr
     sl[t] = l;
     s3[t] = q3;
     __syncthreads();
-    for (int w = ENERGY_SLOTS / 2; w > 0; w >>= 1) {
-        if (t < w) {
-            sq[t] += sq[t + w];
-            sl[t] += sl[t + w];
-            s3[t] += s3[t + w];
-        }
-        __syncthreads();
+    // the pairwise tree of each sum, by waves 0, 1 and 2
+    __shared__ double red[3];
+    const int u = t >> 6;
+    if (u < 3) {
+        const double x = wave_tree1024(u == 0 ? sq : u == 1 ? sl : s3, t & 63);
+        if ((t & 63) == 0) red[u] = x;
     }
-    if (t == 0) E[c] = -0.5 * sq[0] - sl[0] - s3[0] / 3.0;
+    __syncthreads();
+    if (t == 0) E[c] = -0.5 * red[0] - red[1] - red[2] / 3.0;
 }
 
 // CSR energies of the readout of a column-block state (ORDER_COLBLOCK8, no
@@ -406,31 +430,14 @@ __global__ __launch_bounds__(ENERGY_SLOTS) void k_csr_energy_colblock(int N, int
         sl[k * T + t] = l[k];
     }
     __syncthreads();
-    // the same pairwise tree over the T slots of each of the 16 sums (q and
-    // l of 8 columns), one sum per wave, in registers: lane ln holds slots
-    // ln + 64 j (j < 16); the levels of width 512, 256, 128 and 64 add
-    // register j + width / 64 into j, the levels 32 .. 1 add lane ln + width
-    // into lane ln, so slot t + width is added into slot t at every level,
-    // as in the spin-major kernels
-    static_assert(T == 1024, "16 waves of 64 lanes, 16 slots per lane");
+    // the pairwise tree of each of the 16 sums (q and l of 8 columns), one
+    // wave each
+    static_assert(T == 1024, "16 waves, one sum each");
     __shared__ double red[16];
     {
-        const int u = t >> 6, ln = t & 63;
-        const double *src = u < 8 ? sq + u * T : sl + (u - 8) * T;
-        double v[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v[j] = src[ln + 64 * j] + src[ln + 64 * (j + 8)];
-#pragma unroll
-        for (int wd = 4; wd >= 1; wd >>= 1)
-#pragma unroll
-            for (int j = 0; j < wd; ++j) v[j] = v[j] + v[j + wd];
-        double x = v[0];
-#pragma unroll
-        for (int s2 = 32; s2 >= 1; s2 >>= 1) {
-            const double o = __shfl_down(x, s2);
-            if (ln < s2) x = x + o;
-        }
-        if (ln == 0) red[u] = x;
+        const int u = t >> 6;
+        const double x = wave_tree1024(u < 8 ? sq + u * T : sl + (u - 8) * T, t & 63);
+        if ((t & 63) == 0) red[u] = x;
     }
     __syncthreads();
     const double s3 = 0.0;   // no three-body terms on this path
@@ -549,6 +556,29 @@ __global__ __launch_bounds__(1024) void k_best_update(int N, int R, int order, i
     for (int i = t; i < N; i += 1024) best_spins[(int64_t)r * N + i] = x[state_off(order, ld, i, c)] >= 0.0f ? 1 : -1;
 }
 
+// The same update in two launches, so that the spin copy of a large
+// instance runs on many workgroups: k_best_select (one wave per run) writes
+// the winning replica, or -1, to sel[r]; k_best_copy (runs x chunks) copies
+// the winner's spins.
+__global__ __launch_bounds__(64) void k_best_select(int R, const double *__restrict__ E, double *__restrict__ best_E,
+                                                   int64_t *__restrict__ best_step, int *__restrict__ sel, int64_t step,
+                                                   int reset) {
+    __shared__ int s;
+    __shared__ double kept;
+    select_best<false>(E, blockIdx.x, R, threadIdx.x, best_E, best_step, step, reset, &s, &kept);
+    __syncthreads();
+    if (threadIdx.x == 0) sel[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_best_copy(int N, int R, int order, int ld, const float *__restrict__ x,
+                                                  const int *__restrict__ sel, int8_t *__restrict__ best_spins) {
+    const int r = blockIdx.y, k = sel[r];
+    if (k < 0) return;
+    const int c = r * R + k;
+    for (int i = blockIdx.x * 256 + threadIdx.x; i < N; i += gridDim.x * 256)
+        best_spins[(int64_t)r * N + i] = x[state_off(order, ld, i, c)] >= 0.0f ? 1 : -1;
+}
+
 // Row-major N x N float64 rows into the first N columns of rows of length Np.
 // Whole 16-byte vectors, then the tail bytes one by one (thread 0).
 __global__ void k_copy_to_host(const uint8_t *__restrict__ src, uint8_t *__restrict__ dst, size_t bytes) {
@@ -647,7 +677,9 @@ hipError_t launch_csr_energy_state(int N, int order, int ld, int C, const int32_
                                    const double *val, const Tri3 &t3, const double *h, const float *x,
                                    double *partial, int nblk_rows, double *E, hipStream_t st) {
     const int rows_per_blk = (N + nblk_rows - 1) / nblk_rows;
-    dim3 grid((C + 255) / 256, nblk_rows), block(256);
+    // whole waves over the columns, at most 256 threads
+    const int bx = std::min(256, (C + 63) / 64 * 64);
+    dim3 grid((C + bx - 1) / bx, nblk_rows), block(bx);
     hipLaunchKernelGGL(k_csr_energy_partial, grid, block, 0, st, N, order, ld, C, rows_per_blk, row_ptr, col, val, t3,
                        h, x, partial);
     hipLaunchKernelGGL(k_csr_energy_final, dim3(C), dim3(ENERGY_SLOTS), 0, st, C, nblk_rows, partial, E);
@@ -733,7 +765,14 @@ hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const floa
 
 hipError_t launch_best_update(int N, int R, int runs, int order, int ld, const float *x, const double *E,
                               double *best_E, int64_t *best_step, int8_t *best_spins, int64_t step, bool reset,
-                              hipStream_t st) {
+                              int *sel, hipStream_t st) {
+    if (N > BEST_SPLIT_N && sel) {
+        hipLaunchKernelGGL(k_best_select, dim3(runs), dim3(64), 0, st, R, E, best_E, best_step, sel, step,
+                           reset ? 1 : 0);
+        const int chunks = std::min(1024, (N + 256 * 8 - 1) / (256 * 8));
+        hipLaunchKernelGGL(k_best_copy, dim3(chunks, runs), dim3(256), 0, st, N, R, order, ld, x, sel, best_spins);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_best_update, dim3(runs), dim3(1024), 0, st, N, R, order, ld, x, E, best_E, best_step,
                        best_spins, step, reset ? 1 : 0);
     return hipGetLastError();

@@ -325,6 +325,12 @@ void plan_layout(int32_t N, int32_t R, int32_t runs, const InstanceFacts &f, Lay
         const int64_t ncb = (C + 255) / 256;
         L->csr_nrb = (int)std::max<int64_t>(
             1, std::min<int64_t>((N + 3) / 4, std::max<int64_t>(ENERGY_SLOTS, (2048 + ncb - 1) / ncb)));
+        // large instances: shorter row blocks (the first stage walks a
+        // block's rows one after another, a chain of dependent loads per row),
+        // at least 32 rows each, the partials within 64 MiB
+        if (N > 65536)
+            L->csr_nrb = (int)std::max<int64_t>(
+                L->csr_nrb, std::min<int64_t>((N + 31) / 32, ((int64_t)64 << 20) / ((int64_t)C * 24)));
         b += (int64_t)L->csr_nrb * C * 24;
         if (f.n3) b += (int64_t)(N + 1) * 4 + 3 * f.n3 * (8 + 4 + 8);    // three-body lists
         b += (int64_t)N * L->Cs * 4;                                      // phi (fields hook)
@@ -570,6 +576,7 @@ sbqa_status ctx_upload(sbqa_ctx *c, const sbqa_coupling *J, const double *h, con
     }
     HIP_TRY(dalloc(c, &c->E, (size_t)std::max(C, Cp)));
     HIP_TRY(dalloc(c, &c->bestStep, (size_t)runs));
+    if (N > BEST_SPLIT_N) HIP_TRY(dalloc(c, &c->bsel, (size_t)runs));
     c->rbytes = (size_t)8 * runs + 8 + (size_t)runs * N;
     HIP_TRY(dalloc(c, &c->rdev, c->rbytes));
     HIP_TRY(hipHostMalloc((void **)&c->rhost, c->rbytes, hipHostMallocCoherent));
@@ -895,7 +902,7 @@ sbqa_status ctx_evaluate(sbqa_ctx *c, bool reset) {
     sbqa_status st = ctx_state_energies(c);
     if (st != SBQA_OK) return st;
     HIP_TRY(launch_best_update(c->N, c->R, c->runs, c->order, c->ld, c->x[c->cur], c->E, c->bestE, c->bestStep,
-                               c->bestSpins, (int64_t)c->step, reset, c->stream));
+                               c->bestSpins, (int64_t)c->step, reset, c->bsel, c->stream));
     c->last_eval_step = c->step;
     return SBQA_OK;
 }

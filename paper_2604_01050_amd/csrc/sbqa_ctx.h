@@ -142,6 +142,7 @@ struct sbqa_ctx {
     double *csr_partial = nullptr;
     double *E = nullptr;
     int64_t *bestStep = nullptr;
+    int *bsel = nullptr;                // [runs] winning replica of a readout (N > BEST_SPLIT_N)
     // readout block, one device allocation copied to the host in one piece:
     // best energies [runs] float64, the error word of the resident loop (8
     // bytes), best spins [runs][N] int8; rhost is its pinned, coherent host

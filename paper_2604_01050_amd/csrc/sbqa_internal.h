@@ -355,8 +355,12 @@ hipError_t launch_energy_fields(int N, int Np, int C, const float *x, const floa
 // Per-run best over replicas with tie -> lowest k; updates best_E/best_step
 // when strictly lower (than +inf when reset: the previous best is discarded)
 // and copies the winning readout spins; one launch, one workgroup per run.
+// Above BEST_SPLIT_N spins the update runs as two launches (selection, then
+// the spin copy over many workgroups) with sel [runs] int scratch; the
+// results are the same.
+constexpr int BEST_SPLIT_N = 32768;
 hipError_t launch_best_update(int N, int R, int runs, int order, int ld, const float *x, const double *E,
                               double *best_E, int64_t *best_step, int8_t *best_spins, int64_t step, bool reset,
-                              hipStream_t st);
+                              int *sel, hipStream_t st);
 
 }  // namespace sbqa
