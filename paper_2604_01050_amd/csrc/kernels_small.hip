@@ -37,8 +37,10 @@ template <int NMAX, int M, bool FULL>
 __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
     extern __shared__ __align__(16) float sm[];
     const int N = a.N, R = a.R, NS = small_row_stride(N);
-    float *xs = sm;                               // [R][NS] positions of this run
-    float *fs = xs + R * NS;                      // [R][NS] operand f(x), zero past N
+    // two buffers, each [R][NS] positions of this run then [R][NS] operand
+    // f(x) (zero past N): step n reads one and writes the other, so one
+    // barrier per step orders both its reads and the next step's
+    float *const buf0 = sm, *const buf1 = sm + 2 * R * NS;
     const int run = blockIdx.x, tid = threadIdx.x;
     const int G = SM_THREADS / N, i = tid % N, g = tid / N;
     const bool active = g < G;
@@ -48,7 +50,10 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
     float jr[NMAX];
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) jr[j] = (active && j < N) ? a.J[(int64_t)i * N + j] : 0.0f;
-    for (int e = tid; e < R * NS; e += SM_THREADS) fs[e] = 0.0f;
+    for (int e = tid; e < R * NS; e += SM_THREADS) {
+        buf0[R * NS + e] = 0.0f;
+        buf1[R * NS + e] = 0.0f;
+    }
     __syncthreads();
     // this thread's replicas k = g + m * G
     float yv[M], hv[M];
@@ -58,8 +63,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
         if (active && k < R) {
             const int64_t o = (int64_t)(run * R + k) * a.Np + i;
             const float x = a.x[o];
-            xs[k * NS + i] = x;
-            fs[k * NS + i] = f_small(a.fmode, x, a.delta[a.n0]);
+            buf0[k * NS + i] = x;
+            buf0[R * NS + k * NS + i] = f_small(a.fmode, x, a.delta[a.n0]);
             yv[m] = a.y[o];
             hv[m] = a.h[i];
         }
@@ -76,6 +81,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
             dnext_next = a.delta[n + 2];
             jpr_next = a.jp[(int64_t)run * a.S + n + 1];
         }
+        const bool odd = (n - a.n0) & 1;
+        const float *xs = odd ? buf1 : buf0, *fs = xs + R * NS;
+        float *xo = odd ? buf0 : buf1, *fo = xo + R * NS;
         float xn[M];
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -114,16 +122,16 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
             yv[m] = yn;
             xn[m] = xv;
         }
-        __syncthreads();   // every read of step n's positions and operand is done
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int k = g + m * G;
             if (!active || k >= R) continue;
-            xs[k * NS + i] = xn[m];
-            fs[k * NS + i] = f_small(a.fmode, xn[m], dnext);
+            xo[k * NS + i] = xn[m];
+            fo[k * NS + i] = f_small(a.fmode, xn[m], dnext);
         }
-        __syncthreads();
+        __syncthreads();   // step n + 1 reads what step n wrote; step n's reads are done
     }
+    const float *xs = (a.K & 1) ? buf1 : buf0;   // the buffer the last step wrote
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int k = g + m * G;
@@ -137,7 +145,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
 
 }  // namespace
 
-size_t small_lds_bytes(int N, int R) { return sizeof(float) * 2 * (size_t)R * small_row_stride(N); }
+size_t small_lds_bytes(int N, int R) { return sizeof(float) * 4 * (size_t)R * small_row_stride(N); }
 
 hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
     if (a.N < 1 || a.N > SMALL_MAX_N || a.R < 1 || a.R * a.N > SMALL_MAX_ELEMS || a.K < 1 || a.n0 < 0 ||
