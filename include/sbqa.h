@@ -316,8 +316,19 @@ sbqa_status sbqa_set_stream(sbqa_ctx *ctx, void *hip_stream);
 
 sbqa_status sbqa_info(sbqa_ctx *ctx, sbqa_info_t *info);
 
-/* Block until the context's device work has finished. */
+/* Block until the context's device work has finished. EDEVICE when a
+ * resident sparse launch could not complete a step (a ring-neighbour wait
+ * timed out); the state is then invalid. */
 sbqa_status sbqa_sync(sbqa_ctx *ctx);
+
+/* Failure-path test hook of the resident sparse loop: sets the context's
+ * device error word as a ring-neighbour wait timeout would (a neighbouring
+ * workgroup that never published its step), so that the next resident launch
+ * skips its waits and the next call that synchronises (sbqa_best, sbqa_sync)
+ * reports SBQA_EDEVICE; every kernel still runs to its end. The state is
+ * invalid afterwards. EINVAL on a context without the resident sparse loop.
+ * Asynchronous on the context stream. */
+sbqa_status sbqa_inject_wait_timeout(sbqa_ctx *ctx);
 
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *sbqa_last_error(void);

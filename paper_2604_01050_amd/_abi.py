@@ -87,6 +87,7 @@ def _load() -> ct.CDLL:
         "sbqa_set_stream": ([vp, vp], i32),
         "sbqa_info": ([vp, ct.POINTER(Info)], i32),
         "sbqa_sync": ([vp], i32),
+        "sbqa_inject_wait_timeout": ([vp], i32),
         "sbqa_last_error": ([], ct.c_char_p),
         "sbqa_destroy": ([vp], None),
         "sbqa_server_create": ([ct.c_size_t, i32, ct.POINTER(vp)], i32),
@@ -276,6 +277,10 @@ def sbqa_info(ctx: Context) -> dict:
 
 def sbqa_sync(ctx: Context) -> None:
     _check(lib.sbqa_sync(ctx.ptr))
+
+
+def sbqa_inject_wait_timeout(ctx: Context) -> None:
+    _check(lib.sbqa_inject_wait_timeout(ctx.ptr))
 
 
 def sbqa_destroy(ctx: Context) -> None:

@@ -1597,6 +1597,16 @@ sbqa_status sbqa_sync(sbqa_ctx *c) {
     return ctx_sync(c);
 }
 
+sbqa_status sbqa_inject_wait_timeout(sbqa_ctx *c) {
+    clear_error();
+    if (!c) return fail(SBQA_EINVAL, "NULL context");
+    if (!c->resident || c->facts.path != PATH_CSR || !c->err)
+        return fail(SBQA_EINVAL, "the context does not run the resident sparse loop");
+    static const int timed_out = 1;   // the value a timed-out wait stores
+    HIP_TRY(hipMemcpyAsync(c->err, &timed_out, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    return SBQA_OK;
+}
+
 void sbqa_destroy(sbqa_ctx *c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);

@@ -127,6 +127,12 @@ def test_noalloc_energy_argument_errors(abi):
     assert "NULL" in abi.sbqa_last_error()
 
 
+def test_inject_wait_timeout_argument_errors(abi):
+    """The failure-path hook rejects a NULL context before any device work."""
+    assert abi.lib.sbqa_inject_wait_timeout(None) == abi.EINVAL
+    assert "NULL" in abi.sbqa_last_error()
+
+
 def test_server_argument_errors(abi):
     with pytest.raises(abi.SbqaError):
         abi.sbqa_server_create(0, 4)

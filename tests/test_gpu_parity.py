@@ -1035,6 +1035,33 @@ def test_resident_rejects_unfit_instances(sb):
         assert not sb.sbqa_info(ctx)["resident"]
 
 
+def test_resident_wait_timeout_is_reported(sb):
+    """Failure path of the resident sparse loop, forced from the host: with
+    the device error word set as a ring-neighbour wait timeout sets it, the
+    next launch runs through without waiting (every kernel ends normally) and
+    the readout reports EDEVICE; a streaming context rejects the hook."""
+    N = 512
+    E = inst.regular_graph(N, 6, 9101)
+    csr = inst.edges_to_csr(N, E, inst.gaussian_edges(len(E), 9102))
+    ctx = _ctx(sb, csr=csr, R=8, runs=2, steps=40, loop_kernel=sb.LOOP_RESIDENT)
+    _log("resident wait timeout injected: N=%d" % N)
+    sb.sbqa_step(ctx, 5)
+    sb.sbqa_best(ctx)                     # a healthy readout first
+    sb.sbqa_inject_wait_timeout(ctx)
+    sb.sbqa_step(ctx, 5)
+    with pytest.raises(sb.SbqaError) as ei:
+        sb.sbqa_best(ctx)
+    assert ei.value.status == sb.EDEVICE and "timed out" in ei.value.message
+    with pytest.raises(sb.SbqaError) as ei:
+        sb.sbqa_sync(ctx)
+    assert ei.value.status == sb.EDEVICE
+    sb.sbqa_destroy(ctx)
+    stream = _ctx(sb, csr=csr, R=8, runs=2, steps=40, loop_kernel=sb.LOOP_STREAM)
+    with pytest.raises(sb.SbqaError) as ei:
+        sb.sbqa_inject_wait_timeout(stream)
+    assert ei.value.status == sb.EINVAL
+
+
 def test_package_imported_before_torch_keeps_one_runtime(sb):
     """Imported before PyTorch, the binding still leaves one HIP runtime in
     the process (PyTorch's): in a fresh process that imports the package
