@@ -20,7 +20,8 @@ constexpr int SM_THREADS = 512;   // two waves per SIMD
 // count over N <= SMALL_MAX_N and R * N <= SMALL_MAX_ELEMS is 10 (N = 104)
 constexpr int SM_EPT = 10;
 
-__host__ __device__ constexpr int small_row_stride(int N) { return (N + 3) / 4 * 4; }
+// operand row length in LDS: N rounded up to the kernel's 32, 64 or 128
+__host__ __device__ constexpr int small_rows(int N) { return N <= 32 ? 32 : N <= 64 ? 64 : 128; }
 
 __device__ __forceinline__ float f_small(int fmode, float x, float delta) {
     if (fmode == 2) return x;                       // bSB
@@ -30,13 +31,14 @@ __device__ __forceinline__ float f_small(int fmode, float x, float delta) {
 }
 
 #pragma clang fp contract(off)
-// NMAX: N rounded up to 32, 64 or 128 (J row registers); M: replicas per
-// thread, ceil(R / (SM_THREADS / N)) rounded up to 1, 2, 4 or SM_EPT; FULL:
-// N == NMAX (the coupling sum needs no bounds)
-template <int NMAX, int M, bool FULL>
+// NMAX: N rounded up to 32, 64 or 128 (J row registers, operand rows in LDS,
+// both zero past N, so the coupling sum runs over NMAX terms without bounds);
+// M: replicas per thread, ceil(R / (SM_THREADS / N)) rounded up to 1, 2, 4 or
+// SM_EPT
+template <int NMAX, int M>
 __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
     extern __shared__ __align__(16) float sm[];
-    const int N = a.N, R = a.R, NS = small_row_stride(N);
+    const int N = a.N, R = a.R, NS = NMAX;
     // two buffers, each [R][NS] positions of this run then [R][NS] operand
     // f(x) (zero past N): step n reads one and writes the other, so one
     // barrier per step orders both its reads and the next step's
@@ -44,7 +46,6 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
     const int run = blockIdx.x, tid = threadIdx.x;
     const int G = SM_THREADS / N, i = tid % N, g = tid / N;
     const bool active = g < G;
-    const int N4 = N & ~3;
     // row i of J, zero past N: the padding terms add +0 to sums that start
     // at +0 and so never hold -0
     float jr[NMAX];
@@ -90,24 +91,17 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
             const int k = g + m * G;
             if (!active || k >= R) continue;
             const float4 *frow = reinterpret_cast<const float4 *>(fs + k * NS);
-            // four interleaved partial sums over j = 4m + u below N4, the
-            // tail j = N4..N-1 into s0, then (s0 + s1) + (s2 + s3): a fixed
-            // order with four independent FMA chains
+            // four interleaved partial sums over j = 4m + u < NMAX, then
+            // (s0 + s1) + (s2 + s3): a fixed order with four independent FMA
+            // chains (the terms past N are +0 * +0 on sums that start at +0)
             float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
             for (int j = 0; j < NMAX; j += 4) {
-                if (FULL || j < N4) {
-                    const float4 f = frow[j / 4];
-                    s0 = fmaf(jr[j], f.x, s0);
-                    s1 = fmaf(jr[j + 1], f.y, s1);
-                    s2 = fmaf(jr[j + 2], f.z, s2);
-                    s3 = fmaf(jr[j + 3], f.w, s3);
-                } else if (j < N) {
-                    const float4 f = frow[j / 4];
-                    s0 = fmaf(jr[j], f.x, s0);
-                    if (j + 1 < N) s0 = fmaf(jr[j + 1], f.y, s0);
-                    if (j + 2 < N) s0 = fmaf(jr[j + 2], f.z, s0);
-                }
+                const float4 f = frow[j / 4];
+                s0 = fmaf(jr[j], f.x, s0);
+                s1 = fmaf(jr[j + 1], f.y, s1);
+                s2 = fmaf(jr[j + 2], f.z, s2);
+                s3 = fmaf(jr[j + 3], f.w, s3);
             }
             const float phi = (s0 + s1) + (s2 + s3);
             const int kl = (k == 0) ? R - 1 : k - 1, kr = (k == R - 1) ? 0 : k + 1;
@@ -145,7 +139,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
 
 }  // namespace
 
-size_t small_lds_bytes(int N, int R) { return sizeof(float) * 4 * (size_t)R * small_row_stride(N); }
+size_t small_lds_bytes(int N, int R) { return sizeof(float) * 4 * (size_t)R * small_rows(N); }
 
 hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
     if (a.N < 1 || a.N > SMALL_MAX_N || a.R < 1 || a.R * a.N > SMALL_MAX_ELEMS || a.K < 1 || a.n0 < 0 ||
@@ -163,16 +157,10 @@ hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
     const int G = SM_THREADS / a.N, m = (a.R + G - 1) / G;
     auto by_m = [&](auto nmax) -> hipError_t {
         constexpr int NM = decltype(nmax)::value;
-        if (a.N == NM) {
-            if (m <= 1) return go(&k_dense_small<NM, 1, true>);
-            if (m <= 2) return go(&k_dense_small<NM, 2, true>);
-            if (m <= 4) return go(&k_dense_small<NM, 4, true>);
-            return go(&k_dense_small<NM, SM_EPT, true>);
-        }
-        if (m <= 1) return go(&k_dense_small<NM, 1, false>);
-        if (m <= 2) return go(&k_dense_small<NM, 2, false>);
-        if (m <= 4) return go(&k_dense_small<NM, 4, false>);
-        return go(&k_dense_small<NM, SM_EPT, false>);
+        if (m <= 1) return go(&k_dense_small<NM, 1>);
+        if (m <= 2) return go(&k_dense_small<NM, 2>);
+        if (m <= 4) return go(&k_dense_small<NM, 4>);
+        return go(&k_dense_small<NM, SM_EPT>);
     };
     if (a.N <= 32) return by_m(std::integral_constant<int, 32>{});
     if (a.N <= 64) return by_m(std::integral_constant<int, 64>{});
