@@ -173,10 +173,21 @@ def resident_ops_per_step(w):
     N for the small dense loop; the operand -1/0/+1 is read by the FMA in a
     format it takes directly, no conversion), 7 for the kick and drift, 3 for
     the wall, 3 for the ternary decision of Eq. 8: d + 13 (or N + 13). The
-    peak counts one lane operation per lane per cycle, an FMA being one."""
+    peak counts one lane operation per lane per cycle, an FMA being one. The
+    count is the algorithmic unit: the bit-mask small loop forms the N-term
+    sum with about a dozen bit operations and still counts N."""
     N, C = w["N"], w["R"] * w["runs"]
     nnz = len(w["csr"][1]) if "csr" in w else N * N
     return 1.0 * nnz * C + 13.0 * N * C
+
+
+def small_kernel_name(w):
+    """The small dense loop's kernel: the bit-mask form for J in {-1, 0, +1},
+    a ternary or sign operand and N = 32 or 64, else the float32 form."""
+    J = w.get("J")
+    bits = (J is not None and w["N"] in (32, 64) and w.get("fmode", 0) != 2
+            and bool(np.isin(J, (-1.0, 0.0, 1.0)).all()))
+    return "k_dense_small_bits" if bits else "k_dense_small"
 
 
 def dense_kernel_name(info):
@@ -539,7 +550,7 @@ def measure(sb, w, K, warmup, stream, loop_kernel="auto", events=True, workload=
             out["roofline"] = {"bound": "alu", "achieved": ops / avg_s / 1e12, "peak": PEAK_VALU_OPS,
                                "unit": "Tops/s (fp32 VALU lane ops)", "frac": ops / avg_s / 1e12 / PEAK_VALU_OPS,
                                "traffic": None if tr is None else tr * K,
-                               "kernel": "k_csr_resident" if sparse else "k_dense_small",
+                               "kernel": "k_csr_resident" if sparse else small_kernel_name(w),
                                "avg_launch_us": avg_s * 1e6, "steps_per_launch": K,
                                "algorithmic_ops_per_launch": ops}
         elif info["path"] == "csr_fp32":

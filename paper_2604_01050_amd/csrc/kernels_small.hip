@@ -31,6 +31,23 @@ __device__ __forceinline__ float f_small(int fmode, float x, float delta) {
 }
 
 #pragma clang fp contract(off)
+// Eqs. 6-7 for one replica-spin element: the kick with the coupling sum phi,
+// the fields, the ring neighbours' positions xl, xr and the pumping term,
+// then the drift and the wall of Eq. 3; returns the new position, y updated
+// in place
+__device__ __forceinline__ float small_update(float x, float xl, float xr, float phi, float h, float &y, float kA,
+                                              float jpr, const SmallArgs &a) {
+    const float force = (-kA * x + a.kB * (phi + h)) + jpr * (xl + xr);
+    float yn = y + a.dt * force;
+    float xv = x + a.kD * yn;
+    if (fabsf(xv) > 1.0f) {
+        xv = xv > 0.0f ? 1.0f : -1.0f;
+        yn = 0.0f;
+    }
+    y = yn;
+    return xv;
+}
+
 // NMAX: N rounded up to 32, 64 or 128 (J row registers, operand rows in LDS,
 // both zero past N, so the coupling sum runs over NMAX terms without bounds);
 // M: replicas per thread, ceil(R / (SM_THREADS / N)) rounded up to 1, 2, 4 or
@@ -105,16 +122,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
             }
             const float phi = (s0 + s1) + (s2 + s3);
             const int kl = (k == 0) ? R - 1 : k - 1, kr = (k == R - 1) ? 0 : k + 1;
-            const float x = xs[k * NS + i], xl = xs[kl * NS + i], xr = xs[kr * NS + i];
-            const float force = (-kA * x + a.kB * (phi + hv[m])) + jpr * (xl + xr);
-            float yn = yv[m] + a.dt * force;
-            float xv = x + a.kD * yn;
-            if (fabsf(xv) > 1.0f) {
-                xv = xv > 0.0f ? 1.0f : -1.0f;
-                yn = 0.0f;
-            }
-            yv[m] = yn;
-            xn[m] = xv;
+            xn[m] = small_update(xs[k * NS + i], xs[kl * NS + i], xs[kr * NS + i], phi, hv[m], yv[m], kA, jpr, a);
         }
 #pragma unroll
         for (int m = 0; m < M; ++m) {
@@ -130,6 +138,103 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
     for (int m = 0; m < M; ++m) {
         const int k = g + m * G;
         if (!active || k >= R) continue;
+        const int64_t o = (int64_t)(run * R + k) * a.Np + i;
+        a.x[o] = xs[k * NS + i];
+        a.y[o] = yv[m];
+    }
+}
+// The same loop for J in {-1, 0, +1} with a ternary or sign operand and
+// N = NMAX = 32 or 64, so that the N spins of one replica sit in one wave
+// (NMAX = 64) or one half-wave (NMAX = 32), lane order = spin order. Each
+// lane keeps row i of J as two bit masks (nonzero, negative) and the
+// operand of its replica as two masks of the same form, taken with a wave
+// ballot right after the update (the wave holds the whole replica, so the
+// operand never goes through LDS). The coupling sum is then an exact
+// integer count: the terms with both factors nonzero, minus twice those whose
+// product is negative,
+//   phi_i = popc(nzJ_i & nzF) - 2 popc(nzJ_i & nzF & (negJ_i ^ negF)),
+// the value the float32 sum of the other kernel reaches exactly (|phi| <= N),
+// so both kernels give the same bits. Positions of the ring neighbours (other
+// waves) still go through LDS, double-buffered, one barrier per step.
+template <int NMAX, int M>
+__global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs a) {
+    static_assert(NMAX == 32 || NMAX == 64, "a replica's spins in one wave or half-wave");
+    extern __shared__ __align__(16) float sm[];
+    const int R = a.R, NS = NMAX;
+    float *const buf0 = sm, *const buf1 = sm + R * NS;   // [R][NS] positions each
+    const int run = blockIdx.x, tid = threadIdx.x;
+    constexpr int G = SM_THREADS / NMAX;
+    const int i = tid % NMAX, g = tid / NMAX;
+    // the mask bits of this lane's replica: lanes [32 * hw, 32 * hw + 32) of
+    // the wave's ballot for NMAX = 32, all 64 for NMAX = 64
+    const int hw = NMAX == 32 ? (tid & 63) >> 5 : 0;
+    auto own = [&](uint64_t b) -> uint64_t { return NMAX == 32 ? (b >> (32 * hw)) & 0xFFFFFFFFull : b; };
+    uint64_t jnz = 0, jneg = 0;
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j) {
+        const float v = a.J[(int64_t)i * NMAX + j];
+        jnz |= (uint64_t)(v != 0.0f) << j;
+        jneg |= (uint64_t)(v < 0.0f) << j;
+    }
+    // this thread's replicas k = g + m * G (the same k across a wave or
+    // half-wave, so every ballot below covers whole replicas)
+    float yv[M], hv[M];
+    uint64_t fnz[M], fneg[M];
+    const float d0 = a.fmode == 1 ? 0.0f : a.delta[a.n0];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = g + m * G;
+        const bool valid = k < R;
+        float x = 0.0f;
+        if (valid) {
+            const int64_t o = (int64_t)(run * R + k) * a.Np + i;
+            x = a.x[o];
+            buf0[k * NS + i] = x;
+            yv[m] = a.y[o];
+            hv[m] = a.h[i];
+        }
+        fnz[m] = own(__ballot(valid && !(fabsf(x) <= d0)));
+        fneg[m] = own(__ballot(valid && !(fabsf(x) <= d0) && !(x > 0.0f)));
+    }
+    __syncthreads();
+
+    float kA_next = a.coefA[a.n0], dnext_next = a.delta[a.n0 + 1], jpr_next = a.jp[(int64_t)run * a.S + a.n0];
+    for (int n = a.n0; n < a.n0 + a.K; ++n) {
+        const float kA = kA_next, dnext = dnext_next, jpr = jpr_next;
+        if (n + 1 < a.n0 + a.K) {
+            kA_next = a.coefA[n + 1];
+            dnext_next = a.delta[n + 2];
+            jpr_next = a.jp[(int64_t)run * a.S + n + 1];
+        }
+        const float d = a.fmode == 1 ? 0.0f : dnext;
+        const bool odd = (n - a.n0) & 1;
+        const float *xs = odd ? buf1 : buf0;
+        float *xo = odd ? buf0 : buf1;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int k = g + m * G;
+            const bool valid = k < R;
+            float xv = 0.0f;
+            if (valid) {
+                const uint64_t both = jnz & fnz[m], minus = both & (jneg ^ fneg[m]);
+                // (the counts are unsigned: the difference is formed as int)
+                const float phi = (float)((int)__popcll(both) - 2 * (int)__popcll(minus));
+                const int kl = (k == 0) ? R - 1 : k - 1, kr = (k == R - 1) ? 0 : k + 1;
+                xv = small_update(xs[k * NS + i], xs[kl * NS + i], xs[kr * NS + i], phi, hv[m], yv[m], kA, jpr, a);
+                xo[k * NS + i] = xv;
+            }
+            // f of Eq. 8 at the next step's Delta (d = 0 for sign), with the
+            // comparisons of f_small
+            fnz[m] = own(__ballot(valid && !(fabsf(xv) <= d)));
+            fneg[m] = own(__ballot(valid && !(fabsf(xv) <= d) && !(xv > 0.0f)));
+        }
+        __syncthreads();   // step n + 1 reads what step n wrote; step n's reads are done
+    }
+    const float *xs = (a.K & 1) ? buf1 : buf0;   // the buffer the last step wrote
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        const int k = g + m * G;
+        if (k >= R) continue;
         const int64_t o = (int64_t)(run * R + k) * a.Np + i;
         a.x[o] = xs[k * NS + i];
         a.y[o] = yv[m];
@@ -155,6 +260,19 @@ hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
         return hipGetLastError();
     };
     const int G = SM_THREADS / a.N, m = (a.R + G - 1) / G;
+    if (a.jbits && a.fmode != 2 && (a.N == 32 || a.N == 64)) {
+        // every replica of the run has a thread group: m <= 8 (R * N <= 4096)
+        auto by_mb = [&](auto nmax) -> hipError_t {
+            constexpr int NM = decltype(nmax)::value;
+            if (m <= 1) return go(&k_dense_small_bits<NM, 1>);
+            if (m <= 2) return go(&k_dense_small_bits<NM, 2>);
+            if (m <= 4) return go(&k_dense_small_bits<NM, 4>);
+            if (m <= 8) return go(&k_dense_small_bits<NM, 8>);
+            return hipErrorInvalidValue;
+        };
+        if (a.N == 32) return by_mb(std::integral_constant<int, 32>{});
+        return by_mb(std::integral_constant<int, 64>{});
+    }
     auto by_m = [&](auto nmax) -> hipError_t {
         constexpr int NM = decltype(nmax)::value;
         if (m <= 1) return go(&k_dense_small<NM, 1>);

@@ -1185,6 +1185,7 @@ static sbqa_status ctx_step_small(sbqa_ctx *c, uint32_t K) {
     a.n0 = (int)c->step;
     a.K = (int)K;
     a.fmode = c->s.fmode;
+    a.jbits = c->facts.ternary ? 1 : 0;
     a.J = c->Jsm;
     a.h = c->h32;
     a.x = c->x[c->cur];

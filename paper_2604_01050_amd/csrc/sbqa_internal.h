@@ -235,6 +235,7 @@ constexpr int SMALL_MAX_N = 128;
 constexpr int SMALL_MAX_ELEMS = 4096;   // R * N
 struct SmallArgs {
     int N, Np, R, S, n0, K, fmode;
+    int jbits;            // every J entry is -1, 0 or +1: the bit-mask coupling sum may be used
     const float *J;       // [N][N]
     const float *h;       // [Np]
     float *x, *y;         // [C][Np]

@@ -977,6 +977,11 @@ SMALL_CASES = [
     ("sk100_sign_tracking", 100, 5, 3, 1, 7),
     ("sk128_max_elems", 128, 32, 2, 0, 13),
     ("sk1_degenerate", 1, 3, 2, 0, 0),
+    # N = 32 or 64 with J in {-1, 0, +1}: the bit-mask coupling sum
+    ("bits32_partial_halfwaves", 32, 40, 2, 1, 9),
+    ("bits32_max_elems", 32, 128, 1, 0, 0),
+    ("bits64_max_elems_zeros", 64, 64, 2, 0, 11),
+    ("bits64_ring_of_one", 64, 1, 3, 1, 0),
 ]
 
 
@@ -989,6 +994,9 @@ def test_small_dense_loop_matches_streaming(sb, orc, name, N, R, runs, fmode, ee
     first step also matches the oracle."""
     S = 60
     J = inst.sk_pm1(N, 5201) if N > 1 else np.zeros((1, 1))
+    if name.endswith("_zeros"):     # ternary J: about half of the couplings 0
+        keep = np.triu(np.random.default_rng(5205).random((N, N)) < 0.5, 1)
+        J = J * (keep | keep.T)
     h = np.round(inst.gaussian_fields(N, 1.0, 5202))
     _log("small dense loop vs streaming %s N=%d R=%d runs=%d ee=%d" % (name, N, R, runs, ee))
     X0, Y0 = inst.uniform_state(N, R * runs, 0.2, 5203)
