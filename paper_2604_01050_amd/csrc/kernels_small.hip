@@ -144,8 +144,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
     }
 }
 // The same loop for J in {-1, 0, +1} with a ternary or sign operand and
-// N = NMAX = 32 or 64, so that the N spins of one replica sit in one wave
-// (NMAX = 64) or one half-wave (NMAX = 32), lane order = spin order. Each
+// N <= 64, laid out by NMAX = N rounded up to 32 or 64 (lane i % NMAX holds
+// spin i; lanes past N idle), so that the spins of one replica sit in one
+// wave (NMAX = 64) or one half-wave (NMAX = 32), lane order = spin order. Each
 // lane keeps row i of J as two bit masks (nonzero, negative) and the
 // operand of its replica as two masks of the same form, taken with a wave
 // ballot right after the update (the wave holds the whole replica, so the
@@ -156,7 +157,8 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
 // the value the float32 sum of the other kernel reaches exactly (|phi| <= N),
 // so both kernels give the same bits. Positions of the ring neighbours (other
 // waves) still go through LDS, double-buffered, one barrier per step.
-template <int NMAX, int M>
+// (FULL: N = NMAX, every lane holds a spin)
+template <int NMAX, int M, bool FULL>
 __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs a) {
     static_assert(NMAX == 32 || NMAX == 64, "a replica's spins in one wave or half-wave");
     extern __shared__ __align__(16) float sm[];
@@ -164,15 +166,16 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
     float *const buf0 = sm, *const buf1 = sm + R * NS;   // [R][NS] positions each
     const int run = blockIdx.x, tid = threadIdx.x;
     constexpr int G = SM_THREADS / NMAX;
-    const int i = tid % NMAX, g = tid / NMAX;
+    const int N = a.N, i = tid % NMAX, g = tid / NMAX;
+    const bool row = FULL || i < N;
     // the mask bits of this lane's replica: lanes [32 * hw, 32 * hw + 32) of
     // the wave's ballot for NMAX = 32, all 64 for NMAX = 64
     const int hw = NMAX == 32 ? (tid & 63) >> 5 : 0;
     auto own = [&](uint64_t b) -> uint64_t { return NMAX == 32 ? (b >> (32 * hw)) & 0xFFFFFFFFull : b; };
-    uint64_t jnz = 0, jneg = 0;
+    uint64_t jnz = 0, jneg = 0;   // zero past N and for idle lanes
 #pragma unroll
     for (int j = 0; j < NMAX; ++j) {
-        const float v = a.J[(int64_t)i * NMAX + j];
+        const float v = (row && j < N) ? a.J[(int64_t)i * N + j] : 0.0f;
         jnz |= (uint64_t)(v != 0.0f) << j;
         jneg |= (uint64_t)(v < 0.0f) << j;
     }
@@ -184,7 +187,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int k = g + m * G;
-        const bool valid = k < R;
+        const bool valid = row && k < R;
         float x = 0.0f;
         if (valid) {
             const int64_t o = (int64_t)(run * R + k) * a.Np + i;
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
 #pragma unroll
         for (int m = 0; m < M; ++m) {
             const int k = g + m * G;
-            const bool valid = k < R;
+            const bool valid = row && k < R;
             float xv = 0.0f;
             if (valid) {
                 const uint64_t both = jnz & fnz[m], minus = both & (jneg ^ fneg[m]);
@@ -234,7 +237,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int k = g + m * G;
-        if (k >= R) continue;
+        if (!row || k >= R) continue;
         const int64_t o = (int64_t)(run * R + k) * a.Np + i;
         a.x[o] = xs[k * NS + i];
         a.y[o] = yv[m];
@@ -260,18 +263,24 @@ hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
         return hipGetLastError();
     };
     const int G = SM_THREADS / a.N, m = (a.R + G - 1) / G;
-    if (a.jbits && a.fmode != 2 && (a.N == 32 || a.N == 64)) {
-        // every replica of the run has a thread group: m <= 8 (R * N <= 4096)
-        auto by_mb = [&](auto nmax) -> hipError_t {
+    // the bit-mask loop: groups of NMAX = 32 or 64 lanes per replica, at most
+    // 8 replicas per thread (larger R with small N keeps the float32 loop)
+    const int nb = a.N <= 32 ? 32 : 64, Gb = SM_THREADS / nb, mb = (a.R + Gb - 1) / Gb;
+    if (a.jbits && a.fmode != 2 && a.N <= 64 && mb <= 8) {
+        auto by_mb = [&](auto nmax, auto full) -> hipError_t {
             constexpr int NM = decltype(nmax)::value;
-            if (m <= 1) return go(&k_dense_small_bits<NM, 1>);
-            if (m <= 2) return go(&k_dense_small_bits<NM, 2>);
-            if (m <= 4) return go(&k_dense_small_bits<NM, 4>);
-            if (m <= 8) return go(&k_dense_small_bits<NM, 8>);
-            return hipErrorInvalidValue;
+            constexpr bool F = decltype(full)::value;
+            if (mb <= 1) return go(&k_dense_small_bits<NM, 1, F>);
+            if (mb <= 2) return go(&k_dense_small_bits<NM, 2, F>);
+            if (mb <= 4) return go(&k_dense_small_bits<NM, 4, F>);
+            return go(&k_dense_small_bits<NM, 8, F>);
         };
-        if (a.N == 32) return by_mb(std::integral_constant<int, 32>{});
-        return by_mb(std::integral_constant<int, 64>{});
+        auto by_full = [&](auto nmax) -> hipError_t {
+            if (a.N == decltype(nmax)::value) return by_mb(nmax, std::true_type{});
+            return by_mb(nmax, std::false_type{});
+        };
+        if (nb == 32) return by_full(std::integral_constant<int, 32>{});
+        return by_full(std::integral_constant<int, 64>{});
     }
     auto by_m = [&](auto nmax) -> hipError_t {
         constexpr int NM = decltype(nmax)::value;
