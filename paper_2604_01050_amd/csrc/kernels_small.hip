@@ -6,7 +6,9 @@
 // steps of Eqs. 6-7 per launch, so a small all-to-all instance costs one
 // launch per K steps instead of one per step. Fields are summed in a fixed
 // order over j (four interleaved partial sums), so integer couplings with a
-// ternary or sign operand give exactly the fields of the MFMA path.
+// ternary or sign operand give exactly the fields of the MFMA path. For J in
+// {-1, 0, +1} with such an operand a second form (k_dense_small_bits, below)
+// replaces the FMAs by bit counts over masks of J and of the operand.
 #include "sbqa_internal.h"
 
 #include <type_traits>
@@ -143,46 +145,67 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small(const SmallArgs a) {
         a.y[o] = yv[m];
     }
 }
-// The same loop for J in {-1, 0, +1} with a ternary or sign operand and
-// N <= 64, laid out by NMAX = N rounded up to 32 or 64 (lane i % NMAX holds
-// spin i; lanes past N idle), so that the spins of one replica sit in one
-// wave (NMAX = 64) or one half-wave (NMAX = 32), lane order = spin order. Each
-// lane keeps row i of J as two bit masks (nonzero, negative) and the
-// operand of its replica as two masks of the same form, taken with a wave
-// ballot right after the update (the wave holds the whole replica, so the
-// operand never goes through LDS). The coupling sum is then an exact
-// integer count: the terms with both factors nonzero, minus twice those whose
-// product is negative,
+// The same loop for J in {-1, 0, +1} with a ternary or sign operand, laid
+// out by NMAX = N rounded up to 32, 64 or 128 (lane i % NMAX holds spin i;
+// lanes past N idle), so that the spins of one replica sit in one half-wave
+// (NMAX = 32), one wave (64) or two waves (128), lane order = spin order.
+// Each lane keeps row i of J as bit masks (nonzero, negative) and the
+// operand of its replica as masks of the same form, taken with wave ballots
+// right after the update: a wave's own 64 (or 32) spins stay in registers,
+// and with two waves per replica each wave passes its half to the other
+// through LDS, double-buffered with the positions. The coupling sum is then
+// an exact integer count: the terms with both factors nonzero, minus twice
+// those whose product is negative,
 //   phi_i = popc(nzJ_i & nzF) - 2 popc(nzJ_i & nzF & (negJ_i ^ negF)),
 // the value the float32 sum of the other kernel reaches exactly (|phi| <= N),
 // so both kernels give the same bits. Positions of the ring neighbours (other
-// waves) still go through LDS, double-buffered, one barrier per step.
+// waves) go through LDS too, one barrier per step.
 // (FULL: N = NMAX, every lane holds a spin)
 template <int NMAX, int M, bool FULL>
 __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs a) {
-    static_assert(NMAX == 32 || NMAX == 64, "a replica's spins in one wave or half-wave");
+    static_assert(NMAX == 32 || NMAX == 64 || NMAX == 128, "a replica's spins in a half-wave, a wave or two");
+    constexpr bool TWO = NMAX == 128;               // two waves per replica
+    constexpr int JW = NMAX < 64 ? NMAX : 64;       // spins per mask word
     extern __shared__ __align__(16) float sm[];
     const int R = a.R, NS = NMAX;
     float *const buf0 = sm, *const buf1 = sm + R * NS;   // [R][NS] positions each
-    const int run = blockIdx.x, tid = threadIdx.x;
+    // two waves per replica: [parity][R][half][nonzero, negative] masks
+    uint64_t *const mk = reinterpret_cast<uint64_t *>(sm + 2 * R * NS);
+    const int run = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
     constexpr int G = SM_THREADS / NMAX;
     const int N = a.N, i = tid % NMAX, g = tid / NMAX;
     const bool row = FULL || i < N;
-    // the mask bits of this lane's replica: lanes [32 * hw, 32 * hw + 32) of
-    // the wave's ballot for NMAX = 32, all 64 for NMAX = 64
-    const int hw = NMAX == 32 ? (tid & 63) >> 5 : 0;
+    // this lane's bits in its wave's ballot: lanes [32 hw, 32 hw + 32) for
+    // NMAX = 32, all 64 otherwise; hh: the half of the replica this wave holds
+    const int hw = NMAX == 32 ? lane >> 5 : 0;
+    const int hh = TWO ? (tid >> 6) & 1 : 0;
     auto own = [&](uint64_t b) -> uint64_t { return NMAX == 32 ? (b >> (32 * hw)) & 0xFFFFFFFFull : b; };
-    uint64_t jnz = 0, jneg = 0;   // zero past N and for idle lanes
+    // row i of J over the wave's own spins (mine) and the other wave's
+    // (oth, two waves per replica only); zero past N and for idle lanes
+    uint64_t jnz = 0, jneg = 0, onz = 0, oneg = 0;
 #pragma unroll
-    for (int j = 0; j < NMAX; ++j) {
-        const float v = (row && j < N) ? a.J[(int64_t)i * N + j] : 0.0f;
+    for (int j = 0; j < JW; ++j) {
+        const int cm = hh * 64 + j, co = (1 - hh) * 64 + j;
+        const float v = (row && cm < N) ? a.J[(int64_t)i * N + cm] : 0.0f;
         jnz |= (uint64_t)(v != 0.0f) << j;
         jneg |= (uint64_t)(v < 0.0f) << j;
+        if constexpr (TWO) {
+            const float u = (row && co < N) ? a.J[(int64_t)i * N + co] : 0.0f;
+            onz |= (uint64_t)(u != 0.0f) << j;
+            oneg |= (uint64_t)(u < 0.0f) << j;
+        }
     }
     // this thread's replicas k = g + m * G (the same k across a wave or
-    // half-wave, so every ballot below covers whole replicas)
+    // half-wave, so every ballot below covers whole replicas or halves)
     float yv[M], hv[M];
     uint64_t fnz[M], fneg[M];
+    // the wave's operand masks of replica k for the readers of parity b
+    auto pass = [&](int b, int k, uint64_t nz, uint64_t ng) {
+        if (TWO && lane == 0 && k < R) {
+            mk[((b * R + k) * 2 + hh) * 2] = nz;
+            mk[((b * R + k) * 2 + hh) * 2 + 1] = ng;
+        }
+    };
     const float d0 = a.fmode == 1 ? 0.0f : a.delta[a.n0];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -198,6 +221,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
         }
         fnz[m] = own(__ballot(valid && !(fabsf(x) <= d0)));
         fneg[m] = own(__ballot(valid && !(fabsf(x) <= d0) && !(x > 0.0f)));
+        pass(0, k, fnz[m], fneg[m]);
     }
     __syncthreads();
 
@@ -210,7 +234,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
             jpr_next = a.jp[(int64_t)run * a.S + n + 1];
         }
         const float d = a.fmode == 1 ? 0.0f : dnext;
-        const bool odd = (n - a.n0) & 1;
+        const int odd = (n - a.n0) & 1;
         const float *xs = odd ? buf1 : buf0;
         float *xo = odd ? buf0 : buf1;
 #pragma unroll
@@ -221,7 +245,13 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
             if (valid) {
                 const uint64_t both = jnz & fnz[m], minus = both & (jneg ^ fneg[m]);
                 // (the counts are unsigned: the difference is formed as int)
-                const float phi = (float)((int)__popcll(both) - 2 * (int)__popcll(minus));
+                int cnt = (int)__popcll(both) - 2 * (int)__popcll(minus);
+                if constexpr (TWO) {
+                    const uint64_t *om = mk + ((odd * R + k) * 2 + 1 - hh) * 2;
+                    const uint64_t b2 = onz & om[0], m2 = b2 & (oneg ^ om[1]);
+                    cnt += (int)__popcll(b2) - 2 * (int)__popcll(m2);
+                }
+                const float phi = (float)cnt;
                 const int kl = (k == 0) ? R - 1 : k - 1, kr = (k == R - 1) ? 0 : k + 1;
                 xv = small_update(xs[k * NS + i], xs[kl * NS + i], xs[kr * NS + i], phi, hv[m], yv[m], kA, jpr, a);
                 xo[k * NS + i] = xv;
@@ -230,6 +260,7 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
             // comparisons of f_small
             fnz[m] = own(__ballot(valid && !(fabsf(xv) <= d)));
             fneg[m] = own(__ballot(valid && !(fabsf(xv) <= d) && !(xv > 0.0f)));
+            pass(1 - odd, k, fnz[m], fneg[m]);
         }
         __syncthreads();   // step n + 1 reads what step n wrote; step n's reads are done
     }
@@ -263,10 +294,10 @@ hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
         return hipGetLastError();
     };
     const int G = SM_THREADS / a.N, m = (a.R + G - 1) / G;
-    // the bit-mask loop: groups of NMAX = 32 or 64 lanes per replica, at most
-    // 8 replicas per thread (larger R with small N keeps the float32 loop)
-    const int nb = a.N <= 32 ? 32 : 64, Gb = SM_THREADS / nb, mb = (a.R + Gb - 1) / Gb;
-    if (a.jbits && a.fmode != 2 && a.N <= 64 && mb <= 8) {
+    // the bit-mask loop: groups of NMAX = 32, 64 or 128 lanes per replica, at
+    // most 8 replicas per thread (a larger R keeps the float32 loop)
+    const int nb = small_rows(a.N), Gb = SM_THREADS / nb, mb = (a.R + Gb - 1) / Gb;
+    if (a.jbits && a.fmode != 2 && mb <= 8) {
         auto by_mb = [&](auto nmax, auto full) -> hipError_t {
             constexpr int NM = decltype(nmax)::value;
             constexpr bool F = decltype(full)::value;
@@ -280,7 +311,8 @@ hipError_t launch_dense_small(const SmallArgs &a, int runs, hipStream_t st) {
             return by_mb(nmax, std::false_type{});
         };
         if (nb == 32) return by_full(std::integral_constant<int, 32>{});
-        return by_full(std::integral_constant<int, 64>{});
+        if (nb == 64) return by_full(std::integral_constant<int, 64>{});
+        return by_full(std::integral_constant<int, 128>{});
     }
     auto by_m = [&](auto nmax) -> hipError_t {
         constexpr int NM = decltype(nmax)::value;

@@ -977,14 +977,17 @@ SMALL_CASES = [
     ("sk100_sign_tracking", 100, 5, 3, 1, 7),
     ("sk128_max_elems", 128, 32, 2, 0, 13),
     ("sk1_degenerate", 1, 3, 2, 0, 0),
-    # N <= 64 with J in {-1, 0, +1}: the bit-mask coupling sum (the cases
-    # above with N = 1 and 64 take it too; N = 100 and 128 do not)
+    # J in {-1, 0, +1}: the bit-mask coupling sum (the cases above take it
+    # too: N = 100 and 128 with two waves per replica), except with more than
+    # 8 replicas per thread (the last case: the float32 loop)
     ("bits32_partial_halfwaves", 32, 40, 2, 1, 9),
     ("bits20_padded_rows", 20, 100, 2, 0, 7),
     ("bits50_padded_rows_zeros", 50, 20, 3, 1, 0),
     ("bits32_max_elems", 32, 128, 1, 0, 0),
     ("bits64_max_elems_zeros", 64, 64, 2, 0, 11),
     ("bits64_ring_of_one", 64, 1, 3, 1, 0),
+    ("bits90_two_waves_zeros", 90, 12, 2, 0, 6),
+    ("fma20_many_replicas", 20, 200, 1, 0, 5),
 ]
 
 
