@@ -99,10 +99,13 @@ typedef enum { SBQA_JP_LINEAR = 0, SBQA_JP_PAPER = 1, SBQA_JP_TABLE = 2 } sbqa_j
  *             - sparse (CSR): the register-resident loop (ternary or sign f,
  *               R a multiple of 8, N <= 4096, small degree, all column blocks
  *               co-resident on the GPU); it computes the same bits as STREAM;
- *             - dense: the small-instance loop (N <= 128, R*N <= 4096, FP32 or
- *               FP8 precision), one workgroup per run with J and the run's
- *               state in LDS; fields are summed in a fixed order over j (the
- *               same bits as STREAM when J and the operand are integral).
+ *             - dense: the small-instance loop (N <= 128, R*N <= 4096, any
+ *               precision but BF16X3: it computes in float32), one workgroup
+ *               per run with the rows of J in registers and the run's
+ *               positions in LDS; fields are summed in a fixed order over j,
+ *               or counted over bit masks of J and f(x) when J is in
+ *               {-1,0,+1} and f is ternary or sign (the same bits as STREAM
+ *               when J and the operand are integral).
  *             sbqa_create fails with EINVAL when the instance does not fit. */
 typedef enum { SBQA_LOOP_AUTO = 0, SBQA_LOOP_STREAM = 1, SBQA_LOOP_RESIDENT = 2 } sbqa_loop_kernel;
 

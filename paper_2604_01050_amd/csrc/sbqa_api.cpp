@@ -942,7 +942,7 @@ static bool resident_plan(sbqa_ctx *c, const sbqa_coupling *J, std::string *why)
 
 // Whether the small dense resident loop fits this instance.
 static bool small_plan(sbqa_ctx *c, std::string *why) {
-    if (c->facts.path == PATH_BF16X3) { *why = "the small dense loop computes in float32 (FP32, FP8 or INT8 precision only)"; return false; }
+    if (c->facts.path == PATH_BF16X3) { *why = "the small dense loop computes in float32 (every precision but BF16X3)"; return false; }
     if (c->N > SMALL_MAX_N) { *why = "N is above the small dense loop's limit"; return false; }
     if ((int64_t)c->R * c->N > SMALL_MAX_ELEMS) { *why = "R*N is above the small dense loop's limit"; return false; }
     if (small_lds_bytes(c->N, c->R) > 160 * 1024) { *why = "the run state does not fit in LDS"; return false; }
