@@ -182,10 +182,14 @@ def resident_ops_per_step(w):
 
 
 def small_kernel_name(w):
-    """The small dense loop's kernel: the bit-mask form for J in {-1, 0, +1},
-    a ternary or sign operand and N = 32 or 64, else the float32 form."""
-    J = w.get("J")
-    bits = (J is not None and w["N"] in (32, 64) and w.get("fmode", 0) != 2
+    """The small dense loop's kernel (the library's launch rule): the
+    bit-mask form for J in {-1, 0, +1} and a ternary or sign operand when the
+    replicas fill at most 8 groups of N rounded up to 32, 64 or 128 lanes per
+    thread, else the float32 form."""
+    J, N = w.get("J"), w["N"]
+    lanes = 32 if N <= 32 else 64 if N <= 64 else 128
+    per_thread = -(-w["R"] // (512 // lanes))
+    bits = (J is not None and w.get("fmode", 0) != 2 and per_thread <= 8
             and bool(np.isin(J, (-1.0, 0.0, 1.0)).all()))
     return "k_dense_small_bits" if bits else "k_dense_small"
 

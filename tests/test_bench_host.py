@@ -97,6 +97,24 @@ def test_dense_kernel_name():
     assert bench.dense_kernel_name(dict(bf, tile_cols=64)) == "k_dense_step"
 
 
+def test_small_kernel_name():
+    """The small dense loop counts bits for J in {-1, 0, +1} with a ternary or
+    sign operand and at most 8 replicas per thread; else it sums floats."""
+    import numpy as np
+    import bench
+    w = bench.make_workload("sk64")
+    assert bench.small_kernel_name(w) == "k_dense_small_bits"
+    assert bench.small_kernel_name(dict(w, fmode=2)) == "k_dense_small"         # ballistic operand
+    J2 = w["J"].copy()
+    J2[0, 1] = J2[1, 0] = 2.0
+    assert bench.small_kernel_name(dict(w, J=J2)) == "k_dense_small"            # |J| = 2
+    assert bench.small_kernel_name(dict(w, R=64)) == "k_dense_small_bits"       # 8 per thread
+    assert bench.small_kernel_name(dict(w, R=65)) == "k_dense_small"            # 9 per thread
+    w20 = dict(w, N=20, J=np.zeros((20, 20)))
+    assert bench.small_kernel_name(dict(w20, R=128)) == "k_dense_small_bits"    # 16 per 512 threads
+    assert bench.small_kernel_name(dict(w20, R=129)) == "k_dense_small"
+
+
 def test_dense_traffic_summaries_name_the_launched_kernel():
     """The committed counter summaries of the SK N = 16384 packed-J workloads
     and of the Gaussian N = 8192 bf16 hi+lo workload (taken at the 128-column
