@@ -180,8 +180,9 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
     const int hw = NMAX == 32 ? lane >> 5 : 0;
     const int hh = TWO ? (tid >> 6) & 1 : 0;
     auto own = [&](uint64_t b) -> uint64_t { return NMAX == 32 ? (b >> (32 * hw)) & 0xFFFFFFFFull : b; };
-    // row i of J over the wave's own spins (mine) and the other wave's
-    // (oth, two waves per replica only); zero past N and for idle lanes
+    // row i of J over the wave's own spins (jnz, jneg) and over the other
+    // wave's (onz, oneg: two waves per replica only); zero past N and for
+    // idle lanes
     uint64_t jnz = 0, jneg = 0, onz = 0, oneg = 0;
 #pragma unroll
     for (int j = 0; j < JW; ++j) {
