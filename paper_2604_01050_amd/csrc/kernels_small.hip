@@ -207,7 +207,11 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
             mk[((b * R + k) * 2 + hh) * 2 + 1] = ng;
         }
     };
-    const float d0 = a.fmode == 1 ? 0.0f : a.delta[a.n0];
+    // the lane's own positions stay in registers too (xc); with one wave or
+    // half-wave per replica the operand masks are taken at the start of each
+    // step, after the barrier, where they overlap the neighbours' LDS reads
+    float xc[M];
+    float dcur = a.fmode == 1 ? 0.0f : a.delta[a.n0];   // the operand's Delta
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int k = g + m * G;
@@ -220,9 +224,12 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
             yv[m] = a.y[o];
             hv[m] = a.h[i];
         }
-        fnz[m] = own(__ballot(valid && !(fabsf(x) <= d0)));
-        fneg[m] = own(__ballot(valid && !(fabsf(x) <= d0) && !(x > 0.0f)));
-        pass(0, k, fnz[m], fneg[m]);
+        xc[m] = x;
+        if constexpr (TWO) {
+            fnz[m] = __ballot(valid && !(fabsf(x) <= dcur));
+            fneg[m] = __ballot(valid && !(fabsf(x) <= dcur) && !(x > 0.0f));
+            pass(0, k, fnz[m], fneg[m]);
+        }
     }
     __syncthreads();
 
@@ -242,6 +249,11 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
         for (int m = 0; m < M; ++m) {
             const int k = g + m * G;
             const bool valid = row && k < R;
+            if constexpr (!TWO) {
+                // f of Eq. 8 (d = 0 for sign), with the comparisons of f_small
+                fnz[m] = own(__ballot(valid && !(fabsf(xc[m]) <= dcur)));
+                fneg[m] = own(__ballot(valid && !(fabsf(xc[m]) <= dcur) && !(xc[m] > 0.0f)));
+            }
             float xv = 0.0f;
             if (valid) {
                 const uint64_t both = jnz & fnz[m], minus = both & (jneg ^ fneg[m]);
@@ -254,24 +266,27 @@ __global__ __launch_bounds__(SM_THREADS) void k_dense_small_bits(const SmallArgs
                 }
                 const float phi = (float)cnt;
                 const int kl = (k == 0) ? R - 1 : k - 1, kr = (k == R - 1) ? 0 : k + 1;
-                xv = small_update(xs[k * NS + i], xs[kl * NS + i], xs[kr * NS + i], phi, hv[m], yv[m], kA, jpr, a);
+                xv = small_update(xc[m], xs[kl * NS + i], xs[kr * NS + i], phi, hv[m], yv[m], kA, jpr, a);
                 xo[k * NS + i] = xv;
             }
-            // f of Eq. 8 at the next step's Delta (d = 0 for sign), with the
-            // comparisons of f_small
-            fnz[m] = own(__ballot(valid && !(fabsf(xv) <= d)));
-            fneg[m] = own(__ballot(valid && !(fabsf(xv) <= d) && !(xv > 0.0f)));
-            pass(1 - odd, k, fnz[m], fneg[m]);
+            xc[m] = xv;
+            if constexpr (TWO) {
+                // the masks of the next step's operand (Delta d) for both
+                // waves of the replica, before the barrier
+                fnz[m] = __ballot(valid && !(fabsf(xv) <= d));
+                fneg[m] = __ballot(valid && !(fabsf(xv) <= d) && !(xv > 0.0f));
+                pass(1 - odd, k, fnz[m], fneg[m]);
+            }
         }
+        dcur = d;
         __syncthreads();   // step n + 1 reads what step n wrote; step n's reads are done
     }
-    const float *xs = (a.K & 1) ? buf1 : buf0;   // the buffer the last step wrote
 #pragma unroll
     for (int m = 0; m < M; ++m) {
         const int k = g + m * G;
         if (!row || k >= R) continue;
         const int64_t o = (int64_t)(run * R + k) * a.Np + i;
-        a.x[o] = xs[k * NS + i];
+        a.x[o] = xc[m];
         a.y[o] = yv[m];
     }
 }
