@@ -806,14 +806,18 @@ def test_serving_alone_equals_mix_stream_sizes(sb):
     """The serving configuration's shapes: R = 16 x 8 runs (C = 128), a dense
     SK +-1 instance of N = 8192 (bit-packed fp8, built from sign bits on the
     server), a sparse d-regular Gaussian instance of N = 8000, and smaller ones
-    of both kinds; served results equal the standalone runs bit for bit."""
+    of both kinds, one dense instance on the fp4 contraction (the stream's
+    --serve-dense fp4 form); served results equal the standalone runs bit for
+    bit."""
     rng = np.random.default_rng(71)
-    specs = [("dense", 8192), ("sparse", 8000), ("dense", 1536), ("sparse", 700), ("dense", 300)]
+    specs = [("dense", 8192), ("sparse", 8000), ("dense", 1536), ("sparse", 700), ("dense", 300),
+             ("dense_fp4", 4096)]
     items = []
     for q, (kind, N) in enumerate(specs):
         kw = dict(R=16, runs=8, steps=100, seed=740 + q, jp_kind=sb.JP_LINEAR, jp_start=0.5, jp_end=0.0)
-        if kind == "dense":
-            items.append((inst.sk_pm1(N, 750 + q), None, dict(kw, precision=sb.PREC_FP8)))
+        if kind.startswith("dense"):
+            prec = sb.PREC_FP4 if kind == "dense_fp4" else sb.PREC_FP8
+            items.append((inst.sk_pm1(N, 750 + q), None, dict(kw, precision=prec)))
         else:
             d = int(rng.integers(3, 13))
             E = inst.regular_graph(N, d, 760 + q)
