@@ -113,15 +113,39 @@ __global__ __launch_bounds__(NT) void k_csr_resident(ResidentArgs a) {
     const int run = c0 / a.R, part = (c0 - run * a.R) / RES_COLS;
     const int wl = run * P + (part + P - 1) % P, wr = run * P + (part + 1) % P;
 
+    // the prologue issues all of its global loads (weights, state, column
+    // indices of every row) before it waits for any of them: one memory
+    // round trip instead of one per row and kind
+    float wtmp[RPT][D];
+    int32_t ctmp[RPT][D];
+    float xs[RPT][RES_COLS], ys[RPT][RES_COLS];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        int r = t + q * NT;
-        asm volatile("" : "+v"(r));
+        const int r = t + q * NT;
 #pragma unroll
-        for (int p = 0; p < D; ++p) wv[(q * D + p) * NT + t] = a.valpad[(int64_t)p * NR + r];
+        for (int p = 0; p < D; ++p) wtmp[q][p] = a.valpad[(int64_t)p * NR + r];
     }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int r = t + q * NT;
+        const float *xrow = a.x + ((int64_t)w * NR + r) * RES_COLS;
+        const float *yrow = a.y + ((int64_t)w * NR + r) * RES_COLS;
+        const float4 x0 = *reinterpret_cast<const float4 *>(xrow);
+        const float4 x1 = *reinterpret_cast<const float4 *>(xrow + 4);
+        const float4 y0 = *reinterpret_cast<const float4 *>(yrow);
+        const float4 y1 = *reinterpret_cast<const float4 *>(yrow + 4);
+        xs[q][0] = x0.x; xs[q][1] = x0.y; xs[q][2] = x0.z; xs[q][3] = x0.w;
+        xs[q][4] = x1.x; xs[q][5] = x1.y; xs[q][6] = x1.z; xs[q][7] = x1.w;
+        ys[q][0] = y0.x; ys[q][1] = y0.y; ys[q][2] = y0.z; ys[q][3] = y0.w;
+        ys[q][4] = y1.x; ys[q][5] = y1.y; ys[q][6] = y1.z; ys[q][7] = y1.w;
+#pragma unroll
+        for (int p = 0; p < D; ++p) ctmp[q][p] = a.colpad[(int64_t)r * D + p];
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int p = 0; p < D; ++p) wv[(q * D + p) * NT + t] = wtmp[q][p];
 
-    float xs[RPT][RES_COLS], ys[RPT][RES_COLS];
     uint32_t cpk[RPT][(D + 1) / 2];
     // exchange buffer of parity b, block v, edge e (0: first column, 1: last),
     // indexed by row (consecutive lanes, consecutive addresses)
@@ -131,18 +155,7 @@ __global__ __launch_bounds__(NT) void k_csr_resident(ResidentArgs a) {
         const float d0 = a.delta[a.n0];   // the operand of step n0 is f(x) at Delta_n0
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-            int r = t + q * NT;
-            asm volatile("" : "+v"(r));
-            const float *xrow = a.x + ((int64_t)w * NR + r) * RES_COLS;
-            const float *yrow = a.y + ((int64_t)w * NR + r) * RES_COLS;
-            const float4 x0 = *reinterpret_cast<const float4 *>(xrow);
-            const float4 x1 = *reinterpret_cast<const float4 *>(xrow + 4);
-            const float4 y0 = *reinterpret_cast<const float4 *>(yrow);
-            const float4 y1 = *reinterpret_cast<const float4 *>(yrow + 4);
-            xs[q][0] = x0.x; xs[q][1] = x0.y; xs[q][2] = x0.z; xs[q][3] = x0.w;
-            xs[q][4] = x1.x; xs[q][5] = x1.y; xs[q][6] = x1.z; xs[q][7] = x1.w;
-            ys[q][0] = y0.x; ys[q][1] = y0.y; ys[q][2] = y0.z; ys[q][3] = y0.w;
-            ys[q][4] = y1.x; ys[q][5] = y1.y; ys[q][6] = y1.z; ys[q][7] = y1.w;
+            const int r = t + q * NT;
             half8 f0;
 #pragma unroll
             for (int c = 0; c < RES_COLS; ++c) f0[c] = (_Float16)f_value(a.fmode, xs[q][c], d0);
@@ -150,8 +163,8 @@ __global__ __launch_bounds__(NT) void k_csr_resident(ResidentArgs a) {
 #pragma unroll
             for (int p = 0; p < D; p += 2) {
                 // LDS byte offsets of the neighbours' operand rows (< 2^16)
-                const uint32_t j0 = (uint32_t)a.colpad[(int64_t)r * D + p] * (uint32_t)sizeof(half8);
-                const uint32_t j1 = (p + 1 < D) ? (uint32_t)a.colpad[(int64_t)r * D + p + 1] * (uint32_t)sizeof(half8) : 0u;
+                const uint32_t j0 = (uint32_t)ctmp[q][p] * (uint32_t)sizeof(half8);
+                const uint32_t j1 = (p + 1 < D) ? (uint32_t)ctmp[q][p + 1] * (uint32_t)sizeof(half8) : 0u;
                 cpk[q][p / 2] = j0 | (j1 << 16);
             }
             publish(pf + r, xs[q][0]);                   // edges of the starting state
