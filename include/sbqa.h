@@ -188,9 +188,14 @@ typedef struct {
     int32_t loop_kernel;     /* sbqa_loop_kernel                                   */
     int32_t dense_tile;      /* dense path: replica columns per workgroup tile,
                                 64, 128 or 256; 0 = autotuned (each candidate's
-                                step timed once per process on scratch buffers
-                                of the instance's shape; every tile gives the
-                                same bits)                                        */
+                                step timed on scratch buffers of the instance's
+                                shape once per device and shape; every tile
+                                gives the same bits). Choices persist across
+                                processes in a text file: the path in the
+                                environment variable SBQA_TUNE_CACHE ("off":
+                                none), else $XDG_CACHE_HOME/sbqa/dense_tiles.txt,
+                                else $HOME/.cache/sbqa/dense_tiles.txt; a file
+                                that cannot be read or written is ignored     */
     int32_t j_packing;       /* sbqa_j_packing (dense FP8 / FP4 only)              */
     int32_t reorder;         /* sbqa_reorder (CSR couplings only)                  */
 } sbqa_schedule;

@@ -9,11 +9,17 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <tuple>
 #include <string>
+
+#include <fcntl.h>
+#include <sys/stat.h>
+#include <unistd.h>
 #include <thread>
 #include <vector>
 
@@ -363,27 +369,102 @@ void set_tile(Layout *L, int mbw) {
 
 // ------------------------------------------------------------ tile autotuner
 // Dense workgroup tile: 64 * mbw replica columns (mbw m-blocks per wave).
-// Candidates that pad C by at most 2x are timed once per (path, C, Np rounded
-// up to a power of two) and process, on scratch buffers of the instance's
-// shape (the MFMA step's time does not depend on the values); the fastest is
-// kept. Every tile sums each field in the same K order, so the choice never
-// changes results.
+// Candidates that pad C by at most 2x are timed once per (device, path, C, Np
+// rounded up to a power of two), on scratch buffers of the instance's shape
+// (the MFMA step's time does not depend on the values); the fastest is kept.
+// Every tile sums each field in the same K order, so the choice never changes
+// results. Choices persist across processes in a tile file (below), so a new
+// process (a server restart) does not time them again.
+
+// The device a choice was timed on: architecture and compute-unit count.
+static std::string tile_device_tag() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return "";
+    static std::mutex mu;
+    static std::map<int, std::string> tags;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = tags.find(dev);
+    if (it != tags.end()) return it->second;
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "";
+    std::string arch(p.gcnArchName);
+    for (char &ch : arch)
+        if (ch == ' ') ch = '_';
+    return tags[dev] = arch + " " + std::to_string(p.multiProcessorCount);
+}
+
+// The tile file: SBQA_TUNE_CACHE names it ("" or "off": choices stay in the
+// process), else $XDG_CACHE_HOME/sbqa/dense_tiles.txt, else
+// $HOME/.cache/sbqa/dense_tiles.txt. One line per choice,
+//   sbqa-tile-v1 <arch> <CUs> <path> <C> <padded N> <mbw>
+// appended with one write; unreadable files and malformed lines are ignored
+// (a choice is used only when it is one of the key's candidates).
+static std::string tile_file(bool make_dir) {
+    const char *env = std::getenv("SBQA_TUNE_CACHE");
+    if (env) return (std::strcmp(env, "off") == 0) ? std::string() : std::string(env);
+    std::string dir;
+    if (const char *x = std::getenv("XDG_CACHE_HOME"); x && *x) dir = std::string(x) + "/sbqa";
+    else if (const char *h = std::getenv("HOME"); h && *h) dir = std::string(h) + "/.cache/sbqa";
+    else return std::string();
+    if (make_dir) {
+        const size_t cut = dir.rfind('/');
+        if (cut != std::string::npos && cut > 0) (void)::mkdir(dir.substr(0, cut).c_str(), 0755);
+        (void)::mkdir(dir.c_str(), 0755);
+    }
+    return dir + "/dense_tiles.txt";
+}
+
+static void load_tile_file(const std::string &dev, std::map<std::tuple<std::string, int, int, int>, int> *cache) {
+    const std::string f = tile_file(false);
+    if (f.empty()) return;
+    FILE *fp = std::fopen(f.c_str(), "r");
+    if (!fp) return;
+    char line[512];
+    while (std::fgets(line, sizeof line, fp)) {
+        char tag[32], arch[256];
+        int cus = 0, path = 0, C = 0, npb = 0, mbw = 0;
+        if (std::sscanf(line, "%31s %255s %d %d %d %d %d", tag, arch, &cus, &path, &C, &npb, &mbw) != 7) continue;
+        if (std::strcmp(tag, "sbqa-tile-v1") != 0 || std::string(arch) + " " + std::to_string(cus) != dev) continue;
+        if (mbw == 1 || mbw == 2 || mbw == 4) (*cache)[std::make_tuple(dev, path, C, npb)] = mbw;
+    }
+    std::fclose(fp);
+}
+
+static void append_tile_file(const std::string &dev, int path, int C, int npb, int mbw) {
+    const std::string f = tile_file(true);
+    if (f.empty()) return;
+    char line[512];
+    const int n = std::snprintf(line, sizeof line, "sbqa-tile-v1 %s %d %d %d %d\n", dev.c_str(), path, C, npb, mbw);
+    if (n <= 0 || n >= (int)sizeof line) return;
+    const int fd = ::open(f.c_str(), O_WRONLY | O_APPEND | O_CREAT, 0644);
+    if (fd < 0) return;
+    (void)!::write(fd, line, (size_t)n);   // one append: whole lines, also from concurrent processes
+    ::close(fd);
+}
+
 static int tune_dense_mbw(Path path, int C, int Np, hipStream_t st) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int>, int> cache;
+    static std::map<std::tuple<std::string, int, int, int>, int> cache;
+    static std::set<std::string> loaded;
     int npb = 128;
     while (npb < Np) npb *= 2;
-    const auto key = std::make_tuple((int)path, C, npb);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) return it->second;
-    }
     const int fallback = dense_mbw(C);
     std::vector<int> cand;
     for (int m : {1, 2, 4})
         if (m == fallback || round_up(C, 64 * m) <= 2 * round_up(C, 64)) cand.push_back(m);
+    const std::string dev = tile_device_tag();
+    const auto key = std::make_tuple(dev, (int)path, C, npb);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!dev.empty() && !loaded.count(dev)) {
+            load_tile_file(dev, &cache);
+            loaded.insert(dev);
+        }
+        auto it = cache.find(key);
+        if (it != cache.end() && std::find(cand.begin(), cand.end(), it->second) != cand.end()) return it->second;
+    }
     int best = fallback;
+    bool timed = false;
     if (cand.size() > 1) {
         const int planes = path == PATH_BF16X3 ? 2 : 1;
         const int Cgm = (int)round_up(C, 256), nkc = dense_nkc(path, Np);
@@ -439,10 +520,12 @@ static int tune_dense_mbw(Path path, int C, int Np, hipStream_t st) {
         if (e1) (void)hipEventDestroy(e1);
         for (void *p : bufs) (void)hipFree(p);
         if (!ok) best = fallback;
+        timed = ok;
         (void)hipGetLastError();
     }
     std::lock_guard<std::mutex> lk(mu);
     cache[key] = best;
+    if (timed && !dev.empty()) append_tile_file(dev, (int)path, C, npb, best);
     return best;
 }
 

@@ -11,6 +11,7 @@ Bars (see the readings of arXiv 2604.01050 documented with the oracle):
 """
 import math
 import os
+import subprocess
 import sys
 
 import numpy as np
@@ -19,6 +20,8 @@ import pytest
 import sbqa_instances as inst
 
 pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 TOL = 1e-5
 # split bf16: J = J_hi + J_lo + e_J with |e_J| <= 2^-17 |J| (two 8-bit mantissas),
@@ -1026,6 +1029,44 @@ def test_small_dense_loop_matches_streaming(sb, orc, name, N, R, runs, fmode, ee
     P = _orc_problem(orc, sb, ctx, J=J, h=h, fmode=fmode)
     jr = np.full(runs, 0.5)     # linear J_perp at step 0, exact in float32
     _check_step(orc, P, ctx, sb, X0, Y0, 0, S, jr, out[sb.LOOP_RESIDENT][0], out[sb.LOOP_RESIDENT][1], J=J, h=h)
+
+
+_TILE_PROBE = """
+import sys
+sys.path.insert(0, %r)
+import paper_2604_01050_amd as sb
+import sbqa_instances as inst
+ctx = sb.sbqa_create(J=inst.sk_pm1(1024, 5), R=16, runs=12, steps=10, precision=sb.PREC_FP8)
+print("tile", sb.sbqa_info(ctx)["tile_cols"])
+"""
+
+
+def test_tile_choices_persist_across_processes(tmp_path):
+    """The autotuned dense tile (C = 192: candidates of 64, 128 and 256
+    columns) is appended to the tile file named by SBQA_TUNE_CACHE; the next
+    process reads it back instead of timing again (nothing appended), uses an
+    edited choice as long as it is one of the key's candidates, and skips
+    malformed lines."""
+    f = tmp_path / "tiles.txt"
+    env = dict(os.environ, SBQA_TUNE_CACHE=str(f))
+
+    def run():
+        r = subprocess.run([sys.executable, "-c", _TILE_PROBE % ROOT], env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr[-2000:]
+        return int(r.stdout.split()[-1])
+
+    _log("tile file across processes: %s" % f)
+    t1 = run()
+    lines = f.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("sbqa-tile-v1 ") and int(lines[0].split()[-1]) * 64 == t1
+    assert run() == t1 and f.read_text().splitlines() == lines
+    fields = lines[0].split()
+    other = 1 if int(fields[-1]) != 1 else 4
+    f.write_text("garbage\nsbqa-tile-v1 gfx950\n" + " ".join(fields[:-1] + [str(other)]) + "\n")
+    assert run() == 64 * other
+    f.write_text(" ".join(fields[:-1] + ["3"]) + "\n")     # not a candidate: timed again and appended
+    assert run() in (64, 128, 256) and len(f.read_text().splitlines()) == 2
 
 
 def test_resident_rejects_unfit_instances(sb):
